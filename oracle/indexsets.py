@@ -1,0 +1,177 @@
+"""Index sets of the oracle: one-particle lists, invariant tuples, partitions.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Paper passages followed:
+  * O(3) one-particle index k = (n, l, m), |m| <= l  (Sec. 2.4)
+  * invariant tuples: sum of m equal to 0, sum of l even  (Sec. 2.4)
+  * torus one-particle index m, invariant tuples sum m = 0  (Sec. 2.3)
+  * total degree p = 1: sum over the tuple of (n_t + l_t), resp. |m_t|
+    (Sec. 2.5, Eq. (2.3); Sec. 3 explicit sets K_G(nu, D))
+  * integer partitions pi(k, n) of n into exactly k positive parts (Sec. 5.1)
+
+Canonical order (the paper leaves it open; fixed reading):
+  * O(3): one-particle triples sorted by (n + l, l, m) ascending.
+  * torus: m sorted by (|m|, m) ascending, i.e. 0, -1, 1, -2, 2, ...
+  A tuple is the non-decreasing list of positions in that list; sets of
+  tuples are ordered by length, then lexicographically.  The element of
+  largest degree is therefore the last one.
+"""
+
+from __future__ import annotations
+
+from functools import lru_cache
+
+
+# --------------------------------------------------------------------------
+# one-particle lists
+# --------------------------------------------------------------------------
+
+def onebody_o3(n_max: int, l_max: int, degree_max: int) -> list[tuple[int, int, int]]:
+    """All (n, l, m) with 0<=n<=n_max, 0<=l<=l_max, |m|<=l, n+l<=D.
+
+    Sec. 2.4 (phi_nlm = R_n Y_l^m, |m| <= l) with the degree n + l of
+    Sec. 2.5; n starts at 0 (R_0 = T_0 = 1).  Canonical order (n+l, l, m).
+    """
+    out = []
+    for n in range(n_max + 1):
+        for l in range(l_max + 1):
+            if n + l > degree_max:
+                continue
+            for m in range(-l, l + 1):
+                out.append((n, l, m))
+    out.sort(key=lambda t: (t[0] + t[1], t[1], t[2]))
+    return out
+
+
+def onebody_torus(degree_max: int) -> list[int]:
+    """All m with |m| <= D (Sec. 2.3, phi_m = e^{i theta m}); order (|m|, m)."""
+    out = list(range(-degree_max, degree_max + 1))
+    out.sort(key=lambda m: (abs(m), m))
+    return out
+
+
+# --------------------------------------------------------------------------
+# the group-specific data used by enumeration and by the graph builders
+# --------------------------------------------------------------------------
+
+class Group:
+    """Per-one-particle quantities a group needs: degree, m, l parity.
+
+    ``deg[i]``   degree of one-particle function i (n+l, resp. |m|)
+    ``m[i]``     its m quantum number
+    ``l[i]``     its l (0 for the torus)
+    ``check_l``  whether the inversion constraint (sum l even) applies
+    """
+
+    def __init__(self, name, labels, deg, m, l, check_l):
+        self.name = name
+        self.labels = labels
+        self.deg = deg
+        self.m = m
+        self.l = l
+        self.check_l = check_l
+
+    def __len__(self):
+        return len(self.labels)
+
+    def is_invariant(self, tup) -> bool:
+        """Sec. 2.3 / 2.4: sum m_t = 0 and (O(3) only) sum l_t even."""
+        if sum(self.m[i] for i in tup) != 0:
+            return False
+        if self.check_l and sum(self.l[i] for i in tup) % 2 != 0:
+            return False
+        return True
+
+    def degree(self, tup) -> int:
+        """Total degree, p = 1 (Sec. 2.5)."""
+        return sum(self.deg[i] for i in tup)
+
+
+def group_o3(n_max: int, l_max: int, degree_max: int) -> Group:
+    lab = onebody_o3(n_max, l_max, degree_max)
+    return Group("O3", lab, [n + l for (n, l, m) in lab], [m for (_, _, m) in lab],
+                 [l for (_, l, _) in lab], True)
+
+
+def group_torus(degree_max: int) -> Group:
+    lab = onebody_torus(degree_max)
+    return Group("T", lab, [abs(m) for m in lab], list(lab), [0] * len(lab), False)
+
+
+# --------------------------------------------------------------------------
+# invariant tuple sets K_G(nu, D)
+# --------------------------------------------------------------------------
+
+def invariant_tuples(group: Group, nu: int, degree_max: int) -> list[tuple[int, ...]]:
+    """K_G(nu, D): non-decreasing index tuples of length nu, invariant, deg <= D.
+
+    Sec. 3 (explicit sets K_T, K_SO(2), K_O(3)).  Plain depth-first listing
+    in lexicographic order; the only pruning is the degree budget, which is
+    exact because the one-particle list is sorted by degree.
+    """
+    P = len(group)
+    deg = group.deg
+    out: list[tuple[int, ...]] = []
+    cur: list[int] = []
+
+    def rec(start: int, left: int, budget: int):
+        if left == 0:
+            t = tuple(cur)
+            if group.is_invariant(t):
+                out.append(t)
+            return
+        for i in range(start, P):
+            # every later element has degree >= deg[i]
+            if deg[i] * left > budget:
+                break
+            cur.append(i)
+            rec(i, left - 1, budget - deg[i])
+            cur.pop()
+
+    rec(0, nu, degree_max)
+    return out
+
+
+def all_invariant_tuples(group: Group, nu_max: int, degree_max: int) -> list[tuple[int, ...]]:
+    """K = union over nu = 1..nu_max of K_G(nu, D), by length then lex (Eq. (1.1))."""
+    out = []
+    for nu in range(1, nu_max + 1):
+        out.extend(invariant_tuples(group, nu, degree_max))
+    return out
+
+
+# --------------------------------------------------------------------------
+# integer partitions (Sec. 5.1)
+# --------------------------------------------------------------------------
+
+@lru_cache(maxsize=None)
+def partitions_exact(k: int, n: int) -> int:
+    """pi(k, n): number of partitions of n into exactly k positive parts.
+
+    Sec. 5.1 definition, with pi(0, n) = 0 as the paper sets it (and
+    pi(0, 0) = 1 only as the base of the recursion below).  Recursion:
+    either some part equals 1 (remove it: pi(k-1, n-1)) or all parts are
+    >= 2 (subtract 1 from each: pi(k, n-k)).
+    """
+    if k == 0:
+        return 1 if n == 0 else 0
+    if n < k or k < 0:
+        return 0
+    return partitions_exact(k - 1, n - 1) + partitions_exact(k, n - k)
+
+
+def partitions_exact_public(k: int, n: int) -> int:
+    """pi(k, n) with the paper's convention pi(0, n) = 0 for every n."""
+    if k == 0:
+        return 0
+    return partitions_exact(k, n)
+
+
+def torus_aux_count_theorem(nu: int, degree_max: int) -> int:
+    """Thm 3.2(ii): #A_T(nu, D) = 2 sum_{k=2}^{nu-1} sum_{n=1}^{floor(D/2)} pi(k, n)."""
+    s = 0
+    for k in range(2, nu):
+        for n in range(1, degree_max // 2 + 1):
+            s += partitions_exact_public(k, n)
+    return 2 * s

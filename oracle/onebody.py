@@ -1,0 +1,149 @@
+"""One-particle basis phi_nlm(r) = R_n(|r|) Y_l^m(r/|r|), pooled A, gradients.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Paper passages followed:
+  * phi_nlm(r) = R_n(r) Y_l^m(r_hat), standard complex spherical harmonics
+    (Sec. 2.4);  A_k = sum_j phi_k(r_j)  (Sec. 2.1, Eq. (2.1)).
+  * The radial basis is "not essential" (Sec. 2.6); the workloads use
+    R_n(r) = T_n(cos(pi r / r_cut)), Chebyshev polynomials of the first kind,
+    n = 0..n_max.
+Convention for Y (the paper says only "standard complex"): orthonormal on
+the sphere, Condon-Shortley phase, azimuthal factor e^{+i m phi}, which is
+what scipy.special.sph_harm_y returns.
+
+Route of the derivatives (independent of any Cartesian recurrence):
+  dR_n/dr = T_n'(x) dx/dr,  T_n' = n U_{n-1}  (Chebyshev U by recurrence)
+  dY/dphi = i m Y
+  dY/dtheta = m cot(theta) Y_l^m + sqrt((l-m)(l+m+1)) e^{-i phi} Y_l^{m+1}
+  grad Y(r) = (theta_hat dY/dtheta + phi_hat dY/dphi / sin(theta)) / |r|
+The formulas divide by sin(theta); the oracle is only used on random
+directions, where theta is bounded away from 0 and pi.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import sph_harm_y
+
+
+def chebyshev_T(nmax: int, x: np.ndarray) -> np.ndarray:
+    """T_0..T_nmax at x by T_{n+1} = 2 x T_n - T_{n-1}; shape x.shape + (nmax+1,)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.empty(x.shape + (nmax + 1,))
+    out[..., 0] = 1.0
+    if nmax >= 1:
+        out[..., 1] = x
+    for n in range(1, nmax):
+        out[..., n + 1] = 2.0 * x * out[..., n] - out[..., n - 1]
+    return out
+
+
+def chebyshev_U(nmax: int, x: np.ndarray) -> np.ndarray:
+    """U_0..U_nmax at x by U_{n+1} = 2 x U_n - U_{n-1}, U_0 = 1, U_1 = 2x."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.empty(x.shape + (nmax + 1,))
+    out[..., 0] = 1.0
+    if nmax >= 1:
+        out[..., 1] = 2.0 * x
+    for n in range(1, nmax):
+        out[..., n + 1] = 2.0 * x * out[..., n] - out[..., n - 1]
+    return out
+
+
+def radial(nmax: int, r: np.ndarray, r_cut: float) -> np.ndarray:
+    """R_n(r) = T_n(cos(pi r / r_cut)), n = 0..nmax."""
+    return chebyshev_T(nmax, np.cos(np.pi * np.asarray(r) / r_cut))
+
+
+def radial_deriv(nmax: int, r: np.ndarray, r_cut: float) -> np.ndarray:
+    """dR_n/dr = n U_{n-1}(x) * dx/dr with x = cos(pi r / r_cut)."""
+    r = np.asarray(r, dtype=np.float64)
+    x = np.cos(np.pi * r / r_cut)
+    dxdr = -(np.pi / r_cut) * np.sin(np.pi * r / r_cut)
+    U = chebyshev_U(max(nmax - 1, 0), x)
+    out = np.zeros(r.shape + (nmax + 1,))
+    for n in range(1, nmax + 1):
+        out[..., n] = n * U[..., n - 1] * dxdr
+    return out
+
+
+def spherical_coords(pos: np.ndarray):
+    """|r|, polar angle theta in [0, pi], azimuth phi in (-pi, pi]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    r = np.sqrt(np.sum(pos * pos, axis=-1))
+    theta = np.arccos(np.clip(pos[..., 2] / r, -1.0, 1.0))
+    phi = np.arctan2(pos[..., 1], pos[..., 0])
+    return r, theta, phi
+
+
+def ylm(l: int, m: int, theta, phi):
+    """Complex orthonormal Y_l^m (Condon-Shortley, e^{+i m phi}); 0 if |m| > l."""
+    if abs(m) > l:
+        return np.zeros(np.broadcast(theta, phi).shape, dtype=np.complex128)
+    return sph_harm_y(l, m, theta, phi)
+
+
+def onebody_values(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """phi_i(r_j) for every one-particle triple (n, l, m) in `labels`; [J, P1]."""
+    r, th, ph = spherical_coords(pos)
+    nmax = max(n for (n, _, _) in labels)
+    R = radial(nmax, r, r_cut)
+    cache = {}
+    out = np.empty((len(r), len(labels)), dtype=np.complex128)
+    for i, (n, l, m) in enumerate(labels):
+        if (l, m) not in cache:
+            cache[(l, m)] = ylm(l, m, th, ph)
+        out[:, i] = R[:, n] * cache[(l, m)]
+    return out
+
+
+def onebody_gradients(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """grad_r phi_i(r_j); complex [J, P1, 3], by the spherical-coordinate route."""
+    pos = np.asarray(pos, dtype=np.float64)
+    r, th, ph = spherical_coords(pos)
+    nmax = max(n for (n, _, _) in labels)
+    R = radial(nmax, r, r_cut)
+    dR = radial_deriv(nmax, r, r_cut)
+    st, ct = np.sin(th), np.cos(th)
+    sp, cp = np.sin(ph), np.cos(ph)
+    rhat = pos / r[:, None]
+    that = np.stack([ct * cp, ct * sp, -st], axis=-1)
+    phat = np.stack([-sp, cp, np.zeros_like(sp)], axis=-1)
+    Ycache = {}
+
+    def Y(l, m):
+        if (l, m) not in Ycache:
+            Ycache[(l, m)] = ylm(l, m, th, ph)
+        return Ycache[(l, m)]
+
+    gcache = {}
+
+    def gradY(l, m):
+        if (l, m) not in gcache:
+            y = Y(l, m)
+            dth = m * (ct / st) * y
+            if m + 1 <= l:
+                dth = dth + np.sqrt((l - m) * (l + m + 1)) * np.exp(-1j * ph) * Y(l, m + 1)
+            dph = 1j * m * y
+            g = (that * dth[:, None] + phat * (dph / st)[:, None]) / r[:, None]
+            gcache[(l, m)] = g
+        return gcache[(l, m)]
+
+    out = np.empty((len(r), len(labels), 3), dtype=np.complex128)
+    for i, (n, l, m) in enumerate(labels):
+        out[:, i, :] = (dR[:, n] * Y(l, m))[:, None] * rhat + R[:, n][:, None] * gradY(l, m)
+    return out
+
+
+def pooled_A(labels, offsets: np.ndarray, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """A[e, i] = sum_{j in env e} phi_i(r_j)  (Sec. 2.1, Eq. (2.1)); [E, P1]."""
+    offsets = np.asarray(offsets)
+    E = len(offsets) - 1
+    vals = onebody_values(labels, pos, r_cut)
+    A = np.zeros((E, len(labels)), dtype=np.complex128)
+    for e in range(E):
+        a, b = int(offsets[e]), int(offsets[e + 1])
+        if b > a:
+            A[e] = vals[a:b].sum(axis=0)
+    return A
