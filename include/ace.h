@@ -1,0 +1,218 @@
+/*
+ * ace.h -- C ABI of the MI355X (gfx950) evaluator for symmetry-adapted
+ * n-correlations by recursive contraction over a product DAG.
+ *
+ * Method: Kaliuzhnyi & Ortner, "Optimal Evaluation of Symmetry-Adapted
+ * n-Correlations Via Recursive Contraction of Sparse Symmetric Tensors"
+ * (arXiv:2202.04140).
+ *
+ *   phi = sum_{nu=1}^{nu_max} sum_{k in K} c_k prod_{t=1}^{nu} A_{k_t}
+ *                                                       (Eq. (1.1), Eq. (2.1))
+ *   A_{nlm} = sum_j R_n(|r_j|) Y_l^m(r_j / |r_j|)        (Sec. 2.1, Sec. 2.4)
+ *   K = sorted tuples with sum m = 0, sum l even,
+ *       sum (n + l) <= D                                  (Sec. 2.4, 2.5, 3)
+ *
+ * The tuples of K are evaluated through a DAG in which every node of
+ * correlation order >= 2 is the product of two earlier nodes, with the
+ * auxiliary (non-invariant, zero-coefficient) nodes the sparsity requires,
+ * built by the insertion heuristic of Algorithm 1 (Sec. 2.6, Sec. 3.2) or
+ * Algorithm 2 (Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ *   - All floating point is IEEE binary64.  Complex numbers are stored as
+ *     interleaved (re, im) pairs of doubles.
+ *   - Every function returns an ace_status; ACE_OK is 0.  On failure a
+ *     human readable message is available from ace_last_error() (thread
+ *     local, valid until the next failing call on the same thread).  No C++
+ *     exception crosses this boundary.
+ *   - "device" pointers are HIP device allocations on the current device
+ *     (the caller allocates and frees them; the library never frees a
+ *     caller pointer).  "host" pointers are ordinary process memory.
+ *   - Evaluation calls are asynchronous on the given stream (a hipStream_t
+ *     passed as void*, NULL = the legacy default stream); results are valid
+ *     once the stream has been synchronised.  They allocate no memory: the
+ *     caller supplies a device workspace of at least ace_workspace_size()
+ *     bytes.  Calls that share a workspace must not overlap in time.
+ *   - Radial basis: R_n(r) = T_n(cos(pi r / r_cut)) (Chebyshev polynomials
+ *     of the first kind), n = 0..n_max.  Angular basis: complex, orthonormal
+ *     spherical harmonics with the Condon-Shortley phase and e^{+i m phi}
+ *     azimuthal factor, so Y_l^{-m} = (-1)^m conj(Y_l^m).
+ *   - One-particle order (the index i of A_i): triples (n, l, m) sorted by
+ *     (n + l, l, m) ascending.  Tuples are non-decreasing lists of such
+ *     indices; K is ordered by length, then lexicographically.  The
+ *     coefficient array c of every call follows this order of K.
+ */
+#ifndef ACE_H_
+#define ACE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ace_status;
+
+#define ACE_OK                0
+#define ACE_ERR_INVALID_ARG   1  /* a NULL pointer, negative size, bad spec ... */
+#define ACE_ERR_UNSUPPORTED   2  /* valid request this build does not implement */
+#define ACE_ERR_OUT_OF_MEMORY 3  /* host or device allocation failed (graph build) */
+#define ACE_ERR_HIP           4  /* a HIP runtime call failed */
+#define ACE_ERR_INTERNAL      5  /* internal consistency check failed */
+
+/* symmetry group of the one-particle basis (Sec. 2.2-2.4) */
+#define ACE_GROUP_O3    0   /* phi_nlm = R_n Y_l^m, sum m = 0 and sum l even */
+#define ACE_GROUP_TORUS 1   /* phi_m = e^{i m theta}, sum m = 0; graph only  */
+
+/* ace_basis_spec.build_flags */
+#define ACE_BUILD_HOST_ONLY 1u  /* build the DAG on the host only, no device upload */
+
+/* flags of the evaluation calls */
+#define ACE_FLAG_NAIVE 1u  /* evaluate each tuple's product directly (baseline) */
+#define ACE_FLAG_CHECK 2u  /* validate offsets on the host before launching
+                              (synchronous copy of offsets; not capture safe) */
+
+/*
+ * Basis specification.  Sec. 2.5 / Sec. 3 with p = 1 (total degree).
+ *   group       ACE_GROUP_O3 or ACE_GROUP_TORUS
+ *   nu_max      maximal correlation order, 1 <= nu_max <= 8
+ *   degree_max  D >= 0: total-degree cutoff sum_t (n_t + l_t) <= D
+ *               (torus: sum_t |m_t| <= D)
+ *   n_max,l_max radial / angular cutoffs (O(3) only), 0 <= l_max <= 16
+ *   algorithm   1 = Algorithm 1 (Sec. 3.2), 2 = Algorithm 2 (Sec. 3.3)
+ *   alg_n       Algorithm 2's parameter n >= 1 (ignored for algorithm 1)
+ *   r_cut       radial scale of R_n (> 0)
+ */
+typedef struct ace_basis_spec {
+  int32_t group;
+  int32_t nu_max;
+  int32_t degree_max;
+  int32_t n_max;
+  int32_t l_max;
+  int32_t algorithm;
+  int32_t alg_n;
+  int32_t reserved;
+  double r_cut;
+  uint32_t build_flags;
+  uint32_t reserved2;
+} ace_basis_spec;
+
+/* Graph statistics (Sec. 3.1: K, D/I split is not computed; A = aux). */
+typedef struct ace_graph_stats {
+  int64_t n_onep;            /* P1: one-particle functions                   */
+  int64_t n_k;               /* |K| over all orders                          */
+  int64_t n_k_by_order[9];   /* |K_G(nu, D)| for nu = 0..8 (index 0 unused)  */
+  int64_t n_nodes;           /* V: all DAG nodes including one-particle ones */
+  int64_t n_aux;             /* auxiliary nodes (product, not invariant)     */
+  int64_t n_aux_by_order[9];
+  int64_t depth;             /* number of product layers                     */
+  int64_t n_stored;          /* product nodes with at least one child        */
+  int64_t n_childless;       /* product nodes with no child                  */
+  int64_t n_leaf_parents;    /* one-particle nodes that have a child         */
+  int64_t n_layer[16];       /* nodes per layer (layer 0 = one-particle)     */
+  int64_t naive_cmuls;       /* sum over K of (nu - 1)                       */
+} ace_graph_stats;
+
+typedef struct ace_graph ace_graph;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ace_last_error(void);
+
+/* Library version string (static storage). */
+const char* ace_version(void);
+
+/*
+ * Build the DAG for `spec` on the host (K enumeration, Algorithm 1 or 2,
+ * layering, evaluation schedules) and, unless ACE_BUILD_HOST_ONLY is set,
+ * upload the schedules to the current HIP device.  Synchronous.  On success
+ * *out owns host and device memory until ace_graph_free.  The graph is
+ * immutable afterwards and may be shared by concurrent calls on any stream.
+ * Errors: ACE_ERR_INVALID_ARG (spec out of range), ACE_ERR_OUT_OF_MEMORY,
+ * ACE_ERR_HIP (device upload failed).
+ */
+ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
+
+/* Release a graph (NULL is a no-op).  No call using it may be in flight. */
+void ace_graph_free(ace_graph* g);
+
+/* Fill *stats (host).  Sec. 3.1 node and auxiliary counts. */
+ace_status ace_graph_info(const ace_graph* g, ace_graph_stats* stats);
+
+/*
+ * Copy the node list into caller-allocated HOST buffers (any may be NULL):
+ *   onep      [P1][3]       int32 (n, l, m) of each one-particle function
+ *                           (torus: (0, 0, m))
+ *   node_tuple[V][nu_max]   int32 sorted one-particle indices, -1 padded
+ *   parents   [V][2]        int32 parent node ids in insertion order
+ *                           (Sec. 2.6 k = [k1, k2]); -1 for one-particle nodes
+ *   k_to_node [|K|]         int64 node id of every tuple of K
+ * Node ids are insertion order (one-particle nodes 0..P1-1 first).
+ */
+ace_status ace_graph_export(const ace_graph* g, int32_t* onep, int32_t* node_tuple,
+                            int32_t* parents, int64_t* k_to_node);
+
+/* Copy the tuples of K into a caller HOST buffer [|K|][nu_max], -1 padded. */
+ace_status ace_graph_export_k(const ace_graph* g, int32_t* k_tuples);
+
+/*
+ * Device workspace (bytes) needed by the evaluation calls below for n_env
+ * environments and n_nbr neighbour vectors in total, with `flags`.
+ */
+ace_status ace_workspace_size(const ace_graph* g, int64_t n_env, int64_t n_nbr,
+                              uint32_t flags, size_t* bytes);
+
+/*
+ * One-particle basis with pooling, Sec. 2.1 Eq. (2.1) and Sec. 2.4:
+ *   A[e][i] = sum_{j in env e} R_{n_i}(|r_j|) Y_{l_i}^{m_i}(r_j/|r_j|)
+ *   offsets  device int32 [n_env+1], offsets[0] = 0, non-decreasing,
+ *            offsets[n_env] = n_nbr (neighbours of env e are
+ *            offsets[e] .. offsets[e+1]-1)
+ *   pos      device double [n_nbr][3] relative positions, |r_j| > 0
+ *   A        device double [n_env][P1][2] (output)
+ * An environment without neighbours gives A = 0.  O(3) graphs only.
+ */
+ace_status ace_basis(const ace_graph* g, int64_t n_env, const int32_t* offsets,
+                     const double* pos, double* A, void* stream);
+
+/*
+ * Recursive contraction from given one-particle values (Sec. 2.6):
+ *   phi[e]  = sum_{k in K} c_k prod_t A[e][k_t]             (Eq. (2.1))
+ *   Abar[e][i] = d phi[e] / d A[e][i]  (holomorphic derivative; optional)
+ *   coeffs  device double [|K|]
+ *   A       device double [n_env][P1][2]
+ *   phi     device double [n_env][2] (output)
+ *   Abar    device double [n_env][P1][2] (output) or NULL to skip the
+ *           reverse pass
+ *   workspace / ws_bytes   device scratch of >= ace_workspace_size(g,
+ *           n_env, 0, flags) bytes
+ */
+ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env,
+                        const double* A, double* phi, double* Abar,
+                        void* workspace, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
+ * Full path: one-particle basis, recursive DAG contraction (Eq. (2.1)).
+ *   phi  device double [n_env][2] = (Re phi_e, Im phi_e)
+ * Other arguments as for ace_basis / ace_contract.  n_env = 0 is a no-op.
+ */
+ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env,
+                    const int32_t* offsets, const double* pos, double* phi,
+                    void* workspace, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
+ * Full path with gradients: as ace_eval, plus
+ *   grad device double [n_nbr][3] = d Re(phi_e) / d r_j for every neighbour
+ *        j of environment e (forces are -grad)
+ * computed by the reverse pass over the DAG chained into dA/dr_j.
+ */
+ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env,
+                         const int32_t* offsets, const double* pos, double* phi,
+                         double* grad, void* workspace, size_t ws_bytes,
+                         uint32_t flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H_ */

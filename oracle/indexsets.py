@@ -107,15 +107,20 @@ def invariant_tuples(group: Group, nu: int, degree_max: int) -> list[tuple[int, 
     """K_G(nu, D): non-decreasing index tuples of length nu, invariant, deg <= D.
 
     Sec. 3 (explicit sets K_T, K_SO(2), K_O(3)).  Plain depth-first listing
-    in lexicographic order; the only pruning is the degree budget, which is
-    exact because the one-particle list is sorted by degree.
+    in lexicographic order.  Two exact prunings, neither of which drops a
+    member of K: the degree budget (the one-particle list is sorted by
+    degree, so later elements cost at least deg[i] each), and the m-sum
+    (every one-particle function has |m| <= l <= its degree, resp. |m| equal
+    to its degree, so the remaining degree budget bounds how far sum m can
+    still move).  Membership itself is decided by is_invariant.
     """
     P = len(group)
     deg = group.deg
+    mm = group.m
     out: list[tuple[int, ...]] = []
     cur: list[int] = []
 
-    def rec(start: int, left: int, budget: int):
+    def rec(start: int, left: int, budget: int, msum: int):
         if left == 0:
             t = tuple(cur)
             if group.is_invariant(t):
@@ -125,11 +130,14 @@ def invariant_tuples(group: Group, nu: int, degree_max: int) -> list[tuple[int, 
             # every later element has degree >= deg[i]
             if deg[i] * left > budget:
                 break
+            ms = msum + mm[i]
+            if abs(ms) > budget - deg[i]:
+                continue
             cur.append(i)
-            rec(i, left - 1, budget - deg[i])
+            rec(i, left - 1, budget - deg[i], ms)
             cur.pop()
 
-    rec(0, nu, degree_max)
+    rec(0, nu, degree_max, 0)
     return out
 
 

@@ -1,0 +1,342 @@
+"""Python binding of libace.so: recursive DAG evaluation of sparse symmetric
+ACE contractions on MI355X (gfx950), FP64.
+
+The binding only marshals arguments: every step of the evaluation runs in
+the HIP kernels behind the C ABI of include/ace.h.  PyTorch supplies device
+memory and the current stream.  If the library has not been built this
+module raises on first use; there is no CPU fallback.
+
+    g = Graph(nu_max=4, degree_max=12, n_max=6, l_max=6)
+    phi = eval(g, coeffs, offsets, pos)                  # [E, 2] (Re, Im)
+    phi, grad = eval_grad(g, coeffs, offsets, pos)       # grad [N, 3]
+    e = AceEnergy.apply(pos, offsets, coeffs, g)         # Re phi, differentiable
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+__all__ = [
+    "Graph", "basis", "contract", "eval", "eval_grad", "AceEnergy", "AceError",
+    "FLAG_NAIVE", "FLAG_CHECK", "GROUP_O3", "GROUP_TORUS", "library_path",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libace.so")
+
+GROUP_O3 = 0
+GROUP_TORUS = 1
+BUILD_HOST_ONLY = 1
+FLAG_NAIVE = 1
+FLAG_CHECK = 2
+
+_STATUS = {0: "ACE_OK", 1: "ACE_ERR_INVALID_ARG", 2: "ACE_ERR_UNSUPPORTED",
+           3: "ACE_ERR_OUT_OF_MEMORY", 4: "ACE_ERR_HIP", 5: "ACE_ERR_INTERNAL"}
+
+
+class AceError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Spec(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_int32), ("nu_max", ctypes.c_int32),
+                ("degree_max", ctypes.c_int32), ("n_max", ctypes.c_int32),
+                ("l_max", ctypes.c_int32), ("algorithm", ctypes.c_int32),
+                ("alg_n", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("r_cut", ctypes.c_double), ("build_flags", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_onep", ctypes.c_int64), ("n_k", ctypes.c_int64),
+                ("n_k_by_order", ctypes.c_int64 * 9), ("n_nodes", ctypes.c_int64),
+                ("n_aux", ctypes.c_int64), ("n_aux_by_order", ctypes.c_int64 * 9),
+                ("depth", ctypes.c_int64), ("n_stored", ctypes.c_int64),
+                ("n_childless", ctypes.c_int64), ("n_leaf_parents", ctypes.c_int64),
+                ("n_layer", ctypes.c_int64 * 16), ("naive_cmuls", ctypes.c_int64)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_SZ = ctypes.c_size_t
+
+EXPORTED = {
+    "ace_last_error": ([], ctypes.c_char_p),
+    "ace_version": ([], ctypes.c_char_p),
+    "ace_graph_build": ([ctypes.POINTER(_Spec), ctypes.POINTER(_P)], ctypes.c_int32),
+    "ace_graph_free": ([_P], None),
+    "ace_graph_info": ([_P, ctypes.POINTER(_Stats)], ctypes.c_int32),
+    "ace_graph_export": ([_P, _P, _P, _P, _P], ctypes.c_int32),
+    "ace_graph_export_k": ([_P, _P], ctypes.c_int32),
+    "ace_workspace_size": ([_P, _I64, _I64, _U32, ctypes.POINTER(_SZ)], ctypes.c_int32),
+    "ace_basis": ([_P, _I64, _P, _P, _P, _P], ctypes.c_int32),
+    "ace_contract": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
+    "ace_eval": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
+    "ace_eval_grad": ([_P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded libace.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError(
+                    f"{_LIB_PATH} is missing: build it with `python -m paper_2202_04140_amd.build` "
+                    "(there is no CPU fallback)")
+            handle = ctypes.CDLL(_LIB_PATH)
+            for name, (args, res) in EXPORTED.items():
+                fn = getattr(handle, name)
+                fn.argtypes = args
+                fn.restype = res
+            _lib = handle
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise AceError(status, lib().ace_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+class Graph:
+    """The DAG for a basis specification (ace_graph_build)."""
+
+    def __init__(self, nu_max: int, degree_max: int, n_max: int = 0, l_max: int = 0, *,
+                 group: int = GROUP_O3, algorithm: int = 1, alg_n: int = 1, r_cut: float = 5.0,
+                 host_only: bool = False):
+        spec = _Spec(group=group, nu_max=nu_max, degree_max=degree_max, n_max=n_max, l_max=l_max,
+                     algorithm=algorithm, alg_n=alg_n, reserved=0, r_cut=r_cut,
+                     build_flags=BUILD_HOST_ONLY if host_only else 0, reserved2=0)
+        self._h = _P()
+        _check(lib().ace_graph_build(ctypes.byref(spec), ctypes.byref(self._h)))
+        self.spec = dict(group=group, nu_max=nu_max, degree_max=degree_max, n_max=n_max,
+                         l_max=l_max, algorithm=algorithm, alg_n=alg_n, r_cut=r_cut)
+        self.host_only = host_only
+        st = self.stats()
+        self.P1 = st["n_onep"]
+        self.nK = st["n_k"]
+        self.n_nodes = st["n_nodes"]
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ace_graph_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib().ace_graph_info(self._h, ctypes.byref(s)))
+        out = {}
+        for name, _ in _Stats._fields_:
+            v = getattr(s, name)
+            out[name] = list(v) if not isinstance(v, int) else v
+        return out
+
+    def export(self):
+        """(onep [P1,3], node_tuple [V,nu_max], parents [V,2], k_to_node [|K|])."""
+        nu = self.spec["nu_max"]
+        onep = np.zeros((self.P1, 3), dtype=np.int32)
+        tup = np.zeros((self.n_nodes, nu), dtype=np.int32)
+        par = np.zeros((self.n_nodes, 2), dtype=np.int32)
+        k2n = np.zeros(self.nK, dtype=np.int64)
+        _check(lib().ace_graph_export(self._h, onep.ctypes.data, tup.ctypes.data,
+                                      par.ctypes.data, k2n.ctypes.data))
+        return onep, tup, par, k2n
+
+    def k_tuples(self) -> np.ndarray:
+        out = np.zeros((self.nK, self.spec["nu_max"]), dtype=np.int32)
+        _check(lib().ace_graph_export_k(self._h, out.ctypes.data))
+        return out
+
+    def k_degrees(self) -> np.ndarray:
+        """Total degree sum_t (n_t + l_t) of every tuple of K (torus: sum |m|)."""
+        onep = self.export()[0]
+        if self.spec["group"] == GROUP_O3:
+            deg1 = onep[:, 0] + onep[:, 1]
+        else:
+            deg1 = np.abs(onep[:, 2])
+        kt = self.k_tuples()
+        d = np.where(kt >= 0, deg1[np.maximum(kt, 0)], 0)
+        return d.sum(axis=1)
+
+    def workspace_size(self, n_env: int, n_nbr: int = 0, flags: int = 0) -> int:
+        out = _SZ()
+        _check(lib().ace_workspace_size(self._h, int(n_env), int(n_nbr), int(flags), ctypes.byref(out)))
+        return int(out.value)
+
+    def workspace(self, n_env: int, device):
+        """A cached device workspace of at least workspace_size(n_env) bytes."""
+        import torch
+        need = self.workspace_size(n_env)
+        key = str(device)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+
+# ---------------------------------------------------------------------------
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _check_coeffs(g: "Graph", coeffs):
+    if coeffs.dim() != 1 or coeffs.numel() != g.nK:
+        raise ValueError(f"coeffs must have shape [{g.nK}] (one per tuple of K), got {tuple(coeffs.shape)}")
+
+
+def _check_batch(offsets, pos, check: bool):
+    if offsets.dim() != 1 or offsets.numel() < 1:
+        raise ValueError("offsets must be a 1-d tensor of n_env + 1 entries")
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError(f"pos must have shape [n_nbr, 3], got {tuple(pos.shape)}")
+    if check and offsets.numel() > 1:
+        last = int(offsets[-1].item())
+        if last != pos.shape[0]:
+            raise ValueError(f"offsets[-1] = {last} but pos has {pos.shape[0]} rows")
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def basis(g: Graph, offsets, pos):
+    """A[e, i] (ace_basis); returns float64 [E, P1, 2]."""
+    import torch
+    _dev(offsets, torch.int32, "offsets")
+    _dev(pos, torch.float64, "pos")
+    _check_batch(offsets, pos, True)
+    E = offsets.numel() - 1
+    A = torch.empty((E, g.P1, 2), dtype=torch.float64, device=pos.device)
+    _check(lib().ace_basis(g.handle, E, offsets.data_ptr(), pos.data_ptr(), A.data_ptr(),
+                           _stream(pos.device)))
+    return A
+
+
+def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = False):
+    """phi [E,2] (and Abar [E,P1,2]) from given one-particle values A [E,P1,2]."""
+    import torch
+    _dev(coeffs, torch.float64, "coeffs")
+    _dev(A, torch.float64, "A")
+    _check_coeffs(g, coeffs)
+    if A.dim() != 3 or A.shape[1] != g.P1 or A.shape[2] != 2:
+        raise ValueError(f"A must have shape [n_env, {g.P1}, 2], got {tuple(A.shape)}")
+    E = A.shape[0]
+    phi = torch.empty((E, 2), dtype=torch.float64, device=A.device)
+    Abar = torch.empty_like(A) if with_grad else None
+    ws = g.workspace(E, A.device)
+    flags = FLAG_NAIVE if naive else 0
+    _check(lib().ace_contract(g.handle, coeffs.data_ptr(), E, A.data_ptr(), phi.data_ptr(),
+                              Abar.data_ptr() if Abar is not None else None,
+                              ws.data_ptr(), ws.numel(), flags, _stream(A.device)))
+    return (phi, Abar) if with_grad else phi
+
+
+def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False, out=None):
+    """phi [E, 2] = (Re, Im) by ace_eval."""
+    import torch
+    _dev(coeffs, torch.float64, "coeffs")
+    _dev(offsets, torch.int32, "offsets")
+    _dev(pos, torch.float64, "pos")
+    _check_coeffs(g, coeffs)
+    _check_batch(offsets, pos, check)
+    E = offsets.numel() - 1
+    phi = out if out is not None else torch.empty((E, 2), dtype=torch.float64, device=pos.device)
+    ws = g.workspace(E, pos.device)
+    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0)
+    _check(lib().ace_eval(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
+                          phi.data_ptr(), ws.data_ptr(), ws.numel(), flags, _stream(pos.device)))
+    return phi
+
+
+def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False,
+              out=None):
+    """(phi [E, 2], grad [N, 3]) by ace_eval_grad; grad = d Re(phi_e)/d r_j."""
+    import torch
+    _dev(coeffs, torch.float64, "coeffs")
+    _dev(offsets, torch.int32, "offsets")
+    _dev(pos, torch.float64, "pos")
+    _check_coeffs(g, coeffs)
+    _check_batch(offsets, pos, check)
+    E = offsets.numel() - 1
+    if out is not None:
+        phi, grad = out
+    else:
+        phi = torch.empty((E, 2), dtype=torch.float64, device=pos.device)
+        grad = torch.empty_like(pos)
+    ws = g.workspace(E, pos.device)
+    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0)
+    _check(lib().ace_eval_grad(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
+                               phi.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), flags,
+                               _stream(pos.device)))
+    return phi, grad
+
+
+def _autograd():
+    import torch
+
+    class AceEnergy(torch.autograd.Function):
+        """Re(phi_e) per environment; backward scatters grad_out[e] * g_j.
+
+        forward(pos [N,3] f64, offsets [E+1] i32, coeffs [|K|] f64, graph)
+        The gradient with respect to pos comes from ace_eval_grad; offsets,
+        coeffs and the graph get none.  Double backward is not supported.
+        """
+
+        @staticmethod
+        def forward(ctx, pos, offsets, coeffs, graph):
+            phi, grad = eval_grad(graph, coeffs, offsets, pos.detach().contiguous())
+            ctx.save_for_backward(grad, offsets)
+            return phi[:, 0].clone()
+
+        @staticmethod
+        @torch.autograd.function.once_differentiable
+        def backward(ctx, grad_out):
+            grad, offsets = ctx.saved_tensors
+            counts = (offsets[1:] - offsets[:-1]).long()
+            w = torch.repeat_interleave(grad_out.contiguous(), counts, output_size=grad.shape[0])
+            return grad * w[:, None], None, None, None
+
+    return AceEnergy
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _autograd()
+        return getattr(_Lazy._cls, name)
+
+
+AceEnergy = _Lazy()

@@ -1,0 +1,78 @@
+// Device-side argument blocks shared by the kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ace {
+
+constexpr int kMaxLayers = 16;
+
+// One-particle basis (Sec. 2.4): per one-particle index i its n, the offset
+// of (l, |m|) in the per-neighbour Y table, and the signs mapping
+// Y_l^{|m|} to Y_l^{m} (Y_l^{-m} = (-1)^m conj(Y_l^m)).
+struct OnepInfo {
+  int16_t n;
+  int16_t yoff;   // (l*(l+1))/2 + |m|
+  int8_t sre;     // +1 / -1 applied to Re Y_l^{|m|}
+  int8_t sim;     // +1 / -1 applied to Im Y_l^{|m|}
+  int16_t pad;
+};
+
+struct BasisArgs {
+  int64_t n_env;
+  const int32_t* offsets;
+  const double* pos;
+  double2* A;            // [n_env][P1]
+  const OnepInfo* onep;  // [P1]
+  const double* ycoef;   // [3][(L+1)*(L+2)/2]: A, B, start (start only at l = m)
+  int P1, n_max, l_max;
+  double r_cut;
+};
+
+// Forward / adjoint DAG schedule.  Value slots: one-particle nodes
+// 0..P1-1, stored product nodes (nodes with a child) P1..P1+S-1 in layer
+// order.  Childless product nodes have no slot.
+struct DagArgs {
+  int64_t n_env;
+  const double2* A;      // [n_env][P1]
+  double2* phi;          // [n_env]
+  double2* Abar;         // [n_env][P1] or nullptr (forward only)
+  const double* coeffs;  // [|K|]
+  const int2* st_ab;     // [S] parent slots of stored nodes
+  const int32_t* st_k;   // [S] K index or -1
+  const int2* cl_ab;     // [T] parent slots of childless nodes
+  const int32_t* cl_k;   // [T] K index
+  const int32_t* leaf_k; // [P1] K index or -1
+  double2* arena_x;      // [gridDim][slots] when the value arena is not in LDS
+  double2* arena_ab;     // [gridDim][slots] when the adjoint arena is not in LDS
+  int P1, S, slots, depth;
+  int st_off[kMaxLayers + 2];  // stored nodes of layer L: [st_off[L], st_off[L+1])
+  int cl_off[kMaxLayers + 2];
+};
+
+struct NaiveArgs {
+  int64_t n_env;
+  const double2* A;
+  double2* phi;
+  double2* Abar;
+  const double* coeffs;
+  const int16_t* tup;  // [nK][nu_max], padded with P1 (the constant-one slot)
+  int64_t nK;
+  int P1, nu_max;
+};
+
+struct GradArgs {
+  int64_t n_env;
+  const int32_t* offsets;
+  const double* pos;
+  const double2* Abar;       // [n_env][P1]
+  double* grad;              // [n_nbr][3]
+  const int16_t* onep_index; // [(n_max+1)][(l_max+1)][(2 l_max+1)] -> i or -1
+  const double* ycoef;
+  int P1, n_max, l_max;
+  double r_cut;
+};
+
+}  // namespace ace

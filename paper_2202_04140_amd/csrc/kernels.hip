@@ -1,0 +1,430 @@
+// gfx950 kernels of the evaluator.  All arithmetic is binary64 on the
+// vector ALU: the DAG is a chain of sparse complex products, not a dense
+// contraction, so no matrix-core instruction is used.
+//
+//   basis_kernel   A_{nlm} = sum_j R_n(|r_j|) Y_l^m(r_j/|r_j|)   (Sec. 2.1, 2.4)
+//   dag_kernel     x_v = x_a * x_b over the DAG layers, phi = sum_k c_k x_k,
+//                  and optionally the reverse pass giving dphi/dA   (Sec. 2.6)
+//   naive_kernel   phi = sum_k c_k prod_t A_{k_t} tuple by tuple     (Eq. (1.1))
+//   grad_kernel    d Re(phi)/d r_j = Re sum_i Abar_i grad(R_n Y_l^m)(r_j)
+#include "ace_kernels.hpp"
+
+namespace ace {
+
+// ---------------------------------------------------------------------------
+// complex helpers (double2 = (re, im))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// acc += a * b
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc += s * a   (s real)
+__device__ __forceinline__ double2 rfma(double s, double2 a, double2 acc) {
+  acc.x = fma(s, a.x, acc.x);
+  acc.y = fma(s, a.y, acc.y);
+  return acc;
+}
+
+// Sum of one double2 per thread over the block, in a fixed order.
+// `scratch` needs blockDim.x / 64 entries.  Result valid in thread 0.
+__device__ __forceinline__ double2 block_sum(double2 v, double2* scratch) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) scratch[wid] = v;
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) {
+      s.x += scratch[w].x;
+      s.y += scratch[w].y;
+    }
+  }
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// one-particle basis
+// ---------------------------------------------------------------------------
+// Per-neighbour table: T_n(c) for n = 0..n_max, then (Re, Im) Y_l^m for
+// m >= 0 at offset (l(l+1)/2 + m).  Y by the associated-Legendre
+// recurrence in Cartesian form: Y_l^m = q_l^m(z) (x + i y)^m with
+//   q_m^m = start_m,  q_l^m = A_lm z q_{l-1}^m - B_lm q_{l-2}^m
+// (normalisation and Condon-Shortley phase folded into the coefficients
+// on the host).  This form has no division by sin(theta).
+__device__ void neighbour_table(const double* r, const double* ycoef, int n_max, int l_max,
+                                double r_cut, double* tab) {
+  const double rx = r[0], ry = r[1], rz = r[2];
+  const double rr = sqrt(rx * rx + ry * ry + rz * rz);
+  const double inv = 1.0 / rr;
+  const double x = rx * inv, y = ry * inv, z = rz * inv;
+  const double c = cos(M_PI * rr / r_cut);
+  double t0 = 1.0, t1 = c;
+  tab[0] = 1.0;
+  if (n_max >= 1) tab[1] = c;
+  for (int n = 2; n <= n_max; ++n) {
+    const double t2 = 2.0 * c * t1 - t0;
+    tab[n] = t2;
+    t0 = t1;
+    t1 = t2;
+  }
+  double* Y = tab + (n_max + 1);
+  const int NY = (l_max + 1) * (l_max + 2) / 2;
+  const double* cA = ycoef;
+  const double* cB = ycoef + NY;
+  const double* cS = ycoef + 2 * NY;
+  double pr = 1.0, pi = 0.0;  // (x + i y)^m
+  for (int m = 0; m <= l_max; ++m) {
+    double q2 = 0.0, q1 = cS[(m * (m + 1)) / 2 + m];
+    for (int l = m; l <= l_max; ++l) {
+      const int o = (l * (l + 1)) / 2 + m;
+      double q;
+      if (l == m) {
+        q = q1;
+      } else {
+        q = cA[o] * z * q1 - cB[o] * q2;
+        q2 = q1;
+        q1 = q;
+      }
+      Y[2 * o] = q * pr;
+      Y[2 * o + 1] = q * pi;
+    }
+    const double npr = pr * x - pi * y;
+    const double npi = pr * y + pi * x;
+    pr = npr;
+    pi = npi;
+  }
+}
+
+constexpr int kBasisChunk = 32;
+
+__global__ __launch_bounds__(256) void basis_kernel(BasisArgs p) {
+  extern __shared__ double lds_b[];
+  const int NY = (p.l_max + 1) * (p.l_max + 2) / 2;
+  const int stride = (p.n_max + 1) + 2 * NY;
+  double2* acc = reinterpret_cast<double2*>(lds_b);  // [P1]
+  double* tab = lds_b + 2 * p.P1;                     // [kBasisChunk][stride]
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    const int j0 = p.offsets[e];
+    const int J = p.offsets[e + 1] - j0;
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) acc[i] = make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < J; c0 += kBasisChunk) {
+      const int nc = min(kBasisChunk, J - c0);
+      __syncthreads();
+      if (threadIdx.x < nc)
+        neighbour_table(p.pos + 3 * (int64_t)(j0 + c0 + threadIdx.x), p.ycoef, p.n_max, p.l_max, p.r_cut,
+                        tab + threadIdx.x * stride);
+      __syncthreads();
+      for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
+        const OnepInfo o = p.onep[i];
+        double2 a = acc[i];
+        const double sre = (double)o.sre, sim = (double)o.sim;
+        for (int jj = 0; jj < nc; ++jj) {
+          const double* t = tab + jj * stride;
+          const double R = t[o.n];
+          const double* Y = t + (p.n_max + 1) + 2 * o.yoff;
+          a.x = fma(R, sre * Y[0], a.x);
+          a.y = fma(R, sim * Y[1], a.y);
+        }
+        acc[i] = a;
+      }
+    }
+    __syncthreads();
+    double2* Ae = p.A + e * p.P1;
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) Ae[i] = acc[i];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DAG forward + reverse pass
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void atomic_cadd(double2* addr, double2 v) {
+  atomicAdd(&addr->x, v.x);
+  atomicAdd(&addr->y, v.y);
+}
+
+__device__ __forceinline__ double coef_of(const double* coeffs, int k) {
+  return k >= 0 ? coeffs[k] : 0.0;
+}
+
+// XL: value arena in LDS; AL: adjoint arena in LDS.  One block per
+// environment at a time (grid-stride over environments).
+template <bool XL, bool AL>
+__global__ __launch_bounds__(256) void dag_kernel(DagArgs p) {
+  extern __shared__ double2 lds[];
+  const int nl = (XL ? p.slots : 0) + (AL ? p.slots : 0);
+  double2* red = lds + nl;
+  double2* x = XL ? lds : p.arena_x + (int64_t)blockIdx.x * p.slots;
+  double2* ab = AL ? lds + (XL ? p.slots : 0) : p.arena_ab + (int64_t)blockIdx.x * p.slots;
+  const int P1 = p.P1;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    const double2* Ae = p.A + e * P1;
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) x[i] = Ae[i];
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) {
+      const int k = p.leaf_k[i];
+      if (k >= 0) acc = rfma(p.coeffs[k], x[i], acc);
+    }
+    for (int L = 1; L <= p.depth; ++L) {
+      for (int i = p.st_off[L] + threadIdx.x; i < p.st_off[L + 1]; i += blockDim.x) {
+        const int2 ab2 = p.st_ab[i];
+        const double2 v = cmul(x[ab2.x], x[ab2.y]);
+        x[P1 + i] = v;
+        acc = rfma(coef_of(p.coeffs, p.st_k[i]), v, acc);
+      }
+      for (int i = p.cl_off[L] + threadIdx.x; i < p.cl_off[L + 1]; i += blockDim.x) {
+        const int2 ab2 = p.cl_ab[i];
+        const double2 v = cmul(x[ab2.x], x[ab2.y]);
+        acc = rfma(p.coeffs[p.cl_k[i]], v, acc);
+      }
+      __syncthreads();
+    }
+    const double2 phi = block_sum(acc, red);
+    if (threadIdx.x == 0) p.phi[e] = phi;
+
+    if (p.Abar != nullptr) {
+      // reverse pass: abar_s = d phi / d x_s, pushed from children to parents
+      // layer by layer, top down (every child of a layer-L node lies above L)
+      for (int s = threadIdx.x; s < p.slots; s += blockDim.x) {
+        const int k = s < P1 ? p.leaf_k[s] : p.st_k[s - P1];
+        ab[s] = make_double2(coef_of(p.coeffs, k), 0.0);
+      }
+      __syncthreads();
+      for (int L = p.depth; L >= 1; --L) {
+        for (int i = p.cl_off[L] + threadIdx.x; i < p.cl_off[L + 1]; i += blockDim.x) {
+          const int2 ab2 = p.cl_ab[i];
+          const double c = p.coeffs[p.cl_k[i]];
+          const double2 xa = x[ab2.x], xb = x[ab2.y];
+          atomic_cadd(&ab[ab2.x], make_double2(c * xb.x, c * xb.y));
+          atomic_cadd(&ab[ab2.y], make_double2(c * xa.x, c * xa.y));
+        }
+        for (int i = p.st_off[L] + threadIdx.x; i < p.st_off[L + 1]; i += blockDim.x) {
+          const int2 ab2 = p.st_ab[i];
+          const double2 w = ab[P1 + i];
+          atomic_cadd(&ab[ab2.x], cmul(w, x[ab2.y]));
+          atomic_cadd(&ab[ab2.y], cmul(w, x[ab2.x]));
+        }
+        __syncthreads();
+      }
+      double2* Be = p.Abar + e * P1;
+      for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
+    }
+    __syncthreads();
+  }
+}
+
+template __global__ void dag_kernel<true, true>(DagArgs);
+template __global__ void dag_kernel<true, false>(DagArgs);
+template __global__ void dag_kernel<false, false>(DagArgs);
+
+// ---------------------------------------------------------------------------
+// naive per-tuple evaluation (the baseline): phi = sum_k c_k prod_t A_{k_t},
+// gradient by prefix / suffix products.  A sits in LDS with one extra slot
+// holding 1 so shorter tuples need no branch.
+// ---------------------------------------------------------------------------
+template <int NU>
+__global__ __launch_bounds__(256) void naive_kernel(NaiveArgs p) {
+  extern __shared__ double2 lds[];
+  const int P1 = p.P1;
+  double2* x = lds;                // [P1 + 1]
+  double2* ab = lds + (P1 + 1);    // [P1 + 1]
+  double2* red = ab + (P1 + 1);
+  const bool grad = p.Abar != nullptr;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    const double2* Ae = p.A + e * P1;
+    for (int i = threadIdx.x; i <= P1; i += blockDim.x) {
+      x[i] = i < P1 ? Ae[i] : make_double2(1.0, 0.0);
+      ab[i] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t q = threadIdx.x; q < p.nK; q += blockDim.x) {
+      const int16_t* t = p.tup + q * NU;
+      double2 v[NU];
+#pragma unroll
+      for (int s = 0; s < NU; ++s) v[s] = x[t[s]];
+      double2 pre[NU + 1];
+      pre[0] = make_double2(1.0, 0.0);
+#pragma unroll
+      for (int s = 0; s < NU; ++s) pre[s + 1] = cmul(pre[s], v[s]);
+      const double c = p.coeffs[q];
+      acc = rfma(c, pre[NU], acc);
+      if (grad) {
+        double2 suf = make_double2(c, 0.0);
+#pragma unroll
+        for (int s = NU - 1; s >= 0; --s) {
+          atomic_cadd(&ab[t[s]], cmul(pre[s], suf));
+          suf = cmul(suf, v[s]);
+        }
+      }
+    }
+    __syncthreads();
+    const double2 phi = block_sum(acc, red);
+    if (threadIdx.x == 0) p.phi[e] = phi;
+    if (grad) {
+      double2* Be = p.Abar + e * P1;
+      for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
+    }
+    __syncthreads();
+  }
+}
+
+template __global__ void naive_kernel<1>(NaiveArgs);
+template __global__ void naive_kernel<2>(NaiveArgs);
+template __global__ void naive_kernel<3>(NaiveArgs);
+template __global__ void naive_kernel<4>(NaiveArgs);
+template __global__ void naive_kernel<5>(NaiveArgs);
+template __global__ void naive_kernel<6>(NaiveArgs);
+template __global__ void naive_kernel<7>(NaiveArgs);
+template __global__ void naive_kernel<8>(NaiveArgs);
+
+// ---------------------------------------------------------------------------
+// dA/dr chain: one thread per neighbour.
+//   grad(R_n Y_l^m)(r) = R_n'(r) u Y_l^m(u) + R_n(r) grad Y_l^m(r)
+// With S_l^m(r) = (x + i y)^m Q_l^m(z, rho), rho = |r|^2, a homogeneous
+// polynomial of degree l equal to r^l Y_l^m(u) (u = r / |r|),
+//   grad Y_l^m(r) = (grad S(u) - l S(u) u) / |r|,
+// where Q follows the same recurrence as q with the constant term scaled
+// by rho, differentiated in z and rho alongside (no pole singularity).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void grad_kernel(GradArgs p) {
+  extern __shared__ double2 lds[];
+  double2* Ab = lds;  // [P1]
+  int16_t* idx = reinterpret_cast<int16_t*>(lds + p.P1);
+  const int L = p.l_max, N = p.n_max;
+  const int W = 2 * L + 1;
+  const int nidx = (N + 1) * (L + 1) * W;
+  const int NY = (L + 1) * (L + 2) / 2;
+  const double* cA = p.ycoef;
+  const double* cB = p.ycoef + NY;
+  const double* cS = p.ycoef + 2 * NY;
+  for (int i = threadIdx.x; i < nidx; i += blockDim.x) idx[i] = p.onep_index[i];
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    __syncthreads();
+    const double2* Be = p.Abar + e * p.P1;
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) Ab[i] = Be[i];
+    __syncthreads();
+    const int j0 = p.offsets[e];
+    const int J = p.offsets[e + 1] - j0;
+    for (int jj = threadIdx.x; jj < J; jj += blockDim.x) {
+      const int64_t j = j0 + jj;
+      const double rx = p.pos[3 * j], ry = p.pos[3 * j + 1], rz = p.pos[3 * j + 2];
+      const double rr = sqrt(rx * rx + ry * ry + rz * rz);
+      const double inv = 1.0 / rr;
+      const double x = rx * inv, y = ry * inv, z = rz * inv;
+      const double arg = M_PI * rr / p.r_cut;
+      const double c = cos(arg);
+      const double dcdr = -(M_PI / p.r_cut) * sin(arg);
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      // (x + i y)^m and (x + i y)^(m-1)
+      double pr = 1.0, pi = 0.0, qr = 0.0, qi = 0.0;
+      for (int m = 0; m <= L; ++m) {
+        double Q2 = 0.0, Qz2 = 0.0, Qp2 = 0.0;
+        double Q1 = cS[(m * (m + 1)) / 2 + m], Qz1 = 0.0, Qp1 = 0.0;
+        for (int l = m; l <= L; ++l) {
+          const int o = (l * (l + 1)) / 2 + m;
+          double Q, Qz, Qp;
+          if (l == m) {
+            Q = Q1;
+            Qz = 0.0;
+            Qp = 0.0;
+          } else {
+            const double a = cA[o], b = cB[o];
+            Q = a * z * Q1 - b * Q2;
+            Qz = a * (Q1 + z * Qz1) - b * Qz2;
+            Qp = a * z * Qp1 - b * (Q2 + Qp2);
+            Q2 = Q1;
+            Qz2 = Qz1;
+            Qp2 = Qp1;
+            Q1 = Q;
+            Qz1 = Qz;
+            Qp1 = Qp;
+          }
+          // S = (x+iy)^m Q ; grad S at u
+          const double Sr = pr * Q, Si = pi * Q;
+          double dxr = 2.0 * x * Qp * pr, dxi = 2.0 * x * Qp * pi;
+          double dyr = 2.0 * y * Qp * pr, dyi = 2.0 * y * Qp * pi;
+          const double dzr = (Qz + 2.0 * z * Qp) * pr, dzi = (Qz + 2.0 * z * Qp) * pi;
+          if (m > 0) {
+            dxr += m * qr * Q;
+            dxi += m * qi * Q;
+            dyr -= m * qi * Q;  // i m (x+iy)^(m-1) Q
+            dyi += m * qr * Q;
+          }
+          // grad Y = (grad S - l S u) / r
+          const double lf = (double)l;
+          const double gYxr = (dxr - lf * Sr * x) * inv, gYxi = (dxi - lf * Si * x) * inv;
+          const double gYyr = (dyr - lf * Sr * y) * inv, gYyi = (dyi - lf * Si * y) * inv;
+          const double gYzr = (dzr - lf * Sr * z) * inv, gYzi = (dzi - lf * Si * z) * inv;
+          // both signs of m: Y_l^{-m} = (-1)^m conj(Y_l^m), same for grad
+          for (int sgn = 0; sgn < (m > 0 ? 2 : 1); ++sgn) {
+            const int mm = sgn == 0 ? m : -m;
+            const double fr = (sgn == 0 || (m & 1) == 0) ? 1.0 : -1.0;
+            const double fi = sgn == 0 ? fr : -fr;
+            // B0 = sum_n Abar_{n l mm} T_n, B1 = sum_n Abar_{n l mm} T_n'
+            double b0r = 0.0, b0i = 0.0, b1r = 0.0, b1i = 0.0;
+            double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
+            for (int n = 0; n <= N; ++n) {
+              double T, dT;
+              if (n == 0) {
+                T = 1.0;
+                dT = 0.0;
+              } else if (n == 1) {
+                T = c;
+                dT = 1.0;
+              } else {
+                T = 2.0 * c * t1 - t0;
+                dT = 2.0 * t1 + 2.0 * c * d1 - d0;
+                t0 = t1;
+                t1 = T;
+                d0 = d1;
+                d1 = dT;
+              }
+              const int ii = idx[(n * (L + 1) + l) * W + (mm + L)];
+              if (ii >= 0) {
+                const double2 a = Ab[ii];
+                b0r = fma(a.x, T, b0r);
+                b0i = fma(a.y, T, b0i);
+                b1r = fma(a.x, dT, b1r);
+                b1i = fma(a.y, dT, b1i);
+              }
+            }
+            b1r *= dcdr;
+            b1i *= dcdr;
+            // Re(B1 * Y) u + Re(B0 * gradY), with Y -> (fr Re, fi Im)
+            const double Yr = fr * Sr, Yi = fi * Si;
+            const double radial = b1r * Yr - b1i * Yi;
+            gx += radial * x + b0r * fr * gYxr - b0i * fi * gYxi;
+            gy += radial * y + b0r * fr * gYyr - b0i * fi * gYyi;
+            gz += radial * z + b0r * fr * gYzr - b0i * fi * gYzi;
+          }
+        }
+        qr = pr;
+        qi = pi;
+        const double npr = pr * x - pi * y;
+        const double npi = pr * y + pi * x;
+        pr = npr;
+        pi = npi;
+      }
+      p.grad[3 * j] = gx;
+      p.grad[3 * j + 1] = gy;
+      p.grad[3 * j + 2] = gz;
+    }
+  }
+}
+
+}  // namespace ace

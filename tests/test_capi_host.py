@@ -1,0 +1,167 @@
+"""Host-side tests of libace.so: exports, the graph builder (bit-exact
+against the oracle builder), statistics and error handling.  No GPU needed."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2202_04140_amd as ace
+from oracle.graph import OracleGraph
+from oracle.indexsets import group_o3, group_torus
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ace.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ace_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ace.lib()
+    names = header_functions()
+    assert "ace_eval_grad" in names and "ace_graph_build" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a prototype for each of them
+    assert set(names) == set(ace.EXPORTED)
+
+
+def test_version_and_no_error():
+    assert ace.lib().ace_version().startswith(b"ace-dag")
+
+
+def oracle_arrays(group, nu, D, alg=1, n=1):
+    G = OracleGraph(group, nu, D, alg, n)
+    tup = np.full((G.n_nodes(), nu), -1, np.int32)
+    for v, t in enumerate(G.node_tuple):
+        tup[v, :len(t)] = t
+    par = np.array([p if p is not None else (-1, -1) for p in G.parents], np.int32)
+    return G, tup, par, np.array(G.k_to_node, np.int64)
+
+
+@pytest.mark.parametrize("spec,alg,n", [((4, 4, 8, 3), 1, 1), ((6, 6, 12, 4), 1, 1),
+                                        ((4, 4, 8, 3), 2, 2), ((6, 6, 12, 4), 2, 2),
+                                        ((3, 2, 9, 5), 1, 1), ((2, 3, 10, 6), 2, 3)])
+def test_builder_bit_exact_o3(spec, alg, n):
+    nmax, lmax, D, nu = spec
+    g = ace.Graph(nu, D, nmax, lmax, algorithm=alg, alg_n=n, host_only=True)
+    onep, tup, par, k2n = g.export()
+    G, otup, opar, ok2n = oracle_arrays(group_o3(nmax, lmax, D), nu, D, alg, n)
+    assert onep.tolist() == [list(t) for t in G.group.labels]
+    np.testing.assert_array_equal(tup, otup)
+    np.testing.assert_array_equal(par, opar)
+    np.testing.assert_array_equal(k2n, ok2n)
+    kt = g.k_tuples()
+    okt = np.full((len(G.K), nu), -1, np.int32)
+    for q, k in enumerate(G.K):
+        okt[q, :len(k)] = k
+    np.testing.assert_array_equal(kt, okt)
+    st = g.stats()
+    assert st["n_aux"] == G.aux_count()
+    lay = G.layers()
+    assert st["depth"] == max(lay)
+    assert st["n_layer"][:max(lay) + 1] == [lay.count(L) for L in range(max(lay) + 1)]
+
+
+@pytest.mark.parametrize("nu,D,alg,n", [(4, 10, 1, 1), (6, 12, 1, 1), (5, 12, 2, 2)])
+def test_builder_bit_exact_torus(nu, D, alg, n):
+    g = ace.Graph(nu, D, group=ace.GROUP_TORUS, algorithm=alg, alg_n=n, host_only=True)
+    _, tup, par, k2n = g.export()
+    _, otup, opar, ok2n = oracle_arrays(group_torus(D), nu, D, alg, n)
+    np.testing.assert_array_equal(tup, otup)
+    np.testing.assert_array_equal(par, opar)
+    np.testing.assert_array_equal(k2n, ok2n)
+
+
+# Regression values: |K| per order, V, aux per order, depth, layer sizes, stored and
+# childless product nodes, leaves with children, naive complex products.  Computed
+# once from the definitions (Algorithm 1 with the fixed split order); the first two
+# rows are reproduced independently by the oracle builder in the test above.
+REGRESSION = {
+    (4, 4, 8, 3): dict(k=[15, 228, 959], V=1440, aux=[128], depth=2, layers=[125, 356, 959],
+                       S=356, T=959, leafpar=93, naive=2146),
+    (6, 6, 12, 4): dict(k=[28, 1098, 9932, 34918], V=47830, aux=[1058, 481], depth=3,
+                        layers=[343, 2156, 30381, 14950], S=7511, T=39976, leafpar=263, naive=125716),
+    (8, 8, 14, 5): dict(k=[43, 2338, 27320, 122061, 297008], V=453816, aux=[2450, 1585, 374], depth=4,
+                        layers=[680, 4788, 97494, 342789, 8065], S=60743, T=392393, leafpar=461,
+                        naive=1611193),
+}
+
+
+@pytest.mark.parametrize("spec", list(REGRESSION))
+def test_builder_regression_counts(spec):
+    nmax, lmax, D, nu = spec
+    r = REGRESSION[spec]
+    st = ace.Graph(nu, D, nmax, lmax, host_only=True).stats()
+    assert st["n_k_by_order"][1:nu + 1] == r["k"]
+    assert st["n_nodes"] == r["V"]
+    assert st["n_aux_by_order"][2:2 + len(r["aux"])] == r["aux"]
+    assert st["depth"] == r["depth"]
+    assert st["n_layer"][:r["depth"] + 1] == r["layers"]
+    assert st["n_stored"] == r["S"] and st["n_childless"] == r["T"]
+    assert st["n_leaf_parents"] == r["leafpar"]
+    assert st["naive_cmuls"] == r["naive"]
+
+
+@pytest.mark.slow
+def test_builder_large_basis_counts():
+    st = ace.Graph(6, 16, 10, 10, host_only=True).stats()
+    assert st["n_k"] == 3692953
+    assert st["n_nodes"] == 3705306
+    assert st["n_aux_by_order"][2:6] == [4944, 4641, 1373, 314]
+    assert st["n_stored"] == 256091 and st["n_childless"] == 3448074
+
+
+def test_torus_theorem_count_through_the_c_builder():
+    from oracle.indexsets import torus_aux_count_theorem
+    for nu in range(3, 7):
+        for D in (4, 8, 12, 20):
+            st = ace.Graph(nu, D, group=ace.GROUP_TORUS, host_only=True).stats()
+            assert st["n_aux"] == torus_aux_count_theorem(nu, D)
+
+
+# ---- error paths -----------------------------------------------------------------
+@pytest.mark.parametrize("kw", [dict(nu_max=0, degree_max=4), dict(nu_max=9, degree_max=4),
+                                dict(nu_max=3, degree_max=-1), dict(nu_max=3, degree_max=4, l_max=17),
+                                dict(nu_max=3, degree_max=4, algorithm=3),
+                                dict(nu_max=3, degree_max=4, algorithm=2, alg_n=0),
+                                dict(nu_max=3, degree_max=4, r_cut=0.0),
+                                dict(nu_max=3, degree_max=4, group=7)])
+def test_invalid_spec(kw):
+    with pytest.raises(ace.AceError) as ei:
+        ace.Graph(host_only=True, **kw)
+    assert ei.value.status == 1
+    assert len(ace.lib().ace_last_error()) > 0
+
+
+def test_null_arguments():
+    lib = ace.lib()
+    assert lib.ace_graph_build(None, None) == 1
+    assert lib.ace_graph_info(None, None) == 1
+    assert lib.ace_graph_export(None, None, None, None, None) == 1
+    out = ctypes.c_size_t()
+    assert lib.ace_workspace_size(None, 1, 1, 0, ctypes.byref(out)) == 1
+    lib.ace_graph_free(None)  # no-op
+
+
+def test_host_only_graph_rejects_device_calls():
+    g = ace.Graph(3, 8, 4, 4, host_only=True)
+    lib = ace.lib()
+    out = ctypes.c_size_t()
+    assert lib.ace_workspace_size(g.handle, 4, 4, 0, ctypes.byref(out)) == 1
+    assert lib.ace_eval(g.handle, None, 1, None, None, None, None, 0, 0, None) == 1
+    assert b"HOST_ONLY" in lib.ace_last_error()
+
+
+def test_device_build_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(ace.AceError) as ei:
+        ace.Graph(3, 8, 4, 4)
+    assert ei.value.status == 4

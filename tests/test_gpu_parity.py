@@ -1,0 +1,323 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (norm-wise over the batch, complex values for phi and A):
+  A    <= 1e-13      (one-particle basis; ~P1 * J roundings of O(1) terms)
+  phi  <= 1e-11      (stated target)
+  Abar <= 1e-11      (same arithmetic depth as phi)
+  grad <= 1e-9       (stated target for forces)
+The same seeded inputs go to both sides; the oracle computes its own K,
+one-particle list and coefficients' degrees.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import contraction as oc
+from oracle import onebody as ob
+from oracle.indexsets import all_invariant_tuples, group_o3
+
+pytestmark = pytest.mark.gpu
+
+TOL_A, TOL_PHI, TOL_ABAR, TOL_GRAD = 1e-13, 1e-11, 1e-11, 1e-9
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+_ORACLE = {}
+_GRAPH = {}
+
+
+def oracle_basis(wid):
+    """(group, K, c) from the oracle's own enumeration (cached)."""
+    if wid not in _ORACLE:
+        w = wl.WORKLOADS[wid]
+        g = group_o3(w.n_max, w.l_max, w.degree_max)
+        K = all_invariant_tuples(g, w.nu_max, w.degree_max)
+        c = wl.coefficients(w, np.array([g.degree(k) for k in K]))
+        _ORACLE[wid] = (g, K, c)
+    return _ORACLE[wid]
+
+
+def graph(wid, device):
+    import paper_2202_04140_amd as ace
+    if wid not in _GRAPH:
+        w = wl.WORKLOADS[wid]
+        G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
+        g, K, _ = oracle_basis(wid)
+        kt = G.k_tuples()
+        assert kt.shape[0] == len(K)
+        for q in (0, len(K) // 3, len(K) - 1):
+            assert tuple(x for x in kt[q] if x >= 0) == K[q]
+        _GRAPH[wid] = G
+    return _GRAPH[wid]
+
+
+def to_dev(device, *arrs):
+    import torch
+    out = []
+    for a in arrs:
+        if a.dtype == np.int32:
+            out.append(torch.from_numpy(np.ascontiguousarray(a)).to(device))
+        else:
+            out.append(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device))
+    return out
+
+
+def cplx(t):
+    a = t.detach().cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def problem(wid, n_env=None, envs=None):
+    w = wl.WORKLOADS[wid]
+    off, pos = wl.batch(w)
+    if envs is None and n_env is not None:
+        envs = wl.subset(off, n_env)
+    if envs is not None:
+        off, pos = wl.gather(off, pos, envs)
+    return off, pos
+
+
+# ---- one-particle basis ------------------------------------------------------------
+@pytest.mark.parametrize("wid,n_env", [(1, None), (2, 64), (4, 32), (5, 8)])
+def test_basis_parity(device, wid, n_env):
+    import paper_2202_04140_amd as ace
+    print(f"basis wid={wid} n_env={n_env}", flush=True)
+    G = graph(wid, device)
+    g, _, _ = oracle_basis(wid)
+    off, pos = problem(wid, n_env)
+    toff, tpos = to_dev(device, off, pos)
+    A = cplx(ace.basis(G, toff, tpos))
+    ref = ob.pooled_A(g.labels, off, pos, wl.WORKLOADS[wid].r_cut)
+    assert rel(A, ref) <= TOL_A
+
+
+# ---- contraction alone, from random one-particle values ----------------------------
+@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("wid,n_env", [(1, 16), (2, 48), (4, 6)])
+def test_contract_random_A(device, wid, n_env, naive):
+    import paper_2202_04140_amd as ace
+    print(f"contract wid={wid} n_env={n_env} naive={naive}", flush=True)
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    A = wl.random_A(n_env, len(g), seed=100 + wid) * 0.5
+    At = np.stack([A.real, A.imag], -1)
+    tc, tA = to_dev(device, c, At)
+    phi, Ab = ace.contract(G, tc, tA, with_grad=True, naive=naive)
+    phi_ref = oc.phi_naive(K, c, A)
+    ab_ref = oc.abar_naive(K, c, A)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(cplx(Ab), ab_ref) <= TOL_ABAR
+    # forward-only launch gives the same phi
+    phi2 = ace.contract(G, tc, tA, with_grad=False, naive=naive)
+    assert rel(cplx(phi2), phi_ref) <= TOL_PHI
+
+
+# ---- full path ---------------------------------------------------------------------
+@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("wid,n_env", [(1, None), (2, 96)])
+def test_eval_parity(device, wid, n_env, naive):
+    import paper_2202_04140_amd as ace
+    print(f"eval wid={wid} n_env={n_env} naive={naive}", flush=True)
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid, n_env)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi = cplx(ace.eval(G, tc, toff, tpos, naive=naive, check=True))
+    ref = oc.eval_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
+    assert rel(phi, ref) <= TOL_PHI
+
+
+@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("wid,n_env", [(1, None), (3, 64), (4, 12)])
+def test_eval_grad_parity(device, wid, n_env, naive):
+    import paper_2202_04140_amd as ace
+    print(f"eval_grad wid={wid} n_env={n_env} naive={naive}", flush=True)
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid, n_env)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos, naive=naive)
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+
+
+def test_full_size_sampled_and_dag_vs_naive(device):
+    """Workload 3 at full size, in the launch configuration the benchmark times;
+    24 sampled environments (incl. the smallest and largest) against the oracle,
+    and every environment DAG against naive."""
+    import paper_2202_04140_amd as ace
+    wid = 3
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid)
+    print(f"full size wid=3 n_env={len(off) - 1}", flush=True)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos)
+    phi_n, grad_n = ace.eval_grad(G, tc, toff, tpos, naive=True)
+    phi, grad, phi_n, grad_n = cplx(phi), grad.cpu().numpy(), cplx(phi_n), grad_n.cpu().numpy()
+    assert rel(phi, phi_n) <= TOL_PHI
+    assert rel(grad, grad_n) <= TOL_GRAD
+    envs = wl.subset(off, 24)
+    so, sp_ = wl.gather(off, pos, envs)
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, so, sp_, wl.WORKLOADS[wid].r_cut)
+    rows = np.concatenate([np.arange(off[e], off[e + 1]) for e in envs])
+    assert rel(phi[envs], phi_ref) <= TOL_PHI
+    assert rel(grad[rows], g_ref) <= TOL_GRAD
+
+
+# ---- edge cases ----------------------------------------------------------------------
+def test_edge_cases_empty_ragged(device):
+    import paper_2202_04140_amd as ace
+    import torch
+    wid = 1
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    # empty batch: no-op
+    tc, = to_dev(device, c)
+    z = torch.zeros(1, dtype=torch.int32, device=device)
+    p0 = torch.zeros((0, 3), dtype=torch.float64, device=device)
+    assert ace.eval(G, tc, z, p0).shape == (0, 2)
+    # environments with 0, 1, 2 and many neighbours
+    counts = [0, 1, 2, 0, 37, 1, 64]
+    off = np.zeros(len(counts) + 1, np.int32)
+    off[1:] = np.cumsum(counts)
+    pos = wl.positions(int(off[-1]), 77)
+    toff, tpos = to_dev(device, off, pos)
+    for naive in (False, True):
+        phi, grad = ace.eval_grad(G, tc, toff, tpos, naive=naive)
+        phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, 5.0)
+        phi = cplx(phi)
+        assert phi[0] == 0 and phi[3] == 0
+        assert rel(phi, phi_ref) <= TOL_PHI
+        assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+
+
+def test_invalid_offsets_rejected_with_check(device):
+    import paper_2202_04140_amd as ace
+    G = graph(1, device)
+    _, _, c = oracle_basis(1)
+    off = np.array([0, 5, 3], np.int32)   # decreasing
+    pos = wl.positions(5, 78)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    with pytest.raises((ace.AceError, ValueError)):   # binding check
+        ace.eval(G, tc, toff, tpos, check=True)
+    # the library's own check (ACE_FLAG_CHECK) without the binding in front
+    import torch
+    phi = torch.empty((2, 2), dtype=torch.float64, device=device)
+    ws = G.workspace(2, device)
+    st = ace.lib().ace_eval(G.handle, tc.data_ptr(), 2, toff.data_ptr(), tpos.data_ptr(), phi.data_ptr(),
+                            ws.data_ptr(), ws.numel(), ace.FLAG_CHECK, None)
+    assert st == 1 and b"non-decreasing" in ace.lib().ace_last_error()
+
+
+def test_workspace_too_small_is_an_error(device):
+    import ctypes
+    import paper_2202_04140_amd as ace
+    import torch
+    G = graph(1, device)
+    _, _, c = oracle_basis(1)
+    off, pos = problem(1)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi = torch.empty((16, 2), dtype=torch.float64, device=device)
+    ws = torch.empty(64, dtype=torch.uint8, device=device)
+    st = ace.lib().ace_eval(G.handle, tc.data_ptr(), 16, toff.data_ptr(), tpos.data_ptr(), phi.data_ptr(),
+                            ws.data_ptr(), 64, 0, None)
+    assert st == 1
+    assert b"workspace too small" in ace.lib().ace_last_error()
+
+
+# ---- gradient against central differences of the GPU path ---------------------------
+def test_gradient_central_differences(device):
+    import paper_2202_04140_amd as ace
+    import torch
+    wid = 3
+    G = graph(wid, device)
+    _, _, c = oracle_basis(wid)
+    off, pos = problem(wid, 8)
+    tc, toff = to_dev(device, c, off)
+    tpos, = to_dev(device, pos)
+    _, grad = ace.eval_grad(G, tc, toff, tpos)
+    grad = grad.cpu().numpy()
+    h = 1e-6
+    J = np.diff(off)
+    fd = np.zeros_like(pos)
+    for jj in range(int(J.max())):
+        envs = np.nonzero(J > jj)[0]
+        rows = off[envs] + jj
+        for d in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[rows, d] += h
+            pm[rows, d] -= h
+            fp = ace.eval(G, tc, toff, torch.from_numpy(pp).to(device))[:, 0].cpu().numpy()
+            fm = ace.eval(G, tc, toff, torch.from_numpy(pm).to(device))[:, 0].cpu().numpy()
+            fd[rows, d] = (fp[envs] - fm[envs]) / (2 * h)
+    assert rel(grad, fd) <= 1e-6
+
+
+# ---- symmetries and determinism on the device ----------------------------------------
+def test_invariance_and_determinism(device):
+    import paper_2202_04140_amd as ace
+    import torch
+    wid = 3
+    G = graph(wid, device)
+    _, _, c = oracle_basis(wid)
+    off, pos = problem(wid, 32)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi0 = cplx(ace.eval(G, tc, toff, tpos))
+    phi1 = cplx(ace.eval(G, tc, toff, tpos))
+    assert np.array_equal(phi0, phi1)                 # forward pass has a fixed order
+    a = 0.61
+    Q = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    phiq = cplx(ace.eval(G, tc, toff, torch.from_numpy(pos @ Q.T).to(device)))
+    assert rel(phiq, phi0) <= 1e-12
+    phii = cplx(ace.eval(G, tc, toff, torch.from_numpy(-pos).to(device)))
+    assert rel(phii, phi0) <= 1e-12
+    rng = np.random.default_rng(0)
+    perm = np.concatenate([off[e] + rng.permutation(off[e + 1] - off[e]) for e in range(len(off) - 1)])
+    phip = cplx(ace.eval(G, tc, toff, torch.from_numpy(pos[perm]).to(device)))
+    assert rel(phip, phi0) <= 1e-12
+
+
+def test_autograd_function(device):
+    import paper_2202_04140_amd as ace
+    import torch
+    wid = 1
+    G = graph(wid, device)
+    _, _, c = oracle_basis(wid)
+    off, pos = problem(wid)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    p = tpos.clone().requires_grad_(True)
+    e = ace.AceEnergy.apply(p, toff, tc, G)
+    w = torch.linspace(-1, 1, e.shape[0], dtype=torch.float64, device=device)
+    (e * w).sum().backward()
+    _, grad = ace.eval_grad(G, tc, toff, tpos)
+    counts = (toff[1:] - toff[:-1]).long()
+    ref = grad * torch.repeat_interleave(w, counts)[:, None]
+    # separate launches: the reverse pass accumulates with atomics, so allow rounding
+    assert torch.allclose(p.grad, ref, rtol=1e-12, atol=1e-14 * ref.abs().max().item())
+    phi = ace.eval(G, tc, toff, tpos)
+    assert torch.allclose(e.detach(), phi[:, 0], rtol=1e-14, atol=0)
+
+
+# ---- large bases, sampled ----------------------------------------------------------------
+@pytest.mark.parametrize("wid,n_env", [(4, 16), (5, 3)])
+def test_large_basis_eval_grad(device, wid, n_env):
+    import paper_2202_04140_amd as ace
+    print(f"large wid={wid} n_env={n_env}", flush=True)
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid, n_env)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos)
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
