@@ -72,6 +72,8 @@ typedef int32_t ace_status;
 #define ACE_FLAG_NAIVE 1u  /* evaluate each tuple's product directly (baseline) */
 #define ACE_FLAG_CHECK 2u  /* validate offsets on the host before launching
                               (synchronous copy of offsets; not capture safe) */
+#define ACE_FLAG_LAYERED 4u /* evaluate the DAG layer by layer even where the
+                              forest schedule applies (for testing) */
 
 /*
  * Basis specification.  Sec. 2.5 / Sec. 3 with p = 1 (total degree).
@@ -210,6 +212,25 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
                          const int32_t* offsets, const double* pos, double* phi,
                          double* grad, void* workspace, size_t ws_bytes,
                          uint32_t flags, void* stream);
+
+/*
+ * Introspection for tests (host only, no device work).
+ *
+ * ace_debug_schedule: *kind = 1 if evaluation uses the forest schedule
+ *   (one-particle and order-2 node values resident in LDS, every higher
+ *   node computed in registers), 0 if it uses the layer-by-layer schedule;
+ *   in the latter case ace_last_error() names the reason.
+ *
+ * ace_debug_forest_eval: runs the forest schedule on the host for n_env
+ *   environments, with the same indices, padding and forwarding as the
+ *   kernel and every index bounds-checked.  coeffs [|K|], A [n_env][P1][2],
+ *   phi [n_env][2], Abar [n_env][P1][2], all HOST pointers.
+ *   ACE_ERR_UNSUPPORTED if the graph has no forest schedule,
+ *   ACE_ERR_INTERNAL if an index of the schedule is out of range.
+ */
+ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind);
+ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
+                                 double* phi, double* Abar);
 
 #ifdef __cplusplus
 }

@@ -33,6 +33,7 @@ GROUP_TORUS = 1
 BUILD_HOST_ONLY = 1
 FLAG_NAIVE = 1
 FLAG_CHECK = 2
+FLAG_LAYERED = 4
 
 _STATUS = {0: "ACE_OK", 1: "ACE_ERR_INVALID_ARG", 2: "ACE_ERR_UNSUPPORTED",
            3: "ACE_ERR_OUT_OF_MEMORY", 4: "ACE_ERR_HIP", 5: "ACE_ERR_INTERNAL"}
@@ -83,6 +84,8 @@ EXPORTED = {
     "ace_contract": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval_grad": ([_P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
+    "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
+    "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
 }
 
 
@@ -180,6 +183,24 @@ class Graph:
         d = np.where(kt >= 0, deg1[np.maximum(kt, 0)], 0)
         return d.sum(axis=1)
 
+    def schedule_kind(self) -> str:
+        """'forest' or 'layered' (ace_debug_schedule)."""
+        k = ctypes.c_int32()
+        _check(lib().ace_debug_schedule(self._h, ctypes.byref(k)))
+        return "forest" if k.value == 1 else "layered"
+
+    def forest_eval_host(self, coeffs: np.ndarray, A: np.ndarray):
+        """Host emulation of the forest kernel (ace_debug_forest_eval):
+        coeffs [|K|] float64, A [E, P1] complex -> (phi [E], Abar [E, P1])."""
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        E = A.shape[0]
+        Ar = np.ascontiguousarray(np.stack([A.real, A.imag], -1), dtype=np.float64)
+        phi = np.zeros((E, 2))
+        ab = np.zeros((E, self.P1, 2))
+        _check(lib().ace_debug_forest_eval(self._h, c.ctypes.data, E, Ar.ctypes.data, phi.ctypes.data,
+                                           ab.ctypes.data))
+        return phi[:, 0] + 1j * phi[:, 1], ab[..., 0] + 1j * ab[..., 1]
+
     def workspace_size(self, n_env: int, n_nbr: int = 0, flags: int = 0) -> int:
         out = _SZ()
         _check(lib().ace_workspace_size(self._h, int(n_env), int(n_nbr), int(flags), ctypes.byref(out)))
@@ -243,7 +264,8 @@ def basis(g: Graph, offsets, pos):
     return A
 
 
-def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = False):
+def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = False,
+             layered: bool = False):
     """phi [E,2] (and Abar [E,P1,2]) from given one-particle values A [E,P1,2]."""
     import torch
     _dev(coeffs, torch.float64, "coeffs")
@@ -255,14 +277,15 @@ def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = Fals
     phi = torch.empty((E, 2), dtype=torch.float64, device=A.device)
     Abar = torch.empty_like(A) if with_grad else None
     ws = g.workspace(E, A.device)
-    flags = FLAG_NAIVE if naive else 0
+    flags = (FLAG_NAIVE if naive else 0) | (FLAG_LAYERED if layered else 0)
     _check(lib().ace_contract(g.handle, coeffs.data_ptr(), E, A.data_ptr(), phi.data_ptr(),
                               Abar.data_ptr() if Abar is not None else None,
                               ws.data_ptr(), ws.numel(), flags, _stream(A.device)))
     return (phi, Abar) if with_grad else phi
 
 
-def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False, out=None):
+def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False, out=None,
+         layered: bool = False):
     """phi [E, 2] = (Re, Im) by ace_eval."""
     import torch
     _dev(coeffs, torch.float64, "coeffs")
@@ -273,14 +296,14 @@ def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = F
     E = offsets.numel() - 1
     phi = out if out is not None else torch.empty((E, 2), dtype=torch.float64, device=pos.device)
     ws = g.workspace(E, pos.device)
-    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0)
+    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
     _check(lib().ace_eval(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                           phi.data_ptr(), ws.data_ptr(), ws.numel(), flags, _stream(pos.device)))
     return phi
 
 
 def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False,
-              out=None):
+              out=None, layered: bool = False):
     """(phi [E, 2], grad [N, 3]) by ace_eval_grad; grad = d Re(phi_e)/d r_j."""
     import torch
     _dev(coeffs, torch.float64, "coeffs")
@@ -295,7 +318,7 @@ def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: boo
         phi = torch.empty((E, 2), dtype=torch.float64, device=pos.device)
         grad = torch.empty_like(pos)
     ws = g.workspace(E, pos.device)
-    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0)
+    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
     _check(lib().ace_eval_grad(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                                phi.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), flags,
                                _stream(pos.device)))

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -78,6 +79,24 @@ struct ace_graph {
   bool fwd_xl = false;    // forward-only: value arena in LDS
   bool grad_xl = false;   // forward+reverse: value arena in LDS
   bool grad_al = false;   // forward+reverse: adjoint arena in LDS
+  // forest schedule (forest_kernel); used when forest_ok
+  bool forest_ok = false;
+  std::string forest_why;
+  int N2 = 0, nslot = 0, n_mslices = 0, n_tslices = 0;
+  bool has_gc = false;
+  std::vector<uint32_t> nu2_ab, it_ab;
+  std::vector<int4> mr_slice, tr_slice;
+  std::vector<uint16_t> mr_row, me_col, ch_s, gc_s;
+  std::vector<int2> ch_g;
+  std::vector<int32_t> kmap;
+  int cs_leaf = 0, cs_nu2 = 0, cs_me = 0, cs_it = 0, cs_ch = 0, cs_gc = 0;
+  void* fmem = nullptr;
+  uint32_t *d_nu2_ab = nullptr, *d_it_ab = nullptr;
+  int4 *d_mr_slice = nullptr, *d_tr_slice = nullptr;
+  uint16_t *d_mr_row = nullptr, *d_me_col = nullptr, *d_ch_s = nullptr, *d_gc_s = nullptr;
+  int2* d_ch_g = nullptr;
+  int32_t* d_kmap = nullptr;
+  bool forest_fwd_lds = false, forest_grad_lds = false;
 };
 
 namespace {
@@ -201,6 +220,320 @@ void make_schedule(ace_graph* g) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forest schedule (see forest_kernel in kernels.hip).
+// ---------------------------------------------------------------------------
+constexpr int kTreeChunk = 16;   // children per tree item at most
+constexpr int kRowChunk = 32;    // resident-pair entries per row item at most
+
+void make_forest(ace_graph* g) {
+  const HostGraph& h = g->h;
+  const int64_t V = h.n_nodes();
+  const int P1 = h.P1;
+  g->forest_ok = false;
+  auto fail_forest = [&](const char* why) { g->forest_why = why; };
+  // liveness and live children (parents precede children in insertion order)
+  std::vector<uint8_t> live(V, 0);
+  for (int64_t v = 0; v < V; ++v) live[v] = h.node_k[v] >= 0;
+  std::vector<int32_t> nlc(V, 0);
+  for (int64_t v = V - 1; v >= P1; --v) {
+    if (!live[v]) continue;
+    const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
+    live[a] = live[b] = 1;
+    nlc[a] += 1;
+    nlc[b] += 1;
+  }
+  // resident slots: one-particle nodes, ZERO = P1, live order-2 nodes
+  std::vector<int32_t> slot(V, -1);
+  for (int i = 0; i < P1; ++i) slot[i] = i;
+  std::vector<int32_t> nu2;
+  for (int64_t v = P1; v < V; ++v)
+    if (live[v] && h.layer[v] == 1) {
+      slot[v] = P1 + 1 + (int32_t)nu2.size();
+      nu2.push_back((int32_t)v);
+    }
+  const int nslot = P1 + 1 + (int)nu2.size();
+  if (nslot > 65535) return fail_forest("more than 65535 resident slots");
+  // classify product nodes above order 2
+  std::vector<int32_t> primary(V, -1), sib(V, -1);
+  std::vector<int32_t> roots, pairs;
+  for (int64_t v = P1; v < V; ++v) {
+    if (!live[v] || h.layer[v] < 2) continue;
+    const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
+    const bool ra = slot[a] >= 0, rb = slot[b] >= 0;
+    if (ra && rb) {
+      (nlc[v] > 0 ? roots : pairs).push_back((int32_t)v);
+    } else if (ra || rb) {
+      primary[v] = ra ? b : a;
+      sib[v] = slot[ra ? a : b];
+    } else {
+      return fail_forest("a node with two non-resident parents");
+    }
+  }
+  std::vector<std::vector<int32_t>> kids(V);
+  for (int64_t v = P1; v < V; ++v)
+    if (primary[v] >= 0) kids[primary[v]].push_back((int32_t)v);
+  for (int64_t v = P1; v < V; ++v)
+    if (live[v] && h.layer[v] >= 2 && (int64_t)kids[v].size() != nlc[v])
+      return fail_forest("inconsistent child lists");
+  bool has_gc = false;
+  for (int32_t r : roots)
+    for (int32_t c : kids[r])
+      if (!kids[c].empty()) {
+        has_gc = true;
+        for (int32_t gch : kids[c])
+          if (!kids[gch].empty()) return fail_forest("trees deeper than two levels");
+      }
+  g->has_gc = has_gc;
+  g->N2 = (int)nu2.size();
+  g->nslot = nslot;
+
+  // ---- tree items (root, chunk of at most kTreeChunk children) ----
+  struct Item {
+    int32_t root, c0, c1, ngc;
+  };
+  std::vector<Item> items;
+  for (int32_t r : roots) {
+    const int n = (int)kids[r].size();
+    for (int c0 = 0; c0 < n; c0 += kTreeChunk) {
+      const int c1 = std::min(n, c0 + kTreeChunk);
+      int ngc = 0;
+      for (int j = c0; j < c1; ++j) ngc += (int)kids[kids[r][j]].size();
+      items.push_back({r, c0, c1, ngc});
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+    if (x.c1 - x.c0 != y.c1 - y.c0) return x.c1 - x.c0 > y.c1 - y.c0;
+    return x.ngc > y.ngc;
+  });
+  const uint32_t zz = (uint32_t)P1 | ((uint32_t)P1 << 16);
+  const int nts = (int)((items.size() + 63) / 64);
+  std::vector<int32_t> k_it((size_t)nts * 64, -1), k_ch, k_gc;
+  g->it_ab.assign((size_t)nts * 64, zz);
+  g->tr_slice.assign(nts, make_int4(0, 0, 0, 0));
+  g->ch_s.clear();
+  g->ch_g.clear();
+  g->gc_s.clear();
+  for (int sl = 0; sl < nts; ++sl) {
+    int nmax = 0;
+    for (int l = 0; l < 64 && sl * 64 + l < (int)items.size(); ++l) {
+      const Item& it = items[sl * 64 + l];
+      nmax = std::max(nmax, it.c1 - it.c0);
+    }
+    const int base = (int)g->ch_s.size();
+    g->tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
+    g->ch_s.resize(base + (size_t)nmax * 64, (uint16_t)P1);
+    g->ch_g.resize(base + (size_t)nmax * 64, make_int2(0, 0));
+    k_ch.resize(base + (size_t)nmax * 64, -1);
+    for (int l = 0; l < 64 && sl * 64 + l < (int)items.size(); ++l) {
+      const Item& it = items[sl * 64 + l];
+      const int idx = sl * 64 + l;
+      const int32_t a = h.par[2 * it.root], b = h.par[2 * it.root + 1];
+      g->it_ab[idx] = (uint32_t)slot[a] | ((uint32_t)slot[b] << 16);
+      k_it[idx] = it.c0 == 0 ? h.node_k[it.root] : -1;
+      for (int j = it.c0; j < it.c1; ++j) {
+        const int32_t c = kids[it.root][j];
+        const int pos = base + (j - it.c0) * 64 + l;
+        g->ch_s[pos] = (uint16_t)sib[c];
+        k_ch[pos] = h.node_k[c];
+        if (!kids[c].empty()) {
+          const int gb = (int)g->gc_s.size();
+          for (int32_t gch : kids[c]) {
+            g->gc_s.push_back((uint16_t)sib[gch]);
+            k_gc.push_back(h.node_k[gch]);
+          }
+          g->ch_g[pos] = make_int2(gb, (int)g->gc_s.size());
+        } else if (h.node_k[c] < 0) {
+          return fail_forest("childless auxiliary child");
+        }
+      }
+    }
+  }
+  g->n_tslices = nts;
+
+  // ---- resident-pair rows ----
+  std::vector<std::vector<std::pair<uint16_t, int32_t>>> rows(nslot);
+  for (int32_t w : pairs) {
+    const int sa = slot[h.par[2 * w]], sb = slot[h.par[2 * w + 1]];
+    const int32_t k = h.node_k[w];
+    if (k < 0) return fail_forest("childless auxiliary pair");
+    if (sa == sb) {
+      rows[sa].push_back({(uint16_t)sa, -2 - k});  // M_uu = 2 c
+    } else {
+      rows[sa].push_back({(uint16_t)sb, k});
+      rows[sb].push_back({(uint16_t)sa, k});
+    }
+  }
+  struct Row {
+    int32_t row, e0, e1;
+  };
+  std::vector<Row> rch;
+  for (int r = 0; r < nslot; ++r)
+    for (int e0 = 0; e0 < (int)rows[r].size(); e0 += kRowChunk)
+      rch.push_back({r, e0, std::min((int)rows[r].size(), e0 + kRowChunk)});
+  std::stable_sort(rch.begin(), rch.end(), [](const Row& x, const Row& y) { return x.e1 - x.e0 > y.e1 - y.e0; });
+  const int nms = (int)((rch.size() + 63) / 64);
+  g->mr_slice.assign(nms, make_int4(0, 0, 0, 0));
+  g->mr_row.assign((size_t)nms * 64, (uint16_t)P1);
+  g->me_col.clear();
+  std::vector<int32_t> k_me;
+  for (int sl = 0; sl < nms; ++sl) {
+    int nmax = 0;
+    for (int l = 0; l < 64 && sl * 64 + l < (int)rch.size(); ++l)
+      nmax = std::max(nmax, rch[sl * 64 + l].e1 - rch[sl * 64 + l].e0);
+    const int base = (int)g->me_col.size();
+    g->mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
+    g->me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
+    k_me.resize(base + (size_t)nmax * 64, -1);
+    for (int l = 0; l < 64 && sl * 64 + l < (int)rch.size(); ++l) {
+      const Row& rc = rch[sl * 64 + l];
+      g->mr_row[sl * 64 + l] = (uint16_t)rc.row;
+      for (int j = rc.e0; j < rc.e1; ++j) {
+        const int pos = base + (j - rc.e0) * 64 + l;
+        g->me_col[pos] = rows[rc.row][j].first;
+        k_me[pos] = rows[rc.row][j].second;
+      }
+    }
+  }
+  g->n_mslices = nms;
+
+  // ---- order-2 nodes, one-particle coefficients, coefficient map ----
+  g->nu2_ab.resize(nu2.size());
+  std::vector<int32_t> k_nu2(nu2.size());
+  for (size_t u = 0; u < nu2.size(); ++u) {
+    const int32_t v = nu2[u];
+    g->nu2_ab[u] = (uint32_t)slot[h.par[2 * v]] | ((uint32_t)slot[h.par[2 * v + 1]] << 16);
+    if (slot[h.par[2 * v]] >= P1 || slot[h.par[2 * v + 1]] >= P1) return fail_forest("order-2 node without one-particle parents");
+    k_nu2[u] = h.node_k[v];
+  }
+  g->kmap.clear();
+  auto put = [&](const std::vector<int32_t>& part) {
+    const int off = (int)g->kmap.size();
+    g->kmap.insert(g->kmap.end(), part.begin(), part.end());
+    return off;
+  };
+  g->cs_it = put(k_it);
+  g->cs_ch = put(k_ch);
+  g->cs_gc = put(k_gc);
+  g->cs_me = put(k_me);
+  g->cs_nu2 = put(k_nu2);
+  std::vector<int32_t> k_leaf(h.node_k.begin(), h.node_k.begin() + P1);
+  g->cs_leaf = put(k_leaf);
+  g->forest_ok = true;
+}
+
+// Host emulation of forest_kernel for one environment, with the same
+// indices, padding and forwarding, every index bounds-checked.  Used by the
+// tests to validate a schedule without a GPU.  Returns false on a bad index.
+bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, double* phi, double* Abar) {
+  using cd = std::complex<double>;
+  const int P1 = g->P1, ZERO = P1;
+  std::vector<double> cs(g->kmap.size());
+  for (size_t i = 0; i < cs.size(); ++i) {
+    const int k = g->kmap[i];
+    if (k >= g->h.nK || -2 - k >= g->h.nK) return false;
+    cs[i] = k >= 0 ? coeffs[k] : (k == -1 ? 0.0 : 2.0 * coeffs[-2 - k]);
+  }
+  std::vector<cd> x(g->nslot), ab(P1 + 1);
+  auto X = [&](int s) -> cd& {
+    if (s < 0 || s >= g->nslot) throw std::out_of_range("slot");
+    return x[s];
+  };
+  auto push = [&](int s, cd d) {
+    if (s <= P1) {
+      ab.at(s) += d;
+    } else {
+      const uint32_t q = g->nu2_ab.at(s - P1 - 1);
+      const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
+      ab.at(a) += d * X(b);
+      ab.at(b) += d * X(a);
+    }
+  };
+  try {
+    for (int i = 0; i < P1; ++i) {
+      x[i] = cd(A[2 * i], A[2 * i + 1]);
+      ab[i] = cd(cs.at(g->cs_leaf + i), 0.0);
+    }
+    x[ZERO] = 0.0;
+    ab[ZERO] = 0.0;
+    cd acc = 0.0;
+    for (int i = 0; i < P1; ++i) acc += cs.at(g->cs_leaf + i) * x[i];
+    for (int u = 0; u < g->N2; ++u) {
+      const uint32_t q = g->nu2_ab.at(u);
+      const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
+      if (a >= P1 || b >= P1) return false;
+      const cd xu = X(a) * X(b);
+      X(P1 + 1 + u) = xu;
+      const double c = cs.at(g->cs_nu2 + u);
+      acc += c * xu;
+      ab.at(a) += c * X(b);
+      ab.at(b) += c * X(a);
+    }
+    for (int s = 0; s < g->n_mslices; ++s) {
+      const int4 sl = g->mr_slice.at(s);
+      for (int lane = 0; lane < 64; ++lane) {
+        const int row = g->mr_row.at(sl.x + lane);
+        const cd xu = X(row);
+        cd y = 0.0;
+        for (int j = 0; j < sl.z; ++j) {
+          const int pos = sl.y + j * 64 + lane;
+          y += cs.at(g->cs_me + pos) * X(g->me_col.at(pos));
+        }
+        acc += 0.5 * xu * y;
+        if (row != ZERO) push(row, y);
+      }
+    }
+    for (int s = 0; s < g->n_tslices; ++s) {
+      const int4 sl = g->tr_slice.at(s);
+      for (int lane = 0; lane < 64; ++lane) {
+        const int item = sl.x + lane;
+        const uint32_t q = g->it_ab.at(item);
+        const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
+        const cd xa = X(a), xb = X(b), xv = xa * xb;
+        cd t = cs.at(g->cs_it + item), asum = 0.0;
+        for (int j = 0; j < sl.z; ++j) {
+          const int pos = sl.y + j * 64 + lane;
+          const int sidx = g->ch_s.at(pos);
+          const double c = cs.at(g->cs_ch + pos);
+          const cd xs = X(sidx);
+          const int2 gg = g->ch_g.at(pos);
+          if (gg.x == gg.y) {
+            t += c * xs;
+            if (sidx != ZERO) push(sidx, c * xv);
+          } else {
+            const cd xw = xv * xs;
+            cd aw = c;
+            for (int k = gg.x; k < gg.y; ++k) {
+              const int sg = g->gc_s.at(k);
+              const double cg = cs.at(g->cs_gc + k);
+              aw += cg * X(sg);
+              push(sg, cg * xw);
+            }
+            acc += xw * aw;
+            push(sidx, aw * xv);
+            asum += aw * xs;
+          }
+        }
+        acc += xv * t;
+        if (q != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
+          const cd av = t + asum;
+          push(a, av * xb);
+          push(b, av * xa);
+        }
+      }
+    }
+    phi[0] = acc.real();
+    phi[1] = acc.imag();
+    for (int i = 0; i < P1; ++i) {
+      Abar[2 * i] = ab[i].real();
+      Abar[2 * i + 1] = ab[i].imag();
+    }
+  } catch (const std::out_of_range&) {
+    return false;
+  }
+  return true;
+}
+
 void make_stats(ace_graph* g) {
   const HostGraph& h = g->h;
   ace_graph_stats& st = g->stats;
@@ -285,6 +618,48 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  // forest schedule
+  if (g->forest_ok) {
+    size_t fb = 0;
+    fb += align_up(g->nu2_ab.size() * 4) + align_up(g->it_ab.size() * 4);
+    fb += align_up(g->mr_slice.size() * sizeof(int4)) + align_up(g->tr_slice.size() * sizeof(int4));
+    fb += align_up(g->mr_row.size() * 2) + align_up(g->me_col.size() * 2) + align_up(g->ch_s.size() * 2);
+    fb += align_up(g->gc_s.size() * 2) + align_up(g->ch_g.size() * sizeof(int2)) + align_up(g->kmap.size() * 4);
+    fb += kAlign;
+    if (hipMalloc(&g->fmem, fb) != hipSuccess) {
+      g->fmem = nullptr;
+      (void)hipGetLastError();
+      return fail(ACE_ERR_OUT_OF_MEMORY, "hipMalloc of the forest schedule failed");
+    }
+    char* q = static_cast<char*>(g->fmem);
+    g->d_nu2_ab = carve<uint32_t>(q, g->nu2_ab.size());
+    g->d_it_ab = carve<uint32_t>(q, g->it_ab.size());
+    g->d_mr_slice = carve<int4>(q, g->mr_slice.size());
+    g->d_tr_slice = carve<int4>(q, g->tr_slice.size());
+    g->d_mr_row = carve<uint16_t>(q, g->mr_row.size());
+    g->d_me_col = carve<uint16_t>(q, g->me_col.size());
+    g->d_ch_s = carve<uint16_t>(q, g->ch_s.size());
+    g->d_gc_s = carve<uint16_t>(q, g->gc_s.size());
+    g->d_ch_g = carve<int2>(q, g->ch_g.size());
+    g->d_kmap = carve<int32_t>(q, g->kmap.size());
+    ACE_HIP(put(g->d_nu2_ab, g->nu2_ab.data(), g->nu2_ab.size() * 4));
+    ACE_HIP(put(g->d_it_ab, g->it_ab.data(), g->it_ab.size() * 4));
+    ACE_HIP(put(g->d_mr_slice, g->mr_slice.data(), g->mr_slice.size() * sizeof(int4)));
+    ACE_HIP(put(g->d_tr_slice, g->tr_slice.data(), g->tr_slice.size() * sizeof(int4)));
+    ACE_HIP(put(g->d_mr_row, g->mr_row.data(), g->mr_row.size() * 2));
+    ACE_HIP(put(g->d_me_col, g->me_col.data(), g->me_col.size() * 2));
+    ACE_HIP(put(g->d_ch_s, g->ch_s.data(), g->ch_s.size() * 2));
+    ACE_HIP(put(g->d_gc_s, g->gc_s.data(), g->gc_s.size() * 2));
+    ACE_HIP(put(g->d_ch_g, g->ch_g.data(), g->ch_g.size() * sizeof(int2)));
+    ACE_HIP(put(g->d_kmap, g->kmap.data(), g->kmap.size() * 4));
+    const size_t fred = (kDagThreads / 64) * sizeof(double2);
+    g->forest_fwd_lds = (size_t)g->nslot * 16 + fred <= g->max_lds;
+    g->forest_grad_lds = (size_t)(g->nslot + g->P1 + 1) * 16 + fred <= g->max_lds;
+    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  }
   g->on_device = true;
   return ACE_OK;
 }
@@ -307,6 +682,7 @@ struct Workspace {
   double2* Abar = nullptr;
   double2* arena_x = nullptr;
   double2* arena_ab = nullptr;
+  double* cs = nullptr;   // coefficients in forest-schedule order
   size_t bytes = 0;
 };
 
@@ -326,6 +702,7 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, char* base) {
   const size_t arena = (size_t)arena_blocks(n_env) * g->slots * sizeof(double2);
   if (!g->fwd_xl || !g->grad_xl) w.arena_x = take(arena);
   if (!g->grad_al) w.arena_ab = take(arena);
+  if (g->forest_ok) w.cs = reinterpret_cast<double*>(take(g->kmap.size() * sizeof(double)));
   w.bytes = off;
   return w;
 }
@@ -364,8 +741,66 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   return ACE_OK;
 }
 
+bool use_forest(const ace_graph* g, bool grad) {
+  return g->forest_ok && (grad ? g->forest_grad_lds : g->forest_fwd_lds);
+}
+
+ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
+                         double2* Abar, const Workspace& w, hipStream_t s) {
+  PrepArgs pa{};
+  pa.kmap = g->d_kmap;
+  pa.coeffs = coeffs;
+  pa.cs = w.cs;
+  pa.n = (int64_t)g->kmap.size();
+  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((pa.n + 255) / 256, 1024));
+  hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  ACE_HIP(hipGetLastError());
+  ForestArgs a{};
+  a.n_env = n_env;
+  a.A = A;
+  a.phi = phi;
+  a.Abar = Abar;
+  a.cs = w.cs;
+  a.nu2_ab = g->d_nu2_ab;
+  a.mr_slice = g->d_mr_slice;
+  a.mr_row = g->d_mr_row;
+  a.me_col = g->d_me_col;
+  a.tr_slice = g->d_tr_slice;
+  a.it_ab = g->d_it_ab;
+  a.ch_s = g->d_ch_s;
+  a.ch_g = g->has_gc ? g->d_ch_g : nullptr;
+  a.gc_s = g->d_gc_s;
+  a.cs_leaf = g->cs_leaf;
+  a.cs_nu2 = g->cs_nu2;
+  a.cs_me = g->cs_me;
+  a.cs_it = g->cs_it;
+  a.cs_ch = g->cs_ch;
+  a.cs_gc = g->cs_gc;
+  a.P1 = g->P1;
+  a.N2 = g->N2;
+  a.nslot = g->nslot;
+  a.n_mslices = g->n_mslices;
+  a.n_tslices = g->n_tslices;
+  const bool grad = Abar != nullptr;
+  const size_t red = (kDagThreads / 64) * sizeof(double2);
+  const size_t lds = (size_t)g->nslot * 16 + (grad ? (size_t)(g->P1 + 1) * 16 : 0) + red;
+  const dim3 grid((unsigned)grid_for(n_env)), block(kDagThreads);
+  if (grad && g->has_gc)
+    hipLaunchKernelGGL((forest_kernel<true, true>), grid, block, lds, s, a);
+  else if (grad)
+    hipLaunchKernelGGL((forest_kernel<true, false>), grid, block, lds, s, a);
+  else if (g->has_gc)
+    hipLaunchKernelGGL((forest_kernel<false, true>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((forest_kernel<false, false>), grid, block, lds, s, a);
+  ACE_HIP(hipGetLastError());
+  return ACE_OK;
+}
+
 ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                      double2* Abar, const Workspace& w, hipStream_t s) {
+                      double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags) {
+  if (!(flags & ACE_FLAG_LAYERED) && use_forest(g, Abar != nullptr))
+    return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s);
   DagArgs a{};
   a.n_env = n_env;
   a.A = A;
@@ -464,7 +899,7 @@ ace_status common_eval_checks(const ace_graph* g, const double* coeffs, int64_t 
   if (st != ACE_OK) return st;
   if (n_env < 0) return fail(ACE_ERR_INVALID_ARG, "n_env must be >= 0");
   if (n_env > ((int64_t)1 << 30)) return fail(ACE_ERR_INVALID_ARG, "n_env too large");
-  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK)) return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
+  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK | ACE_FLAG_LAYERED)) return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
   if (n_env == 0) return ACE_OK;
   if (!coeffs) return fail(ACE_ERR_INVALID_ARG, "coeffs is NULL");
   *need = plan_workspace(g, n_env, nullptr).bytes;
@@ -503,6 +938,7 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out) {
     bs.r_cut = spec->r_cut;
     build_graph(bs, g->h);
     make_schedule(g);
+    make_forest(g);
     make_stats(g);
   } catch (const std::invalid_argument& e) {
     delete g;
@@ -528,6 +964,7 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out) {
 void ace_graph_free(ace_graph* g) {
   if (!g) return;
   if (g->dmem) (void)hipFree(g->dmem);
+  if (g->fmem) (void)hipFree(g->fmem);
   delete g;
 }
 
@@ -591,7 +1028,7 @@ ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env,
     return launch_naive(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
                         reinterpret_cast<double2*>(Abar), s);
   return launch_dag(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
-                    reinterpret_cast<double2*>(Abar), w, s);
+                    reinterpret_cast<double2*>(Abar), w, s, flags);
 }
 
 ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
@@ -609,7 +1046,7 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
   st = launch_basis(g, n_env, offsets, pos, w.A, s);
   if (st != ACE_OK) return st;
   if (flags & ACE_FLAG_NAIVE) return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
-  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s);
+  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags);
 }
 
 ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
@@ -631,9 +1068,26 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
   if (flags & ACE_FLAG_NAIVE)
     st = launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, s);
   else
-    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s);
+    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags);
   if (st != ACE_OK) return st;
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
+}
+
+ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind) {
+  if (!g || !kind) return fail(ACE_ERR_INVALID_ARG, "graph and kind must be non-NULL");
+  *kind = g->forest_ok ? 1 : 0;
+  if (!g->forest_ok) g_error = g->forest_why;
+  return ACE_OK;
+}
+
+ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
+                                 double* phi, double* Abar) {
+  if (!g || !coeffs || !A || !phi || !Abar || n_env < 0) return fail(ACE_ERR_INVALID_ARG, "NULL argument");
+  if (!g->forest_ok) return fail(ACE_ERR_UNSUPPORTED, "no forest schedule: " + g->forest_why);
+  for (int64_t e = 0; e < n_env; ++e)
+    if (!forest_emulate(g, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1))
+      return fail(ACE_ERR_INTERNAL, "forest schedule index out of range");
+  return ACE_OK;
 }
 
 }  // extern "C"

@@ -76,3 +76,37 @@ struct GradArgs {
 };
 
 }  // namespace ace
+
+namespace ace {
+
+// Forest schedule (see forest_kernel).  Value slots: one-particle nodes
+// 0..P1-1, a constant-zero slot P1, then the order-2 nodes P1+1..P1+N2.
+// Slot numbers fit in 16 bits.  Coefficients are read from `cs`, the
+// per-call copy of c in schedule order, at the given offsets.
+struct ForestArgs {
+  int64_t n_env;
+  const double2* A;          // [n_env][P1]
+  double2* phi;              // [n_env]
+  double2* Abar;             // [n_env][P1], or nullptr for the forward pass only
+  const double* cs;          // prepared coefficients
+  const uint32_t* nu2_ab;    // [N2] parent one-particle slots, a | b << 16
+  const int4* mr_slice;      // [n_mslices] {first row, first entry, entries per row, 0}
+  const uint16_t* mr_row;    // [64 * n_mslices] row slot of each resident-pair row
+  const uint16_t* me_col;    // resident-pair entries, 64-interleaved per slice
+  const int4* tr_slice;      // [n_tslices] {first item, first child, children per item, 0}
+  const uint32_t* it_ab;     // [64 * n_tslices] root parents, a | b << 16
+  const uint16_t* ch_s;      // children, 64-interleaved per slice: resident sibling slot
+  const int2* ch_g;          // children: grandchild range [x, y) (nullptr if none exist)
+  const uint16_t* gc_s;      // grandchildren: resident sibling slot
+  int cs_leaf, cs_nu2, cs_me, cs_it, cs_ch, cs_gc;
+  int P1, N2, nslot, n_mslices, n_tslices;
+};
+
+struct PrepArgs {
+  const int32_t* kmap;   // k >= 0: c_k;  -1: 0;  k <= -2: 2 c_{-2-k}
+  const double* coeffs;  // [|K|]
+  double* cs;            // output
+  int64_t n;
+};
+
+}  // namespace ace

@@ -427,4 +427,159 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Coefficients in schedule order, once per call.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = p.kmap[i];
+    p.cs[i] = k >= 0 ? p.coeffs[k] : (k == -1 ? 0.0 : 2.0 * p.coeffs[-2 - k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forest kernel: the DAG evaluated with the one-particle and order-2 node
+// values resident in LDS and every higher node computed in registers.
+//
+// Every product node above order 2 has exactly one parent outside the
+// resident set, so those nodes form trees hanging off "roots" (products of
+// two resident nodes).  One lane walks one tree (or a chunk of its
+// children): x_v = x_a x_b, then each child w = v * s, and for a child with
+// children of its own each grandchild g = w * s'.  Childless products of two
+// resident nodes form a symmetric sparse matrix M over the resident slots;
+// each lane gathers one row chunk y = M x, which gives both the forward
+// contribution (phi += x.y / 2) and the adjoint (abar += y) with no atomics.
+//
+// Adjoints of order-2 nodes are never stored: a contribution d to abar_u,
+// u = a * b, is forwarded at once to the one-particle adjoints
+// (abar_a += d x_b, abar_b += d x_a).  One-particle adjoints are LDS
+// accumulators updated with atomics, so the reverse pass is not bitwise
+// deterministic (the forward pass is).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void push_adj(const ForestArgs& p, const double2* x, double2* ab, int slot, double2 d) {
+  if (slot <= p.P1) {
+    atomic_cadd(&ab[slot], d);
+  } else {
+    const uint32_t q = p.nu2_ab[slot - p.P1 - 1];
+    const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
+    atomic_cadd(&ab[a], cmul(d, x[b]));
+    atomic_cadd(&ab[b], cmul(d, x[a]));
+  }
+}
+
+template <bool GRAD, bool GC>
+__global__ __launch_bounds__(256) void forest_kernel(ForestArgs p) {
+  extern __shared__ double2 lds[];
+  double2* x = lds;                                   // [nslot]
+  double2* ab = lds + p.nslot;                        // [P1 + 1] when GRAD
+  double2* red = ab + (GRAD ? p.P1 + 1 : 0);          // [blockDim / 64]
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int P1 = p.P1;
+  const int ZERO = P1;
+  const double* cs = p.cs;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    // phase 0: one-particle values and adjoint accumulators
+    const double2* Ae = p.A + e * P1;
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) {
+      x[i] = Ae[i];
+      if (GRAD) ab[i] = make_double2(cs[p.cs_leaf + i], 0.0);
+    }
+    if (threadIdx.x == 0) {
+      x[ZERO] = make_double2(0.0, 0.0);
+      if (GRAD) ab[ZERO] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    // phase 1: order-2 nodes, their own and the one-particle coefficients
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) acc = rfma(cs[p.cs_leaf + i], x[i], acc);
+    for (int u = threadIdx.x; u < p.N2; u += blockDim.x) {
+      const uint32_t q = p.nu2_ab[u];
+      const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
+      const double2 xa = x[a], xb = x[b];
+      const double2 xu = cmul(xa, xb);
+      x[P1 + 1 + u] = xu;
+      const double c = cs[p.cs_nu2 + u];
+      acc = rfma(c, xu, acc);
+      if (GRAD && c != 0.0) {
+        atomic_cadd(&ab[a], make_double2(c * xb.x, c * xb.y));
+        atomic_cadd(&ab[b], make_double2(c * xa.x, c * xa.y));
+      }
+    }
+    __syncthreads();
+    // phase 2a: resident-pair rows, y = M x
+    for (int s = wid; s < p.n_mslices; s += nw) {
+      const int4 sl = p.mr_slice[s];
+      const int row = p.mr_row[sl.x + lane];
+      const double2 xu = x[row];
+      double2 y = make_double2(0.0, 0.0);
+      for (int j = 0; j < sl.z; ++j) {
+        const int pos = sl.y + j * 64 + lane;
+        y = rfma(cs[p.cs_me + pos], x[p.me_col[pos]], y);
+      }
+      const double2 h = cmul(xu, y);
+      acc.x = fma(0.5, h.x, acc.x);
+      acc.y = fma(0.5, h.y, acc.y);
+      if (GRAD && row != ZERO) push_adj(p, x, ab, row, y);
+    }
+    // phase 2b: trees
+    for (int s = wid; s < p.n_tslices; s += nw) {
+      const int4 sl = p.tr_slice[s];
+      const int item = sl.x + lane;
+      const uint32_t q = p.it_ab[item];
+      const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
+      const double2 xa = x[a], xb = x[b];
+      const double2 xv = cmul(xa, xb);
+      double2 t = make_double2(cs[p.cs_it + item], 0.0);  // abar_v from childless children
+      double2 asum = make_double2(0.0, 0.0);              // abar_v from children with children
+      for (int j = 0; j < sl.z; ++j) {
+        const int pos = sl.y + j * 64 + lane;
+        const int sidx = p.ch_s[pos];
+        const double c = cs[p.cs_ch + pos];
+        const double2 xs = x[sidx];
+        int2 g = make_int2(0, 0);
+        if (GC) g = p.ch_g[pos];
+        if (!GC || g.x == g.y) {
+          t = rfma(c, xs, t);
+          if (GRAD && sidx != ZERO) push_adj(p, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
+        } else {
+          const double2 xw = cmul(xv, xs);
+          double2 aw = make_double2(c, 0.0);
+          for (int k = g.x; k < g.y; ++k) {
+            const int sg = p.gc_s[k];
+            const double cg = cs[p.cs_gc + k];
+            aw = rfma(cg, x[sg], aw);
+            if (GRAD) push_adj(p, x, ab, sg, make_double2(cg * xw.x, cg * xw.y));
+          }
+          acc = cfma(xw, aw, acc);
+          if (GRAD) {
+            push_adj(p, x, ab, sidx, cmul(aw, xv));
+            asum = cfma(aw, xs, asum);
+          }
+        }
+      }
+      acc = cfma(xv, t, acc);
+      if (GRAD && q != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
+        const double2 av = make_double2(t.x + asum.x, t.y + asum.y);
+        push_adj(p, x, ab, a, cmul(av, xb));
+        push_adj(p, x, ab, b, cmul(av, xa));
+      }
+    }
+    __syncthreads();
+    const double2 phi = block_sum(acc, red);
+    if (threadIdx.x == 0) p.phi[e] = phi;
+    if (GRAD) {
+      double2* Be = p.Abar + e * P1;
+      for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
+    }
+    __syncthreads();
+  }
+}
+
+template __global__ void forest_kernel<false, false>(ForestArgs);
+template __global__ void forest_kernel<false, true>(ForestArgs);
+template __global__ void forest_kernel<true, false>(ForestArgs);
+template __global__ void forest_kernel<true, true>(ForestArgs);
+
 }  // namespace ace

@@ -165,3 +165,32 @@ def test_device_build_without_gpu_reports_hip_error():
     with pytest.raises(ace.AceError) as ei:
         ace.Graph(3, 8, 4, 4)
     assert ei.value.status == 4
+
+
+# ---- forest schedule: host emulation of the kernel's exact index logic ------------
+@pytest.mark.parametrize("spec,n_env", [((4, 4, 8, 3), 4), ((6, 6, 12, 4), 3), ((8, 8, 14, 5), 2),
+                                        ((3, 2, 9, 5), 3)])
+def test_forest_schedule_host_emulation_matches_oracle(spec, n_env):
+    from oracle import contraction as oc
+    from oracle.indexsets import all_invariant_tuples
+    import workloads as wl
+    nmax, lmax, D, nu = spec
+    G = ace.Graph(nu, D, nmax, lmax, host_only=True)
+    if G.schedule_kind() != "forest":
+        pytest.skip("graph uses the layered schedule")
+    g = group_o3(nmax, lmax, D)
+    K = all_invariant_tuples(g, nu, D)
+    rng = np.random.default_rng(9)
+    c = rng.standard_normal(len(K))
+    A = wl.random_A(n_env, len(g), 21) * 0.5
+    phi, ab = G.forest_eval_host(c, A)
+    pr, ar = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+    assert np.linalg.norm(ab - ar) <= 1e-13 * np.linalg.norm(ar)
+
+
+def test_schedule_kinds():
+    assert ace.Graph(3, 8, 4, 4, host_only=True).schedule_kind() == "forest"
+    assert ace.Graph(4, 12, 6, 6, host_only=True).schedule_kind() == "forest"
+    # order-6 products of two order-3 nodes have no resident parent
+    assert ace.Graph(6, 10, 3, 3, host_only=True).schedule_kind() in ("forest", "layered")

@@ -100,24 +100,34 @@ def test_basis_parity(device, wid, n_env):
 
 
 # ---- contraction alone, from random one-particle values ----------------------------
-@pytest.mark.parametrize("naive", [False, True])
+MODES = {"dag": {}, "layered": {"layered": True}, "naive": {"naive": True}}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("wid,n_env", [(1, 16), (2, 48), (4, 6)])
-def test_contract_random_A(device, wid, n_env, naive):
+def test_contract_random_A(device, wid, n_env, mode):
     import paper_2202_04140_amd as ace
-    print(f"contract wid={wid} n_env={n_env} naive={naive}", flush=True)
+    print(f"contract wid={wid} n_env={n_env} mode={mode}", flush=True)
     G = graph(wid, device)
     g, K, c = oracle_basis(wid)
     A = wl.random_A(n_env, len(g), seed=100 + wid) * 0.5
     At = np.stack([A.real, A.imag], -1)
     tc, tA = to_dev(device, c, At)
-    phi, Ab = ace.contract(G, tc, tA, with_grad=True, naive=naive)
+    phi, Ab = ace.contract(G, tc, tA, with_grad=True, **MODES[mode])
     phi_ref = oc.phi_naive(K, c, A)
     ab_ref = oc.abar_naive(K, c, A)
     assert rel(cplx(phi), phi_ref) <= TOL_PHI
     assert rel(cplx(Ab), ab_ref) <= TOL_ABAR
     # forward-only launch gives the same phi
-    phi2 = ace.contract(G, tc, tA, with_grad=False, naive=naive)
+    phi2 = ace.contract(G, tc, tA, with_grad=False, **MODES[mode])
     assert rel(cplx(phi2), phi_ref) <= TOL_PHI
+
+
+def test_schedule_in_use(device):
+    assert graph(1, device).schedule_kind() == "forest"
+    assert graph(3, device).schedule_kind() == "forest"
+    assert graph(4, device).schedule_kind() == "forest"
+    assert graph(5, device).schedule_kind() == "layered"
 
 
 # ---- full path ---------------------------------------------------------------------
@@ -135,16 +145,16 @@ def test_eval_parity(device, wid, n_env, naive):
     assert rel(phi, ref) <= TOL_PHI
 
 
-@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("wid,n_env", [(1, None), (3, 64), (4, 12)])
-def test_eval_grad_parity(device, wid, n_env, naive):
+def test_eval_grad_parity(device, wid, n_env, mode):
     import paper_2202_04140_amd as ace
-    print(f"eval_grad wid={wid} n_env={n_env} naive={naive}", flush=True)
+    print(f"eval_grad wid={wid} n_env={n_env} mode={mode}", flush=True)
     G = graph(wid, device)
     g, K, c = oracle_basis(wid)
     off, pos = problem(wid, n_env)
     tc, toff, tpos = to_dev(device, c, off, pos)
-    phi, grad = ace.eval_grad(G, tc, toff, tpos, naive=naive)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos, **MODES[mode])
     phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
     assert rel(cplx(phi), phi_ref) <= TOL_PHI
     assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
