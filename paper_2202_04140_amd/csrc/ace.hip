@@ -36,6 +36,7 @@ ace_status fail(ace_status code, const std::string& msg) {
   } while (0)
 
 constexpr int kDagThreads = 256;
+constexpr int kForestThreads = 512;
 constexpr int kNaiveThreads = 256;
 constexpr int kBasisThreads = 256;
 constexpr int kGradThreads = 64;
@@ -97,6 +98,14 @@ struct ace_graph {
   int2* d_ch_g = nullptr;
   int32_t* d_kmap = nullptr;
   bool forest_fwd_lds = false, forest_grad_lds = false;
+  int hot_slot[4] = {0, 0, 0, 0};  // most frequent childless-child siblings
+  int n_items = 0;                 // tree items incl. slice padding (= 64 * n_tslices)
+  int cs_hot = 0;                  // coefficients of the hot columns, [4][n_items]
+  std::vector<int32_t> fw_off;     // full-adjoint mode: order-2 -> one-particle forwarding lists
+  std::vector<uint32_t> fw_ent;
+  int32_t* d_fw_off = nullptr;
+  uint32_t* d_fw_ent = nullptr;
+  bool forest_full = false;        // full-adjoint mode fits in LDS
 };
 
 namespace {
@@ -288,19 +297,59 @@ void make_forest(ace_graph* g) {
   g->N2 = (int)nu2.size();
   g->nslot = nslot;
 
-  // ---- tree items (root, chunk of at most kTreeChunk children) ----
+  // ---- hot siblings: the most frequent siblings of childless tree children get
+  // a fixed column per item, accumulated in registers (no atomics per child) ----
+  {
+    std::vector<int64_t> freq(nslot, 0);
+    int64_t nchild = 0;
+    for (int32_t r : roots)
+      for (int32_t c : kids[r])
+        if (kids[c].empty()) {
+          freq[sib[c]] += 1;
+          ++nchild;
+        }
+    std::vector<int32_t> order(nslot);
+    for (int i = 0; i < nslot; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return freq[x] > freq[y]; });
+    for (int h = 0; h < 4; ++h) {
+      const int sl = order[h];
+      g->hot_slot[h] = (sl != P1 && freq[sl] * 16 >= (int64_t)roots.size() && freq[sl] > 0) ? sl : P1;
+    }
+  }
+  auto hot_col = [&](int slot_) {
+    for (int h = 0; h < 4; ++h)
+      if (g->hot_slot[h] != P1 && g->hot_slot[h] == slot_) return h;
+    return -1;
+  };
+  // ---- tree items: root + hot columns + a chunk of at most kTreeChunk other children ----
   struct Item {
     int32_t root, c0, c1, ngc;
+    int32_t hot[4];  // child node in each hot column, or -1
   };
   std::vector<Item> items;
   for (int32_t r : roots) {
-    const int n = (int)kids[r].size();
-    for (int c0 = 0; c0 < n; c0 += kTreeChunk) {
+    std::vector<int32_t> reg;
+    int32_t hot[4] = {-1, -1, -1, -1};
+    for (int32_t c : kids[r]) {
+      const int hc = kids[c].empty() ? hot_col(sib[c]) : -1;
+      if (hc >= 0 && hot[hc] < 0)
+        hot[hc] = c;
+      else
+        reg.push_back(c);
+    }
+    kids[r] = reg;  // the regular children, in order
+    const int n = (int)reg.size();
+    int c0 = 0;
+    do {
       const int c1 = std::min(n, c0 + kTreeChunk);
       int ngc = 0;
-      for (int j = c0; j < c1; ++j) ngc += (int)kids[kids[r][j]].size();
-      items.push_back({r, c0, c1, ngc});
-    }
+      for (int j = c0; j < c1; ++j) ngc += (int)kids[reg[j]].size();
+      Item it{r, c0, c1, ngc, {-1, -1, -1, -1}};
+      if (c0 == 0)
+        for (int h = 0; h < 4; ++h) it.hot[h] = hot[h];
+      items.push_back(it);
+      c0 = c1;
+    } while (c0 < n);
   }
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
     if (x.c1 - x.c0 != y.c1 - y.c0) return x.c1 - x.c0 > y.c1 - y.c0;
@@ -320,6 +369,7 @@ void make_forest(ace_graph* g) {
       const Item& it = items[sl * 64 + l];
       nmax = std::max(nmax, it.c1 - it.c0);
     }
+    if (!has_gc) nmax = (nmax + 3) / 4 * 4;  // the kernel walks children four at a time
     const int base = (int)g->ch_s.size();
     g->tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
     g->ch_s.resize(base + (size_t)nmax * 64, (uint16_t)P1);
@@ -350,9 +400,18 @@ void make_forest(ace_graph* g) {
     }
   }
   g->n_tslices = nts;
+  g->n_items = nts * 64;
+  std::vector<int32_t> k_hot((size_t)4 * nts * 64, -1);
+  for (size_t i = 0; i < items.size(); ++i)
+    for (int hc = 0; hc < 4; ++hc)
+      if (items[i].hot[hc] >= 0) k_hot[(size_t)hc * nts * 64 + i] = h.node_k[items[i].hot[hc]];
 
   // ---- resident-pair rows ----
   std::vector<std::vector<std::pair<uint16_t, int32_t>>> rows(nslot);
+  // an invariant order-2 node u = a * b contributes c_u x_a x_b: a pair of
+  // one-particle slots, so it joins M instead of needing its own pushes
+  for (int32_t u : nu2)
+    if (h.node_k[u] >= 0) pairs.push_back(u);
   for (int32_t w : pairs) {
     const int sa = slot[h.par[2 * w]], sb = slot[h.par[2 * w + 1]];
     const int32_t k = h.node_k[w];
@@ -381,6 +440,7 @@ void make_forest(ace_graph* g) {
     int nmax = 0;
     for (int l = 0; l < 64 && sl * 64 + l < (int)rch.size(); ++l)
       nmax = std::max(nmax, rch[sl * 64 + l].e1 - rch[sl * 64 + l].e0);
+    nmax = (nmax + 3) / 4 * 4;  // the kernel walks entries four at a time
     const int base = (int)g->me_col.size();
     g->mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
     g->me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
@@ -404,7 +464,7 @@ void make_forest(ace_graph* g) {
     const int32_t v = nu2[u];
     g->nu2_ab[u] = (uint32_t)slot[h.par[2 * v]] | ((uint32_t)slot[h.par[2 * v + 1]] << 16);
     if (slot[h.par[2 * v]] >= P1 || slot[h.par[2 * v + 1]] >= P1) return fail_forest("order-2 node without one-particle parents");
-    k_nu2[u] = h.node_k[v];
+    k_nu2[u] = -1;  // carried by the resident-pair matrix
   }
   g->kmap.clear();
   auto put = [&](const std::vector<int32_t>& part) {
@@ -415,17 +475,38 @@ void make_forest(ace_graph* g) {
   g->cs_it = put(k_it);
   g->cs_ch = put(k_ch);
   g->cs_gc = put(k_gc);
+  g->cs_hot = put(k_hot);
   g->cs_me = put(k_me);
   g->cs_nu2 = put(k_nu2);
   std::vector<int32_t> k_leaf(h.node_k.begin(), h.node_k.begin() + P1);
   g->cs_leaf = put(k_leaf);
+  // forwarding lists: one-particle node i receives abar_u x_j from every
+  // order-2 node u = i * j (a square u = i * i contributes twice)
+  {
+    std::vector<std::vector<uint32_t>> fl(P1);
+    for (size_t u = 0; u < nu2.size(); ++u) {
+      const uint32_t q = g->nu2_ab[u];
+      const uint32_t a = q & 0xffffu, b = q >> 16;
+      const uint32_t us = (uint32_t)(P1 + 1 + u);
+      fl[a].push_back(us | (b << 16));
+      fl[b].push_back(us | (a << 16));
+    }
+    g->fw_off.assign(P1 + 1, 0);
+    g->fw_ent.clear();
+    for (int i = 0; i < P1; ++i) {
+      g->fw_off[i] = (int32_t)g->fw_ent.size();
+      g->fw_ent.insert(g->fw_ent.end(), fl[i].begin(), fl[i].end());
+    }
+    g->fw_off[P1] = (int32_t)g->fw_ent.size();
+  }
   g->forest_ok = true;
 }
 
 // Host emulation of forest_kernel for one environment, with the same
 // indices, padding and forwarding, every index bounds-checked.  Used by the
 // tests to validate a schedule without a GPU.  Returns false on a bad index.
-bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, double* phi, double* Abar) {
+bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, double* phi, double* Abar,
+                    bool full) {
   using cd = std::complex<double>;
   const int P1 = g->P1, ZERO = P1;
   std::vector<double> cs(g->kmap.size());
@@ -434,13 +515,13 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
     if (k >= g->h.nK || -2 - k >= g->h.nK) return false;
     cs[i] = k >= 0 ? coeffs[k] : (k == -1 ? 0.0 : 2.0 * coeffs[-2 - k]);
   }
-  std::vector<cd> x(g->nslot), ab(P1 + 1);
+  std::vector<cd> x(g->nslot), ab(full ? g->nslot : P1 + 1, cd(0.0, 0.0));
   auto X = [&](int s) -> cd& {
     if (s < 0 || s >= g->nslot) throw std::out_of_range("slot");
     return x[s];
   };
   auto push = [&](int s, cd d) {
-    if (s <= P1) {
+    if (full || s <= P1) {
       ab.at(s) += d;
     } else {
       const uint32_t q = g->nu2_ab.at(s - P1 - 1);
@@ -483,6 +564,7 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
         if (row != ZERO) push(row, y);
       }
     }
+    cd hacc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < g->n_tslices; ++s) {
       const int4 sl = g->tr_slice.at(s);
       for (int lane = 0; lane < 64; ++lane) {
@@ -491,6 +573,11 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
         const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
         const cd xa = X(a), xb = X(b), xv = xa * xb;
         cd t = cs.at(g->cs_it + item), asum = 0.0;
+        for (int hc = 0; hc < 4; ++hc) {
+          const double k = cs.at((size_t)g->cs_hot + (size_t)hc * g->n_items + item);
+          t += k * X(g->hot_slot[hc]);
+          hacc[hc] += k * xv;
+        }
         for (int j = 0; j < sl.z; ++j) {
           const int pos = sl.y + j * 64 + lane;
           const int sidx = g->ch_s.at(pos);
@@ -522,6 +609,14 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
         }
       }
     }
+    for (int hc = 0; hc < 4; ++hc)
+      if (g->hot_slot[hc] != ZERO) push(g->hot_slot[hc], hacc[hc]);
+    if (full)
+      for (int i = 0; i < P1; ++i)
+        for (int q = g->fw_off.at(i); q < g->fw_off.at(i + 1); ++q) {
+          const uint32_t en = g->fw_ent.at(q);
+          ab.at(i) += ab.at(en & 0xffffu) * X(en >> 16);
+        }
     phi[0] = acc.real();
     phi[1] = acc.imag();
     for (int i = 0; i < P1; ++i) {
@@ -558,6 +653,15 @@ void make_stats(ace_graph* g) {
   for (int64_t v = 0; v < h.n_nodes(); ++v)
     if (h.layer[v] < 16) st.n_layer[h.layer[v]] += 1;
   for (int64_t q = 0; q < h.nK; ++q) st.naive_cmuls += h.k_len[q] - 1;
+}
+
+// LDS of forest_kernel: values of every resident slot, one-particle
+// adjoints (reverse pass), the order-2 parent table, reduction scratch.
+size_t forest_lds_bytes(const ace_graph* g, bool grad, bool full) {
+  size_t b = (size_t)g->nslot * 16;
+  if (grad && full) b += (size_t)g->nslot * 16;
+  if (grad && !full) b += (size_t)(g->P1 + 1) * 16 + ((size_t)g->N2 * 4 + 15) / 16 * 16;
+  return b + (kForestThreads / 64) * sizeof(double2);
 }
 
 template <typename T>
@@ -625,6 +729,7 @@ ace_status upload(ace_graph* g) {
     fb += align_up(g->mr_slice.size() * sizeof(int4)) + align_up(g->tr_slice.size() * sizeof(int4));
     fb += align_up(g->mr_row.size() * 2) + align_up(g->me_col.size() * 2) + align_up(g->ch_s.size() * 2);
     fb += align_up(g->gc_s.size() * 2) + align_up(g->ch_g.size() * sizeof(int2)) + align_up(g->kmap.size() * 4);
+    fb += align_up(g->fw_off.size() * 4) + align_up(g->fw_ent.size() * 4);
     fb += kAlign;
     if (hipMalloc(&g->fmem, fb) != hipSuccess) {
       g->fmem = nullptr;
@@ -642,6 +747,8 @@ ace_status upload(ace_graph* g) {
     g->d_gc_s = carve<uint16_t>(q, g->gc_s.size());
     g->d_ch_g = carve<int2>(q, g->ch_g.size());
     g->d_kmap = carve<int32_t>(q, g->kmap.size());
+    g->d_fw_off = carve<int32_t>(q, g->fw_off.size());
+    g->d_fw_ent = carve<uint32_t>(q, g->fw_ent.size());
     ACE_HIP(put(g->d_nu2_ab, g->nu2_ab.data(), g->nu2_ab.size() * 4));
     ACE_HIP(put(g->d_it_ab, g->it_ab.data(), g->it_ab.size() * 4));
     ACE_HIP(put(g->d_mr_slice, g->mr_slice.data(), g->mr_slice.size() * sizeof(int4)));
@@ -652,13 +759,15 @@ ace_status upload(ace_graph* g) {
     ACE_HIP(put(g->d_gc_s, g->gc_s.data(), g->gc_s.size() * 2));
     ACE_HIP(put(g->d_ch_g, g->ch_g.data(), g->ch_g.size() * sizeof(int2)));
     ACE_HIP(put(g->d_kmap, g->kmap.data(), g->kmap.size() * 4));
-    const size_t fred = (kDagThreads / 64) * sizeof(double2);
-    g->forest_fwd_lds = (size_t)g->nslot * 16 + fred <= g->max_lds;
-    g->forest_grad_lds = (size_t)(g->nslot + g->P1 + 1) * 16 + fred <= g->max_lds;
-    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-    ACE_HIP(hipFuncSetAttribute((const void*)forest_kernel<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    ACE_HIP(put(g->d_fw_off, g->fw_off.data(), g->fw_off.size() * 4));
+    ACE_HIP(put(g->d_fw_ent, g->fw_ent.data(), g->fw_ent.size() * 4));
+    g->forest_fwd_lds = forest_lds_bytes(g, false, false) <= g->max_lds;
+    g->forest_full = forest_lds_bytes(g, true, true) <= g->max_lds;
+    g->forest_grad_lds = g->forest_full || forest_lds_bytes(g, true, false) <= g->max_lds;
+    const void* fk[] = {(const void*)forest_kernel<false, false, false>, (const void*)forest_kernel<false, true, false>,
+                        (const void*)forest_kernel<true, false, false>, (const void*)forest_kernel<true, true, false>,
+                        (const void*)forest_kernel<true, false, true>, (const void*)forest_kernel<true, true, true>};
+    for (const void* f : fk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
   g->on_device = true;
   return ACE_OK;
@@ -776,23 +885,32 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.cs_it = g->cs_it;
   a.cs_ch = g->cs_ch;
   a.cs_gc = g->cs_gc;
+  a.cs_hot = g->cs_hot;
+  a.n_items = g->n_items;
+  a.hot = make_int4(g->hot_slot[0], g->hot_slot[1], g->hot_slot[2], g->hot_slot[3]);
   a.P1 = g->P1;
   a.N2 = g->N2;
   a.nslot = g->nslot;
   a.n_mslices = g->n_mslices;
   a.n_tslices = g->n_tslices;
+  a.fw_off = g->d_fw_off;
+  a.fw_ent = g->d_fw_ent;
   const bool grad = Abar != nullptr;
-  const size_t red = (kDagThreads / 64) * sizeof(double2);
-  const size_t lds = (size_t)g->nslot * 16 + (grad ? (size_t)(g->P1 + 1) * 16 : 0) + red;
-  const dim3 grid((unsigned)grid_for(n_env)), block(kDagThreads);
-  if (grad && g->has_gc)
-    hipLaunchKernelGGL((forest_kernel<true, true>), grid, block, lds, s, a);
+  const bool full = grad && g->forest_full;
+  const size_t lds = forest_lds_bytes(g, grad, full);
+  const dim3 grid((unsigned)grid_for(n_env)), block(kForestThreads);
+  if (full && g->has_gc)
+    hipLaunchKernelGGL((forest_kernel<true, true, true>), grid, block, lds, s, a);
+  else if (full)
+    hipLaunchKernelGGL((forest_kernel<true, false, true>), grid, block, lds, s, a);
+  else if (grad && g->has_gc)
+    hipLaunchKernelGGL((forest_kernel<true, true, false>), grid, block, lds, s, a);
   else if (grad)
-    hipLaunchKernelGGL((forest_kernel<true, false>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((forest_kernel<true, false, false>), grid, block, lds, s, a);
   else if (g->has_gc)
-    hipLaunchKernelGGL((forest_kernel<false, true>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((forest_kernel<false, true, false>), grid, block, lds, s, a);
   else
-    hipLaunchKernelGGL((forest_kernel<false, false>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((forest_kernel<false, false, false>), grid, block, lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
@@ -1084,9 +1202,20 @@ ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64
                                  double* phi, double* Abar) {
   if (!g || !coeffs || !A || !phi || !Abar || n_env < 0) return fail(ACE_ERR_INVALID_ARG, "NULL argument");
   if (!g->forest_ok) return fail(ACE_ERR_UNSUPPORTED, "no forest schedule: " + g->forest_why);
-  for (int64_t e = 0; e < n_env; ++e)
-    if (!forest_emulate(g, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1))
+  std::vector<double> phi2(2), ab2(2 * (size_t)g->P1);
+  for (int64_t e = 0; e < n_env; ++e) {
+    // both adjoint modes; they must agree
+    if (!forest_emulate(g, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1, true) ||
+        !forest_emulate(g, coeffs, A + 2 * e * g->P1, phi2.data(), ab2.data(), false))
       return fail(ACE_ERR_INTERNAL, "forest schedule index out of range");
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < 2 * g->P1; ++i) {
+      const double d = ab2[i] - Abar[2 * e * g->P1 + i];
+      num += d * d;
+      den += ab2[i] * ab2[i];
+    }
+    if (num > 1e-24 * (den + 1e-300)) return fail(ACE_ERR_INTERNAL, "forest adjoint modes disagree");
+  }
   return ACE_OK;
 }
 

@@ -98,8 +98,14 @@ struct ForestArgs {
   const uint16_t* ch_s;      // children, 64-interleaved per slice: resident sibling slot
   const int2* ch_g;          // children: grandchild range [x, y) (nullptr if none exist)
   const uint16_t* gc_s;      // grandchildren: resident sibling slot
-  int cs_leaf, cs_nu2, cs_me, cs_it, cs_ch, cs_gc;
+  int cs_leaf, cs_nu2, cs_me, cs_it, cs_ch, cs_gc, cs_hot;
   int P1, N2, nslot, n_mslices, n_tslices;
+  int n_items;   // 64 * n_tslices
+  int4 hot;      // slots of the four hot-sibling columns (P1 = unused)
+  // full-adjoint mode: abar for every resident slot in LDS, order-2
+  // adjoints forwarded at the end by a gather per one-particle node
+  const int32_t* fw_off;   // [P1 + 1] CSR offsets
+  const uint32_t* fw_ent;  // entries: order-2 slot | (other parent slot << 16)
 };
 
 struct PrepArgs {

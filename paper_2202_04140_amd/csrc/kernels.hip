@@ -55,6 +55,16 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* scratch) {
   return s;
 }
 
+// Sum of one double2 over the 64 lanes of a wave (every lane gets the sum).
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // one-particle basis
 // ---------------------------------------------------------------------------
@@ -456,29 +466,50 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs p) {
 // accumulators updated with atomics, so the reverse pass is not bitwise
 // deterministic (the forward pass is).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void push_adj(const ForestArgs& p, const double2* x, double2* ab, int slot, double2 d) {
-  if (slot <= p.P1) {
+__device__ __forceinline__ void push_adj(int P1, const uint32_t* n2, const double2* x, double2* ab, int slot,
+                                         double2 d) {
+  if (slot <= P1) {
     atomic_cadd(&ab[slot], d);
   } else {
-    const uint32_t q = p.nu2_ab[slot - p.P1 - 1];
+    const uint32_t q = n2[slot - P1 - 1];
     const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
     atomic_cadd(&ab[a], cmul(d, x[b]));
     atomic_cadd(&ab[b], cmul(d, x[a]));
   }
 }
 
-template <bool GRAD, bool GC>
-__global__ __launch_bounds__(256) void forest_kernel(ForestArgs p) {
+// Push with an adjoint accumulator for every resident slot (full mode) or
+// forwarding order-2 contributions to the one-particle adjoints at once.
+template <bool FULL>
+__device__ __forceinline__ void push_r(int P1, const uint32_t* n2, const double2* x, double2* ab, int slot,
+                                       double2 d) {
+  if (FULL)
+    atomic_cadd(&ab[slot], d);
+  else
+    push_adj(P1, n2, x, ab, slot, d);
+}
+
+constexpr int kForestBlock = 512;
+
+template <bool GRAD, bool GC, bool FULL>
+__global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
   extern __shared__ double2 lds[];
-  double2* x = lds;                                   // [nslot]
-  double2* ab = lds + p.nslot;                        // [P1 + 1] when GRAD
-  double2* red = ab + (GRAD ? p.P1 + 1 : 0);          // [blockDim / 64]
+  // values of the resident slots; adjoints of all resident slots (FULL) or of
+  // the one-particle slots only, with the order-2 parent table (!FULL)
+  constexpr bool TAB = GRAD && !FULL;
+  double2* x = lds;
+  double2* ab = lds + p.nslot;
+  const int nab = GRAD ? (FULL ? p.nslot : p.P1 + 1) : 0;
+  uint32_t* n2 = reinterpret_cast<uint32_t*>(ab + nab);
+  double2* red = reinterpret_cast<double2*>(n2) + (TAB ? (p.N2 + 3) / 4 : 0);
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int P1 = p.P1;
   const int ZERO = P1;
   const double* cs = p.cs;
+  if (TAB)
+    for (int u = threadIdx.x; u < p.N2; u += blockDim.x) n2[u] = p.nu2_ab[u];
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
     // phase 0: one-particle values and adjoint accumulators
     const double2* Ae = p.A + e * P1;
@@ -490,6 +521,8 @@ __global__ __launch_bounds__(256) void forest_kernel(ForestArgs p) {
       x[ZERO] = make_double2(0.0, 0.0);
       if (GRAD) ab[ZERO] = make_double2(0.0, 0.0);
     }
+    if (GRAD && FULL)
+      for (int u = threadIdx.x; u < p.N2; u += blockDim.x) ab[P1 + 1 + u] = make_double2(0.0, 0.0);
     __syncthreads();
     double2 acc = make_double2(0.0, 0.0);
     // phase 1: order-2 nodes, their own and the one-particle coefficients
@@ -508,22 +541,34 @@ __global__ __launch_bounds__(256) void forest_kernel(ForestArgs p) {
       }
     }
     __syncthreads();
-    // phase 2a: resident-pair rows, y = M x
+    // phase 2a: resident-pair rows, y = M x (entry count padded to 4)
     for (int s = wid; s < p.n_mslices; s += nw) {
       const int4 sl = p.mr_slice[s];
       const int row = p.mr_row[sl.x + lane];
-      const double2 xu = x[row];
-      double2 y = make_double2(0.0, 0.0);
-      for (int j = 0; j < sl.z; ++j) {
+      const double* ce = cs + p.cs_me;
+      double2 y0 = make_double2(0.0, 0.0), y1 = make_double2(0.0, 0.0);
+      for (int j = 0; j < sl.z; j += 4) {
         const int pos = sl.y + j * 64 + lane;
-        y = rfma(cs[p.cs_me + pos], x[p.me_col[pos]], y);
+        const int c0 = p.me_col[pos], c1 = p.me_col[pos + 64];
+        const int c2 = p.me_col[pos + 128], c3 = p.me_col[pos + 192];
+        const double k0 = ce[pos], k1 = ce[pos + 64], k2 = ce[pos + 128], k3 = ce[pos + 192];
+        const double2 x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+        y0 = rfma(k0, x0, y0);
+        y1 = rfma(k1, x1, y1);
+        y0 = rfma(k2, x2, y0);
+        y1 = rfma(k3, x3, y1);
       }
-      const double2 h = cmul(xu, y);
+      const double2 y = make_double2(y0.x + y1.x, y0.y + y1.y);
+      const double2 h = cmul(x[row], y);
       acc.x = fma(0.5, h.x, acc.x);
       acc.y = fma(0.5, h.y, acc.y);
-      if (GRAD && row != ZERO) push_adj(p, x, ab, row, y);
+      if (GRAD && row != ZERO) push_r<FULL>(P1, n2, x, ab, row, y);
     }
-    // phase 2b: trees
+    // phase 2b: trees.  Children whose sibling is one of the four hot slots
+    // sit in fixed columns; their adjoint contributions are summed in
+    // registers and pushed once per wave at the end.
+    const double2 xh0 = x[p.hot.x], xh1 = x[p.hot.y], xh2 = x[p.hot.z], xh3 = x[p.hot.w];
+    double2 hacc0 = make_double2(0.0, 0.0), hacc1 = hacc0, hacc2 = hacc0, hacc3 = hacc0;
     for (int s = wid; s < p.n_tslices; s += nw) {
       const int4 sl = p.tr_slice[s];
       const int item = sl.x + lane;
@@ -533,40 +578,95 @@ __global__ __launch_bounds__(256) void forest_kernel(ForestArgs p) {
       const double2 xv = cmul(xa, xb);
       double2 t = make_double2(cs[p.cs_it + item], 0.0);  // abar_v from childless children
       double2 asum = make_double2(0.0, 0.0);              // abar_v from children with children
-      for (int j = 0; j < sl.z; ++j) {
-        const int pos = sl.y + j * 64 + lane;
-        const int sidx = p.ch_s[pos];
-        const double c = cs[p.cs_ch + pos];
-        const double2 xs = x[sidx];
-        int2 g = make_int2(0, 0);
-        if (GC) g = p.ch_g[pos];
-        if (!GC || g.x == g.y) {
-          t = rfma(c, xs, t);
-          if (GRAD && sidx != ZERO) push_adj(p, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
-        } else {
-          const double2 xw = cmul(xv, xs);
-          double2 aw = make_double2(c, 0.0);
-          for (int k = g.x; k < g.y; ++k) {
-            const int sg = p.gc_s[k];
-            const double cg = cs[p.cs_gc + k];
-            aw = rfma(cg, x[sg], aw);
-            if (GRAD) push_adj(p, x, ab, sg, make_double2(cg * xw.x, cg * xw.y));
-          }
-          acc = cfma(xw, aw, acc);
+      {
+        const double* ch = cs + p.cs_hot + item;
+        const double k0 = ch[0], k1 = ch[p.n_items], k2 = ch[2 * p.n_items], k3 = ch[3 * p.n_items];
+        t = rfma(k0, xh0, t);
+        t = rfma(k1, xh1, t);
+        t = rfma(k2, xh2, t);
+        t = rfma(k3, xh3, t);
+        if (GRAD) {
+          hacc0 = rfma(k0, xv, hacc0);
+          hacc1 = rfma(k1, xv, hacc1);
+          hacc2 = rfma(k2, xv, hacc2);
+          hacc3 = rfma(k3, xv, hacc3);
+        }
+      }
+      const double* cc = cs + p.cs_ch;
+      if (!GC) {
+        // children counts padded to 4 (padding: sibling ZERO, coefficient 0)
+        for (int j = 0; j < sl.z; j += 4) {
+          const int pos = sl.y + j * 64 + lane;
+          const int s0 = p.ch_s[pos], s1 = p.ch_s[pos + 64], s2 = p.ch_s[pos + 128], s3 = p.ch_s[pos + 192];
+          const double k0 = cc[pos], k1 = cc[pos + 64], k2 = cc[pos + 128], k3 = cc[pos + 192];
+          const double2 x0 = x[s0], x1 = x[s1], x2 = x[s2], x3 = x[s3];
+          t = rfma(k0, x0, t);
+          t = rfma(k1, x1, t);
+          t = rfma(k2, x2, t);
+          t = rfma(k3, x3, t);
           if (GRAD) {
-            push_adj(p, x, ab, sidx, cmul(aw, xv));
-            asum = cfma(aw, xs, asum);
+            if (s0 != ZERO) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
+            if (s1 != ZERO) push_r<FULL>(P1, n2, x, ab, s1, make_double2(k1 * xv.x, k1 * xv.y));
+            if (s2 != ZERO) push_r<FULL>(P1, n2, x, ab, s2, make_double2(k2 * xv.x, k2 * xv.y));
+            if (s3 != ZERO) push_r<FULL>(P1, n2, x, ab, s3, make_double2(k3 * xv.x, k3 * xv.y));
+          }
+        }
+      } else {
+        for (int j = 0; j < sl.z; ++j) {
+          const int pos = sl.y + j * 64 + lane;
+          const int sidx = p.ch_s[pos];
+          const double c = cc[pos];
+          const int2 g = p.ch_g[pos];
+          const double2 xs = x[sidx];
+          if (g.x == g.y) {
+            t = rfma(c, xs, t);
+            if (GRAD && sidx != ZERO) push_r<FULL>(P1, n2, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
+          } else {
+            const double2 xw = cmul(xv, xs);
+            double2 aw = make_double2(c, 0.0);
+            for (int k = g.x; k < g.y; ++k) {
+              const int sg = p.gc_s[k];
+              const double cg = cs[p.cs_gc + k];
+              aw = rfma(cg, x[sg], aw);
+              if (GRAD) push_r<FULL>(P1, n2, x, ab, sg, make_double2(cg * xw.x, cg * xw.y));
+            }
+            acc = cfma(xw, aw, acc);
+            if (GRAD) {
+              push_r<FULL>(P1, n2, x, ab, sidx, cmul(aw, xv));
+              asum = cfma(aw, xs, asum);
+            }
           }
         }
       }
       acc = cfma(xv, t, acc);
       if (GRAD && q != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
         const double2 av = make_double2(t.x + asum.x, t.y + asum.y);
-        push_adj(p, x, ab, a, cmul(av, xb));
-        push_adj(p, x, ab, b, cmul(av, xa));
+        push_r<FULL>(P1, n2, x, ab, a, cmul(av, xb));
+        push_r<FULL>(P1, n2, x, ab, b, cmul(av, xa));
+      }
+    }
+    if (GRAD) {
+      const double2 h0 = wave_sum(hacc0), h1 = wave_sum(hacc1), h2 = wave_sum(hacc2), h3 = wave_sum(hacc3);
+      if (lane == 0) {
+        if (p.hot.x != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.x, h0);
+        if (p.hot.y != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.y, h1);
+        if (p.hot.z != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.z, h2);
+        if (p.hot.w != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.w, h3);
       }
     }
     __syncthreads();
+    if (GRAD && FULL) {
+      // order-2 adjoints to the one-particle adjoints: abar_a += abar_u x_b
+      for (int i = threadIdx.x; i < P1; i += blockDim.x) {
+        double2 s2 = ab[i];
+        for (int q = p.fw_off[i]; q < p.fw_off[i + 1]; ++q) {
+          const uint32_t en = p.fw_ent[q];
+          s2 = cfma(ab[en & 0xffffu], x[en >> 16], s2);
+        }
+        ab[i] = s2;
+      }
+      __syncthreads();
+    }
     const double2 phi = block_sum(acc, red);
     if (threadIdx.x == 0) p.phi[e] = phi;
     if (GRAD) {
@@ -577,9 +677,11 @@ __global__ __launch_bounds__(256) void forest_kernel(ForestArgs p) {
   }
 }
 
-template __global__ void forest_kernel<false, false>(ForestArgs);
-template __global__ void forest_kernel<false, true>(ForestArgs);
-template __global__ void forest_kernel<true, false>(ForestArgs);
-template __global__ void forest_kernel<true, true>(ForestArgs);
+template __global__ void forest_kernel<false, false, false>(ForestArgs);
+template __global__ void forest_kernel<false, true, false>(ForestArgs);
+template __global__ void forest_kernel<true, false, false>(ForestArgs);
+template __global__ void forest_kernel<true, true, false>(ForestArgs);
+template __global__ void forest_kernel<true, false, true>(ForestArgs);
+template __global__ void forest_kernel<true, true, true>(ForestArgs);
 
 }  // namespace ace
