@@ -219,7 +219,11 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  * ace_debug_schedule: *kind = 1 if evaluation uses the forest schedule
  *   (one-particle and order-2 node values resident in LDS, every higher
  *   node computed in registers), 0 if it uses the layer-by-layer schedule;
- *   in the latter case ace_last_error() names the reason.
+ *   in the latter case ace_last_error() names the reason.  If info is not
+ *   NULL it receives 16 int64 schedule sizes: resident slots, tree slices,
+ *   child positions (padded, real), pair-row slices, pair entries (padded,
+ *   real), grandchildren, the four hot slots, whether all resident adjoints
+ *   fit in LDS; the rest are 0.
  *
  * ace_debug_forest_eval: runs the forest schedule on the host for n_env
  *   environments, with the same indices, padding and forwarding as the
@@ -228,7 +232,7 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   ACE_ERR_UNSUPPORTED if the graph has no forest schedule,
  *   ACE_ERR_INTERNAL if an index of the schedule is out of range.
  */
-ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind);
+ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info);
 ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
                                  double* phi, double* Abar);
 

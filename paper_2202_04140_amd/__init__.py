@@ -84,7 +84,7 @@ EXPORTED = {
     "ace_contract": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval_grad": ([_P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
-    "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
+    "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
     "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
 }
 
@@ -186,8 +186,17 @@ class Graph:
     def schedule_kind(self) -> str:
         """'forest' or 'layered' (ace_debug_schedule)."""
         k = ctypes.c_int32()
-        _check(lib().ace_debug_schedule(self._h, ctypes.byref(k)))
+        _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), None))
         return "forest" if k.value == 1 else "layered"
+
+    def schedule_info(self) -> dict:
+        """Sizes of the forest schedule (ace_debug_schedule)."""
+        k = ctypes.c_int32()
+        info = np.zeros(16, dtype=np.int64)
+        _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
+        names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
+                 "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint"]
+        return {"kind": "forest" if k.value == 1 else "layered", **{n: int(v) for n, v in zip(names, info)}}
 
     def forest_eval_host(self, coeffs: np.ndarray, A: np.ndarray):
         """Host emulation of the forest kernel (ace_debug_forest_eval):

@@ -39,7 +39,7 @@ constexpr int kDagThreads = 256;
 constexpr int kForestThreads = 512;
 constexpr int kNaiveThreads = 256;
 constexpr int kBasisThreads = 256;
-constexpr int kGradThreads = 64;
+constexpr int kGradThreads = 256;
 constexpr int kArenaBlocks = 1024;
 constexpr size_t kAlign = 256;
 
@@ -67,12 +67,14 @@ struct ace_graph {
   std::vector<int16_t> naive_tup;
   std::vector<OnepInfo> onep;
   std::vector<int16_t> onep_index;
+  std::vector<int32_t> nstart;
   std::vector<double> ycoef;
   // device copies (one allocation)
   void* dmem = nullptr;
   int2 *d_st_ab = nullptr, *d_cl_ab = nullptr;
   int32_t *d_st_k = nullptr, *d_cl_k = nullptr, *d_leaf_k = nullptr;
   int16_t *d_naive_tup = nullptr, *d_onep_index = nullptr;
+  int32_t* d_nstart = nullptr;
   OnepInfo* d_onep = nullptr;
   double* d_ycoef = nullptr;
   // LDS plan
@@ -209,6 +211,7 @@ void make_schedule(ace_graph* g) {
   // one-particle tables (O(3) only)
   g->onep.clear();
   g->onep_index.clear();
+  g->nstart.clear();
   g->ycoef.clear();
   if (h.spec.group == 0) {
     const int L = h.spec.l_max, N = h.spec.n_max, W = 2 * L + 1;
@@ -222,10 +225,17 @@ void make_schedule(ace_graph* g) {
       const int sgn = (am & 1) ? -1 : 1;
       o.sre = (int8_t)(m < 0 ? sgn : 1);
       o.sim = (int8_t)(m < 0 ? -sgn : 1);
+      o.l = (int8_t)l;
+      o.am = (int8_t)am;
       g->onep.push_back(o);
       g->onep_index[(size_t)(n * (L + 1) + l) * W + (m + L)] = (int16_t)i;
     }
     make_ycoef(L, g->ycoef);
+    // index of (n, l, -l) per (l, n); the 2l+1 functions of one (n, l) are
+    // consecutive in the canonical order
+    g->nstart.assign((size_t)(L + 1) * (N + 1), -1);
+    for (int i = 0; i < P1; ++i)
+      if (h.on_m[i] == -h.on_l[i]) g->nstart[(size_t)h.on_l[i] * (N + 1) + h.on_n[i]] = i;
   }
 }
 
@@ -356,34 +366,95 @@ void make_forest(ace_graph* g) {
     return x.ngc > y.ngc;
   });
   const uint32_t zz = (uint32_t)P1 | ((uint32_t)P1 << 16);
-  const int nts = (int)((items.size() + 63) / 64);
+  // Pack items into slices of 64 lanes.  Items arrive sorted by size; each
+  // goes to the first slice of a small window of open slices in which no
+  // other lane pushes to the same root parents (same-address LDS atomics in
+  // one instruction serialise), else to the first slice with room.
+  std::vector<std::vector<int>> slices;
+  {
+    // per size class (items with the same regular-child count, which keeps
+    // slices free of column padding): the minimal number of slices, each item
+    // to the slice with room whose lanes share the fewest root parents with it
+    int i0 = 0;
+    while (i0 < (int)items.size()) {
+      int i1 = i0;
+      while (i1 < (int)items.size() && items[i1].c1 - items[i1].c0 == items[i0].c1 - items[i0].c0) ++i1;
+      const int S = (i1 - i0 + 63) / 64;
+      const int first = (int)slices.size();
+      slices.resize(first + S);
+      std::vector<std::vector<int32_t>> ta(S), tb(S);
+      for (int i = i0; i < i1; ++i) {
+        const int32_t a = slot[h.par[2 * items[i].root]], b = slot[h.par[2 * items[i].root + 1]];
+        int best = -1, bestc = 1 << 30;
+        for (int q = 0; q < S; ++q) {
+          if (slices[first + q].size() >= 64) continue;
+          const int c = (int)std::count(ta[q].begin(), ta[q].end(), a) + (int)std::count(tb[q].begin(), tb[q].end(), b);
+          if (c < bestc) {
+            bestc = c;
+            best = q;
+          }
+        }
+        slices[first + best].push_back(i);
+        ta[best].push_back(a);
+        tb[best].push_back(b);
+      }
+      i0 = i1;
+    }
+  }
+  const int nts = (int)slices.size();
   std::vector<int32_t> k_it((size_t)nts * 64, -1), k_ch, k_gc;
+  std::vector<int32_t> item_pos(items.size(), -1);   // item -> lane index sl*64 + l
   g->it_ab.assign((size_t)nts * 64, zz);
   g->tr_slice.assign(nts, make_int4(0, 0, 0, 0));
   g->ch_s.clear();
   g->ch_g.clear();
   g->gc_s.clear();
   for (int sl = 0; sl < nts; ++sl) {
-    int nmax = 0;
-    for (int l = 0; l < 64 && sl * 64 + l < (int)items.size(); ++l) {
-      const Item& it = items[sl * 64 + l];
-      nmax = std::max(nmax, it.c1 - it.c0);
+    // Columns of the regular children: each child takes the lowest column in
+    // which its sibling slot is not yet used by another lane of the slice.
+    const int nl = (int)slices[sl].size();
+    std::vector<std::vector<int32_t>> colsib;          // sibling slots used per column
+    std::vector<std::vector<int32_t>> lanecol(nl);     // column of each child of each lane
+    int ncol = 0, cmax = 0;
+    for (int l = 0; l < nl; ++l) cmax = std::max(cmax, items[slices[sl][l]].c1 - items[slices[sl][l]].c0);
+    const int cap = cmax;   // conflicts are dodged by the order of an item's children only
+    for (int l = 0; l < nl; ++l) {
+      const Item& it = items[slices[sl][l]];
+      std::vector<uint8_t> used;
+      for (int j = it.c0; j < it.c1; ++j) {
+        const int32_t sb = sib[kids[it.root][j]];
+        auto lane_busy = [&](int c) { return c < (int)used.size() && used[c]; };
+        int col = -1;
+        for (int c = 0; c < cap && col < 0; ++c) {
+          if ((int)colsib.size() <= c) colsib.emplace_back();
+          if (!lane_busy(c) && std::find(colsib[c].begin(), colsib[c].end(), sb) == colsib[c].end()) col = c;
+        }
+        if (col < 0)  // no conflict-free column: take the first free one
+          for (int c = 0; c < cap && col < 0; ++c)
+            if (!lane_busy(c)) col = c;
+        colsib[col].push_back(sb);
+        if ((int)used.size() <= col) used.resize(col + 1, 0);
+        used[col] = 1;
+        lanecol[l].push_back(col);
+        ncol = std::max(ncol, col + 1);
+      }
     }
-    if (!has_gc) nmax = (nmax + 3) / 4 * 4;  // the kernel walks children four at a time
+    const int nmax = ncol;
     const int base = (int)g->ch_s.size();
     g->tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
     g->ch_s.resize(base + (size_t)nmax * 64, (uint16_t)P1);
     g->ch_g.resize(base + (size_t)nmax * 64, make_int2(0, 0));
     k_ch.resize(base + (size_t)nmax * 64, -1);
-    for (int l = 0; l < 64 && sl * 64 + l < (int)items.size(); ++l) {
-      const Item& it = items[sl * 64 + l];
+    for (int l = 0; l < nl; ++l) {
+      const Item& it = items[slices[sl][l]];
       const int idx = sl * 64 + l;
+      item_pos[slices[sl][l]] = idx;
       const int32_t a = h.par[2 * it.root], b = h.par[2 * it.root + 1];
       g->it_ab[idx] = (uint32_t)slot[a] | ((uint32_t)slot[b] << 16);
       k_it[idx] = it.c0 == 0 ? h.node_k[it.root] : -1;
       for (int j = it.c0; j < it.c1; ++j) {
         const int32_t c = kids[it.root][j];
-        const int pos = base + (j - it.c0) * 64 + l;
+        const int pos = base + lanecol[l][j - it.c0] * 64 + l;
         g->ch_s[pos] = (uint16_t)sib[c];
         k_ch[pos] = h.node_k[c];
         if (!kids[c].empty()) {
@@ -404,7 +475,7 @@ void make_forest(ace_graph* g) {
   std::vector<int32_t> k_hot((size_t)4 * nts * 64, -1);
   for (size_t i = 0; i < items.size(); ++i)
     for (int hc = 0; hc < 4; ++hc)
-      if (items[i].hot[hc] >= 0) k_hot[(size_t)hc * nts * 64 + i] = h.node_k[items[i].hot[hc]];
+      if (items[i].hot[hc] >= 0) k_hot[(size_t)hc * nts * 64 + item_pos[i]] = h.node_k[items[i].hot[hc]];
 
   // ---- resident-pair rows ----
   std::vector<std::vector<std::pair<uint16_t, int32_t>>> rows(nslot);
@@ -440,7 +511,7 @@ void make_forest(ace_graph* g) {
     int nmax = 0;
     for (int l = 0; l < 64 && sl * 64 + l < (int)rch.size(); ++l)
       nmax = std::max(nmax, rch[sl * 64 + l].e1 - rch[sl * 64 + l].e0);
-    nmax = (nmax + 3) / 4 * 4;  // the kernel walks entries four at a time
+
     const int base = (int)g->me_col.size();
     g->mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
     g->me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
@@ -683,7 +754,7 @@ ace_status upload(ace_graph* g) {
   bytes += align_up(g->cl_ab.size() * sizeof(int2)) + align_up(g->cl_k.size() * 4);
   bytes += align_up(g->leaf_k.size() * 4) + align_up(g->naive_tup.size() * 2);
   bytes += align_up(g->onep.size() * sizeof(OnepInfo)) + align_up(g->onep_index.size() * 2);
-  bytes += align_up(g->ycoef.size() * 8) + kAlign;
+  bytes += align_up(g->ycoef.size() * 8) + align_up(g->nstart.size() * 4) + kAlign;
   if (hipMalloc(&g->dmem, bytes) != hipSuccess) {
     g->dmem = nullptr;
     (void)hipGetLastError();
@@ -699,6 +770,7 @@ ace_status upload(ace_graph* g) {
   g->d_onep = carve<OnepInfo>(p, g->onep.size());
   g->d_onep_index = carve<int16_t>(p, g->onep_index.size());
   g->d_ycoef = carve<double>(p, g->ycoef.size());
+  g->d_nstart = carve<int32_t>(p, g->nstart.size());
   auto put = [](void* d, const void* s, size_t n) { return n ? hipMemcpy(d, s, n, hipMemcpyHostToDevice) : hipSuccess; };
   ACE_HIP(put(g->d_st_ab, g->st_ab.data(), g->st_ab.size() * sizeof(int2)));
   ACE_HIP(put(g->d_st_k, g->st_k.data(), g->st_k.size() * 4));
@@ -709,6 +781,7 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(put(g->d_onep, g->onep.data(), g->onep.size() * sizeof(OnepInfo)));
   ACE_HIP(put(g->d_onep_index, g->onep_index.data(), g->onep_index.size() * 2));
   ACE_HIP(put(g->d_ycoef, g->ycoef.data(), g->ycoef.size() * 8));
+  ACE_HIP(put(g->d_nstart, g->nstart.data(), g->nstart.size() * 4));
 
   // LDS plan for the DAG kernel
   const size_t red = (kDagThreads / 64) * sizeof(double2);
@@ -843,7 +916,8 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   a.l_max = g->h.spec.l_max;
   a.r_cut = g->h.spec.r_cut;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
-  const size_t lds = (size_t)g->P1 * 16 + (size_t)32 * ((a.n_max + 1) + 2 * NY) * 8;
+  const int chunk = kBasisThreads / (a.l_max + 1);
+  const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * ((a.n_max + 1) + 2 * NY) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the basis kernel");
   hipLaunchKernelGGL(basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
   ACE_HIP(hipGetLastError());
@@ -999,14 +1073,18 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.Abar = Abar;
   a.grad = grad;
   a.onep_index = g->d_onep_index;
+  a.nstart = g->d_nstart;
   a.ycoef = g->d_ycoef;
   a.P1 = g->P1;
   a.n_max = g->h.spec.n_max;
   a.l_max = g->h.spec.l_max;
   a.r_cut = g->h.spec.r_cut;
-  const size_t lds = (size_t)g->P1 * 16 + g->onep_index.size() * 2 + 16;
+  const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
+  const int nwb = kGradThreads / 64;
+  const size_t lds = (size_t)nwb * g->P1 * 16 + (size_t)3 * NY * 8 + g->nstart.size() * 4;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
-  hipLaunchKernelGGL(grad_kernel, dim3((unsigned)grid_for(n_env)), dim3(kGradThreads), lds, s, a);
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_env + nwb - 1) / nwb, (int64_t)1 << 20));
+  hipLaunchKernelGGL(grad_kernel, dim3((unsigned)blocks), dim3(kGradThreads), lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
@@ -1191,10 +1269,29 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
 }
 
-ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind) {
+ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) {
   if (!g || !kind) return fail(ACE_ERR_INVALID_ARG, "graph and kind must be non-NULL");
   *kind = g->forest_ok ? 1 : 0;
   if (!g->forest_ok) g_error = g->forest_why;
+  if (info) {
+    for (int i = 0; i < 16; ++i) info[i] = 0;
+    if (g->forest_ok) {
+      info[0] = g->nslot;
+      info[1] = g->n_tslices;
+      info[2] = (int64_t)g->ch_s.size();
+      int64_t realc = 0;
+      for (uint16_t v : g->ch_s) realc += v != (uint16_t)g->P1;
+      info[3] = realc;
+      info[4] = g->n_mslices;
+      info[5] = (int64_t)g->me_col.size();
+      int64_t reale = 0;
+      for (int32_t k : std::vector<int32_t>(g->kmap.begin() + g->cs_me, g->kmap.begin() + g->cs_nu2)) reale += k != -1;
+      info[6] = reale;
+      info[7] = (int64_t)g->gc_s.size();
+      for (int h = 0; h < 4; ++h) info[8 + h] = g->hot_slot[h];
+      info[12] = g->forest_full ? 1 : 0;
+    }
+  }
   return ACE_OK;
 }
 

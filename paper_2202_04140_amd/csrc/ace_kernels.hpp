@@ -17,7 +17,8 @@ struct OnepInfo {
   int16_t yoff;   // (l*(l+1))/2 + |m|
   int8_t sre;     // +1 / -1 applied to Re Y_l^{|m|}
   int8_t sim;     // +1 / -1 applied to Im Y_l^{|m|}
-  int16_t pad;
+  int8_t l;
+  int8_t am;      // |m|
 };
 
 struct BasisArgs {
@@ -70,6 +71,7 @@ struct GradArgs {
   const double2* Abar;       // [n_env][P1]
   double* grad;              // [n_nbr][3]
   const int16_t* onep_index; // [(n_max+1)][(l_max+1)][(2 l_max+1)] -> i or -1
+  const int32_t* nstart;     // [(l_max+1)][(n_max+1)]: index of (n, l, -l), or -1
   const double* ycoef;
   int P1, n_max, l_max;
   double r_cut;

@@ -68,81 +68,79 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
 // ---------------------------------------------------------------------------
 // one-particle basis
 // ---------------------------------------------------------------------------
-// Per-neighbour table: T_n(c) for n = 0..n_max, then (Re, Im) Y_l^m for
-// m >= 0 at offset (l(l+1)/2 + m).  Y by the associated-Legendre
-// recurrence in Cartesian form: Y_l^m = q_l^m(z) (x + i y)^m with
-//   q_m^m = start_m,  q_l^m = A_lm z q_{l-1}^m - B_lm q_{l-2}^m
-// (normalisation and Condon-Shortley phase folded into the coefficients
-// on the host).  This form has no division by sin(theta).
-__device__ void neighbour_table(const double* r, const double* ycoef, int n_max, int l_max,
-                                double r_cut, double* tab) {
-  const double rx = r[0], ry = r[1], rz = r[2];
-  const double rr = sqrt(rx * rx + ry * ry + rz * rz);
-  const double inv = 1.0 / rr;
-  const double x = rx * inv, y = ry * inv, z = rz * inv;
-  const double c = cos(M_PI * rr / r_cut);
-  double t0 = 1.0, t1 = c;
-  tab[0] = 1.0;
-  if (n_max >= 1) tab[1] = c;
-  for (int n = 2; n <= n_max; ++n) {
-    const double t2 = 2.0 * c * t1 - t0;
-    tab[n] = t2;
-    t0 = t1;
-    t1 = t2;
-  }
-  double* Y = tab + (n_max + 1);
-  const int NY = (l_max + 1) * (l_max + 2) / 2;
-  const double* cA = ycoef;
-  const double* cB = ycoef + NY;
-  const double* cS = ycoef + 2 * NY;
-  double pr = 1.0, pi = 0.0;  // (x + i y)^m
-  for (int m = 0; m <= l_max; ++m) {
-    double q2 = 0.0, q1 = cS[(m * (m + 1)) / 2 + m];
-    for (int l = m; l <= l_max; ++l) {
-      const int o = (l * (l + 1)) / 2 + m;
-      double q;
-      if (l == m) {
-        q = q1;
-      } else {
-        q = cA[o] * z * q1 - cB[o] * q2;
-        q2 = q1;
-        q1 = q;
-      }
-      Y[2 * o] = q * pr;
-      Y[2 * o + 1] = q * pi;
-    }
-    const double npr = pr * x - pi * y;
-    const double npi = pr * y + pi * x;
-    pr = npr;
-    pi = npi;
-  }
-}
+constexpr int kBasisBlock = 256;
 
-constexpr int kBasisChunk = 32;
-
-__global__ __launch_bounds__(256) void basis_kernel(BasisArgs p) {
+// One-particle basis.  Per environment, in chunks of neighbours: a table of
+// T_n(cos(pi r / r_cut)) and Y_l^m (m >= 0) per neighbour is built in LDS by
+// (neighbour, m) lanes, each running the Legendre recurrence in l for its m
+// (Y_l^m = q_l^m(z) (x + i y)^m with q_m^m = start_m and
+// q_l^m = A_lm z q_{l-1}^m - B_lm q_{l-2}^m; normalisation and
+// Condon-Shortley phase are folded into the coefficients on the host; the
+// form has no division by sin(theta)).  Then one lane per one-particle
+// index i accumulates R_{n_i} Y_{l_i}^{m_i} over the chunk.
+__global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
   extern __shared__ double lds_b[];
-  const int NY = (p.l_max + 1) * (p.l_max + 2) / 2;
-  const int stride = (p.n_max + 1) + 2 * NY;
+  const int L = p.l_max;
+  const int NY = (L + 1) * (L + 2) / 2;
+  const int stride = (p.n_max + 1) + 2 * NY;        // doubles per neighbour
+  const int chunk = blockDim.x / (L + 1);           // neighbours per chunk
   double2* acc = reinterpret_cast<double2*>(lds_b);  // [P1]
-  double* tab = lds_b + 2 * p.P1;                     // [kBasisChunk][stride]
+  double* tab = lds_b + 2 * p.P1;                    // [chunk][stride]
+  const double* cA = p.ycoef;
+  const double* cB = p.ycoef + NY;
+  const double* cS = p.ycoef + 2 * NY;
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
     for (int i = threadIdx.x; i < p.P1; i += blockDim.x) acc[i] = make_double2(0.0, 0.0);
-    for (int c0 = 0; c0 < J; c0 += kBasisChunk) {
-      const int nc = min(kBasisChunk, J - c0);
+    for (int c0 = 0; c0 < J; c0 += chunk) {
+      const int nc = min(chunk, J - c0);
       __syncthreads();
-      if (threadIdx.x < nc)
-        neighbour_table(p.pos + 3 * (int64_t)(j0 + c0 + threadIdx.x), p.ycoef, p.n_max, p.l_max, p.r_cut,
-                        tab + threadIdx.x * stride);
+      const int jj = threadIdx.x / (L + 1), m = threadIdx.x % (L + 1);
+      if (jj < nc) {
+        const double* r = p.pos + 3 * (int64_t)(j0 + c0 + jj);
+        const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const double inv = 1.0 / rr;
+        const double x = r[0] * inv, y = r[1] * inv, z = r[2] * inv;
+        double* t = tab + jj * stride;
+        if (m == 0) {
+          const double c = cos(M_PI * rr / p.r_cut);
+          double t0 = 1.0, t1 = c;
+          t[0] = 1.0;
+          if (p.n_max >= 1) t[1] = c;
+          for (int n = 2; n <= p.n_max; ++n) {
+            const double t2 = 2.0 * c * t1 - t0;
+            t[n] = t2;
+            t0 = t1;
+            t1 = t2;
+          }
+        }
+        double pr = 1.0, pi = 0.0;  // (x + i y)^m
+        for (int k = 0; k < m; ++k) {
+          const double nr = pr * x - pi * y;
+          pi = pr * y + pi * x;
+          pr = nr;
+        }
+        double* Y = t + (p.n_max + 1);
+        double q2 = 0.0, q1 = cS[(m * (m + 1)) / 2 + m];
+        for (int l = m; l <= L; ++l) {
+          const int o = (l * (l + 1)) / 2 + m;
+          if (l > m) {
+            const double q = cA[o] * z * q1 - cB[o] * q2;
+            q2 = q1;
+            q1 = q;
+          }
+          Y[2 * o] = q1 * pr;
+          Y[2 * o + 1] = q1 * pi;
+        }
+      }
       __syncthreads();
       for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
         const OnepInfo o = p.onep[i];
         double2 a = acc[i];
         const double sre = (double)o.sre, sim = (double)o.sim;
-        for (int jj = 0; jj < nc; ++jj) {
-          const double* t = tab + jj * stride;
+        for (int k = 0; k < nc; ++k) {
+          const double* t = tab + k * stride;
           const double R = t[o.n];
           const double* Y = t + (p.n_max + 1) + 2 * o.yoff;
           a.x = fma(R, sre * Y[0], a.x);
@@ -303,34 +301,54 @@ template __global__ void naive_kernel<7>(NaiveArgs);
 template __global__ void naive_kernel<8>(NaiveArgs);
 
 // ---------------------------------------------------------------------------
-// dA/dr chain: one thread per neighbour.
+// dA/dr chain.
 //   grad(R_n Y_l^m)(r) = R_n'(r) u Y_l^m(u) + R_n(r) grad Y_l^m(r)
 // With S_l^m(r) = (x + i y)^m Q_l^m(z, rho), rho = |r|^2, a homogeneous
 // polynomial of degree l equal to r^l Y_l^m(u) (u = r / |r|),
 //   grad Y_l^m(r) = (grad S(u) - l S(u) u) / |r|,
 // where Q follows the same recurrence as q with the constant term scaled
 // by rho, differentiated in z and rho alongside (no pole singularity).
+//
+// One wave per environment, its adjoint Abar in LDS.  Lanes are
+// (neighbour, group) pairs: group g of G handles m = g, g + G, ... and the
+// G partial gradients of a neighbour are summed by lane shuffles; G is the
+// largest power of two with G * J <= 64 (at most 16).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void grad_kernel(GradArgs p) {
+constexpr int kGradBlock = 256;
+
+__global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
   extern __shared__ double2 lds[];
-  double2* Ab = lds;  // [P1]
-  int16_t* idx = reinterpret_cast<int16_t*>(lds + p.P1);
   const int L = p.l_max, N = p.n_max;
-  const int W = 2 * L + 1;
-  const int nidx = (N + 1) * (L + 1) * W;
   const int NY = (L + 1) * (L + 2) / 2;
-  const double* cA = p.ycoef;
-  const double* cB = p.ycoef + NY;
-  const double* cS = p.ycoef + 2 * NY;
-  for (int i = threadIdx.x; i < nidx; i += blockDim.x) idx[i] = p.onep_index[i];
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nwb = blockDim.x >> 6;
+  double2* Ab = lds + wid * p.P1;                                    // [nwb][P1]
+  double* yc = reinterpret_cast<double*>(lds + nwb * p.P1);           // [3 * NY]
+  int* nst = reinterpret_cast<int*>(yc + 3 * NY);                    // [(L+1)*(N+1)]
+  for (int i = threadIdx.x; i < 3 * NY; i += blockDim.x) yc[i] = p.ycoef[i];
+  for (int i = threadIdx.x; i < (L + 1) * (N + 1); i += blockDim.x) nst[i] = p.nstart[i];
+  const double* cA = yc;
+  const double* cB = yc + NY;
+  const double* cS = yc + 2 * NY;
+  const int64_t rounds = (p.n_env + (int64_t)gridDim.x * nwb - 1) / ((int64_t)gridDim.x * nwb);
+  for (int64_t it = 0; it < rounds; ++it) {
+    const int64_t e = (it * gridDim.x + blockIdx.x) * nwb + wid;   // wave-uniform
     __syncthreads();
-    const double2* Be = p.Abar + e * p.P1;
-    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) Ab[i] = Be[i];
+    if (e < p.n_env) {
+      const double2* Be = p.Abar + e * p.P1;
+      for (int i = lane; i < p.P1; i += 64) Ab[i] = Be[i];
+    }
     __syncthreads();
+    if (e >= p.n_env) continue;
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
-    for (int jj = threadIdx.x; jj < J; jj += blockDim.x) {
+    if (J <= 0) continue;
+    int G = 1;
+    while (G < 16 && 2 * G * J <= 64) G *= 2;
+    const int per = 64 / G;              // neighbours per pass
+    const int g = lane % G, jl = lane / G;
+    for (int c0 = 0; c0 < J; c0 += per) {
+      const int jj = min(c0 + jl, J - 1);   // idle lanes repeat the last neighbour
       const int64_t j = j0 + jj;
       const double rx = p.pos[3 * j], ry = p.pos[3 * j + 1], rz = p.pos[3 * j + 2];
       const double rr = sqrt(rx * rx + ry * ry + rz * rz);
@@ -340,9 +358,32 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs p) {
       const double c = cos(arg);
       const double dcdr = -(M_PI / p.r_cut) * sin(arg);
       double gx = 0.0, gy = 0.0, gz = 0.0;
-      // (x + i y)^m and (x + i y)^(m-1)
-      double pr = 1.0, pi = 0.0, qr = 0.0, qi = 0.0;
-      for (int m = 0; m <= L; ++m) {
+      // (x + i y)^g, (x + i y)^G, (x + i y)^(G-1)
+      double pr = 1.0, pi = 0.0, pGr = 1.0, pGi = 0.0, pG1r = 1.0, pG1i = 0.0;
+      for (int k = 0; k < G; ++k) {
+        if (k == g) {
+          pr = pGr;
+          pi = pGi;
+        }
+        if (k == G - 1) {
+          pG1r = pGr;
+          pG1i = pGi;
+        }
+        const double nr = pGr * x - pGi * y;
+        pGi = pGr * y + pGi * x;
+        pGr = nr;
+      }
+      // (x + i y)^(m-1) for m = g >= 1
+      double qr = 0.0, qi = 0.0;
+      if (g >= 1) {
+        qr = 1.0;
+        for (int k = 1; k < g; ++k) {
+          const double nr = qr * x - qi * y;
+          qi = qr * y + qi * x;
+          qr = nr;
+        }
+      }
+      for (int m = g; m <= L; m += G) {
         double Q2 = 0.0, Qz2 = 0.0, Qp2 = 0.0;
         double Q1 = cS[(m * (m + 1)) / 2 + m], Qz1 = 0.0, Qp1 = 0.0;
         for (int l = m; l <= L; ++l) {
@@ -364,7 +405,6 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs p) {
             Qz1 = Qz;
             Qp1 = Qp;
           }
-          // S = (x+iy)^m Q ; grad S at u
           const double Sr = pr * Q, Si = pi * Q;
           double dxr = 2.0 * x * Qp * pr, dxi = 2.0 * x * Qp * pi;
           double dyr = 2.0 * y * Qp * pr, dyi = 2.0 * y * Qp * pi;
@@ -372,67 +412,79 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs p) {
           if (m > 0) {
             dxr += m * qr * Q;
             dxi += m * qi * Q;
-            dyr -= m * qi * Q;  // i m (x+iy)^(m-1) Q
+            dyr -= m * qi * Q;
             dyi += m * qr * Q;
           }
-          // grad Y = (grad S - l S u) / r
           const double lf = (double)l;
           const double gYxr = (dxr - lf * Sr * x) * inv, gYxi = (dxi - lf * Si * x) * inv;
           const double gYyr = (dyr - lf * Sr * y) * inv, gYyi = (dyi - lf * Si * y) * inv;
           const double gYzr = (dzr - lf * Sr * z) * inv, gYzi = (dzi - lf * Si * z) * inv;
-          // both signs of m: Y_l^{-m} = (-1)^m conj(Y_l^m), same for grad
-          for (int sgn = 0; sgn < (m > 0 ? 2 : 1); ++sgn) {
-            const int mm = sgn == 0 ? m : -m;
-            const double fr = (sgn == 0 || (m & 1) == 0) ? 1.0 : -1.0;
-            const double fi = sgn == 0 ? fr : -fr;
-            // B0 = sum_n Abar_{n l mm} T_n, B1 = sum_n Abar_{n l mm} T_n'
-            double b0r = 0.0, b0i = 0.0, b1r = 0.0, b1i = 0.0;
-            double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
-            for (int n = 0; n <= N; ++n) {
-              double T, dT;
-              if (n == 0) {
-                T = 1.0;
-                dT = 0.0;
-              } else if (n == 1) {
-                T = c;
-                dT = 1.0;
-              } else {
-                T = 2.0 * c * t1 - t0;
-                dT = 2.0 * t1 + 2.0 * c * d1 - d0;
-                t0 = t1;
-                t1 = T;
-                d0 = d1;
-                d1 = dT;
-              }
-              const int ii = idx[(n * (L + 1) + l) * W + (mm + L)];
-              if (ii >= 0) {
-                const double2 a = Ab[ii];
-                b0r = fma(a.x, T, b0r);
-                b0i = fma(a.y, T, b0i);
-                b1r = fma(a.x, dT, b1r);
-                b1i = fma(a.y, dT, b1i);
-              }
+          // B0 = sum_n Abar_{n l (+/-m)} T_n, B1 = sum_n Abar_{n l (+/-m)} T_n'
+          double b0pr = 0.0, b0pi = 0.0, b1pr = 0.0, b1pi = 0.0;   // +m
+          double b0mr = 0.0, b0mi = 0.0, b1mr = 0.0, b1mi = 0.0;   // -m
+          double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
+          for (int n = 0; n <= N; ++n) {
+            double T, dT;
+            if (n == 0) {
+              T = 1.0;
+              dT = 0.0;
+            } else if (n == 1) {
+              T = c;
+              dT = 1.0;
+            } else {
+              T = 2.0 * c * t1 - t0;
+              dT = 2.0 * t1 + 2.0 * c * d1 - d0;
+              t0 = t1;
+              t1 = T;
+              d0 = d1;
+              d1 = dT;
             }
-            b1r *= dcdr;
-            b1i *= dcdr;
-            // Re(B1 * Y) u + Re(B0 * gradY), with Y -> (fr Re, fi Im)
-            const double Yr = fr * Sr, Yi = fi * Si;
-            const double radial = b1r * Yr - b1i * Yi;
-            gx += radial * x + b0r * fr * gYxr - b0i * fi * gYxi;
-            gy += radial * y + b0r * fr * gYyr - b0i * fi * gYyi;
-            gz += radial * z + b0r * fr * gYzr - b0i * fi * gYzi;
+            const int base = nst[l * (N + 1) + n];
+            if (base >= 0) {
+              const double2 ap = Ab[base + l + m];
+              b0pr = fma(ap.x, T, b0pr);
+              b0pi = fma(ap.y, T, b0pi);
+              b1pr = fma(ap.x, dT, b1pr);
+              b1pi = fma(ap.y, dT, b1pi);
+              const double2 am = Ab[base + l - m];
+              b0mr = fma(am.x, T, b0mr);
+              b0mi = fma(am.y, T, b0mi);
+              b1mr = fma(am.x, dT, b1mr);
+              b1mi = fma(am.y, dT, b1mi);
+            }
           }
+          // +m: Y = S; -m: Y_l^{-m} = (-1)^m conj(Y_l^m) (same for the gradient);
+          // for m = 0 both read the same entry, so count it once
+          const double fm = (m & 1) ? -1.0 : 1.0;
+          const double w0 = m == 0 ? 0.0 : 1.0;
+          const double rad = dcdr * ((b1pr * Sr - b1pi * Si) + w0 * fm * (b1mr * Sr + b1mi * Si));
+          gx += rad * x + (b0pr * gYxr - b0pi * gYxi) + w0 * fm * (b0mr * gYxr + b0mi * gYxi);
+          gy += rad * y + (b0pr * gYyr - b0pi * gYyi) + w0 * fm * (b0mr * gYyr + b0mi * gYyi);
+          gz += rad * z + (b0pr * gYzr - b0pi * gYzi) + w0 * fm * (b0mr * gYzr + b0mi * gYzi);
         }
-        qr = pr;
-        qi = pi;
-        const double npr = pr * x - pi * y;
-        const double npi = pr * y + pi * x;
-        pr = npr;
-        pi = npi;
+        // step m -> m + G
+        if (m == 0) {
+          qr = pG1r;
+          qi = pG1i;
+        } else {
+          const double nr = qr * pGr - qi * pGi;
+          qi = qr * pGi + qi * pGr;
+          qr = nr;
+        }
+        const double nr = pr * pGr - pi * pGi;
+        pi = pr * pGi + pi * pGr;
+        pr = nr;
       }
-      p.grad[3 * j] = gx;
-      p.grad[3 * j + 1] = gy;
-      p.grad[3 * j + 2] = gz;
+      for (int off = 1; off < G; off <<= 1) {
+        gx += __shfl_xor(gx, off, 64);
+        gy += __shfl_xor(gy, off, 64);
+        gz += __shfl_xor(gz, off, 64);
+      }
+      if (g == 0 && c0 + jl < J) {
+        p.grad[3 * j] = gx;
+        p.grad[3 * j + 1] = gy;
+        p.grad[3 * j + 2] = gz;
+      }
     }
   }
 }
@@ -547,7 +599,12 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
       const int row = p.mr_row[sl.x + lane];
       const double* ce = cs + p.cs_me;
       double2 y0 = make_double2(0.0, 0.0), y1 = make_double2(0.0, 0.0);
-      for (int j = 0; j < sl.z; j += 4) {
+      const int z4 = sl.z & ~3;
+      for (int j = z4; j < sl.z; ++j) {
+        const int pos = sl.y + j * 64 + lane;
+        y0 = rfma(ce[pos], x[p.me_col[pos]], y0);
+      }
+      for (int j = 0; j < z4; j += 4) {
         const int pos = sl.y + j * 64 + lane;
         const int c0 = p.me_col[pos], c1 = p.me_col[pos + 64];
         const int c2 = p.me_col[pos + 128], c3 = p.me_col[pos + 192];
@@ -594,8 +651,16 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
       }
       const double* cc = cs + p.cs_ch;
       if (!GC) {
-        // children counts padded to 4 (padding: sibling ZERO, coefficient 0)
-        for (int j = 0; j < sl.z; j += 4) {
+        // four children at a time, then the remainder (padding: sibling ZERO, coefficient 0)
+        const int z4 = sl.z & ~3;
+        for (int j = z4; j < sl.z; ++j) {
+          const int pos = sl.y + j * 64 + lane;
+          const int s0 = p.ch_s[pos];
+          const double k0 = cc[pos];
+          t = rfma(k0, x[s0], t);
+          if (GRAD && s0 != ZERO) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
+        }
+        for (int j = 0; j < z4; j += 4) {
           const int pos = sl.y + j * 64 + lane;
           const int s0 = p.ch_s[pos], s1 = p.ch_s[pos + 64], s2 = p.ch_s[pos + 128], s3 = p.ch_s[pos + 192];
           const double k0 = cc[pos], k1 = cc[pos + 64], k2 = cc[pos + 128], k3 = cc[pos + 192];
