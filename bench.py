@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, copy a buffer of this many MiB once (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); environments are "
@@ -198,6 +200,13 @@ def main():
         pc = pd[s_envs, 0] + 1j * pd[s_envs, 1]
         parity.update(oracle_phi=rel(pc, s_phi), oracle_grad=rel(gd[rows], s_grad),
                       oracle_sample=int(len(s_envs)))
+
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": METRIC,

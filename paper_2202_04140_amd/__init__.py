@@ -195,7 +195,8 @@ class Graph:
         info = np.zeros(16, dtype=np.int64)
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
         names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
-                 "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint"]
+                 "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",
+                 "bank_cost_rows_x1000", "bank_cost_children_x1000"]
         return {"kind": "forest" if k.value == 1 else "layered", **{n: int(v) for n, v in zip(names, info)}}
 
     def forest_eval_host(self, coeffs: np.ndarray, A: np.ndarray):

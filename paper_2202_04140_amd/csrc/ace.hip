@@ -245,6 +245,114 @@ void make_schedule(ace_graph* g) {
 constexpr int kTreeChunk = 16;   // children per tree item at most
 constexpr int kRowChunk = 32;    // resident-pair entries per row item at most
 
+// ---------------------------------------------------------------------------
+// LDS bank scheduling.  A 16-byte LDS gather of one wave is served in four
+// quarters of 16 lanes; a quarter costs as many cycles as the largest number
+// of its lanes whose slots share a bank group (slot mod 16).  Entries of a
+// lane may be taken in any order, so each column is chosen by a bipartite
+// matching of the quarter's lanes to bank groups.
+// ---------------------------------------------------------------------------
+struct Ent {
+  int32_t slot;  // resident slot read at this position
+  int32_t pay;   // caller's payload; -1 marks padding (coefficient 0)
+};
+
+bool kuhn(int l, const std::vector<uint32_t>& avail, const int* border, std::vector<int>& bank_of,
+          std::vector<int>& lane_of, uint32_t& seen) {
+  for (int bi = 0; bi < 16; ++bi) {
+    const int b = border[bi];
+    if (!(avail[l] & (1u << b)) || (seen & (1u << b))) continue;
+    seen |= 1u << b;
+    if (lane_of[b] < 0 || kuhn(lane_of[b], avail, border, bank_of, lane_of, seen)) {
+      lane_of[b] = l;
+      bank_of[l] = b;
+      return true;
+    }
+  }
+  return false;
+}
+
+// lanes[l]: entries of lane l (l < 64), consumed.  Returns ncol columns of 64
+// positions.  Padding reads slot pad_slot(bank) with a bank still free.
+template <typename PadSlot>
+std::vector<std::vector<Ent>> bank_columns(std::vector<std::vector<Ent>>& lanes, int ncol, PadSlot pad_slot) {
+  std::vector<std::vector<Ent>> out(ncol, std::vector<Ent>(64, Ent{-1, -1}));
+  lanes.resize(64);
+  for (int j = 0; j < ncol; ++j)
+    for (int q = 0; q < 4; ++q) {
+      std::vector<uint32_t> avail(16, 0);
+      int demand[16] = {0};
+      for (int i = 0; i < 16; ++i)
+        for (const Ent& e : lanes[16 * q + i]) {
+          avail[i] |= 1u << (e.slot & 15);
+          demand[e.slot & 15] += 1;
+        }
+      // banks with the most remaining entries first; lanes with the least slack first
+      int border[16];
+      for (int b = 0; b < 16; ++b) border[b] = b;
+      std::stable_sort(border, border + 16, [&](int x, int y) { return demand[x] > demand[y]; });
+      int lorder[16];
+      for (int i = 0; i < 16; ++i) lorder[i] = i;
+      std::stable_sort(lorder, lorder + 16,
+                       [&](int x, int y) { return lanes[16 * q + x].size() > lanes[16 * q + y].size(); });
+      std::vector<int> bank_of(16, -1), lane_of(16, -1);
+      for (int ii = 0; ii < 16; ++ii) {
+        const int i = lorder[ii];
+        uint32_t seen = 0;
+        if (avail[i]) kuhn(i, avail, border, bank_of, lane_of, seen);
+      }
+      uint32_t used = 0;
+      std::vector<int> pend;
+      for (int i = 0; i < 16; ++i) {
+        std::vector<Ent>& L = lanes[16 * q + i];
+        const int left = ncol - j;
+        if (bank_of[i] >= 0) {
+          auto it = std::find_if(L.begin(), L.end(), [&](const Ent& e) { return (e.slot & 15) == bank_of[i]; });
+          out[j][16 * q + i] = *it;
+          L.erase(it);
+          used |= 1u << bank_of[i];
+        } else if (!L.empty() && (int)L.size() >= left) {
+          out[j][16 * q + i] = L.front();   // no slack left: take it despite the conflict
+          used |= 1u << (L.front().slot & 15);
+          L.erase(L.begin());
+        } else {
+          pend.push_back(i);                // padding now (the lane has slack)
+        }
+      }
+      for (int i : pend) {
+        int b = 0;
+        while (b < 15 && (used & (1u << b))) ++b;
+        used |= 1u << b;
+        out[j][16 * q + i] = Ent{pad_slot(b), -1};
+      }
+    }
+  return out;
+}
+
+// Permutation of up to 64 items into lanes: each goes to a quarter in which
+// its key banks are not yet used, if any has room.
+std::vector<int> bank_lanes(const std::vector<std::pair<int, int>>& keys) {
+  std::vector<int> lane(keys.size(), -1);
+  uint32_t ua[4] = {0, 0, 0, 0}, ub[4] = {0, 0, 0, 0};
+  int fill[4] = {0, 0, 0, 0};
+  for (size_t i = 0; i < keys.size(); ++i) {
+    const uint32_t ma = 1u << (keys[i].first & 15), mb = keys[i].second < 0 ? 0u : 1u << (keys[i].second & 15);
+    int best = -1, bestc = 99;
+    for (int q = 0; q < 4; ++q) {
+      if (fill[q] >= 16) continue;
+      const int c = ((ua[q] & ma) ? 1 : 0) + ((ub[q] & mb) ? 1 : 0);
+      if (c < bestc) {
+        bestc = c;
+        best = q;
+      }
+    }
+    lane[i] = 16 * best + fill[best]++;
+    ua[best] |= ma;
+    ub[best] |= mb;
+  }
+  return lane;
+}
+
 void make_forest(ace_graph* g) {
   const HostGraph& h = g->h;
   const int64_t V = h.n_nodes();
@@ -409,36 +517,26 @@ void make_forest(ace_graph* g) {
   g->ch_s.clear();
   g->ch_g.clear();
   g->gc_s.clear();
+  // a slot in a given bank group for padding (one-particle slots 0..15)
+  auto pad_slot = [&](int bank) { return P1 > 15 ? bank : P1; };
   for (int sl = 0; sl < nts; ++sl) {
-    // Columns of the regular children: each child takes the lowest column in
-    // which its sibling slot is not yet used by another lane of the slice.
     const int nl = (int)slices[sl].size();
-    std::vector<std::vector<int32_t>> colsib;          // sibling slots used per column
-    std::vector<std::vector<int32_t>> lanecol(nl);     // column of each child of each lane
-    int ncol = 0, cmax = 0;
-    for (int l = 0; l < nl; ++l) cmax = std::max(cmax, items[slices[sl][l]].c1 - items[slices[sl][l]].c0);
-    const int cap = cmax;   // conflicts are dodged by the order of an item's children only
+    // lanes: root parents spread over bank groups per quarter
+    std::vector<std::pair<int, int>> keys(nl);
     for (int l = 0; l < nl; ++l) {
       const Item& it = items[slices[sl][l]];
-      std::vector<uint8_t> used;
-      for (int j = it.c0; j < it.c1; ++j) {
-        const int32_t sb = sib[kids[it.root][j]];
-        auto lane_busy = [&](int c) { return c < (int)used.size() && used[c]; };
-        int col = -1;
-        for (int c = 0; c < cap && col < 0; ++c) {
-          if ((int)colsib.size() <= c) colsib.emplace_back();
-          if (!lane_busy(c) && std::find(colsib[c].begin(), colsib[c].end(), sb) == colsib[c].end()) col = c;
-        }
-        if (col < 0)  // no conflict-free column: take the first free one
-          for (int c = 0; c < cap && col < 0; ++c)
-            if (!lane_busy(c)) col = c;
-        colsib[col].push_back(sb);
-        if ((int)used.size() <= col) used.resize(col + 1, 0);
-        used[col] = 1;
-        lanecol[l].push_back(col);
-        ncol = std::max(ncol, col + 1);
-      }
+      keys[l] = {slot[h.par[2 * it.root]], slot[h.par[2 * it.root + 1]]};
     }
+    const std::vector<int> lane_of_item = bank_lanes(keys);
+    // children: any order within an item; bank-matched per column
+    std::vector<std::vector<Ent>> lanes(64);
+    int ncol = 0;
+    for (int l = 0; l < nl; ++l) {
+      const Item& it = items[slices[sl][l]];
+      for (int j = it.c0; j < it.c1; ++j) lanes[lane_of_item[l]].push_back(Ent{sib[kids[it.root][j]], kids[it.root][j]});
+      ncol = std::max(ncol, it.c1 - it.c0);
+    }
+    const std::vector<std::vector<Ent>> cols = bank_columns(lanes, ncol, pad_slot);
     const int nmax = ncol;
     const int base = (int)g->ch_s.size();
     g->tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
@@ -447,15 +545,19 @@ void make_forest(ace_graph* g) {
     k_ch.resize(base + (size_t)nmax * 64, -1);
     for (int l = 0; l < nl; ++l) {
       const Item& it = items[slices[sl][l]];
-      const int idx = sl * 64 + l;
+      const int idx = sl * 64 + lane_of_item[l];
       item_pos[slices[sl][l]] = idx;
       const int32_t a = h.par[2 * it.root], b = h.par[2 * it.root + 1];
       g->it_ab[idx] = (uint32_t)slot[a] | ((uint32_t)slot[b] << 16);
       k_it[idx] = it.c0 == 0 ? h.node_k[it.root] : -1;
-      for (int j = it.c0; j < it.c1; ++j) {
-        const int32_t c = kids[it.root][j];
-        const int pos = base + lanecol[l][j - it.c0] * 64 + l;
-        g->ch_s[pos] = (uint16_t)sib[c];
+    }
+    for (int j = 0; j < nmax; ++j)
+      for (int l = 0; l < 64; ++l) {
+        const Ent& en = cols[j][l];
+        const int pos = base + j * 64 + l;
+        g->ch_s[pos] = (uint16_t)en.slot;
+        if (en.pay < 0) continue;   // padding: coefficient 0
+        const int32_t c = en.pay;
         k_ch[pos] = h.node_k[c];
         if (!kids[c].empty()) {
           const int gb = (int)g->gc_s.size();
@@ -468,7 +570,6 @@ void make_forest(ace_graph* g) {
           return fail_forest("childless auxiliary child");
         }
       }
-    }
   }
   g->n_tslices = nts;
   g->n_items = nts * 64;
@@ -508,23 +609,31 @@ void make_forest(ace_graph* g) {
   g->me_col.clear();
   std::vector<int32_t> k_me;
   for (int sl = 0; sl < nms; ++sl) {
+    const int nl = std::min(64, (int)rch.size() - sl * 64);
+    std::vector<std::pair<int, int>> keys(nl);
     int nmax = 0;
-    for (int l = 0; l < 64 && sl * 64 + l < (int)rch.size(); ++l)
+    for (int l = 0; l < nl; ++l) {
+      keys[l] = {rch[sl * 64 + l].row, -1};
       nmax = std::max(nmax, rch[sl * 64 + l].e1 - rch[sl * 64 + l].e0);
-
+    }
+    const std::vector<int> lane_of_row = bank_lanes(keys);
+    std::vector<std::vector<Ent>> lanes(64);
+    for (int l = 0; l < nl; ++l) {
+      const Row& rc = rch[sl * 64 + l];
+      for (int j = rc.e0; j < rc.e1; ++j) lanes[lane_of_row[l]].push_back(Ent{rows[rc.row][j].first, rows[rc.row][j].second});
+    }
+    const std::vector<std::vector<Ent>> cols = bank_columns(lanes, nmax, pad_slot);
     const int base = (int)g->me_col.size();
     g->mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
     g->me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
     k_me.resize(base + (size_t)nmax * 64, -1);
-    for (int l = 0; l < 64 && sl * 64 + l < (int)rch.size(); ++l) {
-      const Row& rc = rch[sl * 64 + l];
-      g->mr_row[sl * 64 + l] = (uint16_t)rc.row;
-      for (int j = rc.e0; j < rc.e1; ++j) {
-        const int pos = base + (j - rc.e0) * 64 + l;
-        g->me_col[pos] = rows[rc.row][j].first;
-        k_me[pos] = rows[rc.row][j].second;
+    for (int l = 0; l < nl; ++l) g->mr_row[sl * 64 + lane_of_row[l]] = (uint16_t)rch[sl * 64 + l].row;
+    for (int j = 0; j < nmax; ++j)
+      for (int l = 0; l < 64; ++l) {
+        const int pos = base + j * 64 + l;
+        g->me_col[pos] = (uint16_t)cols[j][l].slot;
+        k_me[pos] = cols[j][l].pay;   // padding: -1, coefficient 0
       }
-    }
   }
   g->n_mslices = nms;
 
@@ -657,7 +766,7 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
           const int2 gg = g->ch_g.at(pos);
           if (gg.x == gg.y) {
             t += c * xs;
-            if (sidx != ZERO) push(sidx, c * xv);
+            if (c != 0.0) push(sidx, c * xv);
           } else {
             const cd xw = xv * xs;
             cd aw = c;
@@ -1290,6 +1399,32 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       info[7] = (int64_t)g->gc_s.size();
       for (int h = 0; h < 4; ++h) info[8 + h] = g->hot_slot[h];
       info[12] = g->forest_full ? 1 : 0;
+      // LDS bank cost of the 16-byte gathers: sum over gathers and quarters of
+      // the largest number of lanes sharing a bank group (ideal: 1 each)
+      auto cost = [](const uint16_t* sl) {   // distinct slots per bank group (same slot: broadcast)
+        int64_t c = 0;
+        for (int q = 0; q < 4; ++q) {
+          int mx = 0;
+          for (int b = 0; b < 16; ++b) {
+            int d = 0;
+            for (int i = 0; i < 16; ++i) {
+              const int v = sl[16 * q + i];
+              if ((v & 15) != b) continue;
+              bool first = true;
+              for (int k = 0; k < i; ++k) first &= sl[16 * q + k] != v;
+              d += first;
+            }
+            mx = std::max(mx, d);
+          }
+          c += mx;
+        }
+        return c;
+      };
+      int64_t cm = 0, ct = 0, nm = 0, nt = 0;
+      for (size_t pos = 0; pos + 64 <= g->me_col.size(); pos += 64, ++nm) cm += cost(&g->me_col[pos]);
+      for (size_t pos = 0; pos + 64 <= g->ch_s.size(); pos += 64, ++nt) ct += cost(&g->ch_s[pos]);
+      info[13] = nm ? (1000 * cm) / (4 * nm) : 0;   // mean per quarter, x1000
+      info[14] = nt ? (1000 * ct) / (4 * nt) : 0;
     }
   }
   return ACE_OK;

@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
           const int s0 = p.ch_s[pos];
           const double k0 = cc[pos];
           t = rfma(k0, x[s0], t);
-          if (GRAD && s0 != ZERO) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
+          if (GRAD && k0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
         }
         for (int j = 0; j < z4; j += 4) {
           const int pos = sl.y + j * 64 + lane;
@@ -670,10 +670,10 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
           t = rfma(k2, x2, t);
           t = rfma(k3, x3, t);
           if (GRAD) {
-            if (s0 != ZERO) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
-            if (s1 != ZERO) push_r<FULL>(P1, n2, x, ab, s1, make_double2(k1 * xv.x, k1 * xv.y));
-            if (s2 != ZERO) push_r<FULL>(P1, n2, x, ab, s2, make_double2(k2 * xv.x, k2 * xv.y));
-            if (s3 != ZERO) push_r<FULL>(P1, n2, x, ab, s3, make_double2(k3 * xv.x, k3 * xv.y));
+            if (k0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
+            if (k1 != 0.0) push_r<FULL>(P1, n2, x, ab, s1, make_double2(k1 * xv.x, k1 * xv.y));
+            if (k2 != 0.0) push_r<FULL>(P1, n2, x, ab, s2, make_double2(k2 * xv.x, k2 * xv.y));
+            if (k3 != 0.0) push_r<FULL>(P1, n2, x, ab, s3, make_double2(k3 * xv.x, k3 * xv.y));
           }
         }
       } else {
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
           const double2 xs = x[sidx];
           if (g.x == g.y) {
             t = rfma(c, xs, t);
-            if (GRAD && sidx != ZERO) push_r<FULL>(P1, n2, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
+            if (GRAD && c != 0.0) push_r<FULL>(P1, n2, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
           } else {
             const double2 xw = cmul(xv, xs);
             double2 aw = make_double2(c, 0.0);
