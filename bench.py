@@ -36,20 +36,47 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic operation counts of the DAG kernel (forward + reverse pass)
 # ---------------------------------------------------------------------------
 def dag_flops_per_env(stats: dict) -> dict:
-    """Flops of one environment in the fused forward + reverse DAG launch.
+    """Algorithmic flops of one environment in the fused forward + reverse
+    DAG launch, by the per-node figures of the scope table:
 
-    forward: every product node is one complex product (6 flops); every tuple
-             of K adds c_k * x_k to phi (real times complex, 4 flops).
-    reverse: a childless node pushes c*x_b and c*x_a to its two parents
-             (2 x (2 mul + 2 add) = 8 flops); a node with children pushes
-             abar*x_b and abar*x_a (2 x (6 + 2) = 16 flops).
+    forward = 6 S + 3 T + 2 |K|   (S product nodes with children: a complex
+              product; T childless product nodes: the real part of a product;
+              each tuple of K: a real coefficient times a real part)
+    reverse = 16 S + 8 T          (adjoint pushes to both parents)
+
+    The kernel does more than this (it also returns Im phi), so the achieved
+    rate computed from it is a lower bound.
     """
     S = stats["n_stored"]
     T = stats["n_childless"]
     K = stats["n_k"]
-    fwd = 6 * (S + T) + 4 * K
+    fwd = 6 * S + 3 * T + 2 * K
     adj = 16 * S + 8 * T
     return dict(forward=fwd, reverse=adj, total=fwd + adj)
+
+
+def source_hash() -> str:
+    """Hash of the kernel and schedule sources (ties counter profiles to them)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ace.hip", "ace_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2202_04140_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: int):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    profile, or None if absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "forest_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash() or d.get("workload") != workload:
+        return None
+    return d.get("bytes_per_launch")
 
 
 # ---------------------------------------------------------------------------
@@ -106,6 +133,8 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of hipGraph replays")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a buffer of this many MiB once (scale for HBM counters)")
     args = ap.parse_args()
@@ -159,19 +188,44 @@ def main():
         wall = time.perf_counter() - t
         return a.elapsed_time(b) / steps, wall
 
-    # whole path, DAG and naive
-    ms_dag, wall = timed(lambda: ace.eval_grad(G, tc, toff, tpos, out=(phi, grad)), args.steps, args.warmup)
-    print(f"[bench] DAG phi+forces: {ms_dag:.3f} ms/step", file=sys.stderr, flush=True)
+    # schedule autotuning on this batch (setup, outside the timed region)
+    A = ace.basis(G, toff, tpos)
+    tuned = None
+    if not args.no_tune:
+        from paper_2202_04140_amd import autotune
+        tuned = autotune.tune(G, tc, A)
+        print(f"[bench] schedule {tuned['opts']} ({'cached' if tuned['cached'] else 'tuned'})",
+              file=sys.stderr, flush=True)
+
+    def step_dag():
+        ace.eval_grad(G, tc, toff, tpos, out=(phi, grad))
+
+    def step_naive():
+        ace.eval_grad(G, tc, toff, tpos, naive=True, out=(phi, grad))
+
+    def graphed(fn):
+        """Capture one step in a hipGraph (after eager warm-up) and return its replay."""
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        return g.replay
+
+    # whole path, DAG and naive: hipGraph replays of one step (eager beside)
+    ms_dag_eager, _ = timed(step_dag, args.steps, args.warmup)
+    ms_dag, wall = (ms_dag_eager, None) if args.eager else timed(graphed(step_dag), args.steps, args.warmup)
+    print(f"[bench] DAG phi+forces: {ms_dag:.3f} ms/step (eager {ms_dag_eager:.3f})", file=sys.stderr, flush=True)
     phi_dag, grad_dag = phi.clone(), grad.clone()
-    ms_naive, _ = timed(lambda: ace.eval_grad(G, tc, toff, tpos, naive=True, out=(phi, grad)),
-                        args.steps, args.warmup)
+    ms_naive_eager, _ = timed(step_naive, args.steps, args.warmup)
+    ms_naive = ms_naive_eager if args.eager else timed(graphed(step_naive), args.steps, args.warmup)[0]
     print(f"[bench] naive phi+forces: {ms_naive:.3f} ms/step", file=sys.stderr, flush=True)
     phi_naive, grad_naive = phi.clone(), grad.clone()
     ms_fwd, _ = timed(lambda: ace.eval(G, tc, toff, tpos, out=phi), args.steps, args.warmup)
 
     # dominant kernel alone: the fused forward + reverse DAG launch, timed with
     # events on the stream it is launched on (torch's current stream)
-    A = ace.basis(G, toff, tpos)
     Abar = torch.empty_like(A)
     ws = G.workspace(E, dev)
     stream = torch.cuda.current_stream(dev)
@@ -186,6 +240,8 @@ def main():
     with torch.cuda.stream(stream):
         ms_kernel, _ = timed(dag_launch, args.steps, args.warmup)
     fl = dag_flops_per_env(stats)
+    kernel_name = ("forest_kernel (forward + reverse)" if G.schedule_kind() == "forest"
+                   else "dag_kernel (forward + reverse)")
     achieved = fl["total"] * E / (ms_kernel * 1e-3) / 1e12
 
     # parity of the timed results
@@ -229,9 +285,12 @@ def main():
         "dag_vs_naive": ms_naive / ms_dag,
         "forces_per_s": N / (ms_dag * 1e-3),
         "phi_only_env_per_s": E / (ms_fwd * 1e-3),
-        "roofline": {"bound": "alu", "kernel": "dag_kernel (forward + reverse)", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": kernel_name, "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None, "kernel_ms": ms_kernel, "flops_per_env": fl},
+                     "traffic": profiled_traffic(args.workload), "kernel_ms": ms_kernel, "flops_per_env": fl},
+        "eager_ms_per_step": ms_dag_eager,
+        "timing": "eager launches" if args.eager else "hipGraph replays of one captured step",
+        "schedule": (tuned or {}).get("opts", G.get_schedule()),
         "cpu_baseline": cpu,
         "parity": parity,
         "graph_build_s": t_build,

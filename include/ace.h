@@ -135,6 +135,37 @@ const char* ace_version(void);
  */
 ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
 
+/*
+ * Tunable parameters of the evaluation schedule (not of the DAG itself;
+ * the node list and every result are unchanged up to rounding order).
+ *   row_chunk      resident-pair entries handled per lane item, 4..256
+ *   tree_chunk     children of a tree root handled per lane item, 1..256
+ *   hot_columns    number of most frequent sibling slots given register
+ *                  accumulators instead of per-child atomics, 0..4
+ *   bank_schedule  1: order work so that a quarter-wave's LDS gathers hit
+ *                  distinct bank groups; 0: plain order
+ *   block_threads  threads per block of the DAG kernel, 64..512, multiple of 64
+ */
+typedef struct ace_schedule_opts {
+  int32_t row_chunk;
+  int32_t tree_chunk;
+  int32_t hot_columns;
+  int32_t bank_schedule;
+  int32_t block_threads;
+  int32_t reserved[3];
+} ace_schedule_opts;
+
+/* Current schedule options of a graph (host). */
+ace_status ace_graph_get_schedule(const ace_graph* g, ace_schedule_opts* opts);
+
+/*
+ * Rebuild the evaluation schedule with new options and, for a device graph,
+ * re-upload it (synchronous; allocates device memory owned by the graph).
+ * Must not overlap with evaluation calls on the same graph.
+ * ACE_ERR_INVALID_ARG if an option is out of range.
+ */
+ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* opts);
+
 /* Release a graph (NULL is a no-op).  No call using it may be in flight. */
 void ace_graph_free(ace_graph* g);
 

@@ -54,6 +54,12 @@ class _Spec(ctypes.Structure):
                 ("reserved2", ctypes.c_uint32)]
 
 
+class _Opts(ctypes.Structure):
+    _fields_ = [("row_chunk", ctypes.c_int32), ("tree_chunk", ctypes.c_int32),
+                ("hot_columns", ctypes.c_int32), ("bank_schedule", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("n_onep", ctypes.c_int64), ("n_k", ctypes.c_int64),
                 ("n_k_by_order", ctypes.c_int64 * 9), ("n_nodes", ctypes.c_int64),
@@ -84,6 +90,8 @@ EXPORTED = {
     "ace_contract": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval_grad": ([_P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
+    "ace_graph_get_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
+    "ace_graph_set_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
     "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
 }
@@ -182,6 +190,21 @@ class Graph:
         kt = self.k_tuples()
         d = np.where(kt >= 0, deg1[np.maximum(kt, 0)], 0)
         return d.sum(axis=1)
+
+    SCHEDULE_KEYS = ("row_chunk", "tree_chunk", "hot_columns", "bank_schedule", "block_threads")
+
+    def get_schedule(self) -> dict:
+        o = _Opts()
+        _check(lib().ace_graph_get_schedule(self._h, ctypes.byref(o)))
+        return {k: getattr(o, k) for k in self.SCHEDULE_KEYS}
+
+    def set_schedule(self, **opts):
+        """Rebuild the evaluation schedule (ace_graph_set_schedule); unspecified
+        options keep their current values."""
+        cur = self.get_schedule()
+        cur.update(opts)
+        o = _Opts(**{k: int(cur[k]) for k in self.SCHEDULE_KEYS})
+        _check(lib().ace_graph_set_schedule(self._h, ctypes.byref(o)))
 
     def schedule_kind(self) -> str:
         """'forest' or 'layered' (ace_debug_schedule)."""

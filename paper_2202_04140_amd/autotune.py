@@ -1,0 +1,114 @@
+"""Autotuner for the evaluation schedule of a graph.
+
+The DAG (node list) is fixed by the insertion heuristic; how its evaluation
+is laid out on the GPU is not: how many pair-row entries and tree children a
+lane takes per item, how many hot sibling columns get register
+accumulators, whether lanes and columns are ordered by LDS bank group, and
+the block size of the DAG kernel.  tune() searches these by coordinate
+descent, timing the fused forward + reverse DAG launch (ace_contract with an
+adjoint) on the caller's one-particle values, applies the fastest schedule
+to the graph and records it in a JSON cache keyed by device, basis and batch
+size (ACE_AUTOTUNE_CACHE, default ~/.cache/ace_autotune.json).
+"""
+
+from __future__ import annotations
+
+import json
+import os
+
+from . import Graph, contract
+
+SPACE = {
+    "row_chunk": [16, 32, 64],
+    "tree_chunk": [8, 16, 32],
+    "hot_columns": [0, 2, 4],
+    "bank_schedule": [0, 1],
+    "block_threads": [256, 512],
+}
+
+
+def cache_path() -> str:
+    return os.environ.get("ACE_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                               "ace_autotune.json"))
+
+
+def _key(graph: Graph, n_env: int, device_name: str) -> str:
+    s = graph.spec
+    return (f"{device_name}|g{s['group']}|nu{s['nu_max']}|D{s['degree_max']}|n{s['n_max']}|l{s['l_max']}"
+            f"|alg{s['algorithm']}.{s['alg_n']}|E{n_env}")
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(data: dict) -> None:
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time(graph: Graph, coeffs, A, reps: int) -> float:
+    import torch
+    for _ in range(2):
+        contract(graph, coeffs, A, with_grad=True)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        contract(graph, coeffs, A, with_grad=True)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Pick and apply the fastest schedule for this graph and batch (A: [E, P1, 2]).
+
+    Returns {"opts": ..., "ms": ..., "tried": [(opts, ms), ...], "cached": bool}.
+    """
+    import torch
+    dev = A.device
+    name = torch.cuda.get_device_name(dev)
+    key = _key(graph, A.shape[0], name)
+    data = _load() if use_cache else {}
+    if use_cache and key in data:
+        opts = data[key]["opts"]
+        graph.set_schedule(**opts)
+        return {"opts": opts, "ms": data[key]["ms"], "tried": [], "cached": True}
+    if graph.schedule_kind() != "forest":
+        return {"opts": graph.get_schedule(), "ms": None, "tried": [], "cached": False}
+    best = graph.get_schedule()
+    graph.set_schedule(**best)
+    best_ms = _time(graph, coeffs, A, reps)
+    tried = [(dict(best), best_ms)]
+    for name_, values in SPACE.items():
+        for v in values:
+            if v == best[name_]:
+                continue
+            cand = dict(best)
+            cand[name_] = v
+            graph.set_schedule(**cand)
+            ms = _time(graph, coeffs, A, reps)
+            tried.append((cand, ms))
+            if verbose:
+                print(f"[autotune] {cand}: {ms:.4f} ms", flush=True)
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    graph.set_schedule(**best)
+    if use_cache:
+        data = _load()
+        data[key] = {"opts": best, "ms": best_ms}
+        _store(data)
+    return {"opts": best, "ms": best_ms, "tried": tried, "cached": False}

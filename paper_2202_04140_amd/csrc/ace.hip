@@ -53,8 +53,18 @@ using namespace ace;
 // ---------------------------------------------------------------------------
 // graph object
 // ---------------------------------------------------------------------------
+// Tunable parameters of the forest schedule (ace_schedule_opts).
+struct ScheduleOpts {
+  int row_chunk = 32;      // resident-pair entries per row item at most
+  int tree_chunk = 16;     // regular children per tree item at most
+  int hot_columns = 4;     // hot-sibling register columns (0..4)
+  int bank_schedule = 1;   // order lanes and columns by LDS bank group
+  int block_threads = 512; // forest kernel block size
+};
+
 struct ace_graph {
   HostGraph h;
+  ScheduleOpts opts;
   ace_graph_stats stats{};
   bool on_device = false;
   int device = -1;
@@ -242,8 +252,7 @@ void make_schedule(ace_graph* g) {
 // ---------------------------------------------------------------------------
 // Forest schedule (see forest_kernel in kernels.hip).
 // ---------------------------------------------------------------------------
-constexpr int kTreeChunk = 16;   // children per tree item at most
-constexpr int kRowChunk = 32;    // resident-pair entries per row item at most
+
 
 // ---------------------------------------------------------------------------
 // LDS bank scheduling.  A 16-byte LDS gather of one wave is served in four
@@ -353,6 +362,20 @@ std::vector<int> bank_lanes(const std::vector<std::pair<int, int>>& keys) {
   return lane;
 }
 
+// In-order alternatives (no bank scheduling).
+std::vector<std::vector<Ent>> plain_columns(std::vector<std::vector<Ent>>& lanes, int ncol, int zero) {
+  std::vector<std::vector<Ent>> out(ncol, std::vector<Ent>(64, Ent{zero, -1}));
+  for (int l = 0; l < (int)lanes.size() && l < 64; ++l)
+    for (int j = 0; j < (int)lanes[l].size(); ++j) out[j][l] = lanes[l][j];
+  return out;
+}
+
+std::vector<int> plain_lanes(int n) {
+  std::vector<int> v(n);
+  for (int i = 0; i < n; ++i) v[i] = i;
+  return v;
+}
+
 void make_forest(ace_graph* g) {
   const HostGraph& h = g->h;
   const int64_t V = h.n_nodes();
@@ -431,7 +454,8 @@ void make_forest(ace_graph* g) {
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return freq[x] > freq[y]; });
     for (int h = 0; h < 4; ++h) {
       const int sl = order[h];
-      g->hot_slot[h] = (sl != P1 && freq[sl] * 16 >= (int64_t)roots.size() && freq[sl] > 0) ? sl : P1;
+      g->hot_slot[h] = (h < g->opts.hot_columns && sl != P1 && freq[sl] * 16 >= (int64_t)roots.size() &&
+                        freq[sl] > 0) ? sl : P1;
     }
   }
   auto hot_col = [&](int slot_) {
@@ -459,7 +483,7 @@ void make_forest(ace_graph* g) {
     const int n = (int)reg.size();
     int c0 = 0;
     do {
-      const int c1 = std::min(n, c0 + kTreeChunk);
+      const int c1 = std::min(n, c0 + g->opts.tree_chunk);
       int ngc = 0;
       for (int j = c0; j < c1; ++j) ngc += (int)kids[reg[j]].size();
       Item it{r, c0, c1, ngc, {-1, -1, -1, -1}};
@@ -527,7 +551,7 @@ void make_forest(ace_graph* g) {
       const Item& it = items[slices[sl][l]];
       keys[l] = {slot[h.par[2 * it.root]], slot[h.par[2 * it.root + 1]]};
     }
-    const std::vector<int> lane_of_item = bank_lanes(keys);
+    const std::vector<int> lane_of_item = g->opts.bank_schedule ? bank_lanes(keys) : plain_lanes(nl);
     // children: any order within an item; bank-matched per column
     std::vector<std::vector<Ent>> lanes(64);
     int ncol = 0;
@@ -536,7 +560,8 @@ void make_forest(ace_graph* g) {
       for (int j = it.c0; j < it.c1; ++j) lanes[lane_of_item[l]].push_back(Ent{sib[kids[it.root][j]], kids[it.root][j]});
       ncol = std::max(ncol, it.c1 - it.c0);
     }
-    const std::vector<std::vector<Ent>> cols = bank_columns(lanes, ncol, pad_slot);
+    const std::vector<std::vector<Ent>> cols =
+        g->opts.bank_schedule ? bank_columns(lanes, ncol, pad_slot) : plain_columns(lanes, ncol, P1);
     const int nmax = ncol;
     const int base = (int)g->ch_s.size();
     g->tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
@@ -600,8 +625,8 @@ void make_forest(ace_graph* g) {
   };
   std::vector<Row> rch;
   for (int r = 0; r < nslot; ++r)
-    for (int e0 = 0; e0 < (int)rows[r].size(); e0 += kRowChunk)
-      rch.push_back({r, e0, std::min((int)rows[r].size(), e0 + kRowChunk)});
+    for (int e0 = 0; e0 < (int)rows[r].size(); e0 += g->opts.row_chunk)
+      rch.push_back({r, e0, std::min((int)rows[r].size(), e0 + g->opts.row_chunk)});
   std::stable_sort(rch.begin(), rch.end(), [](const Row& x, const Row& y) { return x.e1 - x.e0 > y.e1 - y.e0; });
   const int nms = (int)((rch.size() + 63) / 64);
   g->mr_slice.assign(nms, make_int4(0, 0, 0, 0));
@@ -616,13 +641,14 @@ void make_forest(ace_graph* g) {
       keys[l] = {rch[sl * 64 + l].row, -1};
       nmax = std::max(nmax, rch[sl * 64 + l].e1 - rch[sl * 64 + l].e0);
     }
-    const std::vector<int> lane_of_row = bank_lanes(keys);
+    const std::vector<int> lane_of_row = g->opts.bank_schedule ? bank_lanes(keys) : plain_lanes(nl);
     std::vector<std::vector<Ent>> lanes(64);
     for (int l = 0; l < nl; ++l) {
       const Row& rc = rch[sl * 64 + l];
       for (int j = rc.e0; j < rc.e1; ++j) lanes[lane_of_row[l]].push_back(Ent{rows[rc.row][j].first, rows[rc.row][j].second});
     }
-    const std::vector<std::vector<Ent>> cols = bank_columns(lanes, nmax, pad_slot);
+    const std::vector<std::vector<Ent>> cols =
+        g->opts.bank_schedule ? bank_columns(lanes, nmax, pad_slot) : plain_columns(lanes, nmax, P1);
     const int base = (int)g->me_col.size();
     g->mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
     g->me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
@@ -851,6 +877,63 @@ T* carve(char*& p, size_t n) {
   return r;
 }
 
+// Upload the forest schedule (replacing a previous one) and plan its LDS.
+ace_status upload_forest(ace_graph* g) {
+  if (g->fmem) {
+    (void)hipFree(g->fmem);
+    g->fmem = nullptr;
+  }
+  auto put = [](void* d, const void* s, size_t n) { return n ? hipMemcpy(d, s, n, hipMemcpyHostToDevice) : hipSuccess; };
+  const int maxl = (int)g->max_lds;
+  if (g->forest_ok) {
+    size_t fb = 0;
+    fb += align_up(g->nu2_ab.size() * 4) + align_up(g->it_ab.size() * 4);
+    fb += align_up(g->mr_slice.size() * sizeof(int4)) + align_up(g->tr_slice.size() * sizeof(int4));
+    fb += align_up(g->mr_row.size() * 2) + align_up(g->me_col.size() * 2) + align_up(g->ch_s.size() * 2);
+    fb += align_up(g->gc_s.size() * 2) + align_up(g->ch_g.size() * sizeof(int2)) + align_up(g->kmap.size() * 4);
+    fb += align_up(g->fw_off.size() * 4) + align_up(g->fw_ent.size() * 4);
+    fb += kAlign;
+    if (hipMalloc(&g->fmem, fb) != hipSuccess) {
+      g->fmem = nullptr;
+      (void)hipGetLastError();
+      return fail(ACE_ERR_OUT_OF_MEMORY, "hipMalloc of the forest schedule failed");
+    }
+    char* q = static_cast<char*>(g->fmem);
+    g->d_nu2_ab = carve<uint32_t>(q, g->nu2_ab.size());
+    g->d_it_ab = carve<uint32_t>(q, g->it_ab.size());
+    g->d_mr_slice = carve<int4>(q, g->mr_slice.size());
+    g->d_tr_slice = carve<int4>(q, g->tr_slice.size());
+    g->d_mr_row = carve<uint16_t>(q, g->mr_row.size());
+    g->d_me_col = carve<uint16_t>(q, g->me_col.size());
+    g->d_ch_s = carve<uint16_t>(q, g->ch_s.size());
+    g->d_gc_s = carve<uint16_t>(q, g->gc_s.size());
+    g->d_ch_g = carve<int2>(q, g->ch_g.size());
+    g->d_kmap = carve<int32_t>(q, g->kmap.size());
+    g->d_fw_off = carve<int32_t>(q, g->fw_off.size());
+    g->d_fw_ent = carve<uint32_t>(q, g->fw_ent.size());
+    ACE_HIP(put(g->d_nu2_ab, g->nu2_ab.data(), g->nu2_ab.size() * 4));
+    ACE_HIP(put(g->d_it_ab, g->it_ab.data(), g->it_ab.size() * 4));
+    ACE_HIP(put(g->d_mr_slice, g->mr_slice.data(), g->mr_slice.size() * sizeof(int4)));
+    ACE_HIP(put(g->d_tr_slice, g->tr_slice.data(), g->tr_slice.size() * sizeof(int4)));
+    ACE_HIP(put(g->d_mr_row, g->mr_row.data(), g->mr_row.size() * 2));
+    ACE_HIP(put(g->d_me_col, g->me_col.data(), g->me_col.size() * 2));
+    ACE_HIP(put(g->d_ch_s, g->ch_s.data(), g->ch_s.size() * 2));
+    ACE_HIP(put(g->d_gc_s, g->gc_s.data(), g->gc_s.size() * 2));
+    ACE_HIP(put(g->d_ch_g, g->ch_g.data(), g->ch_g.size() * sizeof(int2)));
+    ACE_HIP(put(g->d_kmap, g->kmap.data(), g->kmap.size() * 4));
+    ACE_HIP(put(g->d_fw_off, g->fw_off.data(), g->fw_off.size() * 4));
+    ACE_HIP(put(g->d_fw_ent, g->fw_ent.data(), g->fw_ent.size() * 4));
+    g->forest_fwd_lds = forest_lds_bytes(g, false, false) <= g->max_lds;
+    g->forest_full = forest_lds_bytes(g, true, true) <= g->max_lds;
+    g->forest_grad_lds = g->forest_full || forest_lds_bytes(g, true, false) <= g->max_lds;
+    const void* fk[] = {(const void*)forest_kernel<false, false, false>, (const void*)forest_kernel<false, true, false>,
+                        (const void*)forest_kernel<true, false, false>, (const void*)forest_kernel<true, true, false>,
+                        (const void*)forest_kernel<true, false, true>, (const void*)forest_kernel<true, true, true>};
+    for (const void* f : fk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  }
+  return ACE_OK;
+}
+
 ace_status upload(ace_graph* g) {
   int dev = 0;
   ACE_HIP(hipGetDevice(&dev));
@@ -904,52 +987,9 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-  // forest schedule
-  if (g->forest_ok) {
-    size_t fb = 0;
-    fb += align_up(g->nu2_ab.size() * 4) + align_up(g->it_ab.size() * 4);
-    fb += align_up(g->mr_slice.size() * sizeof(int4)) + align_up(g->tr_slice.size() * sizeof(int4));
-    fb += align_up(g->mr_row.size() * 2) + align_up(g->me_col.size() * 2) + align_up(g->ch_s.size() * 2);
-    fb += align_up(g->gc_s.size() * 2) + align_up(g->ch_g.size() * sizeof(int2)) + align_up(g->kmap.size() * 4);
-    fb += align_up(g->fw_off.size() * 4) + align_up(g->fw_ent.size() * 4);
-    fb += kAlign;
-    if (hipMalloc(&g->fmem, fb) != hipSuccess) {
-      g->fmem = nullptr;
-      (void)hipGetLastError();
-      return fail(ACE_ERR_OUT_OF_MEMORY, "hipMalloc of the forest schedule failed");
-    }
-    char* q = static_cast<char*>(g->fmem);
-    g->d_nu2_ab = carve<uint32_t>(q, g->nu2_ab.size());
-    g->d_it_ab = carve<uint32_t>(q, g->it_ab.size());
-    g->d_mr_slice = carve<int4>(q, g->mr_slice.size());
-    g->d_tr_slice = carve<int4>(q, g->tr_slice.size());
-    g->d_mr_row = carve<uint16_t>(q, g->mr_row.size());
-    g->d_me_col = carve<uint16_t>(q, g->me_col.size());
-    g->d_ch_s = carve<uint16_t>(q, g->ch_s.size());
-    g->d_gc_s = carve<uint16_t>(q, g->gc_s.size());
-    g->d_ch_g = carve<int2>(q, g->ch_g.size());
-    g->d_kmap = carve<int32_t>(q, g->kmap.size());
-    g->d_fw_off = carve<int32_t>(q, g->fw_off.size());
-    g->d_fw_ent = carve<uint32_t>(q, g->fw_ent.size());
-    ACE_HIP(put(g->d_nu2_ab, g->nu2_ab.data(), g->nu2_ab.size() * 4));
-    ACE_HIP(put(g->d_it_ab, g->it_ab.data(), g->it_ab.size() * 4));
-    ACE_HIP(put(g->d_mr_slice, g->mr_slice.data(), g->mr_slice.size() * sizeof(int4)));
-    ACE_HIP(put(g->d_tr_slice, g->tr_slice.data(), g->tr_slice.size() * sizeof(int4)));
-    ACE_HIP(put(g->d_mr_row, g->mr_row.data(), g->mr_row.size() * 2));
-    ACE_HIP(put(g->d_me_col, g->me_col.data(), g->me_col.size() * 2));
-    ACE_HIP(put(g->d_ch_s, g->ch_s.data(), g->ch_s.size() * 2));
-    ACE_HIP(put(g->d_gc_s, g->gc_s.data(), g->gc_s.size() * 2));
-    ACE_HIP(put(g->d_ch_g, g->ch_g.data(), g->ch_g.size() * sizeof(int2)));
-    ACE_HIP(put(g->d_kmap, g->kmap.data(), g->kmap.size() * 4));
-    ACE_HIP(put(g->d_fw_off, g->fw_off.data(), g->fw_off.size() * 4));
-    ACE_HIP(put(g->d_fw_ent, g->fw_ent.data(), g->fw_ent.size() * 4));
-    g->forest_fwd_lds = forest_lds_bytes(g, false, false) <= g->max_lds;
-    g->forest_full = forest_lds_bytes(g, true, true) <= g->max_lds;
-    g->forest_grad_lds = g->forest_full || forest_lds_bytes(g, true, false) <= g->max_lds;
-    const void* fk[] = {(const void*)forest_kernel<false, false, false>, (const void*)forest_kernel<false, true, false>,
-                        (const void*)forest_kernel<true, false, false>, (const void*)forest_kernel<true, true, false>,
-                        (const void*)forest_kernel<true, false, true>, (const void*)forest_kernel<true, true, true>};
-    for (const void* f : fk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  {
+    const ace_status fs = upload_forest(g);
+    if (fs != ACE_OK) return fs;
   }
   g->on_device = true;
   return ACE_OK;
@@ -1081,7 +1121,7 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   const bool grad = Abar != nullptr;
   const bool full = grad && g->forest_full;
   const size_t lds = forest_lds_bytes(g, grad, full);
-  const dim3 grid((unsigned)grid_for(n_env)), block(kForestThreads);
+  const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
   if (full && g->has_gc)
     hipLaunchKernelGGL((forest_kernel<true, true, true>), grid, block, lds, s, a);
   else if (full)
@@ -1376,6 +1416,44 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
     st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags);
   if (st != ACE_OK) return st;
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
+}
+
+ace_status ace_graph_get_schedule(const ace_graph* g, ace_schedule_opts* o) {
+  if (!g || !o) return fail(ACE_ERR_INVALID_ARG, "graph and opts must be non-NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->row_chunk = g->opts.row_chunk;
+  o->tree_chunk = g->opts.tree_chunk;
+  o->hot_columns = g->opts.hot_columns;
+  o->bank_schedule = g->opts.bank_schedule;
+  o->block_threads = g->opts.block_threads;
+  return ACE_OK;
+}
+
+ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
+  if (!g || !o) return fail(ACE_ERR_INVALID_ARG, "graph and opts must be non-NULL");
+  if (o->row_chunk < 4 || o->row_chunk > 256 || o->tree_chunk < 1 || o->tree_chunk > 256 || o->hot_columns < 0 ||
+      o->hot_columns > 4 || (o->bank_schedule != 0 && o->bank_schedule != 1) || o->block_threads < 64 ||
+      o->block_threads > 512 || o->block_threads % 64 != 0)
+    return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");
+  const ScheduleOpts old = g->opts;
+  g->opts.row_chunk = o->row_chunk;
+  g->opts.tree_chunk = o->tree_chunk;
+  g->opts.hot_columns = o->hot_columns;
+  g->opts.bank_schedule = o->bank_schedule;
+  g->opts.block_threads = o->block_threads;
+  try {
+    make_forest(g);
+  } catch (const std::bad_alloc&) {
+    g->opts = old;
+    return fail(ACE_ERR_OUT_OF_MEMORY, "host allocation failed while rebuilding the schedule");
+  }
+  if (g->on_device) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device)
+      return fail(ACE_ERR_INVALID_ARG, "graph belongs to another HIP device than the current one");
+    return upload_forest(g);
+  }
+  return ACE_OK;
 }
 
 ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) {
