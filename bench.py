@@ -125,6 +125,46 @@ def cpu_baseline(wid: int, off: np.ndarray, pos: np.ndarray, n_sample: int, chun
 
 
 # ---------------------------------------------------------------------------
+# HBM traffic of the dominant kernel from two rocprofv3 counter databases
+# ---------------------------------------------------------------------------
+def _per_dispatch(db_path: str, counter: str):
+    import sqlite3
+    cur = sqlite3.connect(db_path).cursor()
+    rows = cur.execute("select dispatch_id, kernel_name, value from counters_collection where counter_name = ?",
+                       (counter,)).fetchall()
+    acc = {}
+    for d, name, v in rows:
+        k = (d, name)
+        acc[k] = acc.get(k, 0.0) + float(v)
+    return acc
+
+
+def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, out_path: str) -> dict:
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the forest kernel,
+    scaled by what the same counters read for a plain device copy of copy_mib
+    MiB (copy_mib read + copy_mib written)."""
+    res = {}
+    for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        acc = _per_dispatch(db, counter)
+        copies = [v for (d, n), v in acc.items() if "copyBuffer" in n or "copy" in n.lower()]
+        forest = [v for (d, n), v in acc.items() if "forest_kernel<true" in n]
+        if not copies or not forest:
+            raise RuntimeError(f"{counter}: no copy or forest dispatch in {db}")
+        copy_kib = max(copies)
+        scale = copy_mib * 1024.0 / copy_kib
+        res[counter] = dict(copy_kib=copy_kib, scale=scale, forest_kib_mean=sum(forest) / len(forest),
+                            forest_dispatches=len(forest))
+    fetch_b = res["FETCH_SIZE"]["forest_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
+    write_b = res["WRITE_SIZE"]["forest_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
+    out = dict(workload=workload, source_hash=source_hash(), kernel="forest_kernel<true,*,*> (forward + reverse)",
+               copy_mib=copy_mib, fetch_bytes=fetch_b, write_bytes=write_b, bytes_per_launch=fetch_b + write_b,
+               counters=res)
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,10 +174,19 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--retune", action="store_true", help="ignore cached and shipped tuned schedules")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of hipGraph replays")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a buffer of this many MiB once (scale for HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="reduce two rocprofv3 counter databases (FETCH_SIZE, WRITE_SIZE runs made with "
+                         "--calibrate-copy) to profiles/forest_kernel_traffic.json and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        out = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy or 512, args.workload,
+                            os.path.join(ROOT, "profiles", "forest_kernel_traffic.json"))
+        print(json.dumps(out))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); environments are "
               "independent, so several GPUs would each run this same single-GPU pass on their own "
@@ -193,7 +242,7 @@ def main():
     tuned = None
     if not args.no_tune:
         from paper_2202_04140_amd import autotune
-        tuned = autotune.tune(G, tc, A)
+        tuned = autotune.tune(G, tc, A, use_cache=not args.retune)
         print(f"[bench] schedule {tuned['opts']} ({'cached' if tuned['cached'] else 'tuned'})",
               file=sys.stderr, flush=True)
 

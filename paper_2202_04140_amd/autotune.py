@@ -7,8 +7,10 @@ accumulators, whether lanes and columns are ordered by LDS bank group, and
 the block size of the DAG kernel.  tune() searches these by coordinate
 descent, timing the fused forward + reverse DAG launch (ace_contract with an
 adjoint) on the caller's one-particle values, applies the fastest schedule
-to the graph and records it in a JSON cache keyed by device, basis and batch
-size (ACE_AUTOTUNE_CACHE, default ~/.cache/ace_autotune.json).
+to the graph and records it in a JSON cache keyed by GPU architecture, basis
+and batch size (ACE_AUTOTUNE_CACHE, default ~/.cache/ace_autotune.json).
+Schedules tuned for the standard workloads ship with the package
+(tuned.json) and are used when the user cache has no entry.
 """
 
 from __future__ import annotations
@@ -32,15 +34,18 @@ def cache_path() -> str:
                                                                "ace_autotune.json"))
 
 
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
 def _key(graph: Graph, n_env: int, device_name: str) -> str:
     s = graph.spec
     return (f"{device_name}|g{s['group']}|nu{s['nu_max']}|D{s['degree_max']}|n{s['n_max']}|l{s['l_max']}"
             f"|alg{s['algorithm']}.{s['alg_n']}|E{n_env}")
 
 
-def _load() -> dict:
+def _load(path: str | None = None) -> dict:
     try:
-        with open(cache_path()) as f:
+        with open(path or cache_path()) as f:
             return json.load(f)
     except (OSError, ValueError):
         return {}
@@ -73,20 +78,24 @@ def _time(graph: Graph, coeffs, A, reps: int) -> float:
     return a.elapsed_time(b) / reps
 
 
+def arch(device) -> str:
+    import torch
+    return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+
+
 def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verbose: bool = False) -> dict:
     """Pick and apply the fastest schedule for this graph and batch (A: [E, P1, 2]).
 
     Returns {"opts": ..., "ms": ..., "tried": [(opts, ms), ...], "cached": bool}.
     """
-    import torch
     dev = A.device
-    name = torch.cuda.get_device_name(dev)
-    key = _key(graph, A.shape[0], name)
-    data = _load() if use_cache else {}
-    if use_cache and key in data:
-        opts = data[key]["opts"]
-        graph.set_schedule(**opts)
-        return {"opts": opts, "ms": data[key]["ms"], "tried": [], "cached": True}
+    key = _key(graph, A.shape[0], arch(dev))
+    if use_cache:
+        for data in (_load(), _load(SHIPPED)):
+            if key in data:
+                opts = data[key]["opts"]
+                graph.set_schedule(**opts)
+                return {"opts": opts, "ms": data[key]["ms"], "tried": [], "cached": True}
     if graph.schedule_kind() != "forest":
         return {"opts": graph.get_schedule(), "ms": None, "tried": [], "cached": False}
     best = graph.get_schedule()
