@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "forest", "remat", "layered"],
+                    help="DAG kernel to use (auto: what the library picks, then autotuned)")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
     ap.add_argument("--retune", action="store_true", help="ignore cached and shipped tuned schedules")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of hipGraph replays")
@@ -211,6 +213,8 @@ def main():
     t0 = time.perf_counter()
     G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
     t_build = time.perf_counter() - t0
+    if args.schedule != "auto":
+        G.set_schedule(schedule=args.schedule)
     stats = G.stats()
     c = wl.coefficients(w, G.k_degrees())
     tc = torch.from_numpy(c).to(dev)
@@ -242,7 +246,8 @@ def main():
     tuned = None
     if not args.no_tune:
         from paper_2202_04140_amd import autotune
-        tuned = autotune.tune(G, tc, A, use_cache=not args.retune)
+        tuned = autotune.tune(G, tc, A, use_cache=not args.retune,
+                              kinds=None if args.schedule == "auto" else (args.schedule,))
         print(f"[bench] schedule {tuned['opts']} ({'cached' if tuned['cached'] else 'tuned'})",
               file=sys.stderr, flush=True)
 
@@ -289,8 +294,9 @@ def main():
     with torch.cuda.stream(stream):
         ms_kernel, _ = timed(dag_launch, args.steps, args.warmup)
     fl = dag_flops_per_env(stats)
-    kernel_name = ("forest_kernel (forward + reverse)" if G.schedule_kind() == "forest"
-                   else "dag_kernel (forward + reverse)")
+    kind = G.schedule_kind()
+    kernel_name = {"forest": "forest_kernel", "remat": "remat_kernel", "layered": "dag_kernel"}[kind] + \
+        " (forward + reverse)"
     achieved = fl["total"] * E / (ms_kernel * 1e-3) / 1e12
 
     # parity of the timed results
@@ -339,7 +345,8 @@ def main():
                      "traffic": profiled_traffic(args.workload), "kernel_ms": ms_kernel, "flops_per_env": fl},
         "eager_ms_per_step": ms_dag_eager,
         "timing": "eager launches" if args.eager else "hipGraph replays of one captured step",
-        "schedule": (tuned or {}).get("opts", G.get_schedule()),
+        "schedule": G.get_schedule(),
+        "schedule_kind": kind,
         "cpu_baseline": cpu,
         "parity": parity,
         "graph_build_s": t_build,

@@ -145,14 +145,31 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *   bank_schedule  1: order work so that a quarter-wave's LDS gathers hit
  *                  distinct bank groups; 0: plain order
  *   block_threads  threads per block of the DAG kernel, 64..512, multiple of 64
+ *   schedule       which DAG kernel evaluates the graph (ACE_SCHEDULE_*):
+ *                  AUTO takes the forest schedule when its resident set
+ *                  fits in LDS, else the remat schedule, else the layered
+ *                  one.  FOREST and REMAT fail with ACE_ERR_UNSUPPORTED in
+ *                  ace_graph_set_schedule when the graph has no such
+ *                  schedule.
+ *   term_chunk     remat schedule: terms sharing a base handled per lane
+ *                  item, 1..256
+ * hot_columns also sets the number of one-particle slots whose adjoints
+ * the remat kernel sums in registers.
  */
+#define ACE_SCHEDULE_AUTO 0
+#define ACE_SCHEDULE_FOREST 1   /* one-particle and order-2 values resident in LDS */
+#define ACE_SCHEDULE_REMAT 2    /* one-particle values resident, parents recomputed */
+#define ACE_SCHEDULE_LAYERED 3  /* layer by layer, value arenas in LDS or HBM */
+
 typedef struct ace_schedule_opts {
   int32_t row_chunk;
   int32_t tree_chunk;
   int32_t hot_columns;
   int32_t bank_schedule;
   int32_t block_threads;
-  int32_t reserved[3];
+  int32_t schedule;
+  int32_t term_chunk;
+  int32_t reserved;
 } ace_schedule_opts;
 
 /* Current schedule options of a graph (host). */
@@ -247,14 +264,22 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
 /*
  * Introspection for tests (host only, no device work).
  *
- * ace_debug_schedule: *kind = 1 if evaluation uses the forest schedule
- *   (one-particle and order-2 node values resident in LDS, every higher
- *   node computed in registers), 0 if it uses the layer-by-layer schedule;
- *   in the latter case ace_last_error() names the reason.  If info is not
- *   NULL it receives 16 int64 schedule sizes: resident slots, tree slices,
- *   child positions (padded, real), pair-row slices, pair entries (padded,
- *   real), grandchildren, the four hot slots, whether all resident adjoints
- *   fit in LDS; the rest are 0.
+ * ace_debug_schedule: the schedule ace_eval_grad uses without flags:
+ *   *kind = 1 forest (one-particle and order-2 node values resident in
+ *   LDS, every higher node computed in registers), 2 remat (one-particle
+ *   values resident, the two parents of every term recomputed from their
+ *   one-particle factors), 0 layer by layer.  For a graph built with
+ *   ACE_BUILD_HOST_ONLY the choice assumes 160 KiB of LDS per block.  When
+ *   the forest is not used, ace_last_error() names the reason.  If info is
+ *   not NULL it receives 16 int64 schedule sizes.  Forest: resident slots,
+ *   tree slices, child positions (padded, real), pair-row slices, pair
+ *   entries (padded, real), grandchildren, the four hot slots, whether all
+ *   resident adjoints fit in LDS, the mean LDS bank cost of pair entries
+ *   and of children (x1000).  Remat: LDS slots, slices, term positions
+ *   (padded, real), items, 0, 0, 0, the four hot slots.  The rest are 0.
+ *
+ * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedule
+ *   (ACE_ERR_UNSUPPORTED if the graph has none).
  *
  * ace_debug_forest_eval: runs the forest schedule on the host for n_env
  *   environments, with the same indices, padding and forwarding as the
@@ -266,6 +291,8 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
 ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info);
 ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
                                  double* phi, double* Abar);
+ace_status ace_debug_remat_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
+                                double* phi, double* Abar);
 
 #ifdef __cplusplus
 }

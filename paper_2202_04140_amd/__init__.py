@@ -34,6 +34,8 @@ BUILD_HOST_ONLY = 1
 FLAG_NAIVE = 1
 FLAG_CHECK = 2
 FLAG_LAYERED = 4
+SCHEDULES = {"auto": 0, "forest": 1, "remat": 2, "layered": 3}
+_KIND = {0: "layered", 1: "forest", 2: "remat"}
 
 _STATUS = {0: "ACE_OK", 1: "ACE_ERR_INVALID_ARG", 2: "ACE_ERR_UNSUPPORTED",
            3: "ACE_ERR_OUT_OF_MEMORY", 4: "ACE_ERR_HIP", 5: "ACE_ERR_INTERNAL"}
@@ -57,7 +59,8 @@ class _Spec(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("row_chunk", ctypes.c_int32), ("tree_chunk", ctypes.c_int32),
                 ("hot_columns", ctypes.c_int32), ("bank_schedule", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("block_threads", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("term_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -94,6 +97,7 @@ EXPORTED = {
     "ace_graph_set_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
     "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
+    "ace_debug_remat_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
 }
 
 
@@ -191,36 +195,46 @@ class Graph:
         d = np.where(kt >= 0, deg1[np.maximum(kt, 0)], 0)
         return d.sum(axis=1)
 
-    SCHEDULE_KEYS = ("row_chunk", "tree_chunk", "hot_columns", "bank_schedule", "block_threads")
+    SCHEDULE_KEYS = ("row_chunk", "tree_chunk", "hot_columns", "bank_schedule", "block_threads",
+                     "schedule", "term_chunk")
 
     def get_schedule(self) -> dict:
+        """Schedule options (ace_graph_get_schedule); "schedule" is a name of SCHEDULES."""
         o = _Opts()
         _check(lib().ace_graph_get_schedule(self._h, ctypes.byref(o)))
-        return {k: getattr(o, k) for k in self.SCHEDULE_KEYS}
+        d = {k: getattr(o, k) for k in self.SCHEDULE_KEYS}
+        d["schedule"] = {v: k for k, v in SCHEDULES.items()}[d["schedule"]]
+        return d
 
     def set_schedule(self, **opts):
         """Rebuild the evaluation schedule (ace_graph_set_schedule); unspecified
         options keep their current values."""
         cur = self.get_schedule()
         cur.update(opts)
+        if isinstance(cur["schedule"], str):
+            cur["schedule"] = SCHEDULES[cur["schedule"]]
         o = _Opts(**{k: int(cur[k]) for k in self.SCHEDULE_KEYS})
         _check(lib().ace_graph_set_schedule(self._h, ctypes.byref(o)))
 
     def schedule_kind(self) -> str:
-        """'forest' or 'layered' (ace_debug_schedule)."""
+        """'forest', 'remat' or 'layered': the kernel ace_eval_grad uses (ace_debug_schedule)."""
         k = ctypes.c_int32()
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), None))
-        return "forest" if k.value == 1 else "layered"
+        return _KIND[k.value]
 
     def schedule_info(self) -> dict:
-        """Sizes of the forest schedule (ace_debug_schedule)."""
+        """Sizes of the schedule in use (ace_debug_schedule)."""
         k = ctypes.c_int32()
         info = np.zeros(16, dtype=np.int64)
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
-        names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
-                 "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",
-                 "bank_cost_rows_x1000", "bank_cost_children_x1000"]
-        return {"kind": "forest" if k.value == 1 else "layered", **{n: int(v) for n, v in zip(names, info)}}
+        if k.value == 2:
+            names = ["nslot", "slices", "term_pos", "term_real", "items", "", "", "",
+                     "hot0", "hot1", "hot2", "hot3"]
+        else:
+            names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
+                     "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",
+                     "bank_cost_rows_x1000", "bank_cost_children_x1000"]
+        return {"kind": _KIND[k.value], **{n: int(v) for n, v in zip(names, info) if n}}
 
     def forest_eval_host(self, coeffs: np.ndarray, A: np.ndarray):
         """Host emulation of the forest kernel (ace_debug_forest_eval):
@@ -234,15 +248,26 @@ class Graph:
                                            ab.ctypes.data))
         return phi[:, 0] + 1j * phi[:, 1], ab[..., 0] + 1j * ab[..., 1]
 
+    def remat_eval_host(self, coeffs: np.ndarray, A: np.ndarray):
+        """Host emulation of the remat kernel (ace_debug_remat_eval), as forest_eval_host."""
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        E = A.shape[0]
+        Ar = np.ascontiguousarray(np.stack([A.real, A.imag], -1), dtype=np.float64)
+        phi = np.zeros((E, 2))
+        ab = np.zeros((E, self.P1, 2))
+        _check(lib().ace_debug_remat_eval(self._h, c.ctypes.data, E, Ar.ctypes.data, phi.ctypes.data,
+                                          ab.ctypes.data))
+        return phi[:, 0] + 1j * phi[:, 1], ab[..., 0] + 1j * ab[..., 1]
+
     def workspace_size(self, n_env: int, n_nbr: int = 0, flags: int = 0) -> int:
         out = _SZ()
         _check(lib().ace_workspace_size(self._h, int(n_env), int(n_nbr), int(flags), ctypes.byref(out)))
         return int(out.value)
 
-    def workspace(self, n_env: int, device):
-        """A cached device workspace of at least workspace_size(n_env) bytes."""
+    def workspace(self, n_env: int, device, flags: int = 0):
+        """A cached device workspace of at least workspace_size(n_env, flags=flags) bytes."""
         import torch
-        need = self.workspace_size(n_env)
+        need = self.workspace_size(n_env, flags=flags)
         key = str(device)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < need:
@@ -309,8 +334,8 @@ def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = Fals
     E = A.shape[0]
     phi = torch.empty((E, 2), dtype=torch.float64, device=A.device)
     Abar = torch.empty_like(A) if with_grad else None
-    ws = g.workspace(E, A.device)
     flags = (FLAG_NAIVE if naive else 0) | (FLAG_LAYERED if layered else 0)
+    ws = g.workspace(E, A.device, flags)
     _check(lib().ace_contract(g.handle, coeffs.data_ptr(), E, A.data_ptr(), phi.data_ptr(),
                               Abar.data_ptr() if Abar is not None else None,
                               ws.data_ptr(), ws.numel(), flags, _stream(A.device)))
@@ -328,8 +353,8 @@ def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = F
     _check_batch(offsets, pos, check)
     E = offsets.numel() - 1
     phi = out if out is not None else torch.empty((E, 2), dtype=torch.float64, device=pos.device)
-    ws = g.workspace(E, pos.device)
     flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
+    ws = g.workspace(E, pos.device, flags)
     _check(lib().ace_eval(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                           phi.data_ptr(), ws.data_ptr(), ws.numel(), flags, _stream(pos.device)))
     return phi
@@ -350,8 +375,8 @@ def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: boo
     else:
         phi = torch.empty((E, 2), dtype=torch.float64, device=pos.device)
         grad = torch.empty_like(pos)
-    ws = g.workspace(E, pos.device)
     flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
+    ws = g.workspace(E, pos.device, flags)
     _check(lib().ace_eval_grad(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                                phi.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), flags,
                                _stream(pos.device)))

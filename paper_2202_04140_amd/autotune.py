@@ -1,14 +1,15 @@
 """Autotuner for the evaluation schedule of a graph.
 
 The DAG (node list) is fixed by the insertion heuristic; how its evaluation
-is laid out on the GPU is not: how many pair-row entries and tree children a
-lane takes per item, how many hot sibling columns get register
-accumulators, whether lanes and columns are ordered by LDS bank group, and
-the block size of the DAG kernel.  tune() searches these by coordinate
-descent, timing the fused forward + reverse DAG launch (ace_contract with an
-adjoint) on the caller's one-particle values, applies the fastest schedule
-to the graph and records it in a JSON cache keyed by GPU architecture, basis
-and batch size (ACE_AUTOTUNE_CACHE, default ~/.cache/ace_autotune.json).
+is laid out on the GPU is not: which kernel runs it (forest or remat), how
+many pair-row entries, tree children or terms a lane takes per item, how
+many hot slots get register accumulators, whether lanes and columns are
+ordered by LDS bank group, and the block size of the DAG kernel.  tune()
+searches these by coordinate descent for every available kernel, timing the
+fused forward + reverse DAG launch (ace_contract with an adjoint) on the
+caller's one-particle values, applies the fastest schedule to the graph and
+records it in a JSON cache keyed by GPU architecture, basis and batch size
+(ACE_AUTOTUNE_CACHE, default ~/.cache/ace_autotune.json).
 Schedules tuned for the standard workloads ship with the package
 (tuned.json) and are used when the user cache has no entry.
 """
@@ -20,12 +21,20 @@ import os
 
 from . import Graph, contract
 
+# options that matter for each kernel, with the values searched
 SPACE = {
-    "row_chunk": [16, 32, 64],
-    "tree_chunk": [8, 16, 32],
-    "hot_columns": [0, 2, 4],
-    "bank_schedule": [0, 1],
-    "block_threads": [256, 512],
+    "forest": {
+        "row_chunk": [16, 32, 64],
+        "tree_chunk": [8, 16, 32],
+        "hot_columns": [0, 2, 4],
+        "bank_schedule": [0, 1],
+        "block_threads": [256, 512],
+    },
+    "remat": {
+        "term_chunk": [8, 16, 32, 64],
+        "hot_columns": [0, 2, 4],
+        "block_threads": [256, 512],
+    },
 }
 
 
@@ -83,38 +92,58 @@ def arch(device) -> str:
     return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
 
 
-def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verbose: bool = False) -> dict:
+def _available(graph: Graph, kind: str) -> bool:
+    from . import AceError
+    cur = graph.get_schedule()
+    try:
+        graph.set_schedule(schedule=kind)
+        return graph.schedule_kind() == kind
+    except AceError:
+        return False
+    finally:
+        graph.set_schedule(**cur)
+
+
+def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verbose: bool = False,
+         kinds=None) -> dict:
     """Pick and apply the fastest schedule for this graph and batch (A: [E, P1, 2]).
 
+    kinds: kernels to consider (default: every one the graph supports).
     Returns {"opts": ..., "ms": ..., "tried": [(opts, ms), ...], "cached": bool}.
     """
     dev = A.device
     key = _key(graph, A.shape[0], arch(dev))
     if use_cache:
         for data in (_load(), _load(SHIPPED)):
-            if key in data:
+            if key in data and (kinds is None or data[key]["opts"].get("schedule") in kinds):
                 opts = data[key]["opts"]
                 graph.set_schedule(**opts)
                 return {"opts": opts, "ms": data[key]["ms"], "tried": [], "cached": True}
-    if graph.schedule_kind() != "forest":
+    kinds = [k for k in (kinds or SPACE) if k in SPACE and _available(graph, k)]
+    if not kinds:
         return {"opts": graph.get_schedule(), "ms": None, "tried": [], "cached": False}
-    best = graph.get_schedule()
-    graph.set_schedule(**best)
-    best_ms = _time(graph, coeffs, A, reps)
-    tried = [(dict(best), best_ms)]
-    for name_, values in SPACE.items():
-        for v in values:
-            if v == best[name_]:
-                continue
-            cand = dict(best)
-            cand[name_] = v
-            graph.set_schedule(**cand)
-            ms = _time(graph, coeffs, A, reps)
-            tried.append((cand, ms))
-            if verbose:
-                print(f"[autotune] {cand}: {ms:.4f} ms", flush=True)
-            if ms < best_ms:
-                best, best_ms = cand, ms
+    tried = []
+    best, best_ms = None, float("inf")
+    for kind in kinds:
+        start = dict(graph.get_schedule(), schedule=kind)
+        graph.set_schedule(**start)
+        kbest, kms = start, _time(graph, coeffs, A, reps)
+        tried.append((dict(kbest), kms))
+        for name_, values in SPACE[kind].items():
+            for v in values:
+                if v == kbest[name_]:
+                    continue
+                cand = dict(kbest)
+                cand[name_] = v
+                graph.set_schedule(**cand)
+                ms = _time(graph, coeffs, A, reps)
+                tried.append((cand, ms))
+                if verbose:
+                    print(f"[autotune] {cand}: {ms:.4f} ms", flush=True)
+                if ms < kms:
+                    kbest, kms = cand, ms
+        if kms < best_ms:
+            best, best_ms = kbest, kms
     graph.set_schedule(**best)
     if use_cache:
         data = _load()

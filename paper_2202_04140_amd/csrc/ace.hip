@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -59,7 +61,9 @@ struct ScheduleOpts {
   int tree_chunk = 16;     // regular children per tree item at most
   int hot_columns = 4;     // hot-sibling register columns (0..4)
   int bank_schedule = 1;   // order lanes and columns by LDS bank group
-  int block_threads = 512; // forest kernel block size
+  int block_threads = 512; // forest / remat kernel block size
+  int schedule = 0;        // ACE_SCHEDULE_*
+  int term_chunk = 16;     // remat: terms per lane item at most
 };
 
 struct ace_graph {
@@ -118,6 +122,19 @@ struct ace_graph {
   int32_t* d_fw_off = nullptr;
   uint32_t* d_fw_ent = nullptr;
   bool forest_full = false;        // full-adjoint mode fits in LDS
+  // rematerialising schedule (remat_kernel); used when the forest is not
+  bool remat_ok = false;
+  std::string remat_why;
+  int rm_nslices = 0, rm_nitems = 0, rm_cs_leaf = 0, rm_cs_term = 0;
+  int rm_hot[4] = {0, 0, 0, 0};
+  std::vector<int4> rm_slice;
+  std::vector<uint64_t> rm_blo, rm_bhi, rm_sib;
+  std::vector<int32_t> rm_kmap;
+  void* rmem = nullptr;
+  int4* d_rm_slice = nullptr;
+  uint64_t *d_rm_blo = nullptr, *d_rm_bhi = nullptr, *d_rm_sib = nullptr;
+  int32_t* d_rm_kmap = nullptr;
+  bool remat_lds = false;          // the one-particle values and adjoints fit in LDS
 };
 
 namespace {
@@ -835,6 +852,236 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Rematerialising schedule (remat_kernel).  Terms are the tuples of K of
+// length >= 2; a term is the product of the two parents of its DAG node.
+// The base of a term is the parent of larger order (on a tie, the parent
+// that can serve as base of more terms), the sibling the other one.  Terms
+// are grouped by (base, sibling length) and cut into items of at most
+// term_chunk terms; items of one (base length, sibling length) class are
+// sorted by term count and packed 64 to a slice, so every lane of a slice
+// runs the same loops.
+// ---------------------------------------------------------------------------
+void make_remat(ace_graph* g) {
+  const HostGraph& h = g->h;
+  const int P1 = h.P1, ONE = P1, W = h.width;
+  const int64_t V = h.n_nodes();
+  g->remat_ok = false;
+  g->rm_slice.clear();
+  g->rm_blo.clear();
+  g->rm_bhi.clear();
+  g->rm_sib.clear();
+  g->rm_kmap.clear();
+  if (P1 + 1 > 65535) {
+    g->remat_why = "more than 65534 one-particle functions";
+    return;
+  }
+  if (W > 8) {
+    g->remat_why = "correlation order above 8";
+    return;
+  }
+  struct Term {
+    int32_t base, sib, k;
+  };
+  std::vector<Term> terms;
+  terms.reserve((size_t)h.nK);
+  std::vector<int32_t> tie(V, 0);
+  for (int64_t q = 0; q < h.nK; ++q) {
+    if (h.k_len[q] < 2) continue;
+    const int64_t v = h.k_to_node[q];
+    const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
+    if (h.node_len[a] == h.node_len[b]) {
+      tie[a] += 1;
+      tie[b] += 1;
+    }
+  }
+  for (int64_t q = 0; q < h.nK; ++q) {
+    if (h.k_len[q] < 2) continue;
+    const int64_t v = h.k_to_node[q];
+    const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
+    const int la = h.node_len[a], lb = h.node_len[b];
+    const bool a_base = la > lb || (la == lb && tie[a] >= tie[b]);
+    terms.push_back({a_base ? a : b, a_base ? b : a, (int32_t)q});
+  }
+  std::stable_sort(terms.begin(), terms.end(), [&](const Term& x, const Term& y) {
+    const int sx = h.node_len[x.sib], sy = h.node_len[y.sib];
+    if (x.base != y.base) return x.base < y.base;
+    if (sx != sy) return sx < sy;
+    return x.sib < y.sib;
+  });
+  // items: runs of one (base, sibling length), cut at term_chunk
+  struct Item {
+    int32_t base;
+    int nb, sig;
+    int64_t first;
+    int count;
+  };
+  std::vector<Item> items;
+  const int C = std::max(1, g->opts.term_chunk);
+  for (size_t i = 0; i < terms.size();) {
+    size_t j = i;
+    const int sig = h.node_len[terms[i].sib];
+    while (j < terms.size() && terms[j].base == terms[i].base && h.node_len[terms[j].sib] == sig) ++j;
+    for (size_t c0 = i; c0 < j; c0 += C)
+      items.push_back({terms[i].base, (int)h.node_len[terms[i].base], sig, (int64_t)c0, (int)std::min<size_t>(C, j - c0)});
+    i = j;
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+    if (x.nb != y.nb) return x.nb < y.nb;
+    if (x.sig != y.sig) return x.sig < y.sig;
+    return x.count > y.count;
+  });
+  // hot one-particle slots: the most frequent adjoint push targets
+  std::vector<int64_t> freq(P1 + 1, 0);
+  int64_t npush = 0;
+  for (const Term& t : terms)
+    for (int u = 0; u < h.node_len[t.sib]; ++u) {
+      freq[h.node_flat[(int64_t)t.sib * W + u]] += 1;
+      ++npush;
+    }
+  for (const Item& it : items)
+    for (int u = 0; u < it.nb; ++u) {
+      freq[h.node_flat[(int64_t)it.base * W + u]] += 1;
+      ++npush;
+    }
+  {
+    std::vector<int32_t> ord(P1);
+    for (int i = 0; i < P1; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return freq[x] > freq[y]; });
+    for (int k = 0; k < 4; ++k)
+      g->rm_hot[k] = (k < g->opts.hot_columns && k < P1 && freq[ord[k]] * 64 >= npush) ? ord[k] : ONE;
+  }
+  // slices
+  auto pack = [&](int32_t node, int from, int count) {
+    uint64_t w = 0;
+    for (int u = 0; u < 4; ++u) {
+      const int idx = from + u;
+      const uint64_t sl = idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + idx] : (uint64_t)ONE;
+      w |= sl << (16 * u);
+    }
+    return w;
+  };
+  const uint64_t ones = (uint64_t)ONE | ((uint64_t)ONE << 16) | ((uint64_t)ONE << 32) | ((uint64_t)ONE << 48);
+  g->rm_kmap.assign(P1, -1);
+  for (int i = 0; i < P1; ++i) g->rm_kmap[i] = h.node_k[i];
+  g->rm_cs_leaf = 0;
+  g->rm_cs_term = P1;
+  int64_t pos = 0;
+  for (size_t i0 = 0; i0 < items.size();) {
+    size_t i1 = i0;
+    while (i1 < items.size() && i1 - i0 < 64 && items[i1].nb == items[i0].nb && items[i1].sig == items[i0].sig) ++i1;
+    const int ncol = items[i0].count;
+    if ((int64_t)g->rm_blo.size() + 64 > INT32_MAX || pos + 64LL * ncol > INT32_MAX) {
+      g->remat_why = "schedule larger than 2^31 entries";
+      return;
+    }
+    g->rm_slice.push_back(make_int4((int)g->rm_blo.size(), (int)pos, ncol, items[i0].nb | (items[i0].sig << 8)));
+    const size_t sib0 = g->rm_sib.size();
+    g->rm_sib.resize(sib0 + 64 * (size_t)ncol, ones);
+    g->rm_kmap.resize(P1 + sib0 + 64 * (size_t)ncol, -1);
+    for (int lane = 0; lane < 64; ++lane) {
+      if (i0 + lane < i1) {
+        const Item& it = items[i0 + lane];
+        g->rm_blo.push_back(pack(it.base, 0, it.nb));
+        g->rm_bhi.push_back(pack(it.base, 4, it.nb));
+        for (int j = 0; j < it.count; ++j) {
+          const Term& t = terms[it.first + j];
+          const size_t e = sib0 + (size_t)j * 64 + lane;
+          g->rm_sib[e] = pack(t.sib, 0, h.node_len[t.sib]);
+          g->rm_kmap[P1 + e] = t.k;
+        }
+      } else {
+        g->rm_blo.push_back(ones);
+        g->rm_bhi.push_back(ones);
+      }
+    }
+    pos += 64LL * ncol;
+    i0 = i1;
+  }
+  g->rm_nslices = (int)g->rm_slice.size();
+  g->rm_nitems = (int)g->rm_blo.size();
+  g->remat_ok = true;
+  g->remat_why.clear();
+}
+
+// Host run of the remat schedule for one environment, with the kernel's
+// indices, padding and push order; false if an index is out of range.
+bool remat_emulate(const ace_graph* g, const double* coeffs, const double* A, double* phi, double* Abar) {
+  using cd = std::complex<double>;
+  const int P1 = g->P1, ONE = P1;
+  std::vector<double> cs(g->rm_kmap.size());
+  for (size_t i = 0; i < cs.size(); ++i) {
+    const int k = g->rm_kmap[i];
+    cs[i] = k >= 0 ? coeffs[k] : 0.0;
+  }
+  std::vector<cd> x(P1 + 1), ab(P1 + 1);
+  for (int i = 0; i < P1; ++i) {
+    x[i] = cd(A[2 * i], A[2 * i + 1]);
+    ab[i] = cs[g->rm_cs_leaf + i];
+  }
+  x[ONE] = 1.0;
+  cd acc = 0.0;
+  for (int i = 0; i < P1; ++i) acc += cs[g->rm_cs_leaf + i] * x[i];
+  auto ok = [&](int v) { return v >= 0 && v <= P1; };
+  for (const int4& sl : g->rm_slice) {
+    const int nb = sl.w & 0xff, sig = sl.w >> 8;
+    if (nb < 1 || nb > 8 || sig < 1 || sig > 4) return false;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int item = sl.x + lane;
+      if (item < 0 || item >= g->rm_nitems) return false;
+      int bs[8];
+      cd xv[8], pre[8], xb = 1.0;
+      for (int i = 0; i < 8; ++i) {
+        bs[i] = (int)(((i < 4 ? g->rm_blo[item] : g->rm_bhi[item]) >> (16 * (i & 3))) & 0xffffu);
+        if (i < nb) {
+          if (!ok(bs[i])) return false;
+          xv[i] = x[bs[i]];
+          pre[i] = xb;
+          xb = i == 0 ? xv[0] : xb * xv[i];
+        }
+      }
+      cd t = 0.0;
+      for (int j = 0; j < sl.z; ++j) {
+        const int64_t pos = (int64_t)sl.y + (int64_t)j * 64 + lane;
+        if (pos < 0 || pos >= (int64_t)g->rm_sib.size()) return false;
+        const uint64_t sg = g->rm_sib[pos];
+        const double c = cs[g->rm_cs_term + pos];
+        int ss[4];
+        cd v[4], xs = 1.0;
+        for (int u = 0; u < sig; ++u) {
+          ss[u] = (int)((sg >> (16 * u)) & 0xffffu);
+          if (!ok(ss[u])) return false;
+          v[u] = x[ss[u]];
+          xs = u == 0 ? v[0] : xs * v[u];
+        }
+        t += c * xs;
+        if (c != 0.0)
+          for (int u = 0; u < sig; ++u) {
+            cd d = c * xb;
+            for (int w = 0; w < sig; ++w)
+              if (w != u) d *= v[w];
+            ab[ss[u]] += d;
+          }
+      }
+      acc += xb * t;
+      if (bs[0] != ONE)
+        for (int i = 0; i < nb; ++i) {
+          cd d = t;
+          for (int w = 0; w < nb; ++w)
+            if (w != i) d *= xv[w];
+          ab[bs[i]] += d;
+        }
+    }
+  }
+  phi[0] = acc.real();
+  phi[1] = acc.imag();
+  for (int i = 0; i < P1; ++i) {
+    Abar[2 * i] = ab[i].real();
+    Abar[2 * i + 1] = ab[i].imag();
+  }
+  return true;
+}
+
 void make_stats(ace_graph* g) {
   const HostGraph& h = g->h;
   ace_graph_stats& st = g->stats;
@@ -877,7 +1124,13 @@ T* carve(char*& p, size_t n) {
   return r;
 }
 
-// Upload the forest schedule (replacing a previous one) and plan its LDS.
+// LDS of remat_kernel: one-particle values and adjoints, reduction scratch.
+size_t remat_lds_bytes(const ace_graph* g, bool grad) {
+  return (size_t)(g->P1 + 1) * 16 * (grad ? 2 : 1) + (kRematBlock / 64) * sizeof(double2);
+}
+
+// Upload the forest and remat schedules (replacing previous ones) and plan
+// their LDS.
 ace_status upload_forest(ace_graph* g) {
   if (g->fmem) {
     (void)hipFree(g->fmem);
@@ -930,6 +1183,35 @@ ace_status upload_forest(ace_graph* g) {
                         (const void*)forest_kernel<true, false, false>, (const void*)forest_kernel<true, true, false>,
                         (const void*)forest_kernel<true, false, true>, (const void*)forest_kernel<true, true, true>};
     for (const void* f : fk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  }
+  if (g->rmem) {
+    (void)hipFree(g->rmem);
+    g->rmem = nullptr;
+  }
+  g->remat_lds = false;
+  if (g->remat_ok) {
+    size_t rb = align_up(g->rm_slice.size() * sizeof(int4)) + align_up(g->rm_blo.size() * 8) +
+                align_up(g->rm_bhi.size() * 8) + align_up(g->rm_sib.size() * 8) + align_up(g->rm_kmap.size() * 4) +
+                kAlign;
+    if (hipMalloc(&g->rmem, rb) != hipSuccess) {
+      g->rmem = nullptr;
+      (void)hipGetLastError();
+      return fail(ACE_ERR_OUT_OF_MEMORY, "hipMalloc of the remat schedule failed");
+    }
+    char* q = static_cast<char*>(g->rmem);
+    g->d_rm_slice = carve<int4>(q, g->rm_slice.size());
+    g->d_rm_blo = carve<uint64_t>(q, g->rm_blo.size());
+    g->d_rm_bhi = carve<uint64_t>(q, g->rm_bhi.size());
+    g->d_rm_sib = carve<uint64_t>(q, g->rm_sib.size());
+    g->d_rm_kmap = carve<int32_t>(q, g->rm_kmap.size());
+    ACE_HIP(put(g->d_rm_slice, g->rm_slice.data(), g->rm_slice.size() * sizeof(int4)));
+    ACE_HIP(put(g->d_rm_blo, g->rm_blo.data(), g->rm_blo.size() * 8));
+    ACE_HIP(put(g->d_rm_bhi, g->rm_bhi.data(), g->rm_bhi.size() * 8));
+    ACE_HIP(put(g->d_rm_sib, g->rm_sib.data(), g->rm_sib.size() * 8));
+    ACE_HIP(put(g->d_rm_kmap, g->rm_kmap.data(), g->rm_kmap.size() * 4));
+    g->remat_lds = remat_lds_bytes(g, true) <= g->max_lds;
+    ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
   return ACE_OK;
 }
@@ -1019,7 +1301,36 @@ struct Workspace {
 
 int arena_blocks(int64_t n_env) { return (int)std::max<int64_t>(1, std::min<int64_t>(n_env, kArenaBlocks)); }
 
-Workspace plan_workspace(const ace_graph* g, int64_t n_env, char* base) {
+enum class Sched { Layered, Forest, Remat };
+
+bool use_forest(const ace_graph* g, bool grad) {
+  return g->forest_ok && (grad ? g->forest_grad_lds : g->forest_fwd_lds);
+}
+
+// The kernel that evaluates the DAG: the requested schedule when it is
+// available, else the forest, else remat, else layer by layer.
+Sched pick_schedule(const ace_graph* g, bool grad, uint32_t flags) {
+  if (flags & ACE_FLAG_LAYERED) return Sched::Layered;
+  const bool f = use_forest(g, grad);
+  const bool r = g->remat_ok && g->remat_lds;
+  switch (g->opts.schedule) {
+    case ACE_SCHEDULE_FOREST:
+      if (f) return Sched::Forest;
+      break;
+    case ACE_SCHEDULE_REMAT:
+      if (r) return Sched::Remat;
+      break;
+    case ACE_SCHEDULE_LAYERED:
+      return Sched::Layered;
+    default:
+      break;
+  }
+  if (f) return Sched::Forest;
+  if (r) return Sched::Remat;
+  return Sched::Layered;
+}
+
+Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char* base) {
   Workspace w;
   size_t off = 0;
   auto take = [&](size_t n) {
@@ -1030,10 +1341,12 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, char* base) {
   const size_t per_env = (size_t)g->P1 * sizeof(double2);
   w.A = take((size_t)n_env * per_env);
   w.Abar = take((size_t)n_env * per_env);
+  const bool layered = pick_schedule(g, true, flags) == Sched::Layered || pick_schedule(g, false, flags) == Sched::Layered;
   const size_t arena = (size_t)arena_blocks(n_env) * g->slots * sizeof(double2);
-  if (!g->fwd_xl || !g->grad_xl) w.arena_x = take(arena);
-  if (!g->grad_al) w.arena_ab = take(arena);
-  if (g->forest_ok) w.cs = reinterpret_cast<double*>(take(g->kmap.size() * sizeof(double)));
+  if (layered && (!g->fwd_xl || !g->grad_xl)) w.arena_x = take(arena);
+  if (layered && !g->grad_al) w.arena_ab = take(arena);
+  const size_t ncs = std::max(g->forest_ok ? g->kmap.size() : 0, g->remat_ok ? g->rm_kmap.size() : 0);
+  if (ncs) w.cs = reinterpret_cast<double*>(take(ncs * sizeof(double)));
   w.bytes = off;
   return w;
 }
@@ -1071,10 +1384,6 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   hipLaunchKernelGGL(basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
-}
-
-bool use_forest(const ace_graph* g, bool grad) {
-  return g->forest_ok && (grad ? g->forest_grad_lds : g->forest_fwd_lds);
 }
 
 ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
@@ -1138,10 +1447,52 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   return ACE_OK;
 }
 
+ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
+                        double2* Abar, const Workspace& w, hipStream_t s) {
+  PrepArgs pa{};
+  pa.kmap = g->d_rm_kmap;
+  pa.coeffs = coeffs;
+  pa.cs = w.cs;
+  pa.n = (int64_t)g->rm_kmap.size();
+  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((pa.n + 255) / 256, 1024));
+  hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  ACE_HIP(hipGetLastError());
+  RematArgs a{};
+  a.n_env = n_env;
+  a.A = A;
+  a.phi = phi;
+  a.Abar = Abar;
+  a.cs = w.cs;
+  a.slice = g->d_rm_slice;
+  a.base_lo = g->d_rm_blo;
+  a.base_hi = g->d_rm_bhi;
+  a.sib = g->d_rm_sib;
+  a.cs_leaf = g->rm_cs_leaf;
+  a.cs_term = g->rm_cs_term;
+  a.P1 = g->P1;
+  a.n_slices = g->rm_nslices;
+  a.hot = make_int4(g->rm_hot[0], g->rm_hot[1], g->rm_hot[2], g->rm_hot[3]);
+  const bool grad = Abar != nullptr;
+  const size_t lds = remat_lds_bytes(g, grad);
+  const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
+  if (grad)
+    hipLaunchKernelGGL(remat_kernel<true>, grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL(remat_kernel<false>, grid, block, lds, s, a);
+  ACE_HIP(hipGetLastError());
+  return ACE_OK;
+}
+
 ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
                       double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags) {
-  if (!(flags & ACE_FLAG_LAYERED) && use_forest(g, Abar != nullptr))
-    return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s);
+  switch (pick_schedule(g, Abar != nullptr, flags)) {
+    case Sched::Forest:
+      return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s);
+    case Sched::Remat:
+      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s);
+    default:
+      break;
+  }
   DagArgs a{};
   a.n_env = n_env;
   a.A = A;
@@ -1247,7 +1598,7 @@ ace_status common_eval_checks(const ace_graph* g, const double* coeffs, int64_t 
   if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK | ACE_FLAG_LAYERED)) return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
   if (n_env == 0) return ACE_OK;
   if (!coeffs) return fail(ACE_ERR_INVALID_ARG, "coeffs is NULL");
-  *need = plan_workspace(g, n_env, nullptr).bytes;
+  *need = plan_workspace(g, n_env, flags, nullptr).bytes;
   if (!workspace) return fail(ACE_ERR_INVALID_ARG, "workspace is NULL");
   if (ws_bytes < *need)
     return fail(ACE_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(*need) + " bytes, got " +
@@ -1284,6 +1635,7 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out) {
     build_graph(bs, g->h);
     make_schedule(g);
     make_forest(g);
+    make_remat(g);
     make_stats(g);
   } catch (const std::invalid_argument& e) {
     delete g;
@@ -1310,6 +1662,7 @@ void ace_graph_free(ace_graph* g) {
   if (!g) return;
   if (g->dmem) (void)hipFree(g->dmem);
   if (g->fmem) (void)hipFree(g->fmem);
+  if (g->rmem) (void)hipFree(g->rmem);
   delete g;
 }
 
@@ -1343,11 +1696,10 @@ ace_status ace_graph_export_k(const ace_graph* g, int32_t* k_tuples) {
 
 ace_status ace_workspace_size(const ace_graph* g, int64_t n_env, int64_t n_nbr, uint32_t flags, size_t* bytes) {
   (void)n_nbr;
-  (void)flags;
   if (!g || !bytes) return fail(ACE_ERR_INVALID_ARG, "graph and bytes must be non-NULL");
   if (n_env < 0) return fail(ACE_ERR_INVALID_ARG, "n_env must be >= 0");
   if (!g->on_device) return fail(ACE_ERR_INVALID_ARG, "graph was built with ACE_BUILD_HOST_ONLY");
-  *bytes = plan_workspace(g, n_env, nullptr).bytes;
+  *bytes = plan_workspace(g, n_env, flags, nullptr).bytes;
   return ACE_OK;
 }
 
@@ -1368,7 +1720,7 @@ ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env,
   if (st != ACE_OK || n_env == 0) return st;
   if (!A || !phi) return fail(ACE_ERR_INVALID_ARG, "A and phi must be non-NULL");
   hipStream_t s = (hipStream_t)stream;
-  const Workspace w = plan_workspace(g, n_env, static_cast<char*>(workspace));
+  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   if (flags & ACE_FLAG_NAIVE)
     return launch_naive(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
                         reinterpret_cast<double2*>(Abar), s);
@@ -1387,7 +1739,7 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
     st = check_offsets(offsets, n_env, -1, s);
     if (st != ACE_OK) return st;
   }
-  const Workspace w = plan_workspace(g, n_env, static_cast<char*>(workspace));
+  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   st = launch_basis(g, n_env, offsets, pos, w.A, s);
   if (st != ACE_OK) return st;
   if (flags & ACE_FLAG_NAIVE) return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
@@ -1407,7 +1759,7 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
     st = check_offsets(offsets, n_env, -1, s);
     if (st != ACE_OK) return st;
   }
-  const Workspace w = plan_workspace(g, n_env, static_cast<char*>(workspace));
+  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   st = launch_basis(g, n_env, offsets, pos, w.A, s);
   if (st != ACE_OK) return st;
   if (flags & ACE_FLAG_NAIVE)
@@ -1426,6 +1778,8 @@ ace_status ace_graph_get_schedule(const ace_graph* g, ace_schedule_opts* o) {
   o->hot_columns = g->opts.hot_columns;
   o->bank_schedule = g->opts.bank_schedule;
   o->block_threads = g->opts.block_threads;
+  o->schedule = g->opts.schedule;
+  o->term_chunk = g->opts.term_chunk;
   return ACE_OK;
 }
 
@@ -1433,7 +1787,8 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   if (!g || !o) return fail(ACE_ERR_INVALID_ARG, "graph and opts must be non-NULL");
   if (o->row_chunk < 4 || o->row_chunk > 256 || o->tree_chunk < 1 || o->tree_chunk > 256 || o->hot_columns < 0 ||
       o->hot_columns > 4 || (o->bank_schedule != 0 && o->bank_schedule != 1) || o->block_threads < 64 ||
-      o->block_threads > 512 || o->block_threads % 64 != 0)
+      o->block_threads > 512 || o->block_threads % 64 != 0 || o->schedule < ACE_SCHEDULE_AUTO ||
+      o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256)
     return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");
   const ScheduleOpts old = g->opts;
   g->opts.row_chunk = o->row_chunk;
@@ -1441,11 +1796,22 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   g->opts.hot_columns = o->hot_columns;
   g->opts.bank_schedule = o->bank_schedule;
   g->opts.block_threads = o->block_threads;
+  g->opts.schedule = o->schedule;
+  g->opts.term_chunk = o->term_chunk;
   try {
     make_forest(g);
+    make_remat(g);
   } catch (const std::bad_alloc&) {
     g->opts = old;
     return fail(ACE_ERR_OUT_OF_MEMORY, "host allocation failed while rebuilding the schedule");
+  }
+  if (o->schedule == ACE_SCHEDULE_FOREST && !g->forest_ok) {
+    g->opts.schedule = old.schedule;
+    return fail(ACE_ERR_UNSUPPORTED, "no forest schedule for this graph: " + g->forest_why);
+  }
+  if (o->schedule == ACE_SCHEDULE_REMAT && !g->remat_ok) {
+    g->opts.schedule = old.schedule;
+    return fail(ACE_ERR_UNSUPPORTED, "no remat schedule for this graph: " + g->remat_why);
   }
   if (g->on_device) {
     int dev = -1;
@@ -1458,11 +1824,36 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
 
 ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) {
   if (!g || !kind) return fail(ACE_ERR_INVALID_ARG, "graph and kind must be non-NULL");
-  *kind = g->forest_ok ? 1 : 0;
-  if (!g->forest_ok) g_error = g->forest_why;
+  Sched sc;
+  if (g->on_device) {
+    sc = pick_schedule(g, true, 0);
+  } else {
+    // host-only graph: what a device with 160 KiB of LDS per block would pick
+    const size_t lds = 160 * 1024;
+    const bool f = g->forest_ok && forest_lds_bytes(g, true, false) <= lds;
+    const bool r = g->remat_ok && remat_lds_bytes(g, true) <= lds;
+    const int want = g->opts.schedule;
+    if (want == ACE_SCHEDULE_LAYERED) sc = Sched::Layered;
+    else if (want == ACE_SCHEDULE_REMAT && r) sc = Sched::Remat;
+    else if (f) sc = Sched::Forest;
+    else if (r) sc = Sched::Remat;
+    else sc = Sched::Layered;
+  }
+  *kind = sc == Sched::Forest ? 1 : sc == Sched::Remat ? 2 : 0;
+  if (sc != Sched::Forest) g_error = g->forest_ok ? "forest schedule not selected" : g->forest_why;
   if (info) {
     for (int i = 0; i < 16; ++i) info[i] = 0;
-    if (g->forest_ok) {
+    if (sc == Sched::Remat) {
+      info[0] = g->P1 + 1;
+      info[1] = g->rm_nslices;
+      info[2] = (int64_t)g->rm_sib.size();
+      int64_t real = 0;
+      for (size_t i = g->rm_cs_term; i < g->rm_kmap.size(); ++i) real += g->rm_kmap[i] >= 0;
+      info[3] = real;
+      info[4] = g->rm_nitems;
+      for (int k = 0; k < 4; ++k) info[8 + k] = g->rm_hot[k];
+    }
+    if (sc == Sched::Forest) {
       info[0] = g->nslot;
       info[1] = g->n_tslices;
       info[2] = (int64_t)g->ch_s.size();
@@ -1526,6 +1917,16 @@ ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64
     }
     if (num > 1e-24 * (den + 1e-300)) return fail(ACE_ERR_INTERNAL, "forest adjoint modes disagree");
   }
+  return ACE_OK;
+}
+
+ace_status ace_debug_remat_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
+                                double* phi, double* Abar) {
+  if (!g || !coeffs || !A || !phi || !Abar || n_env < 0) return fail(ACE_ERR_INVALID_ARG, "NULL argument");
+  if (!g->remat_ok) return fail(ACE_ERR_UNSUPPORTED, "no remat schedule: " + g->remat_why);
+  for (int64_t e = 0; e < n_env; ++e)
+    if (!remat_emulate(g, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1))
+      return fail(ACE_ERR_INTERNAL, "remat schedule index out of range");
   return ACE_OK;
 }
 

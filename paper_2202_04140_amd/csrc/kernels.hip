@@ -7,6 +7,11 @@
 //                  and optionally the reverse pass giving dphi/dA   (Sec. 2.6)
 //   naive_kernel   phi = sum_k c_k prod_t A_{k_t} tuple by tuple     (Eq. (1.1))
 //   grad_kernel    d Re(phi)/d r_j = Re sum_i Abar_i grad(R_n Y_l^m)(r_j)
+//   forest_kernel  the DAG with one-particle and order-2 values resident in
+//                  LDS and the higher nodes walked in registers, forward
+//                  and reverse in one pass (the main schedule)
+//   remat_kernel   the DAG with only one-particle values resident and the
+//                  parents of every term recomputed (large DAGs)
 #include "ace_kernels.hpp"
 
 namespace ace {
@@ -741,6 +746,178 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
     __syncthreads();
   }
 }
+
+// ---------------------------------------------------------------------------
+// Rematerialising kernel, for DAGs whose resident set does not fit in LDS.
+//
+// Only the one-particle values A and adjoints Abar of one environment are
+// resident (LDS).  Every term c_k x_k, k in K, is still the product of the
+// two parents its DAG node names (Sec. 2.6), x_k = x_base * x_sib, but the
+// parents are recomputed from their one-particle factors instead of being
+// stored: the base (the parent of larger order) once per lane item, the
+// sibling per term.  An item holds up to term_chunk terms sharing a base:
+//   t = sum_j c_j x_sib_j,   phi += x_base t,   abar_base = t,
+// and the adjoint of every parent reaches its one-particle factors through
+// products of the other factors (prefix and suffix products).  Adjoint
+// contributions to the four hottest one-particle slots are summed in
+// registers and pushed once per wave; the rest are LDS atomics, so the
+// reverse pass is not bitwise deterministic (the forward pass is).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const int4& hot, double2& h0, double2& h1,
+                                         double2& h2, double2& h3) {
+  if (s == hot.x) {
+    h0.x += d.x;
+    h0.y += d.y;
+  } else if (s == hot.y) {
+    h1.x += d.x;
+    h1.y += d.y;
+  } else if (s == hot.z) {
+    h2.x += d.x;
+    h2.y += d.y;
+  } else if (s == hot.w) {
+    h3.x += d.x;
+    h3.y += d.y;
+  } else {
+    atomic_cadd(&ab[s], d);
+  }
+}
+
+template <bool GRAD, int SIG>
+__device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x, double2* ab, const int4& sl, int lane,
+                                           double2& acc, double2& h0, double2& h1, double2& h2, double2& h3) {
+  const int ONE = p.P1;
+  const int nb = sl.w & 0xff;
+  const int item = sl.x + lane;
+  const uint64_t blo = p.base_lo[item], bhi = p.base_hi[item];
+  auto bslot = [&](int i) { return (int)(((i < 4 ? blo : bhi) >> (16 * (i & 3))) & 0xffffu); };
+  // base value (its factors are read again for the adjoint at the end, so
+  // that they hold no registers during the term loop)
+  double2 xb = x[bslot(0)];
+#pragma unroll
+  for (int i = 1; i < 8; ++i)
+    if (i < nb) xb = cmul(xb, x[bslot(i)]);
+  const double* ct = p.cs + p.cs_term;
+  double2 t = make_double2(0.0, 0.0);
+  for (int j = 0; j < sl.z; ++j) {
+    const int pos = sl.y + j * 64 + lane;
+    const uint64_t sg = p.sib[pos];
+    const double c = ct[pos];
+    int ss[SIG];
+    double2 v[SIG];
+#pragma unroll
+    for (int u = 0; u < SIG; ++u) {
+      ss[u] = (int)((sg >> (16 * u)) & 0xffffu);
+      v[u] = x[ss[u]];
+    }
+    double2 xs = v[0];
+#pragma unroll
+    for (int u = 1; u < SIG; ++u) xs = cmul(xs, v[u]);
+    t = rfma(c, xs, t);
+    if (GRAD && c != 0.0) {
+      const double2 g = make_double2(c * xb.x, c * xb.y);
+      if (SIG == 1) {
+        push_hot(ab, ss[0], g, p.hot, h0, h1, h2, h3);
+      } else {
+        // d x_s / d x_u = prod of the other sibling factors
+        double2 sp[SIG];
+        double2 run = g;
+#pragma unroll
+        for (int u = 0; u < SIG; ++u) {
+          sp[u] = run;
+          run = cmul(run, v[u]);
+        }
+        run = make_double2(1.0, 0.0);
+#pragma unroll
+        for (int u = SIG - 1; u >= 0; --u) {
+          push_hot(ab, ss[u], u == SIG - 1 ? sp[u] : cmul(sp[u], run), p.hot, h0, h1, h2, h3);
+          run = u == SIG - 1 ? v[u] : cmul(run, v[u]);
+        }
+      }
+    }
+  }
+  acc = cfma(xb, t, acc);
+  if (GRAD && bslot(0) != ONE) {
+    // abar_base = t reaches factor i as t * prod_{j != i} x_j (prefix and suffix products)
+    double2 pre[8];
+    double2 run = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < nb) {
+        pre[i] = run;
+        run = i == 0 ? x[bslot(0)] : cmul(run, x[bslot(i)]);
+      }
+    double2 suf = t;
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+      if (i < nb) {
+        push_hot(ab, bslot(i), i == 0 ? suf : cmul(pre[i], suf), p.hot, h0, h1, h2, h3);
+        if (i > 0) suf = cmul(suf, x[bslot(i)]);
+      }
+    }
+  }
+}
+
+constexpr int kRematBlock = 512;
+
+template <bool GRAD>
+__global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
+  extern __shared__ double2 lds[];
+  const int P1 = p.P1;
+  const int ONE = P1;
+  double2* x = lds;             // [P1 + 1] one-particle values, constant one
+  double2* ab = lds + P1 + 1;   // [P1 + 1] one-particle adjoints (GRAD)
+  double2* red = ab + (GRAD ? P1 + 1 : 0);
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const double* cs = p.cs;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    const double2* Ae = p.A + e * P1;
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) {
+      x[i] = Ae[i];
+      if (GRAD) ab[i] = make_double2(cs[p.cs_leaf + i], 0.0);
+    }
+    if (threadIdx.x == 0) {
+      x[ONE] = make_double2(1.0, 0.0);
+      if (GRAD) ab[ONE] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) acc = rfma(cs[p.cs_leaf + i], x[i], acc);
+    double2 h0 = make_double2(0.0, 0.0), h1 = h0, h2 = h0, h3 = h0;
+    for (int s = wid; s < p.n_slices; s += nw) {
+      const int4 sl = p.slice[s];
+      switch (sl.w >> 8) {
+        case 1: remat_item<GRAD, 1>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 2: remat_item<GRAD, 2>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 3: remat_item<GRAD, 3>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        default: remat_item<GRAD, 4>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+      }
+    }
+    if (GRAD) {
+      h0 = wave_sum(h0);
+      h1 = wave_sum(h1);
+      h2 = wave_sum(h2);
+      h3 = wave_sum(h3);
+      if (lane == 0) {
+        if (p.hot.x != ONE) atomic_cadd(&ab[p.hot.x], h0);
+        if (p.hot.y != ONE) atomic_cadd(&ab[p.hot.y], h1);
+        if (p.hot.z != ONE) atomic_cadd(&ab[p.hot.z], h2);
+        if (p.hot.w != ONE) atomic_cadd(&ab[p.hot.w], h3);
+      }
+    }
+    const double2 phi = block_sum(acc, red);   // synchronises the block
+    if (threadIdx.x == 0) p.phi[e] = phi;
+    if (GRAD) {
+      double2* Be = p.Abar + e * P1;
+      for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
+    }
+    __syncthreads();
+  }
+}
+
+template __global__ void remat_kernel<false>(RematArgs);
+template __global__ void remat_kernel<true>(RematArgs);
 
 template __global__ void forest_kernel<false, false, false>(ForestArgs);
 template __global__ void forest_kernel<false, true, false>(ForestArgs);

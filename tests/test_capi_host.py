@@ -192,5 +192,42 @@ def test_forest_schedule_host_emulation_matches_oracle(spec, n_env):
 def test_schedule_kinds():
     assert ace.Graph(3, 8, 4, 4, host_only=True).schedule_kind() == "forest"
     assert ace.Graph(4, 12, 6, 6, host_only=True).schedule_kind() == "forest"
-    # order-6 products of two order-3 nodes have no resident parent
-    assert ace.Graph(6, 10, 3, 3, host_only=True).schedule_kind() in ("forest", "layered")
+    # order-6 products of two order-3 nodes have no resident parent: the
+    # forest does not apply and the remat schedule takes over
+    g = ace.Graph(6, 10, 3, 3, host_only=True)
+    assert g.schedule_kind() == "remat"
+    with pytest.raises(ace.AceError) as ei:
+        g.set_schedule(schedule="forest")
+    assert ei.value.status == 2 and b"two non-resident parents" in ace.lib().ace_last_error()
+    g.set_schedule(schedule="layered")
+    assert g.schedule_kind() == "layered"
+    g2 = ace.Graph(3, 8, 4, 4, host_only=True)
+    g2.set_schedule(schedule="remat", term_chunk=3)
+    assert g2.schedule_kind() == "remat" and g2.get_schedule()["term_chunk"] == 3
+    for bad in (dict(term_chunk=0), dict(term_chunk=257), dict(schedule=4)):
+        with pytest.raises(ace.AceError):
+            g2.set_schedule(**bad)
+
+
+# ---- remat schedule: host emulation of the kernel's exact index logic -------------
+@pytest.mark.parametrize("spec,alg,n,chunk", [((4, 4, 8, 3), 1, 1, 16), ((6, 6, 12, 4), 1, 1, 5),
+                                              ((6, 6, 12, 4), 2, 2, 16), ((3, 2, 9, 5), 1, 1, 1),
+                                              ((2, 2, 10, 6), 1, 1, 7), ((2, 2, 10, 6), 2, 3, 16),
+                                              ((2, 1, 8, 8), 1, 1, 4)])
+def test_remat_schedule_host_emulation_matches_oracle(spec, alg, n, chunk):
+    from oracle import contraction as oc
+    from oracle.indexsets import all_invariant_tuples
+    import workloads as wl
+    nmax, lmax, D, nu = spec
+    G = ace.Graph(nu, D, nmax, lmax, algorithm=alg, alg_n=n, host_only=True)
+    G.set_schedule(schedule="remat", term_chunk=chunk, hot_columns=2)
+    info = G.schedule_info()
+    assert info["kind"] == "remat" and info["term_real"] == G.stats()["n_k"] - G.stats()["n_k_by_order"][1]
+    g = group_o3(nmax, lmax, D)
+    K = all_invariant_tuples(g, nu, D)
+    c = np.random.default_rng(8).standard_normal(len(K))
+    A = wl.random_A(3, len(g), 23) * 0.5
+    phi, ab = G.remat_eval_host(c, A)
+    pr, ar = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+    assert np.linalg.norm(ab - ar) <= 1e-13 * np.linalg.norm(ar)

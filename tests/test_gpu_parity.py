@@ -45,18 +45,21 @@ def oracle_basis(wid):
     return _ORACLE[wid]
 
 
-def graph(wid, device):
+def graph(wid, device, schedule=None):
+    """The library graph of a workload (cached), optionally with a forced schedule."""
     import paper_2202_04140_amd as ace
-    if wid not in _GRAPH:
+    if (wid, schedule) not in _GRAPH:
         w = wl.WORKLOADS[wid]
         G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
+        if schedule is not None:
+            G.set_schedule(schedule=schedule)
         g, K, _ = oracle_basis(wid)
         kt = G.k_tuples()
         assert kt.shape[0] == len(K)
         for q in (0, len(K) // 3, len(K) - 1):
             assert tuple(x for x in kt[q] if x >= 0) == K[q]
-        _GRAPH[wid] = G
-    return _GRAPH[wid]
+        _GRAPH[(wid, schedule)] = G
+    return _GRAPH[(wid, schedule)]
 
 
 def to_dev(device, *arrs):
@@ -100,7 +103,9 @@ def test_basis_parity(device, wid, n_env):
 
 
 # ---- contraction alone, from random one-particle values ----------------------------
-MODES = {"dag": {}, "layered": {"layered": True}, "naive": {"naive": True}}
+# call flags and forced schedule of each evaluation mode
+MODES = {"dag": ({}, None), "remat": ({}, "remat"), "layered": ({"layered": True}, None),
+         "naive": ({"naive": True}, None)}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -108,18 +113,19 @@ MODES = {"dag": {}, "layered": {"layered": True}, "naive": {"naive": True}}
 def test_contract_random_A(device, wid, n_env, mode):
     import paper_2202_04140_amd as ace
     print(f"contract wid={wid} n_env={n_env} mode={mode}", flush=True)
-    G = graph(wid, device)
+    kw, sched = MODES[mode]
+    G = graph(wid, device, sched)
     g, K, c = oracle_basis(wid)
     A = wl.random_A(n_env, len(g), seed=100 + wid) * 0.5
     At = np.stack([A.real, A.imag], -1)
     tc, tA = to_dev(device, c, At)
-    phi, Ab = ace.contract(G, tc, tA, with_grad=True, **MODES[mode])
+    phi, Ab = ace.contract(G, tc, tA, with_grad=True, **kw)
     phi_ref = oc.phi_naive(K, c, A)
     ab_ref = oc.abar_naive(K, c, A)
     assert rel(cplx(phi), phi_ref) <= TOL_PHI
     assert rel(cplx(Ab), ab_ref) <= TOL_ABAR
     # forward-only launch gives the same phi
-    phi2 = ace.contract(G, tc, tA, with_grad=False, **MODES[mode])
+    phi2 = ace.contract(G, tc, tA, with_grad=False, **kw)
     assert rel(cplx(phi2), phi_ref) <= TOL_PHI
 
 
@@ -127,7 +133,8 @@ def test_schedule_in_use(device):
     assert graph(1, device).schedule_kind() == "forest"
     assert graph(3, device).schedule_kind() == "forest"
     assert graph(4, device).schedule_kind() == "forest"
-    assert graph(5, device).schedule_kind() == "layered"
+    assert graph(5, device).schedule_kind() == "remat"
+    assert graph(2, device, "remat").schedule_kind() == "remat"
 
 
 # ---- full path ---------------------------------------------------------------------
@@ -150,11 +157,12 @@ def test_eval_parity(device, wid, n_env, naive):
 def test_eval_grad_parity(device, wid, n_env, mode):
     import paper_2202_04140_amd as ace
     print(f"eval_grad wid={wid} n_env={n_env} mode={mode}", flush=True)
-    G = graph(wid, device)
+    kw, sched = MODES[mode]
+    G = graph(wid, device, sched)
     g, K, c = oracle_basis(wid)
     off, pos = problem(wid, n_env)
     tc, toff, tpos = to_dev(device, c, off, pos)
-    phi, grad = ace.eval_grad(G, tc, toff, tpos, **MODES[mode])
+    phi, grad = ace.eval_grad(G, tc, toff, tpos, **kw)
     phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
     assert rel(cplx(phi), phi_ref) <= TOL_PHI
     assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
