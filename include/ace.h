@@ -275,11 +275,15 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   tree slices, child positions (padded, real), pair-row slices, pair
  *   entries (padded, real), grandchildren, the four hot slots, whether all
  *   resident adjoints fit in LDS, the mean LDS bank cost of pair entries
- *   and of children (x1000).  Remat: LDS slots, slices, term positions
- *   (padded, real), items, 0, 0, 0, the four hot slots.  The rest are 0.
+ *   and of children (x1000).  Remat: LDS slots, then of the schedule with
+ *   the adjoint slices, entry positions (padded, real), items, then of the
+ *   forward-only schedule slices, entry positions (padded, real), the four
+ *   hot slots.  The rest are 0.
  *
- * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedule
- *   (ACE_ERR_UNSUPPORTED if the graph has none).
+ * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedules
+ *   (phi and Abar from the one with the adjoint; ACE_ERR_INTERNAL also if
+ *   the forward-only one gives another phi; ACE_ERR_UNSUPPORTED if the
+ *   graph has none).
  *
  * ace_debug_forest_eval: runs the forest schedule on the host for n_env
  *   environments, with the same indices, padding and forwarding as the

@@ -228,8 +228,8 @@ class Graph:
         info = np.zeros(16, dtype=np.int64)
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
         if k.value == 2:
-            names = ["nslot", "slices", "term_pos", "term_real", "items", "", "", "",
-                     "hot0", "hot1", "hot2", "hot3"]
+            names = ["nslot", "slices", "entry_pos", "entry_real", "items", "fwd_slices", "fwd_entry_pos",
+                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3"]
         else:
             names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
                      "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",

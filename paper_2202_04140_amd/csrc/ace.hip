@@ -122,18 +122,21 @@ struct ace_graph {
   int32_t* d_fw_off = nullptr;
   uint32_t* d_fw_ent = nullptr;
   bool forest_full = false;        // full-adjoint mode fits in LDS
-  // rematerialising schedule (remat_kernel); used when the forest is not
+  // rematerialising schedule (remat_kernel): [0] forward only (each term in
+  // one row), [1] with adjoint (each term in the rows of both parents)
   bool remat_ok = false;
   std::string remat_why;
-  int rm_nslices = 0, rm_nitems = 0, rm_cs_leaf = 0, rm_cs_term = 0;
-  int rm_hot[4] = {0, 0, 0, 0};
-  std::vector<int4> rm_slice;
-  std::vector<uint64_t> rm_blo, rm_bhi, rm_sib;
-  std::vector<int32_t> rm_kmap;
+  struct Remat {
+    int nslices = 0, nitems = 0, cs_leaf = 0, cs_ent = 0;
+    int hot[4] = {0, 0, 0, 0};
+    std::vector<int4> slice;
+    std::vector<uint64_t> rlo, rhi, olo, ohi;
+    std::vector<int32_t> kmap;
+    int4* d_slice = nullptr;
+    uint64_t *d_rlo = nullptr, *d_rhi = nullptr, *d_olo = nullptr, *d_ohi = nullptr;
+    int32_t* d_kmap = nullptr;
+  } rm[2];
   void* rmem = nullptr;
-  int4* d_rm_slice = nullptr;
-  uint64_t *d_rm_blo = nullptr, *d_rm_bhi = nullptr, *d_rm_sib = nullptr;
-  int32_t* d_rm_kmap = nullptr;
   bool remat_lds = false;          // the one-particle values and adjoints fit in LDS
 };
 
@@ -853,38 +856,137 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
 }
 
 // ---------------------------------------------------------------------------
-// Rematerialising schedule (remat_kernel).  Terms are the tuples of K of
-// length >= 2; a term is the product of the two parents of its DAG node.
-// The base of a term is the parent of larger order (on a tie, the parent
-// that can serve as base of more terms), the sibling the other one.  Terms
-// are grouped by (base, sibling length) and cut into items of at most
-// term_chunk terms; items of one (base length, sibling length) class are
-// sorted by term count and packed 64 to a slice, so every lane of a slice
-// runs the same loops.
+// Rematerialising schedule (remat_kernel).  A term is a tuple of K of length
+// >= 2, evaluated as the product of the two parents of its DAG node.  Rows
+// are keyed by a parent; the entries of a row are (other parent,
+// coefficient).  Forward only: a term sits in the row of its parent of
+// larger order (on a tie, the parent that can head more rows).  With the
+// adjoint: a term sits in the rows of both parents (a square once, with
+// coefficient 2c).  Entries of one (row, order of the other parent) are cut
+// into items of at most term_chunk; items of one (row order, other order)
+// class are sorted by entry count and packed 64 to a slice, so every lane
+// of a slice runs the same loops.
 // ---------------------------------------------------------------------------
-void make_remat(ace_graph* g) {
+namespace {
+struct REnt {
+  int32_t row, oth, kmap;
+};
+
+void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
   const HostGraph& h = g->h;
   const int P1 = h.P1, ONE = P1, W = h.width;
+  R.slice.clear();
+  R.rlo.clear();
+  R.rhi.clear();
+  R.olo.clear();
+  R.ohi.clear();
+  R.kmap.assign(P1, -1);
+  for (int i = 0; i < P1; ++i) R.kmap[i] = h.node_k[i];
+  R.cs_leaf = 0;
+  R.cs_ent = P1;
+  std::stable_sort(ents.begin(), ents.end(), [&](const REnt& x, const REnt& y) {
+    if (x.row != y.row) return x.row < y.row;
+    const int sx = h.node_len[x.oth], sy = h.node_len[y.oth];
+    if (sx != sy) return sx < sy;
+    return x.oth < y.oth;
+  });
+  struct Item {
+    int32_t row;
+    int nb, sig;
+    int64_t first;
+    int count;
+  };
+  std::vector<Item> items;
+  const int C = std::max(1, g->opts.term_chunk);
+  for (size_t i = 0; i < ents.size();) {
+    size_t j = i;
+    const int sig = h.node_len[ents[i].oth];
+    while (j < ents.size() && ents[j].row == ents[i].row && h.node_len[ents[j].oth] == sig) ++j;
+    for (size_t c0 = i; c0 < j; c0 += C)
+      items.push_back({ents[i].row, (int)h.node_len[ents[i].row], sig, (int64_t)c0, (int)std::min<size_t>(C, j - c0)});
+    i = j;
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+    if (x.nb != y.nb) return x.nb < y.nb;
+    if (x.sig != y.sig) return x.sig < y.sig;
+    return x.count > y.count;
+  });
+  // hot one-particle slots: the most frequent adjoint push targets
+  {
+    std::vector<int64_t> freq(P1 + 1, 0);
+    int64_t npush = 0;
+    for (const Item& it : items)
+      for (int u = 0; u < it.nb; ++u) {
+        freq[h.node_flat[(int64_t)it.row * W + u]] += 1;
+        ++npush;
+      }
+    std::vector<int32_t> ord(P1);
+    for (int i = 0; i < P1; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return freq[x] > freq[y]; });
+    for (int k = 0; k < 4; ++k)
+      R.hot[k] = (k < g->opts.hot_columns && k < P1 && freq[ord[k]] * 64 >= npush) ? ord[k] : ONE;
+  }
+  auto pack = [&](int32_t node, int from) {
+    const int count = h.node_len[node];
+    uint64_t w = 0;
+    for (int u = 0; u < 4; ++u) {
+      const int idx = from + u;
+      const uint64_t sl = idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + idx] : (uint64_t)ONE;
+      w |= sl << (16 * u);
+    }
+    return w;
+  };
+  const uint64_t ones = (uint64_t)ONE | ((uint64_t)ONE << 16) | ((uint64_t)ONE << 32) | ((uint64_t)ONE << 48);
+  int64_t pos = 0;
+  for (size_t i0 = 0; i0 < items.size();) {
+    size_t i1 = i0;
+    while (i1 < items.size() && i1 - i0 < 64 && items[i1].nb == items[i0].nb && items[i1].sig == items[i0].sig) ++i1;
+    const int ncol = items[i0].count;
+    if ((int64_t)R.rlo.size() + 64 > INT32_MAX || pos + 64LL * ncol > INT32_MAX)
+      throw std::length_error("remat schedule larger than 2^31 entries");
+    R.slice.push_back(make_int4((int)R.rlo.size(), (int)pos, ncol, items[i0].nb | (items[i0].sig << 8)));
+    const size_t e0 = R.olo.size();
+    R.olo.resize(e0 + 64 * (size_t)ncol, ones);
+    R.ohi.resize(e0 + 64 * (size_t)ncol, ones);
+    R.kmap.resize(P1 + e0 + 64 * (size_t)ncol, -1);
+    for (int lane = 0; lane < 64; ++lane) {
+      if (i0 + lane < i1) {
+        const Item& it = items[i0 + lane];
+        R.rlo.push_back(pack(it.row, 0));
+        R.rhi.push_back(pack(it.row, 4));
+        for (int j = 0; j < it.count; ++j) {
+          const REnt& t = ents[it.first + j];
+          const size_t e = e0 + (size_t)j * 64 + lane;
+          R.olo[e] = pack(t.oth, 0);
+          R.ohi[e] = pack(t.oth, 4);
+          R.kmap[P1 + e] = t.kmap;
+        }
+      } else {
+        R.rlo.push_back(ones);
+        R.rhi.push_back(ones);
+      }
+    }
+    pos += 64LL * ncol;
+    i0 = i1;
+  }
+  R.nslices = (int)R.slice.size();
+  R.nitems = (int)R.rlo.size();
+}
+}  // namespace
+
+void make_remat(ace_graph* g) {
+  const HostGraph& h = g->h;
+  const int P1 = h.P1;
   const int64_t V = h.n_nodes();
   g->remat_ok = false;
-  g->rm_slice.clear();
-  g->rm_blo.clear();
-  g->rm_bhi.clear();
-  g->rm_sib.clear();
-  g->rm_kmap.clear();
   if (P1 + 1 > 65535) {
     g->remat_why = "more than 65534 one-particle functions";
     return;
   }
-  if (W > 8) {
+  if (h.width > 8) {
     g->remat_why = "correlation order above 8";
     return;
   }
-  struct Term {
-    int32_t base, sib, k;
-  };
-  std::vector<Term> terms;
-  terms.reserve((size_t)h.nK);
   std::vector<int32_t> tie(V, 0);
   for (int64_t q = 0; q < h.nK; ++q) {
     if (h.k_len[q] < 2) continue;
@@ -895,190 +997,101 @@ void make_remat(ace_graph* g) {
       tie[b] += 1;
     }
   }
+  std::vector<REnt> one, two;
+  one.reserve((size_t)h.nK);
+  two.reserve(2 * (size_t)h.nK);
   for (int64_t q = 0; q < h.nK; ++q) {
     if (h.k_len[q] < 2) continue;
     const int64_t v = h.k_to_node[q];
     const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
     const int la = h.node_len[a], lb = h.node_len[b];
-    const bool a_base = la > lb || (la == lb && tie[a] >= tie[b]);
-    terms.push_back({a_base ? a : b, a_base ? b : a, (int32_t)q});
+    const bool a_row = la > lb || (la == lb && tie[a] >= tie[b]);
+    one.push_back({a_row ? a : b, a_row ? b : a, (int32_t)q});
+    if (a == b) {
+      two.push_back({a, a, -2 - (int32_t)q});   // M_aa = 2 c
+    } else {
+      two.push_back({a, b, (int32_t)q});
+      two.push_back({b, a, (int32_t)q});
+    }
   }
-  std::stable_sort(terms.begin(), terms.end(), [&](const Term& x, const Term& y) {
-    const int sx = h.node_len[x.sib], sy = h.node_len[y.sib];
-    if (x.base != y.base) return x.base < y.base;
-    if (sx != sy) return sx < sy;
-    return x.sib < y.sib;
-  });
-  // items: runs of one (base, sibling length), cut at term_chunk
-  struct Item {
-    int32_t base;
-    int nb, sig;
-    int64_t first;
-    int count;
-  };
-  std::vector<Item> items;
-  const int C = std::max(1, g->opts.term_chunk);
-  for (size_t i = 0; i < terms.size();) {
-    size_t j = i;
-    const int sig = h.node_len[terms[i].sib];
-    while (j < terms.size() && terms[j].base == terms[i].base && h.node_len[terms[j].sib] == sig) ++j;
-    for (size_t c0 = i; c0 < j; c0 += C)
-      items.push_back({terms[i].base, (int)h.node_len[terms[i].base], sig, (int64_t)c0, (int)std::min<size_t>(C, j - c0)});
-    i = j;
+  try {
+    pack_remat(g, one, g->rm[0]);
+    pack_remat(g, two, g->rm[1]);
+  } catch (const std::length_error& e) {
+    g->remat_why = e.what();
+    return;
   }
-  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
-    if (x.nb != y.nb) return x.nb < y.nb;
-    if (x.sig != y.sig) return x.sig < y.sig;
-    return x.count > y.count;
-  });
-  // hot one-particle slots: the most frequent adjoint push targets
-  std::vector<int64_t> freq(P1 + 1, 0);
-  int64_t npush = 0;
-  for (const Term& t : terms)
-    for (int u = 0; u < h.node_len[t.sib]; ++u) {
-      freq[h.node_flat[(int64_t)t.sib * W + u]] += 1;
-      ++npush;
-    }
-  for (const Item& it : items)
-    for (int u = 0; u < it.nb; ++u) {
-      freq[h.node_flat[(int64_t)it.base * W + u]] += 1;
-      ++npush;
-    }
-  {
-    std::vector<int32_t> ord(P1);
-    for (int i = 0; i < P1; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return freq[x] > freq[y]; });
-    for (int k = 0; k < 4; ++k)
-      g->rm_hot[k] = (k < g->opts.hot_columns && k < P1 && freq[ord[k]] * 64 >= npush) ? ord[k] : ONE;
-  }
-  // slices
-  auto pack = [&](int32_t node, int from, int count) {
-    uint64_t w = 0;
-    for (int u = 0; u < 4; ++u) {
-      const int idx = from + u;
-      const uint64_t sl = idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + idx] : (uint64_t)ONE;
-      w |= sl << (16 * u);
-    }
-    return w;
-  };
-  const uint64_t ones = (uint64_t)ONE | ((uint64_t)ONE << 16) | ((uint64_t)ONE << 32) | ((uint64_t)ONE << 48);
-  g->rm_kmap.assign(P1, -1);
-  for (int i = 0; i < P1; ++i) g->rm_kmap[i] = h.node_k[i];
-  g->rm_cs_leaf = 0;
-  g->rm_cs_term = P1;
-  int64_t pos = 0;
-  for (size_t i0 = 0; i0 < items.size();) {
-    size_t i1 = i0;
-    while (i1 < items.size() && i1 - i0 < 64 && items[i1].nb == items[i0].nb && items[i1].sig == items[i0].sig) ++i1;
-    const int ncol = items[i0].count;
-    if ((int64_t)g->rm_blo.size() + 64 > INT32_MAX || pos + 64LL * ncol > INT32_MAX) {
-      g->remat_why = "schedule larger than 2^31 entries";
-      return;
-    }
-    g->rm_slice.push_back(make_int4((int)g->rm_blo.size(), (int)pos, ncol, items[i0].nb | (items[i0].sig << 8)));
-    const size_t sib0 = g->rm_sib.size();
-    g->rm_sib.resize(sib0 + 64 * (size_t)ncol, ones);
-    g->rm_kmap.resize(P1 + sib0 + 64 * (size_t)ncol, -1);
-    for (int lane = 0; lane < 64; ++lane) {
-      if (i0 + lane < i1) {
-        const Item& it = items[i0 + lane];
-        g->rm_blo.push_back(pack(it.base, 0, it.nb));
-        g->rm_bhi.push_back(pack(it.base, 4, it.nb));
-        for (int j = 0; j < it.count; ++j) {
-          const Term& t = terms[it.first + j];
-          const size_t e = sib0 + (size_t)j * 64 + lane;
-          g->rm_sib[e] = pack(t.sib, 0, h.node_len[t.sib]);
-          g->rm_kmap[P1 + e] = t.k;
-        }
-      } else {
-        g->rm_blo.push_back(ones);
-        g->rm_bhi.push_back(ones);
-      }
-    }
-    pos += 64LL * ncol;
-    i0 = i1;
-  }
-  g->rm_nslices = (int)g->rm_slice.size();
-  g->rm_nitems = (int)g->rm_blo.size();
   g->remat_ok = true;
   g->remat_why.clear();
 }
 
-// Host run of the remat schedule for one environment, with the kernel's
-// indices, padding and push order; false if an index is out of range.
-bool remat_emulate(const ace_graph* g, const double* coeffs, const double* A, double* phi, double* Abar) {
+// Host run of a remat schedule for one environment (grad: the two-sided
+// one), with the kernel's indices, padding and push order; false if an
+// index is out of range.
+bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const double* A, double* phi, double* Abar) {
   using cd = std::complex<double>;
+  const ace_graph::Remat& R = g->rm[grad ? 1 : 0];
   const int P1 = g->P1, ONE = P1;
-  std::vector<double> cs(g->rm_kmap.size());
+  std::vector<double> cs(R.kmap.size());
   for (size_t i = 0; i < cs.size(); ++i) {
-    const int k = g->rm_kmap[i];
-    cs[i] = k >= 0 ? coeffs[k] : 0.0;
+    const int k = R.kmap[i];
+    cs[i] = k >= 0 ? coeffs[k] : (k == -1 ? 0.0 : 2.0 * coeffs[-2 - k]);
   }
   std::vector<cd> x(P1 + 1), ab(P1 + 1);
   for (int i = 0; i < P1; ++i) {
     x[i] = cd(A[2 * i], A[2 * i + 1]);
-    ab[i] = cs[g->rm_cs_leaf + i];
+    ab[i] = cs[R.cs_leaf + i];
   }
   x[ONE] = 1.0;
   cd acc = 0.0;
-  for (int i = 0; i < P1; ++i) acc += cs[g->rm_cs_leaf + i] * x[i];
+  for (int i = 0; i < P1; ++i) acc += cs[R.cs_leaf + i] * x[i];
   auto ok = [&](int v) { return v >= 0 && v <= P1; };
-  for (const int4& sl : g->rm_slice) {
+  auto slot = [](uint64_t lo, uint64_t hi, int i) { return (int)(((i < 4 ? lo : hi) >> (16 * (i & 3))) & 0xffffu); };
+  for (const int4& sl : R.slice) {
     const int nb = sl.w & 0xff, sig = sl.w >> 8;
-    if (nb < 1 || nb > 8 || sig < 1 || sig > 4) return false;
+    if (nb < 1 || nb > 8 || sig < 1 || sig > 7) return false;
     for (int lane = 0; lane < 64; ++lane) {
       const int item = sl.x + lane;
-      if (item < 0 || item >= g->rm_nitems) return false;
-      int bs[8];
-      cd xv[8], pre[8], xb = 1.0;
-      for (int i = 0; i < 8; ++i) {
-        bs[i] = (int)(((i < 4 ? g->rm_blo[item] : g->rm_bhi[item]) >> (16 * (i & 3))) & 0xffffu);
-        if (i < nb) {
-          if (!ok(bs[i])) return false;
-          xv[i] = x[bs[i]];
-          pre[i] = xb;
-          xb = i == 0 ? xv[0] : xb * xv[i];
-        }
+      if (item < 0 || item >= R.nitems) return false;
+      cd xb = 1.0;
+      for (int i = 0; i < nb; ++i) {
+        const int v = slot(R.rlo[item], R.rhi[item], i);
+        if (!ok(v)) return false;
+        xb = i == 0 ? x[v] : xb * x[v];
       }
-      cd t = 0.0;
+      cd y = 0.0;
       for (int j = 0; j < sl.z; ++j) {
         const int64_t pos = (int64_t)sl.y + (int64_t)j * 64 + lane;
-        if (pos < 0 || pos >= (int64_t)g->rm_sib.size()) return false;
-        const uint64_t sg = g->rm_sib[pos];
-        const double c = cs[g->rm_cs_term + pos];
-        int ss[4];
-        cd v[4], xs = 1.0;
+        if (pos < 0 || pos >= (int64_t)R.olo.size()) return false;
+        cd xo = 1.0;
         for (int u = 0; u < sig; ++u) {
-          ss[u] = (int)((sg >> (16 * u)) & 0xffffu);
-          if (!ok(ss[u])) return false;
-          v[u] = x[ss[u]];
-          xs = u == 0 ? v[0] : xs * v[u];
+          const int v = slot(R.olo[pos], R.ohi[pos], u);
+          if (!ok(v)) return false;
+          xo = u == 0 ? x[v] : xo * x[v];
         }
-        t += c * xs;
-        if (c != 0.0)
-          for (int u = 0; u < sig; ++u) {
-            cd d = c * xb;
-            for (int w = 0; w < sig; ++w)
-              if (w != u) d *= v[w];
-            ab[ss[u]] += d;
-          }
+        y += cs[R.cs_ent + pos] * xo;
       }
-      acc += xb * t;
-      if (bs[0] != ONE)
+      if (!grad) {
+        acc += xb * y;
+        continue;
+      }
+      acc += xb * (0.5 * y);
+      if (slot(R.rlo[item], R.rhi[item], 0) != ONE)
         for (int i = 0; i < nb; ++i) {
-          cd d = t;
+          cd d = y;
           for (int w = 0; w < nb; ++w)
-            if (w != i) d *= xv[w];
-          ab[bs[i]] += d;
+            if (w != i) d *= x[slot(R.rlo[item], R.rhi[item], w)];
+          ab[slot(R.rlo[item], R.rhi[item], i)] += d;
         }
     }
   }
   phi[0] = acc.real();
   phi[1] = acc.imag();
-  for (int i = 0; i < P1; ++i) {
-    Abar[2 * i] = ab[i].real();
-    Abar[2 * i + 1] = ab[i].imag();
-  }
+  if (Abar)
+    for (int i = 0; i < P1; ++i) {
+      Abar[2 * i] = ab[i].real();
+      Abar[2 * i + 1] = ab[i].imag();
+    }
   return true;
 }
 
@@ -1190,25 +1203,30 @@ ace_status upload_forest(ace_graph* g) {
   }
   g->remat_lds = false;
   if (g->remat_ok) {
-    size_t rb = align_up(g->rm_slice.size() * sizeof(int4)) + align_up(g->rm_blo.size() * 8) +
-                align_up(g->rm_bhi.size() * 8) + align_up(g->rm_sib.size() * 8) + align_up(g->rm_kmap.size() * 4) +
-                kAlign;
+    size_t rb = kAlign;
+    for (const auto& R : g->rm)
+      rb += align_up(R.slice.size() * sizeof(int4)) + align_up(R.rlo.size() * 8) + align_up(R.rhi.size() * 8) +
+            align_up(R.olo.size() * 8) + align_up(R.ohi.size() * 8) + align_up(R.kmap.size() * 4);
     if (hipMalloc(&g->rmem, rb) != hipSuccess) {
       g->rmem = nullptr;
       (void)hipGetLastError();
       return fail(ACE_ERR_OUT_OF_MEMORY, "hipMalloc of the remat schedule failed");
     }
     char* q = static_cast<char*>(g->rmem);
-    g->d_rm_slice = carve<int4>(q, g->rm_slice.size());
-    g->d_rm_blo = carve<uint64_t>(q, g->rm_blo.size());
-    g->d_rm_bhi = carve<uint64_t>(q, g->rm_bhi.size());
-    g->d_rm_sib = carve<uint64_t>(q, g->rm_sib.size());
-    g->d_rm_kmap = carve<int32_t>(q, g->rm_kmap.size());
-    ACE_HIP(put(g->d_rm_slice, g->rm_slice.data(), g->rm_slice.size() * sizeof(int4)));
-    ACE_HIP(put(g->d_rm_blo, g->rm_blo.data(), g->rm_blo.size() * 8));
-    ACE_HIP(put(g->d_rm_bhi, g->rm_bhi.data(), g->rm_bhi.size() * 8));
-    ACE_HIP(put(g->d_rm_sib, g->rm_sib.data(), g->rm_sib.size() * 8));
-    ACE_HIP(put(g->d_rm_kmap, g->rm_kmap.data(), g->rm_kmap.size() * 4));
+    for (auto& R : g->rm) {
+      R.d_slice = carve<int4>(q, R.slice.size());
+      R.d_rlo = carve<uint64_t>(q, R.rlo.size());
+      R.d_rhi = carve<uint64_t>(q, R.rhi.size());
+      R.d_olo = carve<uint64_t>(q, R.olo.size());
+      R.d_ohi = carve<uint64_t>(q, R.ohi.size());
+      R.d_kmap = carve<int32_t>(q, R.kmap.size());
+      ACE_HIP(put(R.d_slice, R.slice.data(), R.slice.size() * sizeof(int4)));
+      ACE_HIP(put(R.d_rlo, R.rlo.data(), R.rlo.size() * 8));
+      ACE_HIP(put(R.d_rhi, R.rhi.data(), R.rhi.size() * 8));
+      ACE_HIP(put(R.d_olo, R.olo.data(), R.olo.size() * 8));
+      ACE_HIP(put(R.d_ohi, R.ohi.data(), R.ohi.size() * 8));
+      ACE_HIP(put(R.d_kmap, R.kmap.data(), R.kmap.size() * 4));
+    }
     g->remat_lds = remat_lds_bytes(g, true) <= g->max_lds;
     ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
     ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
@@ -1345,7 +1363,8 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char
   const size_t arena = (size_t)arena_blocks(n_env) * g->slots * sizeof(double2);
   if (layered && (!g->fwd_xl || !g->grad_xl)) w.arena_x = take(arena);
   if (layered && !g->grad_al) w.arena_ab = take(arena);
-  const size_t ncs = std::max(g->forest_ok ? g->kmap.size() : 0, g->remat_ok ? g->rm_kmap.size() : 0);
+  const size_t ncs = std::max({g->forest_ok ? g->kmap.size() : (size_t)0, g->remat_ok ? g->rm[0].kmap.size() : (size_t)0,
+                               g->remat_ok ? g->rm[1].kmap.size() : (size_t)0});
   if (ncs) w.cs = reinterpret_cast<double*>(take(ncs * sizeof(double)));
   w.bytes = off;
   return w;
@@ -1449,11 +1468,13 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
 
 ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
                         double2* Abar, const Workspace& w, hipStream_t s) {
+  const bool grad = Abar != nullptr;
+  const ace_graph::Remat& R = g->rm[grad ? 1 : 0];
   PrepArgs pa{};
-  pa.kmap = g->d_rm_kmap;
+  pa.kmap = R.d_kmap;
   pa.coeffs = coeffs;
   pa.cs = w.cs;
-  pa.n = (int64_t)g->rm_kmap.size();
+  pa.n = (int64_t)R.kmap.size();
   const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((pa.n + 255) / 256, 1024));
   hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
   ACE_HIP(hipGetLastError());
@@ -1463,16 +1484,16 @@ ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env,
   a.phi = phi;
   a.Abar = Abar;
   a.cs = w.cs;
-  a.slice = g->d_rm_slice;
-  a.base_lo = g->d_rm_blo;
-  a.base_hi = g->d_rm_bhi;
-  a.sib = g->d_rm_sib;
-  a.cs_leaf = g->rm_cs_leaf;
-  a.cs_term = g->rm_cs_term;
+  a.slice = R.d_slice;
+  a.row_lo = R.d_rlo;
+  a.row_hi = R.d_rhi;
+  a.oth_lo = R.d_olo;
+  a.oth_hi = R.d_ohi;
+  a.cs_leaf = R.cs_leaf;
+  a.cs_ent = R.cs_ent;
   a.P1 = g->P1;
-  a.n_slices = g->rm_nslices;
-  a.hot = make_int4(g->rm_hot[0], g->rm_hot[1], g->rm_hot[2], g->rm_hot[3]);
-  const bool grad = Abar != nullptr;
+  a.n_slices = R.nslices;
+  a.hot = make_int4(R.hot[0], R.hot[1], R.hot[2], R.hot[3]);
   const size_t lds = remat_lds_bytes(g, grad);
   const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
   if (grad)
@@ -1844,14 +1865,20 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
   if (info) {
     for (int i = 0; i < 16; ++i) info[i] = 0;
     if (sc == Sched::Remat) {
+      const ace_graph::Remat& R = g->rm[1];
       info[0] = g->P1 + 1;
-      info[1] = g->rm_nslices;
-      info[2] = (int64_t)g->rm_sib.size();
+      info[1] = R.nslices;
+      info[2] = (int64_t)R.olo.size();
       int64_t real = 0;
-      for (size_t i = g->rm_cs_term; i < g->rm_kmap.size(); ++i) real += g->rm_kmap[i] >= 0;
+      for (size_t i = R.cs_ent; i < R.kmap.size(); ++i) real += R.kmap[i] != -1;
       info[3] = real;
-      info[4] = g->rm_nitems;
-      for (int k = 0; k < 4; ++k) info[8 + k] = g->rm_hot[k];
+      info[4] = R.nitems;
+      info[5] = g->rm[0].nslices;
+      info[6] = (int64_t)g->rm[0].olo.size();
+      int64_t real0 = 0;
+      for (size_t i = g->rm[0].cs_ent; i < g->rm[0].kmap.size(); ++i) real0 += g->rm[0].kmap[i] != -1;
+      info[7] = real0;
+      for (int k = 0; k < 4; ++k) info[8 + k] = R.hot[k];
     }
     if (sc == Sched::Forest) {
       info[0] = g->nslot;
@@ -1924,9 +1951,15 @@ ace_status ace_debug_remat_eval(const ace_graph* g, const double* coeffs, int64_
                                 double* phi, double* Abar) {
   if (!g || !coeffs || !A || !phi || !Abar || n_env < 0) return fail(ACE_ERR_INVALID_ARG, "NULL argument");
   if (!g->remat_ok) return fail(ACE_ERR_UNSUPPORTED, "no remat schedule: " + g->remat_why);
-  for (int64_t e = 0; e < n_env; ++e)
-    if (!remat_emulate(g, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1))
+  double phi1[2];
+  for (int64_t e = 0; e < n_env; ++e) {
+    // both schedules; their phi must agree
+    if (!remat_emulate(g, true, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1) ||
+        !remat_emulate(g, false, coeffs, A + 2 * e * g->P1, phi1, nullptr))
       return fail(ACE_ERR_INTERNAL, "remat schedule index out of range");
+    const double d = std::hypot(phi1[0] - phi[2 * e], phi1[1] - phi[2 * e + 1]);
+    if (d > 1e-10 * (std::hypot(phi1[0], phi1[1]) + 1e-300)) return fail(ACE_ERR_INTERNAL, "remat schedules disagree");
+  }
   return ACE_OK;
 }
 

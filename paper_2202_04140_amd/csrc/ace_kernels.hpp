@@ -111,19 +111,20 @@ struct ForestArgs {
 };
 
 // Rematerialising schedule (see remat_kernel).  LDS slots: one-particle
-// nodes 0..P1-1 and a constant-one slot P1 (padding).  Leaf lists are
-// packed 16 bits per slot, unused fields hold P1.
+// nodes 0..P1-1 and a constant-one slot P1 (padding).  Factor lists are
+// packed 16 bits per slot, four to a 64-bit word; unused fields hold P1.
 struct RematArgs {
   int64_t n_env;
   const double2* A;          // [n_env][P1]
   double2* phi;              // [n_env]
   double2* Abar;             // [n_env][P1], or nullptr for the forward pass only
   const double* cs;          // prepared coefficients
-  const int4* slice;         // [n_slices] {first item, first term position, terms per item, nb | sigma << 8}
-  const uint64_t* base_lo;   // [n_items] base one-particle slots 0..3
-  const uint64_t* base_hi;   // [n_items] base one-particle slots 4..7
-  const uint64_t* sib;       // term positions, 64-interleaved per slice: sibling one-particle slots
-  int cs_leaf, cs_term;
+  const int4* slice;         // [n_slices] {first item, first entry, entries per item, nrow | nother << 8}
+  const uint64_t* row_lo;    // [n_items] row factors 0..3
+  const uint64_t* row_hi;    // [n_items] row factors 4..7
+  const uint64_t* oth_lo;    // entries, 64-interleaved per slice: factors 0..3 of the other parent
+  const uint64_t* oth_hi;    // entries: factors 4..7 (read only when the other parent has more than 4)
+  int cs_leaf, cs_ent;
   int P1, n_slices;
   int4 hot;                  // one-particle slots whose adjoints are summed in registers (P1 = unused)
 };

@@ -752,16 +752,22 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
 //
 // Only the one-particle values A and adjoints Abar of one environment are
 // resident (LDS).  Every term c_k x_k, k in K, is still the product of the
-// two parents its DAG node names (Sec. 2.6), x_k = x_base * x_sib, but the
-// parents are recomputed from their one-particle factors instead of being
-// stored: the base (the parent of larger order) once per lane item, the
-// sibling per term.  An item holds up to term_chunk terms sharing a base:
-//   t = sum_j c_j x_sib_j,   phi += x_base t,   abar_base = t,
-// and the adjoint of every parent reaches its one-particle factors through
-// products of the other factors (prefix and suffix products).  Adjoint
-// contributions to the four hottest one-particle slots are summed in
-// registers and pushed once per wave; the rest are LDS atomics, so the
-// reverse pass is not bitwise deterministic (the forward pass is).
+// two parents its DAG node names (Sec. 2.6), but the parents are recomputed
+// from their one-particle factors instead of being stored.  Terms are
+// grouped into rows keyed by a parent p ("row"); a lane item is a chunk of
+// one row, y = sum_j M_j x_other_j, with every other parent of the chunk of
+// the same order.
+//   forward only: each term sits in the row of one parent, M = c, and
+//                 phi += x_p y;
+//   with adjoint: the terms form the symmetric matrix M over parents
+//                 (M_pq = M_qp = c, M_pp = 2c), each term sits in the rows
+//                 of both parents, phi += x_p y / 2 and abar_p = y exactly,
+//                 so no adjoint is scattered per term.
+// abar_p reaches the one-particle factors of p as y prod_{j != i} x_j
+// (prefix and suffix products): one push per factor and item, with the
+// four hottest one-particle slots summed in registers and pushed once per
+// wave.  The rest are LDS atomics, so the reverse pass is not bitwise
+// deterministic (the forward pass is).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const int4& hot, double2& h0, double2& h1,
                                          double2& h2, double2& h3) {
@@ -782,76 +788,55 @@ __device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const in
   }
 }
 
+__device__ __forceinline__ int slot16(uint64_t lo, uint64_t hi, int i) {
+  return (int)(((i < 4 ? lo : hi) >> (16 * (i & 3))) & 0xffffu);
+}
+
 template <bool GRAD, int SIG>
 __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x, double2* ab, const int4& sl, int lane,
                                            double2& acc, double2& h0, double2& h1, double2& h2, double2& h3) {
   const int ONE = p.P1;
   const int nb = sl.w & 0xff;
   const int item = sl.x + lane;
-  const uint64_t blo = p.base_lo[item], bhi = p.base_hi[item];
-  auto bslot = [&](int i) { return (int)(((i < 4 ? blo : bhi) >> (16 * (i & 3))) & 0xffffu); };
-  // base value (its factors are read again for the adjoint at the end, so
-  // that they hold no registers during the term loop)
-  double2 xb = x[bslot(0)];
+  const uint64_t blo = p.row_lo[item], bhi = p.row_hi[item];
+  // row value (its factors are read again for the adjoint at the end, so
+  // that they hold no registers during the entry loop)
+  double2 xb = x[slot16(blo, bhi, 0)];
 #pragma unroll
   for (int i = 1; i < 8; ++i)
-    if (i < nb) xb = cmul(xb, x[bslot(i)]);
-  const double* ct = p.cs + p.cs_term;
-  double2 t = make_double2(0.0, 0.0);
+    if (i < nb) xb = cmul(xb, x[slot16(blo, bhi, i)]);
+  const double* ce = p.cs + p.cs_ent;
+  double2 y = make_double2(0.0, 0.0);
   for (int j = 0; j < sl.z; ++j) {
     const int pos = sl.y + j * 64 + lane;
-    const uint64_t sg = p.sib[pos];
-    const double c = ct[pos];
-    int ss[SIG];
-    double2 v[SIG];
+    const uint64_t olo = p.oth_lo[pos];
+    const uint64_t ohi = SIG > 4 ? p.oth_hi[pos] : 0;
+    const double c = ce[pos];
+    double2 xo = x[slot16(olo, ohi, 0)];
 #pragma unroll
-    for (int u = 0; u < SIG; ++u) {
-      ss[u] = (int)((sg >> (16 * u)) & 0xffffu);
-      v[u] = x[ss[u]];
-    }
-    double2 xs = v[0];
-#pragma unroll
-    for (int u = 1; u < SIG; ++u) xs = cmul(xs, v[u]);
-    t = rfma(c, xs, t);
-    if (GRAD && c != 0.0) {
-      const double2 g = make_double2(c * xb.x, c * xb.y);
-      if (SIG == 1) {
-        push_hot(ab, ss[0], g, p.hot, h0, h1, h2, h3);
-      } else {
-        // d x_s / d x_u = prod of the other sibling factors
-        double2 sp[SIG];
-        double2 run = g;
-#pragma unroll
-        for (int u = 0; u < SIG; ++u) {
-          sp[u] = run;
-          run = cmul(run, v[u]);
-        }
-        run = make_double2(1.0, 0.0);
-#pragma unroll
-        for (int u = SIG - 1; u >= 0; --u) {
-          push_hot(ab, ss[u], u == SIG - 1 ? sp[u] : cmul(sp[u], run), p.hot, h0, h1, h2, h3);
-          run = u == SIG - 1 ? v[u] : cmul(run, v[u]);
-        }
-      }
-    }
+    for (int u = 1; u < SIG; ++u) xo = cmul(xo, x[slot16(olo, ohi, u)]);
+    y = rfma(c, xo, y);
   }
-  acc = cfma(xb, t, acc);
-  if (GRAD && bslot(0) != ONE) {
-    // abar_base = t reaches factor i as t * prod_{j != i} x_j (prefix and suffix products)
+  if (!GRAD) {
+    acc = cfma(xb, y, acc);
+    return;
+  }
+  acc = cfma(xb, make_double2(0.5 * y.x, 0.5 * y.y), acc);
+  if (slot16(blo, bhi, 0) != ONE) {
     double2 pre[8];
     double2 run = make_double2(1.0, 0.0);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       if (i < nb) {
         pre[i] = run;
-        run = i == 0 ? x[bslot(0)] : cmul(run, x[bslot(i)]);
+        run = i == 0 ? x[slot16(blo, bhi, 0)] : cmul(run, x[slot16(blo, bhi, i)]);
       }
-    double2 suf = t;
+    double2 suf = y;
 #pragma unroll
     for (int i = 7; i >= 0; --i) {
       if (i < nb) {
-        push_hot(ab, bslot(i), i == 0 ? suf : cmul(pre[i], suf), p.hot, h0, h1, h2, h3);
-        if (i > 0) suf = cmul(suf, x[bslot(i)]);
+        push_hot(ab, slot16(blo, bhi, i), i == 0 ? suf : cmul(pre[i], suf), p.hot, h0, h1, h2, h3);
+        if (i > 0) suf = cmul(suf, x[slot16(blo, bhi, i)]);
       }
     }
   }
@@ -891,7 +876,10 @@ __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
         case 1: remat_item<GRAD, 1>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
         case 2: remat_item<GRAD, 2>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
         case 3: remat_item<GRAD, 3>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        default: remat_item<GRAD, 4>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 4: remat_item<GRAD, 4>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 5: remat_item<GRAD, 5>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 6: remat_item<GRAD, 6>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        default: remat_item<GRAD, 7>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
       }
     }
     if (GRAD) {
