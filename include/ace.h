@@ -153,6 +153,9 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *                  schedule.
  *   term_chunk     remat schedule: terms sharing a base handled per lane
  *                  item, 1..256
+ *   pair_slots     remat schedule: products of two one-particle values
+ *                  precomputed in LDS per environment and used as factors,
+ *                  0..8192 (the most frequent pairs are taken)
  * hot_columns also sets the number of one-particle slots whose adjoints
  * the remat kernel sums in registers.
  */
@@ -169,7 +172,7 @@ typedef struct ace_schedule_opts {
   int32_t block_threads;
   int32_t schedule;
   int32_t term_chunk;
-  int32_t reserved;
+  int32_t pair_slots;
 } ace_schedule_opts;
 
 /* Current schedule options of a graph (host). */
@@ -275,10 +278,11 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   tree slices, child positions (padded, real), pair-row slices, pair
  *   entries (padded, real), grandchildren, the four hot slots, whether all
  *   resident adjoints fit in LDS, the mean LDS bank cost of pair entries
- *   and of children (x1000).  Remat: LDS slots, then of the schedule with
- *   the adjoint slices, entry positions (padded, real), items, then of the
- *   forward-only schedule slices, entry positions (padded, real), the four
- *   hot slots.  The rest are 0.
+ *   and of children (x1000).  Remat: LDS value slots, then of the schedule
+ *   with the adjoint slices, entry positions (padded, real), items, then of
+ *   the forward-only schedule slices, entry positions (padded, real), the
+ *   four hot slots, the pair slots of the schedule with the adjoint.  The
+ *   rest are 0.
  *
  * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedules
  *   (phi and Abar from the one with the adjoint; ACE_ERR_INTERNAL also if

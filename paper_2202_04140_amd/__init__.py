@@ -60,7 +60,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("row_chunk", ctypes.c_int32), ("tree_chunk", ctypes.c_int32),
                 ("hot_columns", ctypes.c_int32), ("bank_schedule", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("term_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("term_chunk", ctypes.c_int32), ("pair_slots", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -196,7 +196,7 @@ class Graph:
         return d.sum(axis=1)
 
     SCHEDULE_KEYS = ("row_chunk", "tree_chunk", "hot_columns", "bank_schedule", "block_threads",
-                     "schedule", "term_chunk")
+                     "schedule", "term_chunk", "pair_slots")
 
     def get_schedule(self) -> dict:
         """Schedule options (ace_graph_get_schedule); "schedule" is a name of SCHEDULES."""
@@ -229,7 +229,7 @@ class Graph:
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
         if k.value == 2:
             names = ["nslot", "slices", "entry_pos", "entry_real", "items", "fwd_slices", "fwd_entry_pos",
-                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3"]
+                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3", "pairs"]
         else:
             names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
                      "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",

@@ -64,6 +64,7 @@ struct ScheduleOpts {
   int block_threads = 512; // forest / remat kernel block size
   int schedule = 0;        // ACE_SCHEDULE_*
   int term_chunk = 16;     // remat: terms per lane item at most
+  int pair_slots = 2048;   // remat: precomputed one-particle pair products at most
 };
 
 struct ace_graph {
@@ -132,9 +133,11 @@ struct ace_graph {
     std::vector<int4> slice;
     std::vector<uint64_t> rlo, rhi, olo, ohi;
     std::vector<int32_t> kmap;
+    std::vector<uint32_t> pairs;   // pair products: one-particle slots a | b << 16
     int4* d_slice = nullptr;
     uint64_t *d_rlo = nullptr, *d_rhi = nullptr, *d_olo = nullptr, *d_ohi = nullptr;
     int32_t* d_kmap = nullptr;
+    uint32_t* d_pairs = nullptr;
   } rm[2];
   void* rmem = nullptr;
   bool remat_lds = false;          // the one-particle values and adjoints fit in LDS
@@ -872,9 +875,83 @@ struct REnt {
   int32_t row, oth, kmap;
 };
 
+// Factor lists of the other parents: the most frequent pairs of one-particle
+// factors (counted over all entries) become pair slots P1 + 1 + r; each
+// other parent takes disjoint pairs greedily over its sorted factors.
+struct Factors {
+  std::vector<int8_t> n;     // [V] factor count, -1 if the node is no other parent
+  std::vector<uint64_t> lo, hi;
+};
+
+void compress_others(const HostGraph& h, const std::vector<REnt>& ents, int budget, ace_graph::Remat& R,
+                     Factors& F) {
+  const int P1 = h.P1, ONE = P1, W = h.width;
+  const int64_t V = h.n_nodes();
+  std::vector<int32_t> mult(V, 0);
+  for (const REnt& e : ents) mult[e.oth] += 1;
+  R.pairs.clear();
+  std::vector<int32_t> pslot;
+  if (budget > 0 && P1 <= 4096) {
+    std::vector<int64_t> cnt((size_t)P1 * P1, 0);
+    for (int64_t v = 0; v < V; ++v) {
+      if (!mult[v] || h.node_len[v] < 2) continue;
+      const int32_t* f = &h.node_flat[(size_t)v * W];
+      const int L = h.node_len[v];
+      for (int i = 0; i < L; ++i)
+        for (int j = i + 1; j < L; ++j) cnt[(size_t)f[i] * P1 + f[j]] += mult[v];   // tuples are sorted
+    }
+    std::vector<int32_t> idx;
+    for (size_t q = 0; q < cnt.size(); ++q)
+      if (cnt[q] > 0) idx.push_back((int32_t)q);
+    const size_t take = std::min<size_t>((size_t)budget, idx.size());
+    std::partial_sort(idx.begin(), idx.begin() + take, idx.end(), [&](int32_t x, int32_t y) {
+      return cnt[x] != cnt[y] ? cnt[x] > cnt[y] : x < y;
+    });
+    idx.resize(take);
+    std::sort(idx.begin(), idx.end());
+    pslot.assign((size_t)P1 * P1, -1);
+    for (size_t r = 0; r < idx.size(); ++r) {
+      pslot[idx[r]] = ONE + 1 + (int32_t)r;
+      R.pairs.push_back((uint32_t)(idx[r] / P1) | ((uint32_t)(idx[r] % P1) << 16));
+    }
+  }
+  F.n.assign(V, -1);
+  F.lo.assign(V, 0);
+  F.hi.assign(V, 0);
+  for (int64_t v = 0; v < V; ++v) {
+    if (!mult[v]) continue;
+    const int32_t* f = &h.node_flat[(size_t)v * W];
+    const int L = h.node_len[v];
+    int out[8], no = 0;
+    bool used[8] = {false, false, false, false, false, false, false, false};
+    if (!pslot.empty())
+      for (int i = 0; i < L; ++i) {
+        if (used[i]) continue;
+        for (int j = i + 1; j < L; ++j)
+          if (!used[j] && pslot[(size_t)f[i] * P1 + f[j]] >= 0) {
+            used[i] = used[j] = true;
+            out[no++] = pslot[(size_t)f[i] * P1 + f[j]];
+            break;
+          }
+      }
+    for (int i = 0; i < L; ++i)
+      if (!used[i]) out[no++] = f[i];
+    uint64_t lo = 0, hi = 0;
+    for (int u = 0; u < 8; ++u) {
+      const uint64_t sl = u < no ? (uint64_t)out[u] : (uint64_t)ONE;
+      (u < 4 ? lo : hi) |= sl << (16 * (u & 3));
+    }
+    F.n[v] = (int8_t)no;
+    F.lo[v] = lo;
+    F.hi[v] = hi;
+  }
+}
+
 void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
   const HostGraph& h = g->h;
   const int P1 = h.P1, ONE = P1, W = h.width;
+  Factors F;
+  compress_others(h, ents, std::max(0, std::min(g->opts.pair_slots, 65534 - P1 - 1)), R, F);
   R.slice.clear();
   R.rlo.clear();
   R.rhi.clear();
@@ -886,7 +963,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
   R.cs_ent = P1;
   std::stable_sort(ents.begin(), ents.end(), [&](const REnt& x, const REnt& y) {
     if (x.row != y.row) return x.row < y.row;
-    const int sx = h.node_len[x.oth], sy = h.node_len[y.oth];
+    const int sx = F.n[x.oth], sy = F.n[y.oth];
     if (sx != sy) return sx < sy;
     return x.oth < y.oth;
   });
@@ -900,8 +977,8 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
   const int C = std::max(1, g->opts.term_chunk);
   for (size_t i = 0; i < ents.size();) {
     size_t j = i;
-    const int sig = h.node_len[ents[i].oth];
-    while (j < ents.size() && ents[j].row == ents[i].row && h.node_len[ents[j].oth] == sig) ++j;
+    const int sig = F.n[ents[i].oth];
+    while (j < ents.size() && ents[j].row == ents[i].row && F.n[ents[j].oth] == sig) ++j;
     for (size_t c0 = i; c0 < j; c0 += C)
       items.push_back({ents[i].row, (int)h.node_len[ents[i].row], sig, (int64_t)c0, (int)std::min<size_t>(C, j - c0)});
     i = j;
@@ -957,8 +1034,8 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
         for (int j = 0; j < it.count; ++j) {
           const REnt& t = ents[it.first + j];
           const size_t e = e0 + (size_t)j * 64 + lane;
-          R.olo[e] = pack(t.oth, 0);
-          R.ohi[e] = pack(t.oth, 4);
+          R.olo[e] = F.lo[t.oth];
+          R.ohi[e] = F.hi[t.oth];
           R.kmap[P1 + e] = t.kmap;
         }
       } else {
@@ -1037,15 +1114,22 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
     const int k = R.kmap[i];
     cs[i] = k >= 0 ? coeffs[k] : (k == -1 ? 0.0 : 2.0 * coeffs[-2 - k]);
   }
-  std::vector<cd> x(P1 + 1), ab(P1 + 1);
+  const int NP = (int)R.pairs.size();
+  std::vector<cd> x(P1 + 1 + NP), ab(P1 + 1);
   for (int i = 0; i < P1; ++i) {
     x[i] = cd(A[2 * i], A[2 * i + 1]);
     ab[i] = cs[R.cs_leaf + i];
   }
   x[ONE] = 1.0;
+  for (int r = 0; r < NP; ++r) {
+    const int a = (int)(R.pairs[r] & 0xffffu), b = (int)(R.pairs[r] >> 16);
+    if (a >= P1 || b >= P1) return false;
+    x[ONE + 1 + r] = x[a] * x[b];
+  }
   cd acc = 0.0;
   for (int i = 0; i < P1; ++i) acc += cs[R.cs_leaf + i] * x[i];
-  auto ok = [&](int v) { return v >= 0 && v <= P1; };
+  auto ok = [&](int v) { return v >= 0 && v <= P1 + NP; };
+  auto okrow = [&](int v) { return v >= 0 && v <= P1; };
   auto slot = [](uint64_t lo, uint64_t hi, int i) { return (int)(((i < 4 ? lo : hi) >> (16 * (i & 3))) & 0xffffu); };
   for (const int4& sl : R.slice) {
     const int nb = sl.w & 0xff, sig = sl.w >> 8;
@@ -1056,7 +1140,7 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
       cd xb = 1.0;
       for (int i = 0; i < nb; ++i) {
         const int v = slot(R.rlo[item], R.rhi[item], i);
-        if (!ok(v)) return false;
+        if (!okrow(v)) return false;
         xb = i == 0 ? x[v] : xb * x[v];
       }
       cd y = 0.0;
@@ -1139,7 +1223,8 @@ T* carve(char*& p, size_t n) {
 
 // LDS of remat_kernel: one-particle values and adjoints, reduction scratch.
 size_t remat_lds_bytes(const ace_graph* g, bool grad) {
-  return (size_t)(g->P1 + 1) * 16 * (grad ? 2 : 1) + (kRematBlock / 64) * sizeof(double2);
+  const size_t np = g->rm[grad ? 1 : 0].pairs.size();
+  return (size_t)(g->P1 + 1 + np) * 16 + (grad ? (size_t)(g->P1 + 1) * 16 : 0) + (kRematBlock / 64) * sizeof(double2);
 }
 
 // Upload the forest and remat schedules (replacing previous ones) and plan
@@ -1206,7 +1291,8 @@ ace_status upload_forest(ace_graph* g) {
     size_t rb = kAlign;
     for (const auto& R : g->rm)
       rb += align_up(R.slice.size() * sizeof(int4)) + align_up(R.rlo.size() * 8) + align_up(R.rhi.size() * 8) +
-            align_up(R.olo.size() * 8) + align_up(R.ohi.size() * 8) + align_up(R.kmap.size() * 4);
+            align_up(R.olo.size() * 8) + align_up(R.ohi.size() * 8) + align_up(R.kmap.size() * 4) +
+            align_up(R.pairs.size() * 4);
     if (hipMalloc(&g->rmem, rb) != hipSuccess) {
       g->rmem = nullptr;
       (void)hipGetLastError();
@@ -1220,6 +1306,8 @@ ace_status upload_forest(ace_graph* g) {
       R.d_olo = carve<uint64_t>(q, R.olo.size());
       R.d_ohi = carve<uint64_t>(q, R.ohi.size());
       R.d_kmap = carve<int32_t>(q, R.kmap.size());
+      R.d_pairs = carve<uint32_t>(q, R.pairs.size());
+      ACE_HIP(put(R.d_pairs, R.pairs.data(), R.pairs.size() * 4));
       ACE_HIP(put(R.d_slice, R.slice.data(), R.slice.size() * sizeof(int4)));
       ACE_HIP(put(R.d_rlo, R.rlo.data(), R.rlo.size() * 8));
       ACE_HIP(put(R.d_rhi, R.rhi.data(), R.rhi.size() * 8));
@@ -1227,7 +1315,7 @@ ace_status upload_forest(ace_graph* g) {
       ACE_HIP(put(R.d_ohi, R.ohi.data(), R.ohi.size() * 8));
       ACE_HIP(put(R.d_kmap, R.kmap.data(), R.kmap.size() * 4));
     }
-    g->remat_lds = remat_lds_bytes(g, true) <= g->max_lds;
+    g->remat_lds = remat_lds_bytes(g, true) <= g->max_lds && remat_lds_bytes(g, false) <= g->max_lds;
     ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
     ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
@@ -1493,6 +1581,8 @@ ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env,
   a.cs_ent = R.cs_ent;
   a.P1 = g->P1;
   a.n_slices = R.nslices;
+  a.pairs = R.d_pairs;
+  a.n_pairs = (int)R.pairs.size();
   a.hot = make_int4(R.hot[0], R.hot[1], R.hot[2], R.hot[3]);
   const size_t lds = remat_lds_bytes(g, grad);
   const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
@@ -1801,6 +1891,7 @@ ace_status ace_graph_get_schedule(const ace_graph* g, ace_schedule_opts* o) {
   o->block_threads = g->opts.block_threads;
   o->schedule = g->opts.schedule;
   o->term_chunk = g->opts.term_chunk;
+  o->pair_slots = g->opts.pair_slots;
   return ACE_OK;
 }
 
@@ -1809,7 +1900,8 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   if (o->row_chunk < 4 || o->row_chunk > 256 || o->tree_chunk < 1 || o->tree_chunk > 256 || o->hot_columns < 0 ||
       o->hot_columns > 4 || (o->bank_schedule != 0 && o->bank_schedule != 1) || o->block_threads < 64 ||
       o->block_threads > 512 || o->block_threads % 64 != 0 || o->schedule < ACE_SCHEDULE_AUTO ||
-      o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256)
+      o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256 ||
+      o->pair_slots < 0 || o->pair_slots > 8192)
     return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");
   const ScheduleOpts old = g->opts;
   g->opts.row_chunk = o->row_chunk;
@@ -1819,6 +1911,7 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   g->opts.block_threads = o->block_threads;
   g->opts.schedule = o->schedule;
   g->opts.term_chunk = o->term_chunk;
+  g->opts.pair_slots = o->pair_slots;
   try {
     make_forest(g);
     make_remat(g);
@@ -1866,7 +1959,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
     for (int i = 0; i < 16; ++i) info[i] = 0;
     if (sc == Sched::Remat) {
       const ace_graph::Remat& R = g->rm[1];
-      info[0] = g->P1 + 1;
+      info[0] = g->P1 + 1 + (int64_t)R.pairs.size();
       info[1] = R.nslices;
       info[2] = (int64_t)R.olo.size();
       int64_t real = 0;
@@ -1879,6 +1972,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       for (size_t i = g->rm[0].cs_ent; i < g->rm[0].kmap.size(); ++i) real0 += g->rm[0].kmap[i] != -1;
       info[7] = real0;
       for (int k = 0; k < 4; ++k) info[8 + k] = R.hot[k];
+      info[12] = (int64_t)R.pairs.size();
     }
     if (sc == Sched::Forest) {
       info[0] = g->nslot;

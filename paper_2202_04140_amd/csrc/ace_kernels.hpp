@@ -111,8 +111,10 @@ struct ForestArgs {
 };
 
 // Rematerialising schedule (see remat_kernel).  LDS slots: one-particle
-// nodes 0..P1-1 and a constant-one slot P1 (padding).  Factor lists are
-// packed 16 bits per slot, four to a 64-bit word; unused fields hold P1.
+// nodes 0..P1-1, a constant-one slot P1 (padding), then n_pairs products of
+// two one-particle values.  Factor lists are packed 16 bits per slot, four
+// to a 64-bit word; unused fields hold P1.  Row factors are one-particle
+// slots only.
 struct RematArgs {
   int64_t n_env;
   const double2* A;          // [n_env][P1]
@@ -124,8 +126,9 @@ struct RematArgs {
   const uint64_t* row_hi;    // [n_items] row factors 4..7
   const uint64_t* oth_lo;    // entries, 64-interleaved per slice: factors 0..3 of the other parent
   const uint64_t* oth_hi;    // entries: factors 4..7 (read only when the other parent has more than 4)
+  const uint32_t* pairs;     // [n_pairs] one-particle slots a | b << 16 of the pair products
   int cs_leaf, cs_ent;
-  int P1, n_slices;
+  int P1, n_slices, n_pairs;
   int4 hot;                  // one-particle slots whose adjoints are summed in registers (P1 = unused)
 };
 

@@ -560,7 +560,7 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
   uint32_t* n2 = reinterpret_cast<uint32_t*>(ab + nab);
   double2* red = reinterpret_cast<double2*>(n2) + (TAB ? (p.N2 + 3) / 4 : 0);
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int nw = blockDim.x >> 6;
   const int P1 = p.P1;
   const int ZERO = P1;
@@ -763,6 +763,9 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
 //                 (M_pq = M_qp = c, M_pp = 2c), each term sits in the rows
 //                 of both parents, phi += x_p y / 2 and abar_p = y exactly,
 //                 so no adjoint is scattered per term.
+// The factors of the other parents may be precomputed products of two
+// one-particle values (pair slots, filled in LDS per environment), which
+// saves a read and a product per pair; row factors are one-particle slots.
 // abar_p reaches the one-particle factors of p as y prod_{j != i} x_j
 // (prefix and suffix products): one push per factor and item, with the
 // four hottest one-particle slots summed in registers and pushed once per
@@ -805,13 +808,28 @@ __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x,
 #pragma unroll
   for (int i = 1; i < 8; ++i)
     if (i < nb) xb = cmul(xb, x[slot16(blo, bhi, i)]);
-  const double* ce = p.cs + p.cs_ent;
+  // entry metadata of this slice, one entry ahead of its use
+  const uint64_t* olo_p = p.oth_lo + sl.y + lane;
+  const uint64_t* ohi_p = p.oth_hi + sl.y + lane;
+  const double* c_p = p.cs + p.cs_ent + sl.y + lane;
+  const int n = sl.z;
   double2 y = make_double2(0.0, 0.0);
-  for (int j = 0; j < sl.z; ++j) {
-    const int pos = sl.y + j * 64 + lane;
-    const uint64_t olo = p.oth_lo[pos];
-    const uint64_t ohi = SIG > 4 ? p.oth_hi[pos] : 0;
-    const double c = ce[pos];
+  uint64_t olo_n = 0, ohi_n = 0;
+  double c_n = 0.0;
+  if (n > 0) {
+    olo_n = olo_p[0];
+    if (SIG > 4) ohi_n = ohi_p[0];
+    c_n = c_p[0];
+  }
+  for (int j = 0; j < n; ++j) {
+    const uint64_t olo = olo_n, ohi = ohi_n;
+    const double c = c_n;
+    if (j + 1 < n) {
+      const unsigned o = (unsigned)(j + 1) * 64u;
+      olo_n = olo_p[o];
+      if (SIG > 4) ohi_n = ohi_p[o];
+      c_n = c_p[o];
+    }
     double2 xo = x[slot16(olo, ohi, 0)];
 #pragma unroll
     for (int u = 1; u < SIG; ++u) xo = cmul(xo, x[slot16(olo, ohi, u)]);
@@ -849,11 +867,13 @@ __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
   extern __shared__ double2 lds[];
   const int P1 = p.P1;
   const int ONE = P1;
-  double2* x = lds;             // [P1 + 1] one-particle values, constant one
-  double2* ab = lds + P1 + 1;   // [P1 + 1] one-particle adjoints (GRAD)
+  double2* x = lds;             // [P1 + 1 + n_pairs] one-particle values, constant one, pair products
+  double2* ab = lds + P1 + 1 + p.n_pairs;   // [P1 + 1] one-particle adjoints (GRAD)
   double2* red = ab + (GRAD ? P1 + 1 : 0);
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
+  // wave index, made visibly uniform so that slice descriptors and loop
+  // bounds live in scalar registers
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
   const double* cs = p.cs;
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
@@ -865,6 +885,11 @@ __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
     if (threadIdx.x == 0) {
       x[ONE] = make_double2(1.0, 0.0);
       if (GRAD) ab[ONE] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < p.n_pairs; r += blockDim.x) {
+      const uint32_t q = p.pairs[r];
+      x[ONE + 1 + r] = cmul(x[q & 0xffffu], x[q >> 16]);
     }
     __syncthreads();
     double2 acc = make_double2(0.0, 0.0);

@@ -210,21 +210,22 @@ def test_schedule_kinds():
 
 
 # ---- remat schedule: host emulation of the kernel's exact index logic -------------
-@pytest.mark.parametrize("spec,alg,n,chunk", [((4, 4, 8, 3), 1, 1, 16), ((6, 6, 12, 4), 1, 1, 5),
-                                              ((6, 6, 12, 4), 2, 2, 16), ((3, 2, 9, 5), 1, 1, 1),
-                                              ((2, 2, 10, 6), 1, 1, 7), ((2, 2, 10, 6), 2, 3, 16),
-                                              ((2, 1, 8, 8), 1, 1, 4)])
-def test_remat_schedule_host_emulation_matches_oracle(spec, alg, n, chunk):
+@pytest.mark.parametrize("spec,alg,n,chunk,pairs", [((4, 4, 8, 3), 1, 1, 16, 0), ((6, 6, 12, 4), 1, 1, 5, 64),
+                                                    ((6, 6, 12, 4), 2, 2, 16, 2048), ((3, 2, 9, 5), 1, 1, 1, 7),
+                                                    ((2, 2, 10, 6), 1, 1, 7, 30), ((2, 2, 10, 6), 2, 3, 16, 0),
+                                                    ((2, 1, 8, 8), 1, 1, 4, 100)])
+def test_remat_schedule_host_emulation_matches_oracle(spec, alg, n, chunk, pairs):
     from oracle import contraction as oc
     from oracle.indexsets import all_invariant_tuples
     import workloads as wl
     nmax, lmax, D, nu = spec
     G = ace.Graph(nu, D, nmax, lmax, algorithm=alg, alg_n=n, host_only=True)
-    G.set_schedule(schedule="remat", term_chunk=chunk, hot_columns=2)
+    G.set_schedule(schedule="remat", term_chunk=chunk, hot_columns=2, pair_slots=pairs)
     info = G.schedule_info()
     n_terms = G.stats()["n_k"] - G.stats()["n_k_by_order"][1]
     assert info["kind"] == "remat" and info["fwd_entry_real"] == n_terms
     assert n_terms < info["entry_real"] <= 2 * n_terms
+    assert info["pairs"] <= pairs
     g = group_o3(nmax, lmax, D)
     K = all_invariant_tuples(g, nu, D)
     c = np.random.default_rng(8).standard_normal(len(K))
