@@ -281,8 +281,8 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   and of children (x1000).  Remat: LDS value slots, then of the schedule
  *   with the adjoint slices, entry positions (padded, real), items, then of
  *   the forward-only schedule slices, entry positions (padded, real), the
- *   four hot slots, the pair slots of the schedule with the adjoint.  The
- *   rest are 0.
+ *   four hot slots, the pair slots of the schedule with the adjoint and
+ *   the mean LDS bank cost of its entry reads (x1000).  The rest are 0.
  *
  * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedules
  *   (phi and Abar from the one with the adjoint; ACE_ERR_INTERNAL also if

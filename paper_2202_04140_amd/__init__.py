@@ -229,7 +229,7 @@ class Graph:
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
         if k.value == 2:
             names = ["nslot", "slices", "entry_pos", "entry_real", "items", "fwd_slices", "fwd_entry_pos",
-                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3", "pairs"]
+                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3", "pairs", "bank_cost_x1000"]
         else:
             names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
                      "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",

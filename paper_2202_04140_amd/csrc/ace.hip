@@ -971,7 +971,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
     int32_t row;
     int nb, sig;
     int64_t first;
-    int count;
+    int count, chunk;
   };
   std::vector<Item> items;
   const int C = std::max(1, g->opts.term_chunk);
@@ -979,14 +979,19 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
     size_t j = i;
     const int sig = F.n[ents[i].oth];
     while (j < ents.size() && ents[j].row == ents[i].row && F.n[ents[j].oth] == sig) ++j;
+    int chunk = 0;
     for (size_t c0 = i; c0 < j; c0 += C)
-      items.push_back({ents[i].row, (int)h.node_len[ents[i].row], sig, (int64_t)c0, (int)std::min<size_t>(C, j - c0)});
+      items.push_back({ents[i].row, (int)h.node_len[ents[i].row], sig, (int64_t)c0, (int)std::min<size_t>(C, j - c0),
+                       chunk++});
     i = j;
   }
+  // chunks of one row go to different slices where possible: their adjoint
+  // pushes hit the same addresses, which a wave would serialise
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
     if (x.nb != y.nb) return x.nb < y.nb;
     if (x.sig != y.sig) return x.sig < y.sig;
-    return x.count > y.count;
+    if (x.count != y.count) return x.count > y.count;
+    return x.chunk < y.chunk;
   });
   // hot one-particle slots: the most frequent adjoint push targets
   {
@@ -1021,27 +1026,82 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
     const int ncol = items[i0].count;
     if ((int64_t)R.rlo.size() + 64 > INT32_MAX || pos + 64LL * ncol > INT32_MAX)
       throw std::length_error("remat schedule larger than 2^31 entries");
-    R.slice.push_back(make_int4((int)R.rlo.size(), (int)pos, ncol, items[i0].nb | (items[i0].sig << 8)));
+    const int sig = items[i0].sig;
+    R.slice.push_back(make_int4((int)R.rlo.size(), (int)pos, ncol, items[i0].nb | (sig << 8)));
     const size_t e0 = R.olo.size();
     R.olo.resize(e0 + 64 * (size_t)ncol, ones);
     R.ohi.resize(e0 + 64 * (size_t)ncol, ones);
     R.kmap.resize(P1 + e0 + 64 * (size_t)ncol, -1);
+    // per lane: its entries, then their column and factor rotation
+    std::vector<std::vector<int64_t>> lane_ents(64);
     for (int lane = 0; lane < 64; ++lane) {
       if (i0 + lane < i1) {
         const Item& it = items[i0 + lane];
         R.rlo.push_back(pack(it.row, 0));
         R.rhi.push_back(pack(it.row, 4));
-        for (int j = 0; j < it.count; ++j) {
-          const REnt& t = ents[it.first + j];
-          const size_t e = e0 + (size_t)j * 64 + lane;
-          R.olo[e] = F.lo[t.oth];
-          R.ohi[e] = F.hi[t.oth];
-          R.kmap[P1 + e] = t.kmap;
-        }
+        for (int j = 0; j < it.count; ++j) lane_ents[lane].push_back(it.first + j);
       } else {
         R.rlo.push_back(ones);
         R.rhi.push_back(ones);
       }
+    }
+    auto factor = [&](int64_t ei, int u) {
+      const int32_t o = ents[ei].oth;
+      return (int)(((u < 4 ? F.lo[o] : F.hi[o]) >> (16 * (u & 3))) & 0xffffu);
+    };
+    auto put_entry = [&](int lane, int j, int64_t ei, int rot) {
+      const size_t e = e0 + (size_t)j * 64 + lane;
+      uint64_t lo = 0, hi = 0;
+      for (int u = 0; u < 8; ++u) {
+        const uint64_t sl = u < sig ? (uint64_t)factor(ei, (u + rot) % sig) : (uint64_t)ONE;
+        (u < 4 ? lo : hi) |= sl << (16 * (u & 3));
+      }
+      R.olo[e] = lo;
+      R.ohi[e] = hi;
+      R.kmap[P1 + e] = ents[ei].kmap;
+    };
+    if (!g->opts.bank_schedule) {
+      for (int lane = 0; lane < 64; ++lane)
+        for (size_t j = 0; j < lane_ents[lane].size(); ++j) put_entry(lane, (int)j, lane_ents[lane][j], 0);
+    } else {
+      // Greedy per column and quarter-wave: each lane takes the remaining
+      // entry and factor rotation that adds the fewest 16-byte bank-group
+      // collisions (slot mod 16) over the factor reads of that column; a
+      // slot already read in the quarter is a broadcast and costs nothing.
+      for (int q = 0; q < 4; ++q)
+        for (int j = 0; j < ncol; ++j) {
+          int16_t seen[8][16];   // per factor position and bank group: a slot read there, or -1 (-2: several)
+          for (auto& r : seen)
+            for (auto& v : r) v = -1;
+          for (int lane = 16 * q; lane < 16 * q + 16; ++lane) {
+            auto& L = lane_ents[lane];
+            if (L.empty()) continue;
+            int best = 0, best_rot = 0, best_cost = INT32_MAX;
+            const int ncand = std::min<int>((int)L.size(), 24);
+            for (int c = 0; c < ncand; ++c)
+              for (int rot = 0; rot < sig; ++rot) {
+                int cost = 0;
+                for (int u = 0; u < sig; ++u) {
+                  const int sl = factor(L[c], (u + rot) % sig);
+                  const int16_t v = seen[u][sl & 15];
+                  cost += (v != -1 && v != sl) ? 1 : 0;
+                }
+                if (cost < best_cost) {
+                  best_cost = cost;
+                  best = c;
+                  best_rot = rot;
+                }
+              }
+            const int64_t ei = L[best];
+            L.erase(L.begin() + best);
+            for (int u = 0; u < sig; ++u) {
+              const int sl = factor(ei, (u + best_rot) % sig);
+              int16_t& v = seen[u][sl & 15];
+              v = (v == -1 || v == sl) ? (int16_t)sl : (int16_t)-2;
+            }
+            put_entry(lane, j, ei, best_rot);
+          }
+        }
     }
     pos += 64LL * ncol;
     i0 = i1;
@@ -1973,6 +2033,35 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       info[7] = real0;
       for (int k = 0; k < 4; ++k) info[8 + k] = R.hot[k];
       info[12] = (int64_t)R.pairs.size();
+      // mean LDS bank cost of the factor reads of the entries, per quarter-wave (x1000)
+      int64_t cost = 0, nq = 0;
+      for (const int4& sl : R.slice) {
+        const int sig = sl.w >> 8;
+        for (int j = 0; j < sl.z; ++j)
+          for (int u = 0; u < sig; ++u)
+            for (int q = 0; q < 4; ++q) {
+              int slots[16];
+              for (int i = 0; i < 16; ++i) {
+                const size_t e = (size_t)sl.y + (size_t)j * 64 + 16 * q + i;
+                const uint64_t w = u < 4 ? R.olo[e] : R.ohi[e];
+                slots[i] = (int)((w >> (16 * (u & 3))) & 0xffffu);
+              }
+              int mx = 0;
+              for (int b = 0; b < 16; ++b) {
+                int d = 0;
+                for (int i = 0; i < 16; ++i) {
+                  if ((slots[i] & 15) != b) continue;
+                  bool first = true;
+                  for (int k = 0; k < i; ++k) first &= slots[k] != slots[i];
+                  d += first;
+                }
+                mx = std::max(mx, d);
+              }
+              cost += mx;
+              ++nq;
+            }
+      }
+      info[13] = nq ? (1000 * cost) / nq : 0;
     }
     if (sc == Sched::Forest) {
       info[0] = g->nslot;

@@ -76,7 +76,11 @@ def test_graph_replay_follows_new_inputs(device):
 
 
 @pytest.mark.parametrize("opts", [dict(row_chunk=8, tree_chunk=2, hot_columns=0, bank_schedule=0, block_threads=256),
-                                  dict(row_chunk=64, tree_chunk=32, hot_columns=2, bank_schedule=1, block_threads=128)])
+                                  dict(row_chunk=64, tree_chunk=32, hot_columns=2, bank_schedule=1, block_threads=128),
+                                  dict(schedule="remat", term_chunk=3, pair_slots=0, bank_schedule=0, hot_columns=0,
+                                       block_threads=64),
+                                  dict(schedule="remat", term_chunk=64, pair_slots=4096, bank_schedule=1,
+                                       hot_columns=4, block_threads=512)])
 def test_schedule_variants_keep_parity(device, opts):
     print(f"schedule {opts}", flush=True)
     import torch
