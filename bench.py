@@ -246,7 +246,7 @@ def main():
     tuned = None
     if not args.no_tune:
         from paper_2202_04140_amd import autotune
-        tuned = autotune.tune(G, tc, A, use_cache=not args.retune,
+        tuned = autotune.tune(G, tc, A, use_cache=not args.retune, verbose=args.retune,
                               kinds=None if args.schedule == "auto" else (args.schedule,))
         print(f"[bench] schedule {tuned['opts']} ({'cached' if tuned['cached'] else 'tuned'})",
               file=sys.stderr, flush=True)

@@ -155,7 +155,8 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *                  item, 1..256
  *   pair_slots     remat schedule: products of two one-particle values
  *                  precomputed in LDS per environment and used as factors,
- *                  0..8192 (the most frequent pairs are taken)
+ *                  0..8192 (the most frequent pairs are taken), or -1: as
+ *                  many as fit without lowering the kernel's occupancy
  * hot_columns also sets the number of one-particle slots whose adjoints
  * the remat kernel sums in registers.
  */

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import json
 import os
+import sys
 
 from . import Graph, contract
 
@@ -31,7 +32,8 @@ SPACE = {
         "block_threads": [256, 512],
     },
     "remat": {
-        "term_chunk": [8, 16, 32, 64],
+        "term_chunk": [16, 32, 64, 128, 256],
+        "pair_slots": [-1, 0, 512, 1024, 2048],
         "hot_columns": [0, 2, 4],
         "block_threads": [256, 512],
     },
@@ -139,7 +141,7 @@ def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verb
                 ms = _time(graph, coeffs, A, reps)
                 tried.append((cand, ms))
                 if verbose:
-                    print(f"[autotune] {cand}: {ms:.4f} ms", flush=True)
+                    print(f"[autotune] {cand}: {ms:.4f} ms", file=sys.stderr, flush=True)
                 if ms < kms:
                     kbest, kms = cand, ms
         if kms < best_ms:

@@ -63,8 +63,8 @@ struct ScheduleOpts {
   int bank_schedule = 1;   // order lanes and columns by LDS bank group
   int block_threads = 512; // forest / remat kernel block size
   int schedule = 0;        // ACE_SCHEDULE_*
-  int term_chunk = 16;     // remat: terms per lane item at most
-  int pair_slots = 2048;   // remat: precomputed one-particle pair products at most
+  int term_chunk = 64;     // remat: terms per lane item at most
+  int pair_slots = -1;     // remat: precomputed one-particle pair products at most (-1: fill LDS)
 };
 
 struct ace_graph {
@@ -947,11 +947,25 @@ void compress_others(const HostGraph& h, const std::vector<REnt>& ents, int budg
   }
 }
 
-void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R) {
+// Pair slots that fit beside the one-particle values (and adjoints) without
+// lowering the number of resident waves below what the kernel's registers
+// allow: remat_kernel<true> holds 4 waves per SIMD, <false> 7 (gfx950,
+// 512 VGPRs per lane), i.e. 16 and 28 waves per CU of 160 KiB LDS.
+int auto_pair_slots(const ace_graph* g, bool grad) {
+  const int wave_per_block = std::max(1, g->opts.block_threads / 64);
+  const int waves_cu = grad ? 16 : 28;
+  const int blocks = std::max(1, waves_cu / wave_per_block);
+  const size_t per_block = (size_t)160 * 1024 / blocks;
+  const size_t base = (size_t)(g->P1 + 1) * 16 * (grad ? 2 : 1) + 8 * 16 + 256;
+  return per_block > base ? (int)std::min<size_t>(8192, (per_block - base) / 16) : 0;
+}
+
+void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool grad) {
   const HostGraph& h = g->h;
   const int P1 = h.P1, ONE = P1, W = h.width;
   Factors F;
-  compress_others(h, ents, std::max(0, std::min(g->opts.pair_slots, 65534 - P1 - 1)), R, F);
+  const int budget = g->opts.pair_slots >= 0 ? g->opts.pair_slots : auto_pair_slots(g, grad);
+  compress_others(h, ents, std::max(0, std::min(budget, 65534 - P1 - 1)), R, F);
   R.slice.clear();
   R.rlo.clear();
   R.rhi.clear();
@@ -1152,8 +1166,8 @@ void make_remat(ace_graph* g) {
     }
   }
   try {
-    pack_remat(g, one, g->rm[0]);
-    pack_remat(g, two, g->rm[1]);
+    pack_remat(g, one, g->rm[0], false);
+    pack_remat(g, two, g->rm[1], true);
   } catch (const std::length_error& e) {
     g->remat_why = e.what();
     return;
@@ -1961,7 +1975,7 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
       o->hot_columns > 4 || (o->bank_schedule != 0 && o->bank_schedule != 1) || o->block_threads < 64 ||
       o->block_threads > 512 || o->block_threads % 64 != 0 || o->schedule < ACE_SCHEDULE_AUTO ||
       o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256 ||
-      o->pair_slots < 0 || o->pair_slots > 8192)
+      o->pair_slots < -1 || o->pair_slots > 8192)
     return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");
   const ScheduleOpts old = g->opts;
   g->opts.row_chunk = o->row_chunk;
