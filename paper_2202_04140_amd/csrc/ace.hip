@@ -43,6 +43,7 @@ constexpr int kNaiveThreads = 256;
 constexpr int kBasisThreads = 256;
 constexpr int kGradThreads = 256;
 constexpr int kArenaBlocks = 1024;
+constexpr int kRematMaxSlots = 4096;   // remat factor fields are 16-bit LDS byte offsets
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -938,7 +939,7 @@ void compress_others(const HostGraph& h, const std::vector<REnt>& ents, int budg
       if (!used[i]) out[no++] = f[i];
     uint64_t lo = 0, hi = 0;
     for (int u = 0; u < 8; ++u) {
-      const uint64_t sl = u < no ? (uint64_t)out[u] : (uint64_t)ONE;
+      const uint64_t sl = 16 * (u < no ? (uint64_t)out[u] : (uint64_t)ONE);   // LDS byte offset
       (u < 4 ? lo : hi) |= sl << (16 * (u & 3));
     }
     F.n[v] = (int8_t)no;
@@ -949,11 +950,11 @@ void compress_others(const HostGraph& h, const std::vector<REnt>& ents, int budg
 
 // Pair slots that fit beside the one-particle values (and adjoints) without
 // lowering the number of resident waves below what the kernel's registers
-// allow: remat_kernel<true> holds 4 waves per SIMD, <false> 7 (gfx950,
-// 512 VGPRs per lane), i.e. 16 and 28 waves per CU of 160 KiB LDS.
+// allow: remat_kernel<true> holds 4 waves per SIMD, <false> 5 (gfx950,
+// 512 VGPRs per lane), i.e. 16 and 20 waves per CU of 160 KiB LDS.
 int auto_pair_slots(const ace_graph* g, bool grad) {
   const int wave_per_block = std::max(1, g->opts.block_threads / 64);
-  const int waves_cu = grad ? 16 : 28;
+  const int waves_cu = grad ? 16 : 20;
   const int blocks = std::max(1, waves_cu / wave_per_block);
   const size_t per_block = (size_t)160 * 1024 / blocks;
   const size_t base = (size_t)(g->P1 + 1) * 16 * (grad ? 2 : 1) + 8 * 16 + 256;
@@ -965,7 +966,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   const int P1 = h.P1, ONE = P1, W = h.width;
   Factors F;
   const int budget = g->opts.pair_slots >= 0 ? g->opts.pair_slots : auto_pair_slots(g, grad);
-  compress_others(h, ents, std::max(0, std::min(budget, 65534 - P1 - 1)), R, F);
+  compress_others(h, ents, std::max(0, std::min(budget, kRematMaxSlots - P1 - 1)), R, F);
   R.slice.clear();
   R.rlo.clear();
   R.rhi.clear();
@@ -1027,12 +1028,13 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     uint64_t w = 0;
     for (int u = 0; u < 4; ++u) {
       const int idx = from + u;
-      const uint64_t sl = idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + idx] : (uint64_t)ONE;
+      const uint64_t sl = 16 * (idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + idx] : (uint64_t)ONE);
       w |= sl << (16 * u);
     }
     return w;
   };
-  const uint64_t ones = (uint64_t)ONE | ((uint64_t)ONE << 16) | ((uint64_t)ONE << 32) | ((uint64_t)ONE << 48);
+  const uint64_t one16 = 16 * (uint64_t)ONE;
+  const uint64_t ones = one16 | (one16 << 16) | (one16 << 32) | (one16 << 48);
   int64_t pos = 0;
   for (size_t i0 = 0; i0 < items.size();) {
     size_t i1 = i0;
@@ -1067,7 +1069,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       const size_t e = e0 + (size_t)j * 64 + lane;
       uint64_t lo = 0, hi = 0;
       for (int u = 0; u < 8; ++u) {
-        const uint64_t sl = u < sig ? (uint64_t)factor(ei, (u + rot) % sig) : (uint64_t)ONE;
+        const uint64_t sl = u < sig ? (uint64_t)factor(ei, (u + rot) % sig) : one16;
         (u < 4 ? lo : hi) |= sl << (16 * (u & 3));
       }
       R.olo[e] = lo;
@@ -1096,7 +1098,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
               for (int rot = 0; rot < sig; ++rot) {
                 int cost = 0;
                 for (int u = 0; u < sig; ++u) {
-                  const int sl = factor(L[c], (u + rot) % sig);
+                  const int sl = factor(L[c], (u + rot) % sig) >> 4;
                   const int16_t v = seen[u][sl & 15];
                   cost += (v != -1 && v != sl) ? 1 : 0;
                 }
@@ -1109,7 +1111,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
             const int64_t ei = L[best];
             L.erase(L.begin() + best);
             for (int u = 0; u < sig; ++u) {
-              const int sl = factor(ei, (u + best_rot) % sig);
+              const int sl = factor(ei, (u + best_rot) % sig) >> 4;
               int16_t& v = seen[u][sl & 15];
               v = (v == -1 || v == sl) ? (int16_t)sl : (int16_t)-2;
             }
@@ -1130,8 +1132,8 @@ void make_remat(ace_graph* g) {
   const int P1 = h.P1;
   const int64_t V = h.n_nodes();
   g->remat_ok = false;
-  if (P1 + 1 > 65535) {
-    g->remat_why = "more than 65534 one-particle functions";
+  if (P1 + 1 > kRematMaxSlots) {
+    g->remat_why = "more than 4095 one-particle functions";
     return;
   }
   if (h.width > 8) {
@@ -1204,7 +1206,9 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
   for (int i = 0; i < P1; ++i) acc += cs[R.cs_leaf + i] * x[i];
   auto ok = [&](int v) { return v >= 0 && v <= P1 + NP; };
   auto okrow = [&](int v) { return v >= 0 && v <= P1; };
-  auto slot = [](uint64_t lo, uint64_t hi, int i) { return (int)(((i < 4 ? lo : hi) >> (16 * (i & 3))) & 0xffffu); };
+  auto slot = [](uint64_t lo, uint64_t hi, int i) {   // fields are LDS byte offsets of 16-byte slots
+    return (int)((((i < 4 ? lo : hi) >> (16 * (i & 3))) & 0xffffu) >> 4);
+  };
   for (const int4& sl : R.slice) {
     const int nb = sl.w & 0xff, sig = sl.w >> 8;
     if (nb < 1 || nb > 8 || sig < 1 || sig > 7) return false;
@@ -2058,7 +2062,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
               for (int i = 0; i < 16; ++i) {
                 const size_t e = (size_t)sl.y + (size_t)j * 64 + 16 * q + i;
                 const uint64_t w = u < 4 ? R.olo[e] : R.ohi[e];
-                slots[i] = (int)((w >> (16 * (u & 3))) & 0xffffu);
+                slots[i] = (int)(((w >> (16 * (u & 3))) & 0xffffu) >> 4);
               }
               int mx = 0;
               for (int b = 0; b < 16; ++b) {

@@ -112,9 +112,9 @@ struct ForestArgs {
 
 // Rematerialising schedule (see remat_kernel).  LDS slots: one-particle
 // nodes 0..P1-1, a constant-one slot P1 (padding), then n_pairs products of
-// two one-particle values.  Factor lists are packed 16 bits per slot, four
-// to a 64-bit word; unused fields hold P1.  Row factors are one-particle
-// slots only.
+// two one-particle values.  Factor lists hold the LDS byte offset 16 * slot
+// of each factor, 16 bits each, four to a 64-bit word; unused fields hold
+// 16 * P1.  Row factors are one-particle slots only.
 struct RematArgs {
   int64_t n_env;
   const double2* A;          // [n_env][P1]

@@ -763,7 +763,9 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
 //                 (M_pq = M_qp = c, M_pp = 2c), each term sits in the rows
 //                 of both parents, phi += x_p y / 2 and abar_p = y exactly,
 //                 so no adjoint is scattered per term.
-// The factors of the other parents may be precomputed products of two
+// Factor lists hold LDS byte offsets of 16-byte slots (so the slots must
+// number at most 4096).  The factors of the other parents may be
+// precomputed products of two
 // one-particle values (pair slots, filled in LDS per environment), which
 // saves a read and a product per pair; row factors are one-particle slots.
 // abar_p reaches the one-particle factors of p as y prod_{j != i} x_j
@@ -791,70 +793,86 @@ __device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const in
   }
 }
 
+// Field i of a packed factor list: the LDS byte offset of a 16-byte slot.
 __device__ __forceinline__ int slot16(uint64_t lo, uint64_t hi, int i) {
   return (int)(((i < 4 ? lo : hi) >> (16 * (i & 3))) & 0xffffu);
+}
+__device__ __forceinline__ double2 lds_at(const double2* base, int byte_off) {
+  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// value of one packed factor list of SIG factors
+template <int SIG>
+__device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo, uint64_t hi) {
+  double2 v = lds_at(x, slot16(lo, hi, 0));
+#pragma unroll
+  for (int u = 1; u < SIG; ++u) v = cmul(v, lds_at(x, slot16(lo, hi, u)));
+  return v;
 }
 
 template <bool GRAD, int SIG>
 __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x, double2* ab, const int4& sl, int lane,
                                            double2& acc, double2& h0, double2& h1, double2& h2, double2& h3) {
-  const int ONE = p.P1;
+  const int ONE_OFF = 16 * p.P1;
   const int nb = sl.w & 0xff;
   const int item = sl.x + lane;
   const uint64_t blo = p.row_lo[item], bhi = p.row_hi[item];
   // row value (its factors are read again for the adjoint at the end, so
   // that they hold no registers during the entry loop)
-  double2 xb = x[slot16(blo, bhi, 0)];
+  double2 xb = lds_at(x, slot16(blo, bhi, 0));
 #pragma unroll
   for (int i = 1; i < 8; ++i)
-    if (i < nb) xb = cmul(xb, x[slot16(blo, bhi, i)]);
-  // entry metadata of this slice, one entry ahead of its use
+    if (i < nb) xb = cmul(xb, lds_at(x, slot16(blo, bhi, i)));
+  // entry metadata of this slice, prefetched one entry ahead of its use in
+  // two register sets (the loop is unrolled by two)
   const uint64_t* olo_p = p.oth_lo + sl.y + lane;
   const uint64_t* ohi_p = p.oth_hi + sl.y + lane;
   const double* c_p = p.cs + p.cs_ent + sl.y + lane;
   const int n = sl.z;
   double2 y = make_double2(0.0, 0.0);
-  uint64_t olo_n = 0, ohi_n = 0;
-  double c_n = 0.0;
+  uint64_t a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
+  double a_c = 0.0, b_c = 0.0;
   if (n > 0) {
-    olo_n = olo_p[0];
-    if (SIG > 4) ohi_n = ohi_p[0];
-    c_n = c_p[0];
+    a_lo = olo_p[0];
+    if (SIG > 4) a_hi = ohi_p[0];
+    a_c = c_p[0];
   }
-  for (int j = 0; j < n; ++j) {
-    const uint64_t olo = olo_n, ohi = ohi_n;
-    const double c = c_n;
-    if (j + 1 < n) {
-      const unsigned o = (unsigned)(j + 1) * 64u;
-      olo_n = olo_p[o];
-      if (SIG > 4) ohi_n = ohi_p[o];
-      c_n = c_p[o];
+  int j = 0;
+  for (; j + 1 < n; j += 2) {
+    const unsigned o1 = (unsigned)(j + 1) * 64u;
+    b_lo = olo_p[o1];
+    if (SIG > 4) b_hi = ohi_p[o1];
+    b_c = c_p[o1];
+    y = rfma(a_c, factor_product<SIG>(x, a_lo, a_hi), y);
+    if (j + 2 < n) {
+      const unsigned o2 = (unsigned)(j + 2) * 64u;
+      a_lo = olo_p[o2];
+      if (SIG > 4) a_hi = ohi_p[o2];
+      a_c = c_p[o2];
     }
-    double2 xo = x[slot16(olo, ohi, 0)];
-#pragma unroll
-    for (int u = 1; u < SIG; ++u) xo = cmul(xo, x[slot16(olo, ohi, u)]);
-    y = rfma(c, xo, y);
+    y = rfma(b_c, factor_product<SIG>(x, b_lo, b_hi), y);
   }
+  if (j < n) y = rfma(a_c, factor_product<SIG>(x, a_lo, a_hi), y);
   if (!GRAD) {
     acc = cfma(xb, y, acc);
     return;
   }
   acc = cfma(xb, make_double2(0.5 * y.x, 0.5 * y.y), acc);
-  if (slot16(blo, bhi, 0) != ONE) {
+  if (slot16(blo, bhi, 0) != ONE_OFF) {
     double2 pre[8];
     double2 run = make_double2(1.0, 0.0);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       if (i < nb) {
         pre[i] = run;
-        run = i == 0 ? x[slot16(blo, bhi, 0)] : cmul(run, x[slot16(blo, bhi, i)]);
+        run = i == 0 ? lds_at(x, slot16(blo, bhi, 0)) : cmul(run, lds_at(x, slot16(blo, bhi, i)));
       }
     double2 suf = y;
 #pragma unroll
     for (int i = 7; i >= 0; --i) {
       if (i < nb) {
-        push_hot(ab, slot16(blo, bhi, i), i == 0 ? suf : cmul(pre[i], suf), p.hot, h0, h1, h2, h3);
-        if (i > 0) suf = cmul(suf, x[slot16(blo, bhi, i)]);
+        push_hot(ab, slot16(blo, bhi, i) >> 4, i == 0 ? suf : cmul(pre[i], suf), p.hot, h0, h1, h2, h3);
+        if (i > 0) suf = cmul(suf, lds_at(x, slot16(blo, bhi, i)));
       }
     }
   }
