@@ -74,6 +74,9 @@ typedef int32_t ace_status;
                               (synchronous copy of offsets; not capture safe) */
 #define ACE_FLAG_LAYERED 4u /* evaluate the DAG layer by layer even where the
                               forest schedule applies (for testing) */
+#define ACE_FLAG_UNFOLDED 8u /* ace_eval / ace_eval_grad: evaluate every tuple of K
+                              even where the schedule could fold conjugate pairs
+                              (for testing; ace_contract never folds) */
 
 /*
  * Basis specification.  Sec. 2.5 / Sec. 3 with p = 1 (total degree).
@@ -282,13 +285,17 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   and of children (x1000).  Remat: LDS value slots, then of the schedule
  *   with the adjoint slices, entry positions (padded, real), items, then of
  *   the forward-only schedule slices, entry positions (padded, real), the
- *   four hot slots, the pair slots of the schedule with the adjoint and
- *   the mean LDS bank cost of its entry reads (x1000).  The rest are 0.
+ *   four hot slots, the pair slots of the schedule with the adjoint, the
+ *   mean LDS bank cost of its entry reads (x1000), and the entries (real)
+ *   of the folded schedule with the adjoint.  The rest are 0.
  *
  * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedules
  *   (phi and Abar from the one with the adjoint; ACE_ERR_INTERNAL also if
  *   the forward-only one gives another phi; ACE_ERR_UNSUPPORTED if the
- *   graph has none).
+ *   graph has none).  folded != 0 runs the schedules with conjugate pairs
+ *   folded, which are exact only for A with A_{n,l,-m} = (-1)^m
+ *   conj(A_{n,l,m}); their Abar then gives d Re(phi) as Re sum_i Abar_i dA_i
+ *   for such A but is not dphi/dA itself.
  *
  * ace_debug_forest_eval: runs the forest schedule on the host for n_env
  *   environments, with the same indices, padding and forwarding as the
@@ -301,7 +308,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info);
 ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
                                  double* phi, double* Abar);
 ace_status ace_debug_remat_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
-                                double* phi, double* Abar);
+                                double* phi, double* Abar, int32_t folded);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "Graph", "basis", "contract", "eval", "eval_grad", "AceEnergy", "AceError",
-    "FLAG_NAIVE", "FLAG_CHECK", "GROUP_O3", "GROUP_TORUS", "library_path",
+    "FLAG_NAIVE", "FLAG_CHECK", "FLAG_LAYERED", "FLAG_UNFOLDED", "GROUP_O3", "GROUP_TORUS", "library_path",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,6 +34,7 @@ BUILD_HOST_ONLY = 1
 FLAG_NAIVE = 1
 FLAG_CHECK = 2
 FLAG_LAYERED = 4
+FLAG_UNFOLDED = 8
 SCHEDULES = {"auto": 0, "forest": 1, "remat": 2, "layered": 3}
 _KIND = {0: "layered", 1: "forest", 2: "remat"}
 
@@ -97,7 +98,7 @@ EXPORTED = {
     "ace_graph_set_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
     "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
-    "ace_debug_remat_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
+    "ace_debug_remat_eval": ([_P, _P, _I64, _P, _P, _P, ctypes.c_int32], ctypes.c_int32),
 }
 
 
@@ -229,7 +230,8 @@ class Graph:
         _check(lib().ace_debug_schedule(self._h, ctypes.byref(k), info.ctypes.data))
         if k.value == 2:
             names = ["nslot", "slices", "entry_pos", "entry_real", "items", "fwd_slices", "fwd_entry_pos",
-                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3", "pairs", "bank_cost_x1000"]
+                     "fwd_entry_real", "hot0", "hot1", "hot2", "hot3", "pairs", "bank_cost_x1000",
+                     "folded_entry_real"]
         else:
             names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
                      "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",
@@ -248,15 +250,16 @@ class Graph:
                                            ab.ctypes.data))
         return phi[:, 0] + 1j * phi[:, 1], ab[..., 0] + 1j * ab[..., 1]
 
-    def remat_eval_host(self, coeffs: np.ndarray, A: np.ndarray):
-        """Host emulation of the remat kernel (ace_debug_remat_eval), as forest_eval_host."""
+    def remat_eval_host(self, coeffs: np.ndarray, A: np.ndarray, folded: bool = False):
+        """Host emulation of the remat kernel (ace_debug_remat_eval), as forest_eval_host;
+        folded: the schedules with conjugate pairs folded (exact only for conjugate-symmetric A)."""
         c = np.ascontiguousarray(coeffs, dtype=np.float64)
         E = A.shape[0]
         Ar = np.ascontiguousarray(np.stack([A.real, A.imag], -1), dtype=np.float64)
         phi = np.zeros((E, 2))
         ab = np.zeros((E, self.P1, 2))
         _check(lib().ace_debug_remat_eval(self._h, c.ctypes.data, E, Ar.ctypes.data, phi.ctypes.data,
-                                          ab.ctypes.data))
+                                          ab.ctypes.data, int(folded)))
         return phi[:, 0] + 1j * phi[:, 1], ab[..., 0] + 1j * ab[..., 1]
 
     def workspace_size(self, n_env: int, n_nbr: int = 0, flags: int = 0) -> int:
@@ -343,7 +346,7 @@ def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = Fals
 
 
 def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False, out=None,
-         layered: bool = False):
+         layered: bool = False, unfolded: bool = False):
     """phi [E, 2] = (Re, Im) by ace_eval."""
     import torch
     _dev(coeffs, torch.float64, "coeffs")
@@ -353,7 +356,8 @@ def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = F
     _check_batch(offsets, pos, check)
     E = offsets.numel() - 1
     phi = out if out is not None else torch.empty((E, 2), dtype=torch.float64, device=pos.device)
-    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
+    flags = ((FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
+             | (FLAG_UNFOLDED if unfolded else 0))
     ws = g.workspace(E, pos.device, flags)
     _check(lib().ace_eval(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                           phi.data_ptr(), ws.data_ptr(), ws.numel(), flags, _stream(pos.device)))
@@ -361,7 +365,7 @@ def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = F
 
 
 def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = False,
-              out=None, layered: bool = False):
+              out=None, layered: bool = False, unfolded: bool = False):
     """(phi [E, 2], grad [N, 3]) by ace_eval_grad; grad = d Re(phi_e)/d r_j."""
     import torch
     _dev(coeffs, torch.float64, "coeffs")
@@ -375,7 +379,8 @@ def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: boo
     else:
         phi = torch.empty((E, 2), dtype=torch.float64, device=pos.device)
         grad = torch.empty_like(pos)
-    flags = (FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
+    flags = ((FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
+             | (FLAG_UNFOLDED if unfolded else 0))
     ws = g.workspace(E, pos.device, flags)
     _check(lib().ace_eval_grad(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                                phi.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), flags,

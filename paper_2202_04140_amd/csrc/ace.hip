@@ -125,21 +125,25 @@ struct ace_graph {
   uint32_t* d_fw_ent = nullptr;
   bool forest_full = false;        // full-adjoint mode fits in LDS
   // rematerialising schedule (remat_kernel): [0] forward only (each term in
-  // one row), [1] with adjoint (each term in the rows of both parents)
+  // one row), [1] with adjoint (each term in the rows of both parents),
+  // [2], [3] the same over one tuple of each conjugate pair
   bool remat_ok = false;
   std::string remat_why;
   struct Remat {
+    bool fold = false;             // conjugate pairs folded (coefficients as (Re, Im) weights)
     int nslices = 0, nitems = 0, cs_leaf = 0, cs_ent = 0;
     int hot[4] = {0, 0, 0, 0};
     std::vector<int4> slice;
     std::vector<uint64_t> rlo, rhi, olo, ohi;
     std::vector<int32_t> kmap;
     std::vector<uint32_t> pairs;   // pair products: one-particle slots a | b << 16
+    std::vector<int32_t> kbar;     // folded: conjugate partner of each kmap entry (-1: self)
     int4* d_slice = nullptr;
     uint64_t *d_rlo = nullptr, *d_rhi = nullptr, *d_olo = nullptr, *d_ohi = nullptr;
     int32_t* d_kmap = nullptr;
+    int32_t* d_kbar = nullptr;
     uint32_t* d_pairs = nullptr;
-  } rm[2];
+  } rm[4];   // forward only, with adjoint; the same two with conjugate pairs folded
   void* rmem = nullptr;
   bool remat_lds = false;          // the one-particle values and adjoints fit in LDS
 };
@@ -873,7 +877,7 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
 // ---------------------------------------------------------------------------
 namespace {
 struct REnt {
-  int32_t row, oth, kmap;
+  int32_t row, oth, kmap, kbar;
 };
 
 // Factor lists of the other parents: the most frequent pairs of one-particle
@@ -974,6 +978,8 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   R.ohi.clear();
   R.kmap.assign(P1, -1);
   for (int i = 0; i < P1; ++i) R.kmap[i] = h.node_k[i];
+  R.kbar.clear();
+  if (R.fold) R.kbar.assign(P1, -1);   // tuples of length one in K have m = 0: self-conjugate
   R.cs_leaf = 0;
   R.cs_ent = P1;
   std::stable_sort(ents.begin(), ents.end(), [&](const REnt& x, const REnt& y) {
@@ -1048,6 +1054,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     R.olo.resize(e0 + 64 * (size_t)ncol, ones);
     R.ohi.resize(e0 + 64 * (size_t)ncol, ones);
     R.kmap.resize(P1 + e0 + 64 * (size_t)ncol, -1);
+    if (R.fold) R.kbar.resize(P1 + e0 + 64 * (size_t)ncol, -1);
     // per lane: its entries, then their column and factor rotation
     std::vector<std::vector<int64_t>> lane_ents(64);
     for (int lane = 0; lane < 64; ++lane) {
@@ -1075,6 +1082,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       R.olo[e] = lo;
       R.ohi[e] = hi;
       R.kmap[P1 + e] = ents[ei].kmap;
+      if (R.fold) R.kbar[P1 + e] = ents[ei].kbar;
     };
     if (!g->opts.bank_schedule) {
       for (int lane = 0; lane < 64; ++lane)
@@ -1127,6 +1135,45 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
 }
 }  // namespace
 
+// Conjugate partner of every tuple of K: the tuple with every m negated
+// (x_kbar = conj(x_k) when A_{n,l,-m} = (-1)^m conj(A_{n,l,m}) and the
+// m of k sum to zero).  K is sorted lexicographically within each length,
+// so the partner is found by binary search.
+std::vector<int64_t> conj_partners(const HostGraph& h) {
+  const int P1 = h.P1, W = h.width;
+  std::vector<int32_t> cj(P1, -1);
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j)
+      if (h.on_n[j] == h.on_n[i] && h.on_l[j] == h.on_l[i] && h.on_m[j] == -h.on_m[i]) {
+        cj[i] = j;
+        break;
+      }
+  for (int i = 0; i < P1; ++i)
+    if (cj[i] < 0) throw std::logic_error("one-particle set not closed under m -> -m");
+  std::vector<int64_t> out(h.nK, -1);
+  int64_t first[9] = {0};
+  for (int nu = 1; nu <= 8; ++nu) first[nu] = first[nu - 1] + (nu - 1 >= 1 ? h.nK_by_order[nu - 1] : 0);
+  for (int64_t q = 0; q < h.nK; ++q) {
+    const int L = h.k_len[q];
+    int32_t t[8];
+    for (int u = 0; u < L; ++u) t[u] = cj[h.k_flat[(size_t)q * W + u]];
+    std::sort(t, t + L);
+    int64_t lo = first[L], hi = first[L] + h.nK_by_order[L];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      const int32_t* r = &h.k_flat[(size_t)mid * W];
+      if (std::lexicographical_compare(r, r + L, t, t + L))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo >= first[L] + h.nK_by_order[L] || !std::equal(t, t + L, &h.k_flat[(size_t)lo * W]))
+      throw std::logic_error("K not closed under m -> -m");
+    out[q] = lo;
+  }
+  return out;
+}
+
 void make_remat(ace_graph* g) {
   const HostGraph& h = g->h;
   const int P1 = h.P1;
@@ -1150,29 +1197,38 @@ void make_remat(ace_graph* g) {
       tie[b] += 1;
     }
   }
-  std::vector<REnt> one, two;
-  one.reserve((size_t)h.nK);
-  two.reserve(2 * (size_t)h.nK);
-  for (int64_t q = 0; q < h.nK; ++q) {
-    if (h.k_len[q] < 2) continue;
-    const int64_t v = h.k_to_node[q];
-    const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
-    const int la = h.node_len[a], lb = h.node_len[b];
-    const bool a_row = la > lb || (la == lb && tie[a] >= tie[b]);
-    one.push_back({a_row ? a : b, a_row ? b : a, (int32_t)q});
-    if (a == b) {
-      two.push_back({a, a, -2 - (int32_t)q});   // M_aa = 2 c
-    } else {
-      two.push_back({a, b, (int32_t)q});
-      two.push_back({b, a, (int32_t)q});
+  const std::vector<int64_t> kbar = conj_partners(h);
+  for (int f = 0; f < 2; ++f) {
+    std::vector<REnt> one, two;
+    one.reserve((size_t)h.nK);
+    two.reserve(2 * (size_t)h.nK);
+    for (int64_t q = 0; q < h.nK; ++q) {
+      if (h.k_len[q] < 2) continue;
+      int32_t kb = -1;
+      if (f) {
+        if (kbar[q] < q) continue;   // the partner with the smaller index carries the pair
+        kb = kbar[q] == q ? -1 : (int32_t)kbar[q];
+      }
+      const int64_t v = h.k_to_node[q];
+      const int32_t a = h.par[2 * v], b = h.par[2 * v + 1];
+      const int la = h.node_len[a], lb = h.node_len[b];
+      const bool a_row = la > lb || (la == lb && tie[a] >= tie[b]);
+      one.push_back({a_row ? a : b, a_row ? b : a, (int32_t)q, kb});
+      if (a == b) {
+        two.push_back({a, a, -2 - (int32_t)q, kb});   // M_aa = 2 c
+      } else {
+        two.push_back({a, b, (int32_t)q, kb});
+        two.push_back({b, a, (int32_t)q, kb});
+      }
     }
-  }
-  try {
-    pack_remat(g, one, g->rm[0], false);
-    pack_remat(g, two, g->rm[1], true);
-  } catch (const std::length_error& e) {
-    g->remat_why = e.what();
-    return;
+    g->rm[2 * f].fold = g->rm[2 * f + 1].fold = f == 1;
+    try {
+      pack_remat(g, one, g->rm[2 * f], false);
+      pack_remat(g, two, g->rm[2 * f + 1], true);
+    } catch (const std::length_error& e) {
+      g->remat_why = e.what();
+      return;
+    }
   }
   g->remat_ok = true;
   g->remat_why.clear();
@@ -1181,14 +1237,21 @@ void make_remat(ace_graph* g) {
 // Host run of a remat schedule for one environment (grad: the two-sided
 // one), with the kernel's indices, padding and push order; false if an
 // index is out of range.
-bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const double* A, double* phi, double* Abar) {
+bool remat_emulate(const ace_graph* g, int which, const double* coeffs, const double* A, double* phi, double* Abar) {
   using cd = std::complex<double>;
-  const ace_graph::Remat& R = g->rm[grad ? 1 : 0];
+  const ace_graph::Remat& R = g->rm[which];
+  const bool grad = which & 1;
   const int P1 = g->P1, ONE = P1;
-  std::vector<double> cs(R.kmap.size());
+  // (Re weight, Im weight) of every coefficient position
+  std::vector<double> cs(R.kmap.size()), cs2(R.kmap.size());
   for (size_t i = 0; i < cs.size(); ++i) {
     const int k = R.kmap[i];
-    cs[i] = k >= 0 ? coeffs[k] : (k == -1 ? 0.0 : 2.0 * coeffs[-2 - k]);
+    if (k == -1) continue;
+    const int q = k >= 0 ? k : -2 - k;
+    const double sc = k >= 0 ? 1.0 : 2.0;
+    const int kb = R.fold ? R.kbar[i] : -1;
+    cs[i] = sc * (kb >= 0 ? coeffs[q] + coeffs[kb] : coeffs[q]);
+    cs2[i] = sc * (kb >= 0 ? coeffs[q] - coeffs[kb] : coeffs[q]);
   }
   const int NP = (int)R.pairs.size();
   std::vector<cd> x(P1 + 1 + NP), ab(P1 + 1);
@@ -1202,8 +1265,11 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
     if (a >= P1 || b >= P1) return false;
     x[ONE + 1 + r] = x[a] * x[b];
   }
-  cd acc = 0.0;
-  for (int i = 0; i < P1; ++i) acc += cs[R.cs_leaf + i] * x[i];
+  double acc_re = 0.0, acc_im = 0.0;
+  for (int i = 0; i < P1; ++i) {
+    acc_re += cs[R.cs_leaf + i] * x[i].real();
+    acc_im += cs2[R.cs_leaf + i] * x[i].imag();
+  }
   auto ok = [&](int v) { return v >= 0 && v <= P1 + NP; };
   auto okrow = [&](int v) { return v >= 0 && v <= P1; };
   auto slot = [](uint64_t lo, uint64_t hi, int i) {   // fields are LDS byte offsets of 16-byte slots
@@ -1221,7 +1287,7 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
         if (!okrow(v)) return false;
         xb = i == 0 ? x[v] : xb * x[v];
       }
-      cd y = 0.0;
+      cd y = 0.0, y2 = 0.0;
       for (int j = 0; j < sl.z; ++j) {
         const int64_t pos = (int64_t)sl.y + (int64_t)j * 64 + lane;
         if (pos < 0 || pos >= (int64_t)R.olo.size()) return false;
@@ -1232,12 +1298,12 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
           xo = u == 0 ? x[v] : xo * x[v];
         }
         y += cs[R.cs_ent + pos] * xo;
+        y2 += cs2[R.cs_ent + pos] * xo;
       }
-      if (!grad) {
-        acc += xb * y;
-        continue;
-      }
-      acc += xb * (0.5 * y);
+      const double w = grad ? 0.5 : 1.0;
+      acc_re += w * (xb * y).real();
+      acc_im += w * (xb * y2).imag();
+      if (!grad) continue;
       if (slot(R.rlo[item], R.rhi[item], 0) != ONE)
         for (int i = 0; i < nb; ++i) {
           cd d = y;
@@ -1247,8 +1313,8 @@ bool remat_emulate(const ace_graph* g, bool grad, const double* coeffs, const do
         }
     }
   }
-  phi[0] = acc.real();
-  phi[1] = acc.imag();
+  phi[0] = acc_re;
+  phi[1] = acc_im;
   if (Abar)
     for (int i = 0; i < P1; ++i) {
       Abar[2 * i] = ab[i].real();
@@ -1300,8 +1366,9 @@ T* carve(char*& p, size_t n) {
 }
 
 // LDS of remat_kernel: one-particle values and adjoints, reduction scratch.
-size_t remat_lds_bytes(const ace_graph* g, bool grad) {
-  const size_t np = g->rm[grad ? 1 : 0].pairs.size();
+size_t remat_lds_bytes(const ace_graph* g, int which) {
+  const bool grad = which & 1;
+  const size_t np = g->rm[which].pairs.size();
   return (size_t)(g->P1 + 1 + np) * 16 + (grad ? (size_t)(g->P1 + 1) * 16 : 0) + (kRematBlock / 64) * sizeof(double2);
 }
 
@@ -1370,7 +1437,7 @@ ace_status upload_forest(ace_graph* g) {
     for (const auto& R : g->rm)
       rb += align_up(R.slice.size() * sizeof(int4)) + align_up(R.rlo.size() * 8) + align_up(R.rhi.size() * 8) +
             align_up(R.olo.size() * 8) + align_up(R.ohi.size() * 8) + align_up(R.kmap.size() * 4) +
-            align_up(R.pairs.size() * 4);
+            align_up(R.pairs.size() * 4) + align_up(R.kbar.size() * 4);
     if (hipMalloc(&g->rmem, rb) != hipSuccess) {
       g->rmem = nullptr;
       (void)hipGetLastError();
@@ -1385,7 +1452,9 @@ ace_status upload_forest(ace_graph* g) {
       R.d_ohi = carve<uint64_t>(q, R.ohi.size());
       R.d_kmap = carve<int32_t>(q, R.kmap.size());
       R.d_pairs = carve<uint32_t>(q, R.pairs.size());
+      R.d_kbar = carve<int32_t>(q, R.kbar.size());
       ACE_HIP(put(R.d_pairs, R.pairs.data(), R.pairs.size() * 4));
+      ACE_HIP(put(R.d_kbar, R.kbar.data(), R.kbar.size() * 4));
       ACE_HIP(put(R.d_slice, R.slice.data(), R.slice.size() * sizeof(int4)));
       ACE_HIP(put(R.d_rlo, R.rlo.data(), R.rlo.size() * 8));
       ACE_HIP(put(R.d_rhi, R.rhi.data(), R.rhi.size() * 8));
@@ -1393,9 +1462,11 @@ ace_status upload_forest(ace_graph* g) {
       ACE_HIP(put(R.d_ohi, R.ohi.data(), R.ohi.size() * 8));
       ACE_HIP(put(R.d_kmap, R.kmap.data(), R.kmap.size() * 4));
     }
-    g->remat_lds = remat_lds_bytes(g, true) <= g->max_lds && remat_lds_bytes(g, false) <= g->max_lds;
-    ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-    ACE_HIP(hipFuncSetAttribute((const void*)remat_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    g->remat_lds = true;
+    for (int which = 0; which < 4; ++which) g->remat_lds &= remat_lds_bytes(g, which) <= g->max_lds;
+    const void* rk[] = {(const void*)remat_kernel<false, false>, (const void*)remat_kernel<true, false>,
+                        (const void*)remat_kernel<false, true>, (const void*)remat_kernel<true, true>};
+    for (const void* f : rk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
   return ACE_OK;
 }
@@ -1529,8 +1600,9 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char
   const size_t arena = (size_t)arena_blocks(n_env) * g->slots * sizeof(double2);
   if (layered && (!g->fwd_xl || !g->grad_xl)) w.arena_x = take(arena);
   if (layered && !g->grad_al) w.arena_ab = take(arena);
-  const size_t ncs = std::max({g->forest_ok ? g->kmap.size() : (size_t)0, g->remat_ok ? g->rm[0].kmap.size() : (size_t)0,
-                               g->remat_ok ? g->rm[1].kmap.size() : (size_t)0});
+  size_t ncs = g->forest_ok ? g->kmap.size() : 0;
+  if (g->remat_ok)
+    for (const auto& R : g->rm) ncs = std::max(ncs, R.kmap.size() * (R.fold ? 2 : 1));
   if (ncs) w.cs = reinterpret_cast<double*>(take(ncs * sizeof(double)));
   w.bytes = off;
   return w;
@@ -1633,16 +1705,28 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
 }
 
 ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                        double2* Abar, const Workspace& w, hipStream_t s) {
+                        double2* Abar, const Workspace& w, hipStream_t s, bool fold) {
   const bool grad = Abar != nullptr;
-  const ace_graph::Remat& R = g->rm[grad ? 1 : 0];
-  PrepArgs pa{};
-  pa.kmap = R.d_kmap;
-  pa.coeffs = coeffs;
-  pa.cs = w.cs;
-  pa.n = (int64_t)R.kmap.size();
-  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((pa.n + 255) / 256, 1024));
-  hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  const int which = (fold ? 2 : 0) + (grad ? 1 : 0);
+  const ace_graph::Remat& R = g->rm[which];
+  const int64_t nk = (int64_t)R.kmap.size();
+  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nk + 255) / 256, 1024));
+  if (fold) {
+    PrepFoldArgs pa{};
+    pa.kmap = R.d_kmap;
+    pa.kbar = R.d_kbar;
+    pa.coeffs = coeffs;
+    pa.cs = reinterpret_cast<double2*>(w.cs);
+    pa.n = nk;
+    hipLaunchKernelGGL(prep_fold_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  } else {
+    PrepArgs pa{};
+    pa.kmap = R.d_kmap;
+    pa.coeffs = coeffs;
+    pa.cs = w.cs;
+    pa.n = nk;
+    hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  }
   ACE_HIP(hipGetLastError());
   RematArgs a{};
   a.n_env = n_env;
@@ -1662,23 +1746,27 @@ ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env,
   a.pairs = R.d_pairs;
   a.n_pairs = (int)R.pairs.size();
   a.hot = make_int4(R.hot[0], R.hot[1], R.hot[2], R.hot[3]);
-  const size_t lds = remat_lds_bytes(g, grad);
+  const size_t lds = remat_lds_bytes(g, which);
   const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
-  if (grad)
-    hipLaunchKernelGGL(remat_kernel<true>, grid, block, lds, s, a);
-  else
-    hipLaunchKernelGGL(remat_kernel<false>, grid, block, lds, s, a);
+  switch (which) {
+    case 0: hipLaunchKernelGGL((remat_kernel<false, false>), grid, block, lds, s, a); break;
+    case 1: hipLaunchKernelGGL((remat_kernel<true, false>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((remat_kernel<false, true>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((remat_kernel<true, true>), grid, block, lds, s, a); break;
+  }
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
 
+// conj_ok: A satisfies A_{n,l,-m} = (-1)^m conj(A_{n,l,m}) (it comes from
+// the basis kernel), so schedules with folded conjugate pairs may be used.
 ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                      double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags) {
+                      double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags, bool conj_ok) {
   switch (pick_schedule(g, Abar != nullptr, flags)) {
     case Sched::Forest:
       return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s);
     case Sched::Remat:
-      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s);
+      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s, conj_ok && !(flags & ACE_FLAG_UNFOLDED));
     default:
       break;
   }
@@ -1784,7 +1872,8 @@ ace_status common_eval_checks(const ace_graph* g, const double* coeffs, int64_t 
   if (st != ACE_OK) return st;
   if (n_env < 0) return fail(ACE_ERR_INVALID_ARG, "n_env must be >= 0");
   if (n_env > ((int64_t)1 << 30)) return fail(ACE_ERR_INVALID_ARG, "n_env too large");
-  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK | ACE_FLAG_LAYERED)) return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
+  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK | ACE_FLAG_LAYERED | ACE_FLAG_UNFOLDED))
+    return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
   if (n_env == 0) return ACE_OK;
   if (!coeffs) return fail(ACE_ERR_INVALID_ARG, "coeffs is NULL");
   *need = plan_workspace(g, n_env, flags, nullptr).bytes;
@@ -1914,7 +2003,7 @@ ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env,
     return launch_naive(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
                         reinterpret_cast<double2*>(Abar), s);
   return launch_dag(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
-                    reinterpret_cast<double2*>(Abar), w, s, flags);
+                    reinterpret_cast<double2*>(Abar), w, s, flags, false);
 }
 
 ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
@@ -1932,7 +2021,7 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
   st = launch_basis(g, n_env, offsets, pos, w.A, s);
   if (st != ACE_OK) return st;
   if (flags & ACE_FLAG_NAIVE) return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
-  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags);
+  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags, true);
 }
 
 ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
@@ -1954,7 +2043,7 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
   if (flags & ACE_FLAG_NAIVE)
     st = launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, s);
   else
-    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags);
+    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags, true);
   if (st != ACE_OK) return st;
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
 }
@@ -2023,7 +2112,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
     // host-only graph: what a device with 160 KiB of LDS per block would pick
     const size_t lds = 160 * 1024;
     const bool f = g->forest_ok && forest_lds_bytes(g, true, false) <= lds;
-    const bool r = g->remat_ok && remat_lds_bytes(g, true) <= lds;
+    const bool r = g->remat_ok && remat_lds_bytes(g, 1) <= lds && remat_lds_bytes(g, 3) <= lds;
     const int want = g->opts.schedule;
     if (want == ACE_SCHEDULE_LAYERED) sc = Sched::Layered;
     else if (want == ACE_SCHEDULE_REMAT && r) sc = Sched::Remat;
@@ -2080,6 +2169,9 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
             }
       }
       info[13] = nq ? (1000 * cost) / nq : 0;
+      int64_t real3 = 0;
+      for (size_t i = g->rm[3].cs_ent; i < g->rm[3].kmap.size(); ++i) real3 += g->rm[3].kmap[i] != -1;
+      info[14] = real3;
     }
     if (sc == Sched::Forest) {
       info[0] = g->nslot;
@@ -2149,14 +2241,15 @@ ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64
 }
 
 ace_status ace_debug_remat_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
-                                double* phi, double* Abar) {
+                                double* phi, double* Abar, int32_t folded) {
   if (!g || !coeffs || !A || !phi || !Abar || n_env < 0) return fail(ACE_ERR_INVALID_ARG, "NULL argument");
   if (!g->remat_ok) return fail(ACE_ERR_UNSUPPORTED, "no remat schedule: " + g->remat_why);
+  const int base = folded ? 2 : 0;
   double phi1[2];
   for (int64_t e = 0; e < n_env; ++e) {
     // both schedules; their phi must agree
-    if (!remat_emulate(g, true, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1) ||
-        !remat_emulate(g, false, coeffs, A + 2 * e * g->P1, phi1, nullptr))
+    if (!remat_emulate(g, base + 1, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1) ||
+        !remat_emulate(g, base, coeffs, A + 2 * e * g->P1, phi1, nullptr))
       return fail(ACE_ERR_INTERNAL, "remat schedule index out of range");
     const double d = std::hypot(phi1[0] - phi[2 * e], phi1[1] - phi[2 * e + 1]);
     if (d > 1e-10 * (std::hypot(phi1[0], phi1[1]) + 1e-300)) return fail(ACE_ERR_INTERNAL, "remat schedules disagree");

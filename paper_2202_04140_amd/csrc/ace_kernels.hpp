@@ -120,7 +120,7 @@ struct RematArgs {
   const double2* A;          // [n_env][P1]
   double2* phi;              // [n_env]
   double2* Abar;             // [n_env][P1], or nullptr for the forward pass only
-  const double* cs;          // prepared coefficients
+  const double* cs;          // prepared coefficients (double2 pairs for a folded schedule)
   const int4* slice;         // [n_slices] {first item, first entry, entries per item, nrow | nother << 8}
   const uint64_t* row_lo;    // [n_items] row factors 0..3
   const uint64_t* row_hi;    // [n_items] row factors 4..7
@@ -130,6 +130,14 @@ struct RematArgs {
   int cs_leaf, cs_ent;
   int P1, n_slices, n_pairs;
   int4 hot;                  // one-particle slots whose adjoints are summed in registers (P1 = unused)
+};
+
+struct PrepFoldArgs {
+  const int32_t* kmap;   // k >= 0: c_k;  -1: 0;  k <= -2: doubled c_{-2-k}
+  const int32_t* kbar;   // conjugate partner of k, or -1 if k is self-conjugate
+  const double* coeffs;  // [|K|]
+  double2* cs;           // output (Re weight, Im weight)
+  int64_t n;
 };
 
 struct PrepArgs {

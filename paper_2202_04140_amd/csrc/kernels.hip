@@ -773,6 +773,14 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
 // four hottest one-particle slots summed in registers and pushed once per
 // wave.  The rest are LDS atomics, so the reverse pass is not bitwise
 // deterministic (the forward pass is).
+//
+// Folded schedules (FOLD) serve A with A_{n,l,-m} = (-1)^m conj(A_{n,l,m}),
+// as the basis kernel produces: then x_kbar = conj(x_k) for the tuple kbar
+// with every m negated, and a conjugate pair contributes
+// (c_k + c_kbar) Re x_k + i (c_k - c_kbar) Im x_k to phi.  Only one tuple
+// of each pair is evaluated; the adjoint of the real part uses the Re
+// weight, which gives d Re(phi)/dA in the form Re sum_i abar_i dA_i (the
+// adjoint itself differs from the unfolded one).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const int4& hot, double2& h0, double2& h1,
                                          double2& h2, double2& h3) {
@@ -810,7 +818,41 @@ __device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo,
   return v;
 }
 
-template <bool GRAD, int SIG>
+// Coefficients of a remat entry: c (plain), or (c', c'') for a folded
+// conjugate pair (Re and Im weights).
+template <bool FOLD>
+struct RCoef;
+template <>
+struct RCoef<false> {
+  double c;
+};
+template <>
+struct RCoef<true> {
+  double2 c;
+};
+
+template <bool FOLD>
+__device__ __forceinline__ RCoef<FOLD> load_coef(const double* cs, unsigned i) {
+  RCoef<FOLD> r;
+  if constexpr (FOLD)
+    r.c = reinterpret_cast<const double2*>(cs)[i];
+  else
+    r.c = cs[i];
+  return r;
+}
+
+// y1 += c' x (and y2 += c'' x when folded)
+template <bool FOLD>
+__device__ __forceinline__ void coef_fma(const RCoef<FOLD>& k, double2 v, double2& y1, double2& y2) {
+  if constexpr (FOLD) {
+    y1 = rfma(k.c.x, v, y1);
+    y2 = rfma(k.c.y, v, y2);
+  } else {
+    y1 = rfma(k.c, v, y1);
+  }
+}
+
+template <bool GRAD, int SIG, bool FOLD>
 __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x, double2* ab, const int4& sl, int lane,
                                            double2& acc, double2& h0, double2& h1, double2& h2, double2& h3) {
   const int ONE_OFF = 16 * p.P1;
@@ -827,37 +869,43 @@ __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x,
   // two register sets (the loop is unrolled by two)
   const uint64_t* olo_p = p.oth_lo + sl.y + lane;
   const uint64_t* ohi_p = p.oth_hi + sl.y + lane;
-  const double* c_p = p.cs + p.cs_ent + sl.y + lane;
+  const unsigned c0 = (unsigned)(p.cs_ent + sl.y + lane);
   const int n = sl.z;
-  double2 y = make_double2(0.0, 0.0);
+  double2 y1 = make_double2(0.0, 0.0), y2 = y1;
   uint64_t a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
-  double a_c = 0.0, b_c = 0.0;
+  RCoef<FOLD> a_c{}, b_c{};
   if (n > 0) {
     a_lo = olo_p[0];
     if (SIG > 4) a_hi = ohi_p[0];
-    a_c = c_p[0];
+    a_c = load_coef<FOLD>(p.cs, c0);
   }
   int j = 0;
   for (; j + 1 < n; j += 2) {
     const unsigned o1 = (unsigned)(j + 1) * 64u;
     b_lo = olo_p[o1];
     if (SIG > 4) b_hi = ohi_p[o1];
-    b_c = c_p[o1];
-    y = rfma(a_c, factor_product<SIG>(x, a_lo, a_hi), y);
+    b_c = load_coef<FOLD>(p.cs, c0 + o1);
+    coef_fma<FOLD>(a_c, factor_product<SIG>(x, a_lo, a_hi), y1, y2);
     if (j + 2 < n) {
       const unsigned o2 = (unsigned)(j + 2) * 64u;
       a_lo = olo_p[o2];
       if (SIG > 4) a_hi = ohi_p[o2];
-      a_c = c_p[o2];
+      a_c = load_coef<FOLD>(p.cs, c0 + o2);
     }
-    y = rfma(b_c, factor_product<SIG>(x, b_lo, b_hi), y);
+    coef_fma<FOLD>(b_c, factor_product<SIG>(x, b_lo, b_hi), y1, y2);
   }
-  if (j < n) y = rfma(a_c, factor_product<SIG>(x, a_lo, a_hi), y);
-  if (!GRAD) {
-    acc = cfma(xb, y, acc);
-    return;
+  if (j < n) coef_fma<FOLD>(a_c, factor_product<SIG>(x, a_lo, a_hi), y1, y2);
+  // phi: Re from the c' sums, Im from the c'' sums when folded
+  const double w = GRAD ? 0.5 : 1.0;
+  if constexpr (FOLD) {
+    acc.x = fma(w, xb.x * y1.x - xb.y * y1.y, acc.x);
+    acc.y = fma(w, xb.x * y2.y + xb.y * y2.x, acc.y);
+  } else {
+    const double2 h = cmul(xb, y1);
+    acc.x = fma(w, h.x, acc.x);
+    acc.y = fma(w, h.y, acc.y);
   }
-  acc = cfma(xb, make_double2(0.5 * y.x, 0.5 * y.y), acc);
+  if (!GRAD) return;
   if (slot16(blo, bhi, 0) != ONE_OFF) {
     double2 pre[8];
     double2 run = make_double2(1.0, 0.0);
@@ -867,7 +915,7 @@ __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x,
         pre[i] = run;
         run = i == 0 ? lds_at(x, slot16(blo, bhi, 0)) : cmul(run, lds_at(x, slot16(blo, bhi, i)));
       }
-    double2 suf = y;
+    double2 suf = y1;
 #pragma unroll
     for (int i = 7; i >= 0; --i) {
       if (i < nb) {
@@ -880,7 +928,7 @@ __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x,
 
 constexpr int kRematBlock = 512;
 
-template <bool GRAD>
+template <bool GRAD, bool FOLD>
 __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
   extern __shared__ double2 lds[];
   const int P1 = p.P1;
@@ -893,12 +941,21 @@ __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
   // bounds live in scalar registers
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
-  const double* cs = p.cs;
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
     const double2* Ae = p.A + e * P1;
+    double2 acc = make_double2(0.0, 0.0);
     for (int i = threadIdx.x; i < P1; i += blockDim.x) {
-      x[i] = Ae[i];
-      if (GRAD) ab[i] = make_double2(cs[p.cs_leaf + i], 0.0);
+      const double2 a = Ae[i];
+      const RCoef<FOLD> k = load_coef<FOLD>(p.cs, (unsigned)(p.cs_leaf + i));
+      x[i] = a;
+      if constexpr (FOLD) {
+        if (GRAD) ab[i] = make_double2(k.c.x, 0.0);
+        acc.x = fma(k.c.x, a.x, acc.x);
+        acc.y = fma(k.c.y, a.y, acc.y);
+      } else {
+        if (GRAD) ab[i] = make_double2(k.c, 0.0);
+        acc = rfma(k.c, a, acc);
+      }
     }
     if (threadIdx.x == 0) {
       x[ONE] = make_double2(1.0, 0.0);
@@ -910,19 +967,17 @@ __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
       x[ONE + 1 + r] = cmul(x[q & 0xffffu], x[q >> 16]);
     }
     __syncthreads();
-    double2 acc = make_double2(0.0, 0.0);
-    for (int i = threadIdx.x; i < P1; i += blockDim.x) acc = rfma(cs[p.cs_leaf + i], x[i], acc);
     double2 h0 = make_double2(0.0, 0.0), h1 = h0, h2 = h0, h3 = h0;
     for (int s = wid; s < p.n_slices; s += nw) {
       const int4 sl = p.slice[s];
       switch (sl.w >> 8) {
-        case 1: remat_item<GRAD, 1>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 2: remat_item<GRAD, 2>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 3: remat_item<GRAD, 3>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 4: remat_item<GRAD, 4>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 5: remat_item<GRAD, 5>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 6: remat_item<GRAD, 6>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        default: remat_item<GRAD, 7>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 1: remat_item<GRAD, 1, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 2: remat_item<GRAD, 2, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 3: remat_item<GRAD, 3, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 4: remat_item<GRAD, 4, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 5: remat_item<GRAD, 5, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 6: remat_item<GRAD, 6, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        default: remat_item<GRAD, 7, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
       }
     }
     if (GRAD) {
@@ -947,8 +1002,28 @@ __global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
   }
 }
 
-template __global__ void remat_kernel<false>(RematArgs);
-template __global__ void remat_kernel<true>(RematArgs);
+template __global__ void remat_kernel<false, false>(RematArgs);
+template __global__ void remat_kernel<true, false>(RematArgs);
+template __global__ void remat_kernel<false, true>(RematArgs);
+template __global__ void remat_kernel<true, true>(RematArgs);
+
+// Folded coefficients of a conjugate pair {k, kbar} (Re and Im weights):
+// (c_k + c_kbar, c_k - c_kbar); a self-conjugate tuple gives (c_k, c_k).
+// kmap: k >= 0, -1 (padding: 0), or -2-k (doubled diagonal); kbar < 0: self.
+__global__ __launch_bounds__(256) void prep_fold_kernel(PrepFoldArgs p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = p.kmap[i], kb = p.kbar[i];
+    double2 r = make_double2(0.0, 0.0);
+    if (k != -1) {
+      const int q = k >= 0 ? k : -2 - k;
+      const double sc = k >= 0 ? 1.0 : 2.0;
+      const double a = p.coeffs[q];
+      const double b = kb >= 0 ? p.coeffs[kb] : a;
+      r = kb >= 0 ? make_double2(sc * (a + b), sc * (a - b)) : make_double2(sc * a, sc * a);
+    }
+    p.cs[i] = r;
+  }
+}
 
 template __global__ void forest_kernel<false, false, false>(ForestArgs);
 template __global__ void forest_kernel<false, true, false>(ForestArgs);

@@ -234,3 +234,34 @@ def test_remat_schedule_host_emulation_matches_oracle(spec, alg, n, chunk, pairs
     pr, ar = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
     assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
     assert np.linalg.norm(ab - ar) <= 1e-13 * np.linalg.norm(ar)
+
+
+# ---- folded remat schedules (conjugate pairs) -------------------------------------
+@pytest.mark.parametrize("spec,alg,n", [((4, 4, 8, 3), 1, 1), ((6, 6, 12, 4), 1, 1), ((6, 6, 12, 4), 2, 2),
+                                        ((2, 2, 10, 6), 1, 1)])
+def test_folded_remat_matches_oracle_for_conjugate_symmetric_A(spec, alg, n):
+    """phi from one tuple of each conjugate pair, and Re sum_i Abar'_i dA_i equal to
+    the oracle's d Re(phi) for conjugate-symmetric directions dA."""
+    from oracle import contraction as oc
+    from oracle.indexsets import all_invariant_tuples
+    import workloads as wl
+    nmax, lmax, D, nu = spec
+    G = ace.Graph(nu, D, nmax, lmax, algorithm=alg, alg_n=n, host_only=True)
+    G.set_schedule(schedule="remat")
+    info = G.schedule_info()
+    g = group_o3(nmax, lmax, D)
+    K = all_invariant_tuples(g, nu, D)
+    # one tuple per conjugate pair (self-conjugate tuples stay)
+    n_terms = G.stats()["n_k"] - G.stats()["n_k_by_order"][1]
+    assert info["folded_entry_real"] < 0.8 * info["entry_real"]
+    c = np.random.default_rng(12).standard_normal(len(K))
+    A = wl.random_A_conj(3, g.labels, 31) * 0.5
+    dA = wl.random_A_conj(3, g.labels, 32)
+    phi, ab = G.remat_eval_host(c, A, folded=True)
+    pr, ar = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+    lhs = np.real(np.sum(ab * dA, axis=1))
+    rhs = np.real(np.sum(ar * dA, axis=1))
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+    # for a general A the folded adjoint is not dphi/dA
+    assert np.linalg.norm(ab - ar) > 1e-6 * np.linalg.norm(ar)

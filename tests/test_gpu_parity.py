@@ -339,3 +339,26 @@ def test_large_basis_eval_grad(device, wid, n_env):
     phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
     assert rel(cplx(phi), phi_ref) <= TOL_PHI
     assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+
+
+# ---- conjugate-pair folding (remat schedule) -----------------------------------------
+@pytest.mark.parametrize("wid,n_env", [(4, 24), (5, 4)])
+def test_folded_and_unfolded_eval_grad_agree(device, wid, n_env):
+    """ace_eval_grad folds conjugate pairs on the remat schedule; the flag
+    ACE_FLAG_UNFOLDED evaluates every tuple.  Both match, and the oracle."""
+    import paper_2202_04140_amd as ace
+    print(f"folded wid={wid} n_env={n_env}", flush=True)
+    G = graph(wid, device, "remat")
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid, n_env)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi_f, grad_f = ace.eval_grad(G, tc, toff, tpos)
+    phi_u, grad_u = ace.eval_grad(G, tc, toff, tpos, unfolded=True)
+    assert rel(cplx(phi_f), cplx(phi_u)) <= TOL_PHI
+    assert rel(grad_f.cpu().numpy(), grad_u.cpu().numpy()) <= TOL_GRAD
+    phi_e = ace.eval(G, tc, toff, tpos)
+    assert rel(cplx(phi_e), cplx(phi_u)) <= TOL_PHI
+    if wid == 4:
+        phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
+        assert rel(cplx(phi_f), phi_ref) <= TOL_PHI
+        assert rel(grad_f.cpu().numpy(), g_ref) <= TOL_GRAD

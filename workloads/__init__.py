@@ -138,3 +138,18 @@ def random_A(n_env: int, P1: int, seed: int) -> np.ndarray:
     contraction alone; [n_env, P1] complex128."""
     g = np.random.Generator(np.random.PCG64(seed))
     return g.standard_normal((n_env, P1)) + 1j * g.standard_normal((n_env, P1))
+
+
+def random_A_conj(n_env: int, labels, seed: int) -> np.ndarray:
+    """Random one-particle values with the symmetry of pooled complex spherical
+    harmonics, A[n, l, -m] = (-1)^m conj(A[n, l, m]) (so A[n, l, 0] is real);
+    labels: the (n, l, m) of each one-particle index.  [n_env, P1] complex128."""
+    A = random_A(n_env, len(labels), seed)
+    where = {tuple(int(v) for v in t): i for i, t in enumerate(labels)}
+    for i, (n, l, m) in enumerate(labels):
+        n, l, m = int(n), int(l), int(m)
+        if m == 0:
+            A[:, i] = A[:, i].real
+        elif m < 0:
+            A[:, i] = (-1) ** m * np.conj(A[:, where[(n, l, -m)]])
+    return A
