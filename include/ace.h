@@ -76,7 +76,13 @@ typedef int32_t ace_status;
                               forest schedule applies (for testing) */
 #define ACE_FLAG_UNFOLDED 8u /* ace_eval / ace_eval_grad: evaluate every tuple of K
                               even where the schedule could fold conjugate pairs
-                              (for testing; ace_contract never folds) */
+                              (for testing) */
+#define ACE_FLAG_CONJ_SYMMETRIC 16u /* ace_contract: the caller guarantees
+                              A[e][(n,l,-m)] = (-1)^m conj(A[e][(n,l,m)]), as ace_basis
+                              produces, so conjugate pairs of K may be folded (one
+                              tuple per pair is evaluated).  Abar then satisfies
+                              Re sum_i Abar_i dA_i = d Re(phi) for such dA but is not
+                              dphi/dA itself.  ace_eval / ace_eval_grad imply it. */
 
 /*
  * Basis specification.  Sec. 2.5 / Sec. 3 with p = 1 (total degree).

@@ -22,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "Graph", "basis", "contract", "eval", "eval_grad", "AceEnergy", "AceError",
-    "FLAG_NAIVE", "FLAG_CHECK", "FLAG_LAYERED", "FLAG_UNFOLDED", "GROUP_O3", "GROUP_TORUS", "library_path",
+    "FLAG_NAIVE", "FLAG_CHECK", "FLAG_LAYERED", "FLAG_UNFOLDED", "FLAG_CONJ_SYMMETRIC", "GROUP_O3", "GROUP_TORUS", "library_path",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,7 @@ FLAG_NAIVE = 1
 FLAG_CHECK = 2
 FLAG_LAYERED = 4
 FLAG_UNFOLDED = 8
+FLAG_CONJ_SYMMETRIC = 16
 SCHEDULES = {"auto": 0, "forest": 1, "remat": 2, "layered": 3}
 _KIND = {0: "layered", 1: "forest", 2: "remat"}
 
@@ -326,8 +327,10 @@ def basis(g: Graph, offsets, pos):
 
 
 def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = False,
-             layered: bool = False):
-    """phi [E,2] (and Abar [E,P1,2]) from given one-particle values A [E,P1,2]."""
+             layered: bool = False, conj_symmetric: bool = False):
+    """phi [E,2] (and Abar [E,P1,2]) from given one-particle values A [E,P1,2].
+    conj_symmetric: A has the symmetry of ace_basis output (ACE_FLAG_CONJ_SYMMETRIC),
+    so conjugate pairs may be folded; Abar is then a Re-gradient equivalent."""
     import torch
     _dev(coeffs, torch.float64, "coeffs")
     _dev(A, torch.float64, "A")
@@ -337,7 +340,8 @@ def contract(g: Graph, coeffs, A, *, with_grad: bool = False, naive: bool = Fals
     E = A.shape[0]
     phi = torch.empty((E, 2), dtype=torch.float64, device=A.device)
     Abar = torch.empty_like(A) if with_grad else None
-    flags = (FLAG_NAIVE if naive else 0) | (FLAG_LAYERED if layered else 0)
+    flags = ((FLAG_NAIVE if naive else 0) | (FLAG_LAYERED if layered else 0)
+             | (FLAG_CONJ_SYMMETRIC if conj_symmetric else 0))
     ws = g.workspace(E, A.device, flags)
     _check(lib().ace_contract(g.handle, coeffs.data_ptr(), E, A.data_ptr(), phi.data_ptr(),
                               Abar.data_ptr() if Abar is not None else None,

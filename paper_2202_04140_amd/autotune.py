@@ -75,15 +75,16 @@ def _store(data: dict) -> None:
 
 
 def _time(graph: Graph, coeffs, A, reps: int) -> float:
+    # A comes from ace_basis, so the launch folds conjugate pairs as ace_eval_grad does
     import torch
     for _ in range(2):
-        contract(graph, coeffs, A, with_grad=True)
+        contract(graph, coeffs, A, with_grad=True, conj_symmetric=True)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
-        contract(graph, coeffs, A, with_grad=True)
+        contract(graph, coeffs, A, with_grad=True, conj_symmetric=True)
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
@@ -108,7 +109,8 @@ def _available(graph: Graph, kind: str) -> bool:
 
 def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verbose: bool = False,
          kinds=None) -> dict:
-    """Pick and apply the fastest schedule for this graph and batch (A: [E, P1, 2]).
+    """Pick and apply the fastest schedule for this graph and batch (A: [E, P1, 2],
+    one-particle values from ace_basis).
 
     kinds: kernels to consider (default: every one the graph supports).
     Returns {"opts": ..., "ms": ..., "tried": [(opts, ms), ...], "cached": bool}.

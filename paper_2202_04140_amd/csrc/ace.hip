@@ -1872,7 +1872,7 @@ ace_status common_eval_checks(const ace_graph* g, const double* coeffs, int64_t 
   if (st != ACE_OK) return st;
   if (n_env < 0) return fail(ACE_ERR_INVALID_ARG, "n_env must be >= 0");
   if (n_env > ((int64_t)1 << 30)) return fail(ACE_ERR_INVALID_ARG, "n_env too large");
-  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK | ACE_FLAG_LAYERED | ACE_FLAG_UNFOLDED))
+  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_CHECK | ACE_FLAG_LAYERED | ACE_FLAG_UNFOLDED | ACE_FLAG_CONJ_SYMMETRIC))
     return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
   if (n_env == 0) return ACE_OK;
   if (!coeffs) return fail(ACE_ERR_INVALID_ARG, "coeffs is NULL");
@@ -2003,7 +2003,7 @@ ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env,
     return launch_naive(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
                         reinterpret_cast<double2*>(Abar), s);
   return launch_dag(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
-                    reinterpret_cast<double2*>(Abar), w, s, flags, false);
+                    reinterpret_cast<double2*>(Abar), w, s, flags, (flags & ACE_FLAG_CONJ_SYMMETRIC) != 0);
 }
 
 ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,

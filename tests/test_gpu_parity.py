@@ -362,3 +362,24 @@ def test_folded_and_unfolded_eval_grad_agree(device, wid, n_env):
         phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
         assert rel(cplx(phi_f), phi_ref) <= TOL_PHI
         assert rel(grad_f.cpu().numpy(), g_ref) <= TOL_GRAD
+
+
+@pytest.mark.parametrize("wid,n_env", [(2, 32), (4, 8)])
+def test_contract_conj_symmetric_folds(device, wid, n_env):
+    """ace_contract with ACE_FLAG_CONJ_SYMMETRIC on conjugate-symmetric A: phi as
+    the oracle's, and Abar gives the oracle's d Re(phi) along symmetric directions."""
+    import paper_2202_04140_amd as ace
+    print(f"contract conj wid={wid} n_env={n_env}", flush=True)
+    for sched in ("remat", None):
+        G = graph(wid, device, sched)
+        g, K, c = oracle_basis(wid)
+        A = wl.random_A_conj(n_env, g.labels, 200 + wid) * 0.5
+        dA = wl.random_A_conj(n_env, g.labels, 300 + wid)
+        tc, tA = to_dev(device, c, np.stack([A.real, A.imag], -1))
+        phi, Ab = ace.contract(G, tc, tA, with_grad=True, conj_symmetric=True)
+        phi_ref = oc.phi_naive(K, c, A)
+        ab_ref = oc.abar_naive(K, c, A)
+        assert rel(cplx(phi), phi_ref) <= TOL_PHI
+        lhs = np.real(np.sum(cplx(Ab) * dA, axis=1))
+        rhs = np.real(np.sum(ab_ref * dA, axis=1))
+        assert rel(lhs, rhs) <= TOL_ABAR
