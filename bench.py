@@ -65,10 +65,14 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def traffic_path(workload: int) -> str:
+    return os.path.join(ROOT, "profiles", f"dag_kernel_traffic_w{workload}.json")
+
+
 def profiled_traffic(workload: int):
     """HBM bytes per launch of the dominant kernel from the committed counter
     profile, or None if absent or taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "forest_kernel_traffic.json")
+    path = traffic_path(workload)
     try:
         with open(path) as f:
             d = json.load(f)
@@ -140,23 +144,30 @@ def _per_dispatch(db_path: str, counter: str):
 
 
 def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, out_path: str) -> dict:
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the forest kernel,
-    scaled by what the same counters read for a plain device copy of copy_mib
-    MiB (copy_mib read + copy_mib written)."""
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the fused forward +
+    reverse DAG kernel (the forest or remat kernel with its adjoint, whichever
+    the run dispatched most), scaled by what the same counters read for a
+    plain device copy of copy_mib MiB (copy_mib read + copy_mib written)."""
     res = {}
+    kernel = None
     for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
         acc = _per_dispatch(db, counter)
         copies = [v for (d, n), v in acc.items() if "copyBuffer" in n or "copy" in n.lower()]
-        forest = [v for (d, n), v in acc.items() if "forest_kernel<true" in n]
-        if not copies or not forest:
-            raise RuntimeError(f"{counter}: no copy or forest dispatch in {db}")
+        names = {}
+        for (d, n), v in acc.items():
+            if "forest_kernel<true" in n or "remat_kernel<true" in n:
+                names.setdefault(n, []).append(v)
+        if not copies or not names:
+            raise RuntimeError(f"{counter}: no copy or DAG dispatch in {db}")
+        kernel = kernel or max(names, key=lambda n: len(names[n]))
+        dag = names[kernel]
         copy_kib = max(copies)
         scale = copy_mib * 1024.0 / copy_kib
-        res[counter] = dict(copy_kib=copy_kib, scale=scale, forest_kib_mean=sum(forest) / len(forest),
-                            forest_dispatches=len(forest))
-    fetch_b = res["FETCH_SIZE"]["forest_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
-    write_b = res["WRITE_SIZE"]["forest_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
-    out = dict(workload=workload, source_hash=source_hash(), kernel="forest_kernel<true,*,*> (forward + reverse)",
+        res[counter] = dict(copy_kib=copy_kib, scale=scale, kernel_kib_mean=sum(dag) / len(dag),
+                            kernel_dispatches=len(dag))
+    fetch_b = res["FETCH_SIZE"]["kernel_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
+    write_b = res["WRITE_SIZE"]["kernel_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
+    out = dict(workload=workload, source_hash=source_hash(), kernel=kernel,
                copy_mib=copy_mib, fetch_bytes=fetch_b, write_bytes=write_b, bytes_per_launch=fetch_b + write_b,
                counters=res)
     with open(out_path, "w") as f:
@@ -186,7 +197,7 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         out = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy or 512, args.workload,
-                            os.path.join(ROOT, "profiles", "forest_kernel_traffic.json"))
+                            traffic_path(args.workload))
         print(json.dumps(out))
         return
     if args.gpus != 1:
