@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -184,6 +185,11 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--algorithm", type=int, default=1, choices=[1, 2],
+                    help="insertion heuristic of the DAG (Algorithm 1 or 2)")
+    ap.add_argument("--alg-n", type=int, default=2, help="Algorithm 2's parameter n")
+    ap.add_argument("--degree-p", default="1", choices=["1", "2", "inf"],
+                    help="degree notion of the basis: p-norm of the element degrees")
     ap.add_argument("--schedule", default="auto", choices=["auto", "forest", "remat", "layered"],
                     help="DAG kernel to use (auto: what the library picks, then autotuned)")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
@@ -211,6 +217,8 @@ def main():
     E, N = len(off) - 1, len(pos)
 
     cpu = None
+    if args.degree_p != "1":
+        args.no_cpu_baseline = True   # the oracle baseline lists the total-degree set
     if not args.no_cpu_baseline:
         print(f"[bench] oracle CPU baseline on a {args.cpu_sample}-environment sample ...", file=sys.stderr,
               flush=True)
@@ -222,7 +230,9 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
+    degree_p = {"1": 1, "2": 2, "inf": math.inf}[args.degree_p]
+    G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut, algorithm=args.algorithm,
+                  alg_n=args.alg_n if args.algorithm == 2 else 1, degree_p=degree_p)
     t_build = time.perf_counter() - t0
     if args.schedule != "auto":
         G.set_schedule(schedule=args.schedule)
@@ -344,7 +354,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {E} environments, {N} neighbour vectors, nu<={w.nu_max}, "
-                               f"total degree<={w.degree_max}, n<={w.n_max}, l<={w.l_max}, Algorithm 1",
+                               f"{'total degree' if degree_p == 1 else f'degree p={args.degree_p}'}<={w.degree_max}, "
+                               f"n<={w.n_max}, l<={w.l_max}, Algorithm {args.algorithm}"
+                               + (f" (n={args.alg_n})" if args.algorithm == 2 else ""),
                    "n_env": E, "n_nbr": N, "nu_max": w.nu_max, "degree_max": w.degree_max,
                    "n_max": w.n_max, "l_max": w.l_max},
         "naive": {"value": E / (ms_naive * 1e-3), "ms_per_step": ms_naive},

@@ -85,16 +85,22 @@ typedef int32_t ace_status;
                               dphi/dA itself.  ace_eval / ace_eval_grad imply it. */
 
 /*
- * Basis specification.  Sec. 2.5 / Sec. 3 with p = 1 (total degree).
+ * Basis specification (Sec. 2.5, Sec. 3).
  *   group       ACE_GROUP_O3 or ACE_GROUP_TORUS
  *   nu_max      maximal correlation order, 1 <= nu_max <= 8
- *   degree_max  D >= 0: total-degree cutoff sum_t (n_t + l_t) <= D
- *               (torus: sum_t |m_t| <= D)
+ *   degree_max  D >= 0: degree cutoff ||k||_p <= D over the element degrees
+ *               n_t + l_t (torus: |m_t|); every one-particle function has
+ *               n + l <= D
  *   n_max,l_max radial / angular cutoffs (O(3) only), 0 <= l_max <= 16
  *   algorithm   1 = Algorithm 1 (Sec. 3.2), 2 = Algorithm 2 (Sec. 3.3)
  *   alg_n       Algorithm 2's parameter n >= 1 (ignored for algorithm 1)
+ *   degree_p    ACE_DEGREE_P1 (total degree, also 0), ACE_DEGREE_P2 (sum of
+ *               squared degrees <= D^2) or ACE_DEGREE_PINF (largest degree <= D)
  *   r_cut       radial scale of R_n (> 0)
  */
+#define ACE_DEGREE_P1 1
+#define ACE_DEGREE_P2 2
+#define ACE_DEGREE_PINF (-1)
 typedef struct ace_basis_spec {
   int32_t group;
   int32_t nu_max;
@@ -103,7 +109,7 @@ typedef struct ace_basis_spec {
   int32_t l_max;
   int32_t algorithm;
   int32_t alg_n;
-  int32_t reserved;
+  int32_t degree_p;
   double r_cut;
   uint32_t build_flags;
   uint32_t reserved2;

@@ -42,7 +42,7 @@ class OracleGraph:
     """
 
     def __init__(self, group: Group, nu_max: int, degree_max: int,
-                 algorithm: int = 1, alg_n: int = 1):
+                 algorithm: int = 1, alg_n: int = 1, p=1):
         self.group = group
         self.nu_max = nu_max
         self.degree_max = degree_max
@@ -52,7 +52,7 @@ class OracleGraph:
         # Sec. 2.6: first insert the one-particle nodes {[k]}
         for i in range(len(group)):
             self._add((i,), None)
-        self.K = all_invariant_tuples(group, nu_max, degree_max)
+        self.K = all_invariant_tuples(group, nu_max, degree_max, p)
         for k in self.K:
             if algorithm == 1:
                 self.insert_alg1(k)

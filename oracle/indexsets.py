@@ -7,7 +7,9 @@ Paper passages followed:
   * invariant tuples: sum of m equal to 0, sum of l even  (Sec. 2.4)
   * torus one-particle index m, invariant tuples sum m = 0  (Sec. 2.3)
   * total degree p = 1: sum over the tuple of (n_t + l_t), resp. |m_t|
-    (Sec. 2.5, Eq. (2.3); Sec. 3 explicit sets K_G(nu, D))
+    (Sec. 2.5, Eq. (2.3); Sec. 3 explicit sets K_G(nu, D)); the other
+    degree notions of Sec. 2.5, the p-norm of the per-element degrees, for
+    p = 2 and p = infinity (the maximal element degree)
   * integer partitions pi(k, n) of n into exactly k positive parts (Sec. 5.1)
 
 Canonical order (the paper leaves it open; fixed reading):
@@ -20,6 +22,7 @@ Canonical order (the paper leaves it open; fixed reading):
 
 from __future__ import annotations
 
+import math
 from functools import lru_cache
 
 
@@ -87,6 +90,18 @@ class Group:
         """Total degree, p = 1 (Sec. 2.5)."""
         return sum(self.deg[i] for i in tup)
 
+    def within(self, tup, degree_max: int, p=1) -> bool:
+        """||k||_p <= D for the element degrees (Sec. 2.5); p = 1, 2 or math.inf,
+        compared in integers (sum of squares against D^2 for p = 2)."""
+        d = [self.deg[i] for i in tup]
+        if p == 1:
+            return sum(d) <= degree_max
+        if p == 2:
+            return sum(x * x for x in d) <= degree_max * degree_max
+        if p == math.inf:
+            return max(d, default=0) <= degree_max
+        raise ValueError(f"p must be 1, 2 or inf, got {p}")
+
 
 def group_o3(n_max: int, l_max: int, degree_max: int) -> Group:
     lab = onebody_o3(n_max, l_max, degree_max)
@@ -103,8 +118,8 @@ def group_torus(degree_max: int) -> Group:
 # invariant tuple sets K_G(nu, D)
 # --------------------------------------------------------------------------
 
-def invariant_tuples(group: Group, nu: int, degree_max: int) -> list[tuple[int, ...]]:
-    """K_G(nu, D): non-decreasing index tuples of length nu, invariant, deg <= D.
+def invariant_tuples(group: Group, nu: int, degree_max: int, p=1) -> list[tuple[int, ...]]:
+    """K_G^p(nu, D): non-decreasing index tuples of length nu, invariant, ||k||_p <= D.
 
     Sec. 3 (explicit sets K_T, K_SO(2), K_O(3)).  Plain depth-first listing
     in lexicographic order.  Two exact prunings, neither of which drops a
@@ -113,12 +128,39 @@ def invariant_tuples(group: Group, nu: int, degree_max: int) -> list[tuple[int, 
     (every one-particle function has |m| <= l <= its degree, resp. |m| equal
     to its degree, so the remaining degree budget bounds how far sum m can
     still move).  Membership itself is decided by is_invariant.
+
+    For p = 2 and p = infinity (Eq. (2.3)) the listing prunes only by the
+    degree of the next element (no later element may exceed D, and for p = 2
+    each costs at least deg[i]^2 of D^2) and by the m-sum (every later
+    element has |m| <= D); membership is decided by within() and
+    is_invariant.
     """
     P = len(group)
     deg = group.deg
     mm = group.m
     out: list[tuple[int, ...]] = []
     cur: list[int] = []
+    if p != 1:
+        D = degree_max
+
+        def rec_p(start: int, left: int, sq: int, msum: int):
+            if left == 0:
+                t = tuple(cur)
+                if group.within(t, D, p) and group.is_invariant(t):
+                    out.append(t)
+                return
+            for i in range(start, P):
+                if deg[i] > D or (p == 2 and sq + deg[i] * deg[i] * left > D * D):
+                    break
+                ms = msum + mm[i]
+                if abs(ms) > (left - 1) * D:
+                    continue
+                cur.append(i)
+                rec_p(i, left - 1, sq + deg[i] * deg[i], ms)
+                cur.pop()
+
+        rec_p(0, nu, 0, 0)
+        return out
 
     def rec(start: int, left: int, budget: int, msum: int):
         if left == 0:
@@ -141,11 +183,11 @@ def invariant_tuples(group: Group, nu: int, degree_max: int) -> list[tuple[int, 
     return out
 
 
-def all_invariant_tuples(group: Group, nu_max: int, degree_max: int) -> list[tuple[int, ...]]:
-    """K = union over nu = 1..nu_max of K_G(nu, D), by length then lex (Eq. (1.1))."""
+def all_invariant_tuples(group: Group, nu_max: int, degree_max: int, p=1) -> list[tuple[int, ...]]:
+    """K = union over nu = 1..nu_max of K_G^p(nu, D), by length then lex (Eq. (1.1))."""
     out = []
     for nu in range(1, nu_max + 1):
-        out.extend(invariant_tuples(group, nu, degree_max))
+        out.extend(invariant_tuples(group, nu, degree_max, p))
     return out
 
 

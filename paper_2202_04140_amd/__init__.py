@@ -15,6 +15,7 @@ module raises on first use; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -53,7 +54,7 @@ class _Spec(ctypes.Structure):
     _fields_ = [("group", ctypes.c_int32), ("nu_max", ctypes.c_int32),
                 ("degree_max", ctypes.c_int32), ("n_max", ctypes.c_int32),
                 ("l_max", ctypes.c_int32), ("algorithm", ctypes.c_int32),
-                ("alg_n", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alg_n", ctypes.c_int32), ("degree_p", ctypes.c_int32),
                 ("r_cut", ctypes.c_double), ("build_flags", ctypes.c_uint32),
                 ("reserved2", ctypes.c_uint32)]
 
@@ -136,14 +137,19 @@ class Graph:
 
     def __init__(self, nu_max: int, degree_max: int, n_max: int = 0, l_max: int = 0, *,
                  group: int = GROUP_O3, algorithm: int = 1, alg_n: int = 1, r_cut: float = 5.0,
-                 host_only: bool = False):
+                 degree_p=1, host_only: bool = False):
+        """degree_p: 1 (total degree), 2 or math.inf: the p-norm of the element
+        degrees bounded by degree_max (Sec. 2.5)."""
+        code = {1: 1, 2: 2, math.inf: -1}.get(degree_p)
+        if code is None:
+            raise ValueError(f"degree_p must be 1, 2 or math.inf, got {degree_p!r}")
         spec = _Spec(group=group, nu_max=nu_max, degree_max=degree_max, n_max=n_max, l_max=l_max,
-                     algorithm=algorithm, alg_n=alg_n, reserved=0, r_cut=r_cut,
+                     algorithm=algorithm, alg_n=alg_n, degree_p=code, r_cut=r_cut,
                      build_flags=BUILD_HOST_ONLY if host_only else 0, reserved2=0)
         self._h = _P()
         _check(lib().ace_graph_build(ctypes.byref(spec), ctypes.byref(self._h)))
         self.spec = dict(group=group, nu_max=nu_max, degree_max=degree_max, n_max=n_max,
-                         l_max=l_max, algorithm=algorithm, alg_n=alg_n, r_cut=r_cut)
+                         l_max=l_max, algorithm=algorithm, alg_n=alg_n, r_cut=r_cut, degree_p=degree_p)
         self.host_only = host_only
         st = self.stats()
         self.P1 = st["n_onep"]

@@ -1909,6 +1909,7 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out) {
     bs.l_max = spec->l_max;
     bs.algorithm = spec->algorithm;
     bs.alg_n = spec->alg_n;
+    bs.degree_p = spec->degree_p == 0 ? 1 : spec->degree_p;
     bs.r_cut = spec->r_cut;
     build_graph(bs, g->h);
     make_schedule(g);

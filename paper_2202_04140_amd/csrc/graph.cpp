@@ -19,6 +19,7 @@
 #include "graph.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <stdexcept>
 
@@ -202,17 +203,19 @@ void make_onebody(HostGraph& g) {
   }
 }
 
-// K_G(nu, D) for nu = 1..nu_max (Sec. 3), depth-first in lexicographic order
+// K_G^p(nu, D) for nu = 1..nu_max (Sec. 2.5, Sec. 3), depth-first in
+// lexicographic order.  `budget` is what is left of D (p = 1), of D^2
+// (p = 2, sum of squared degrees) or D itself (p = infinity).
 void enumerate_k(HostGraph& g) {
   const int P = g.P1;
   const int D = g.spec.degree_max;
+  const int p = g.spec.degree_p;
   const bool check_l = g.spec.group == 0;
   int32_t cur[8];
   for (int nu = 1; nu <= g.spec.nu_max; ++nu) {
-    // iterative DFS state
     struct Rec {
-      static void go(HostGraph& g, int32_t* cur, int depth, int nu, int start, int budget, int msum,
-                     int lsum, int P, bool check_l) {
+      static void go(HostGraph& g, int32_t* cur, int depth, int nu, int start, int budget, int msum, int lsum,
+                     int P, bool check_l, int p, int D) {
         if (depth == nu) {
           if (msum != 0) return;
           if (check_l && (lsum & 1)) return;
@@ -223,19 +226,27 @@ void enumerate_k(HostGraph& g) {
         const int left = nu - depth;
         for (int i = start; i < P; ++i) {
           const int d = g.on_deg[i];
-          if (d * left > budget) break;  // later elements have degree >= d
+          // later elements have degree >= d
+          const int cost = p == 2 ? d * d : (p == 1 ? d : 0);
+          if (p == -1 ? d > D : cost * left > budget) break;
           const int ms = msum + g.on_m[i];
-          // |m| <= deg for every later element: the remaining degree budget
-          // bounds how far the m-sum can still move
-          const int rest = budget - d;
-          if ((ms < 0 ? -ms : ms) > rest) continue;
+          // |m| <= deg for every later element: bound how far the m-sum can still move
+          const int rest = budget - cost;
+          int reach;
+          if (p == 1)
+            reach = rest;
+          else if (p == 2)
+            reach = (int)std::floor(std::sqrt((double)(left - 1) * (double)rest) + 1e-9);
+          else
+            reach = (left - 1) * D;
+          if ((ms < 0 ? -ms : ms) > reach) continue;
           cur[depth] = i;
-          go(g, cur, depth + 1, nu, i, rest, ms, lsum + g.on_l[i], P, check_l);
+          go(g, cur, depth + 1, nu, i, rest, ms, lsum + g.on_l[i], P, check_l, p, D);
         }
       }
     };
     const size_t before = g.k_len.size();
-    Rec::go(g, cur, 0, nu, 0, D, 0, 0, P, check_l);
+    Rec::go(g, cur, 0, nu, 0, p == 2 ? D * D : D, 0, 0, P, check_l, p, D);
     g.nK_by_order[nu] = (int64_t)(g.k_len.size() - before);
   }
   g.nK = (int64_t)g.k_len.size();
@@ -253,6 +264,8 @@ void build_graph(const BuildSpec& spec, HostGraph& g) {
   }
   if (spec.algorithm != 1 && spec.algorithm != 2) throw std::invalid_argument("algorithm must be 1 or 2");
   if (spec.algorithm == 2 && spec.alg_n < 1) throw std::invalid_argument("alg_n must be >= 1");
+  if (spec.degree_p != 1 && spec.degree_p != 2 && spec.degree_p != -1)
+    throw std::invalid_argument("degree_p must be 1, 2 or -1 (infinity)");
   if (!(spec.r_cut > 0.0)) throw std::invalid_argument("r_cut must be > 0");
 
   g = HostGraph();

@@ -22,6 +22,7 @@ struct BuildSpec {
   int l_max = 0;
   int algorithm = 1;
   int alg_n = 1;
+  int degree_p = 1;    // 1, 2, or -1 for p = infinity (Sec. 2.5)
   double r_cut = 5.0;
 };
 

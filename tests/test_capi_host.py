@@ -2,6 +2,7 @@
 against the oracle builder), statistics and error handling.  No GPU needed."""
 
 import ctypes
+import math
 import os
 import re
 
@@ -35,8 +36,8 @@ def test_version_and_no_error():
     assert ace.lib().ace_version().startswith(b"ace-dag")
 
 
-def oracle_arrays(group, nu, D, alg=1, n=1):
-    G = OracleGraph(group, nu, D, alg, n)
+def oracle_arrays(group, nu, D, alg=1, n=1, p=1):
+    G = OracleGraph(group, nu, D, alg, n, p=p)
     tup = np.full((G.n_nodes(), nu), -1, np.int32)
     for v, t in enumerate(G.node_tuple):
         tup[v, :len(t)] = t
@@ -66,6 +67,42 @@ def test_builder_bit_exact_o3(spec, alg, n):
     lay = G.layers()
     assert st["depth"] == max(lay)
     assert st["n_layer"][:max(lay) + 1] == [lay.count(L) for L in range(max(lay) + 1)]
+
+
+@pytest.mark.parametrize("p", [2, math.inf])
+@pytest.mark.parametrize("spec,alg,n", [((3, 3, 6, 3), 1, 1), ((3, 3, 6, 4), 1, 1), ((3, 3, 6, 4), 2, 2),
+                                        ((2, 2, 5, 5), 2, 3)])
+def test_builder_bit_exact_o3_p_norm(spec, alg, n, p):
+    nmax, lmax, D, nu = spec
+    g = ace.Graph(nu, D, nmax, lmax, algorithm=alg, alg_n=n, degree_p=p, host_only=True)
+    onep, tup, par, k2n = g.export()
+    G, otup, opar, ok2n = oracle_arrays(group_o3(nmax, lmax, D), nu, D, alg, n, p)
+    assert onep.tolist() == [list(t) for t in G.group.labels]
+    np.testing.assert_array_equal(tup, otup)
+    np.testing.assert_array_equal(par, opar)
+    np.testing.assert_array_equal(k2n, ok2n)
+    assert g.stats()["n_aux"] == G.aux_count()
+
+
+@pytest.mark.parametrize("p", [2, math.inf])
+def test_builder_bit_exact_torus_p_norm(p):
+    for nu, D, alg, n in [(4, 8, 1, 1), (5, 8, 2, 2)]:
+        g = ace.Graph(nu, D, group=ace.GROUP_TORUS, algorithm=alg, alg_n=n, degree_p=p, host_only=True)
+        _, tup, par, k2n = g.export()
+        _, otup, opar, ok2n = oracle_arrays(group_torus(D), nu, D, alg, n, p)
+        np.testing.assert_array_equal(tup, otup)
+        np.testing.assert_array_equal(par, opar)
+        np.testing.assert_array_equal(k2n, ok2n)
+
+
+def test_invalid_degree_p():
+    with pytest.raises(ValueError):
+        ace.Graph(3, 6, 2, 2, degree_p=3, host_only=True)
+    spec = ace._Spec(group=0, nu_max=3, degree_max=6, n_max=2, l_max=2, algorithm=1, alg_n=1, degree_p=5,
+                     r_cut=5.0, build_flags=1, reserved2=0)
+    h = ctypes.c_void_p()
+    assert ace.lib().ace_graph_build(ctypes.byref(spec), ctypes.byref(h)) == 1
+    assert b"degree_p" in ace.lib().ace_last_error()
 
 
 @pytest.mark.parametrize("nu,D,alg,n", [(4, 10, 1, 1), (6, 12, 1, 1), (5, 12, 2, 2)])

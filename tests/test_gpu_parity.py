@@ -383,3 +383,35 @@ def test_contract_conj_symmetric_folds(device, wid, n_env):
         lhs = np.real(np.sum(cplx(Ab) * dA, axis=1))
         rhs = np.real(np.sum(ab_ref * dA, axis=1))
         assert rel(lhs, rhs) <= TOL_ABAR
+
+
+# ---- Algorithm 2 and p-norm degree sets (Sec. 2.5, Sec. 3.3) ---------------------------
+F1_SPECS = [dict(nu=4, D=8, nl=4, alg=2, n=2, p=1), dict(nu=3, D=6, nl=3, alg=1, n=1, p=2),
+            dict(nu=4, D=6, nl=3, alg=2, n=2, p=2), dict(nu=3, D=5, nl=3, alg=2, n=2, p=math.inf)]
+
+
+@pytest.mark.parametrize("sched", [None, "remat"])
+@pytest.mark.parametrize("k", range(len(F1_SPECS)))
+def test_alg2_and_p_norm_graphs_eval_grad(device, k, sched):
+    import paper_2202_04140_amd as ace
+    sp = F1_SPECS[k]
+    print(f"f1 spec={sp} sched={sched}", flush=True)
+    G = ace.Graph(sp["nu"], sp["D"], sp["nl"], sp["nl"], algorithm=sp["alg"], alg_n=sp["n"], degree_p=sp["p"])
+    if sched:
+        G.set_schedule(schedule=sched)
+    g = group_o3(sp["nl"], sp["nl"], sp["D"])
+    K = all_invariant_tuples(g, sp["nu"], sp["D"], sp["p"])
+    kt = G.k_tuples()
+    assert [tuple(x for x in row if x >= 0) for row in kt] == K
+    c = np.random.default_rng(40 + k).standard_normal(len(K)) / (1.0 + np.array([g.degree(t) for t in K])) ** 2
+    counts = [5, 9, 1, 12, 0, 30]
+    off = np.zeros(len(counts) + 1, np.int32)
+    off[1:] = np.cumsum(counts)
+    pos = wl.positions(int(off[-1]), 90 + k)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos)
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, 5.0)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+    phi_n, grad_n = ace.eval_grad(G, tc, toff, tpos, naive=True)
+    assert rel(cplx(phi_n), phi_ref) <= TOL_PHI

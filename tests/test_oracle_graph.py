@@ -4,6 +4,8 @@ Oracle functions pinned: OracleGraph (insert_alg1, insert_alg2, _try_split),
 aux_count, layers.
 """
 
+import math
+
 import pytest
 
 from oracle.indexsets import group_o3, group_torus, torus_aux_count_theorem
@@ -161,3 +163,30 @@ def test_golden_paper_examples():
             assert {G.node_tuple[a], G.node_tuple[b]} == {tor(G, list(p)) for p in parts}
         elif kind == "two_splits":
             assert tuple(sorted(parts[:2])) in splits and tuple(sorted(parts[2:])) in splits
+
+
+@pytest.mark.parametrize("p", [2, math.inf])
+def test_alg2_fewer_aux_than_alg1_for_p_above_1(p):
+    # Sec. 3.4 (discussion of the O(3) computations): for p > 1 the generalized
+    # heuristic with n = 2 inserts fewer auxiliary nodes than Algorithm 1
+    for nu, D, nl in [(3, 6, 3), (4, 5, 3)]:
+        g = group_o3(nl, nl, D)
+        a1 = OracleGraph(g, nu, D, 1, p=p).aux_count()
+        a2 = OracleGraph(g, nu, D, 2, 2, p=p).aux_count()
+        assert a2 < a1
+
+
+@pytest.mark.parametrize("p", [2, math.inf])
+def test_dag_structure_p_norm(p):
+    g = group_o3(3, 3, 6)
+    for alg, n in [(1, 1), (2, 2)]:
+        G = OracleGraph(g, 4, 6, alg, n, p=p)
+        kset = set(G.K)
+        for v, par in enumerate(G.parents):
+            if par is None:
+                continue
+            a, b = par
+            assert a < v and b < v
+            assert tuple(sorted(G.node_tuple[a] + G.node_tuple[b])) == G.node_tuple[v]
+        assert all(G.node_tuple[G.k_to_node[q]] == k for q, k in enumerate(G.K))
+        assert len(kset) == len(G.K)

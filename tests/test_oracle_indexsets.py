@@ -148,3 +148,52 @@ def test_torus_K_difference_property3():
         a = len(ix.invariant_tuples(ix.group_torus(D), nu, D))
         b = len(ix.invariant_tuples(ix.group_torus(D - 1), nu, D - 1)) if D >= 1 else 0
         assert a - b == sum(slice_count_enumerated(k, D) for k in range(1, nu + 1))
+
+
+# ---- p-norm degree sets (Sec. 2.5: p = 2 and p = infinity) ----------------------
+def brute_force_K_p(group, nu, D, p):
+    """Every multiset of one-particle indices, kept when invariant and its element
+    degrees have p-norm <= D (floating-point norm, compared with a margin)."""
+    out = []
+    for t in itertools.combinations_with_replacement(range(len(group)), nu):
+        d = [group.deg[i] for i in t]
+        norm = max(d) if p == math.inf else sum(x ** p for x in d) ** (1.0 / p)
+        if group.is_invariant(t) and norm <= D + 1e-9:
+            out.append(t)
+    return out
+
+
+@pytest.mark.parametrize("p", [2, math.inf])
+@pytest.mark.parametrize("nu", [1, 2, 3])
+def test_K_p_matches_brute_force_o3(nu, p):
+    g = ix.group_o3(2, 2, 4)
+    assert ix.invariant_tuples(g, nu, 4, p) == brute_force_K_p(g, nu, 4, p)
+
+
+@pytest.mark.parametrize("p", [2, math.inf])
+@pytest.mark.parametrize("nu,D", [(2, 5), (3, 4), (4, 3)])
+def test_K_p_matches_brute_force_torus(nu, D, p):
+    g = ix.group_torus(D)
+    assert ix.invariant_tuples(g, nu, D, p) == brute_force_K_p(g, nu, D, p)
+
+
+def test_K_p_nested_and_equal_for_single_elements():
+    # ||k||_inf <= ||k||_2 <= ||k||_1, so K^1 within K^2 within K^inf; one element: all equal
+    g = ix.group_o3(3, 3, 6)
+    for nu in (1, 2, 3, 4):
+        k1, k2, ki = (set(ix.invariant_tuples(g, nu, 6, p)) for p in (1, 2, math.inf))
+        assert k1 <= k2 <= ki
+        if nu == 1:
+            assert k1 == k2 == ki
+        else:
+            assert len(k1) < len(k2) < len(ki)
+
+
+@pytest.mark.parametrize("D", [3, 4, 7, 10])
+def test_K_p_torus_pairs_closed_form(D):
+    # torus, nu = 2: the invariant pairs are {m, -m}, m >= 0, with degree vector (m, m):
+    # p = 1: 2m <= D;  p = 2: 2 m^2 <= D^2;  p = inf: m <= D
+    g = ix.group_torus(D)
+    assert len(ix.invariant_tuples(g, 2, D, 1)) == D // 2 + 1
+    assert len(ix.invariant_tuples(g, 2, D, 2)) == math.isqrt(D * D // 2) + 1
+    assert len(ix.invariant_tuples(g, 2, D, math.inf)) == D + 1
