@@ -6,6 +6,8 @@ Paper passages followed:
   * O(3) one-particle index k = (n, l, m), |m| <= l  (Sec. 2.4)
   * invariant tuples: sum of m equal to 0, sum of l even  (Sec. 2.4)
   * torus one-particle index m, invariant tuples sum m = 0  (Sec. 2.3)
+  * SO(2) one-particle index (n, m), invariant tuples sum m = 0; degree
+    n + |m|  (Sec. 2.2, Sec. 2.5)
   * total degree p = 1: sum over the tuple of (n_t + l_t), resp. |m_t|
     (Sec. 2.5, Eq. (2.3); Sec. 3 explicit sets K_G(nu, D)); the other
     degree notions of Sec. 2.5, the p-norm of the per-element degrees, for
@@ -15,6 +17,7 @@ Paper passages followed:
 Canonical order (the paper leaves it open; fixed reading):
   * O(3): one-particle triples sorted by (n + l, l, m) ascending.
   * torus: m sorted by (|m|, m) ascending, i.e. 0, -1, 1, -2, 2, ...
+  * SO(2): pairs (n, m) sorted by (n + |m|, |m|, m) ascending.
   A tuple is the non-decreasing list of positions in that list; sets of
   tuples are ordered by length, then lexicographically.  The element of
   largest degree is therefore the last one.
@@ -44,6 +47,14 @@ def onebody_o3(n_max: int, l_max: int, degree_max: int) -> list[tuple[int, int, 
             for m in range(-l, l + 1):
                 out.append((n, l, m))
     out.sort(key=lambda t: (t[0] + t[1], t[1], t[2]))
+    return out
+
+
+def onebody_so2(n_max: int, m_max: int, degree_max: int) -> list[tuple[int, int]]:
+    """SO(2) one-particle pairs (n, m), Sec. 2.2 (phi_nm = R_n(r) e^{-i theta m}),
+    n <= n_max, |m| <= m_max, degree n + |m| <= D, sorted by (n + |m|, |m|, m)."""
+    out = [(n, m) for n in range(n_max + 1) for m in range(-m_max, m_max + 1) if n + abs(m) <= degree_max]
+    out.sort(key=lambda t: (t[0] + abs(t[1]), abs(t[1]), t[1]))
     return out
 
 
@@ -107,6 +118,13 @@ def group_o3(n_max: int, l_max: int, degree_max: int) -> Group:
     lab = onebody_o3(n_max, l_max, degree_max)
     return Group("O3", lab, [n + l for (n, l, m) in lab], [m for (_, _, m) in lab],
                  [l for (_, l, _) in lab], True)
+
+
+def group_so2(n_max: int, m_max: int, degree_max: int) -> Group:
+    """Sec. 2.2: invariance is sum m = 0 only (no parity constraint)."""
+    lab = onebody_so2(n_max, m_max, degree_max)
+    return Group("SO2", lab, [n + abs(m) for (n, m) in lab], [m for (_, m) in lab],
+                 [abs(m) for (_, m) in lab], False)
 
 
 def group_torus(degree_max: int) -> Group:

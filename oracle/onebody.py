@@ -1,4 +1,5 @@
-"""One-particle basis phi_nlm(r) = R_n(|r|) Y_l^m(r/|r|), pooled A, gradients.
+"""One-particle bases, pooled A, gradients: O(3) phi_nlm(r) = R_n(|r|) Y_l^m(r/|r|);
+the planar groups of Sec. 2.2 and 2.3 (torus e^{i m theta}, SO(2) R_n(r) e^{-i m theta}).
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
@@ -84,8 +85,59 @@ def ylm(l: int, m: int, theta, phi):
     return sph_harm_y(l, m, theta, phi)
 
 
+def _planar(labels) -> bool:
+    """Torus labels are integers m, SO(2) labels pairs (n, m), O(3) labels triples."""
+    return len(labels) > 0 and (not isinstance(labels[0], tuple) or len(labels[0]) == 2)
+
+
+def planar_values(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """Planar one-particle functions at r_j = (x_j, y_j) (z ignored), with
+    theta = atan2(y, x) and r = |(x, y)|; [J, P1]:
+      torus (Sec. 2.3): phi_m = e^{+i m theta};
+      SO(2) (Sec. 2.2): phi_nm = R_n(r) e^{-i m theta}."""
+    pos = np.asarray(pos, dtype=np.float64)
+    th = np.arctan2(pos[:, 1], pos[:, 0])
+    out = np.empty((pos.shape[0], len(labels)), dtype=np.complex128)
+    if not isinstance(labels[0], tuple):
+        for i, m in enumerate(labels):
+            out[:, i] = np.exp(1j * m * th)
+        return out
+    r = np.hypot(pos[:, 0], pos[:, 1])
+    R = radial(max(n for (n, _) in labels), r, r_cut)
+    for i, (n, m) in enumerate(labels):
+        out[:, i] = R[:, n] * np.exp(-1j * m * th)
+    return out
+
+
+def planar_gradients(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """grad phi_i(r_j) of the planar functions; complex [J, P1, 3], z part 0.
+    grad theta = (-y, x) / r^2, grad r = (x, y) / r."""
+    pos = np.asarray(pos, dtype=np.float64)
+    x, y = pos[:, 0], pos[:, 1]
+    r2 = x * x + y * y
+    r = np.sqrt(r2)
+    th = np.arctan2(y, x)
+    gth = np.stack([-y / r2, x / r2, np.zeros_like(x)], axis=-1)
+    grr = np.stack([x / r, y / r, np.zeros_like(x)], axis=-1)
+    out = np.empty((pos.shape[0], len(labels), 3), dtype=np.complex128)
+    if not isinstance(labels[0], tuple):
+        for i, m in enumerate(labels):
+            out[:, i, :] = (1j * m * np.exp(1j * m * th))[:, None] * gth
+        return out
+    nmax = max(n for (n, _) in labels)
+    R = radial(nmax, r, r_cut)
+    dR = radial_deriv(nmax, r, r_cut)
+    for i, (n, m) in enumerate(labels):
+        e = np.exp(-1j * m * th)
+        out[:, i, :] = (dR[:, n] * e)[:, None] * grr + (R[:, n] * (-1j * m) * e)[:, None] * gth
+    return out
+
+
 def onebody_values(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
-    """phi_i(r_j) for every one-particle triple (n, l, m) in `labels`; [J, P1]."""
+    """phi_i(r_j) for every one-particle label; [J, P1].  O(3) triples (n, l, m);
+    torus and SO(2) labels go to planar_values."""
+    if _planar(labels):
+        return planar_values(labels, pos, r_cut)
     r, th, ph = spherical_coords(pos)
     nmax = max(n for (n, _, _) in labels)
     R = radial(nmax, r, r_cut)
@@ -99,7 +151,10 @@ def onebody_values(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
 
 
 def onebody_gradients(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
-    """grad_r phi_i(r_j); complex [J, P1, 3], by the spherical-coordinate route."""
+    """grad_r phi_i(r_j); complex [J, P1, 3], by the spherical-coordinate route
+    (torus and SO(2) labels go to planar_gradients)."""
+    if _planar(labels):
+        return planar_gradients(labels, pos, r_cut)
     pos = np.asarray(pos, dtype=np.float64)
     r, th, ph = spherical_coords(pos)
     nmax = max(n for (n, _, _) in labels)
