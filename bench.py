@@ -93,9 +93,14 @@ _W = {}
 def _worker_init(wid):
     from threadpoolctl import threadpool_limits
     threadpool_limits(1)
-    from oracle.indexsets import all_invariant_tuples, group_o3
+    from oracle.indexsets import all_invariant_tuples, group_o3, group_so2, group_torus
     w = wl.WORKLOADS[wid]
-    g = group_o3(w.n_max, w.l_max, w.degree_max)
+    if w.group == 0:
+        g = group_o3(w.n_max, w.l_max, w.degree_max)
+    elif w.group == 2:
+        g = group_so2(w.n_max, w.l_max, w.degree_max)
+    else:
+        g = group_torus(w.degree_max)
     K = all_invariant_tuples(g, w.nu_max, w.degree_max)
     c = wl.coefficients(w, np.array([g.degree(k) for k in K]))
     _W.update(w=w, g=g, K=K, c=c)
@@ -232,7 +237,7 @@ def main():
     t0 = time.perf_counter()
     degree_p = {"1": 1, "2": 2, "inf": math.inf}[args.degree_p]
     G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut, algorithm=args.algorithm,
-                  alg_n=args.alg_n if args.algorithm == 2 else 1, degree_p=degree_p)
+                  alg_n=args.alg_n if args.algorithm == 2 else 1, degree_p=degree_p, group=w.group)
     t_build = time.perf_counter() - t0
     if args.schedule != "auto":
         G.set_schedule(schedule=args.schedule)
@@ -353,9 +358,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {E} environments, {N} neighbour vectors, nu<={w.nu_max}, "
+        "config": {"workload": f"{w.name}: {E} environments, {N} neighbour vectors, "
+                               f"{['O(3)', 'torus', 'SO(2)'][w.group]}, nu<={w.nu_max}, "
                                f"{'total degree' if degree_p == 1 else f'degree p={args.degree_p}'}<={w.degree_max}, "
-                               f"n<={w.n_max}, l<={w.l_max}, Algorithm {args.algorithm}"
+                               + ("" if w.group == 1 else f"n<={w.n_max}, {'l' if w.group == 0 else '|m|'}<={w.l_max}, ")
+                               + f"Algorithm {args.algorithm}"
                                + (f" (n={args.alg_n})" if args.algorithm == 2 else ""),
                    "n_env": E, "n_nbr": N, "nu_max": w.nu_max, "degree_max": w.degree_max,
                    "n_max": w.n_max, "l_max": w.l_max},

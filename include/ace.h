@@ -62,8 +62,9 @@ typedef int32_t ace_status;
 #define ACE_ERR_INTERNAL      5  /* internal consistency check failed */
 
 /* symmetry group of the one-particle basis (Sec. 2.2-2.4) */
-#define ACE_GROUP_O3    0   /* phi_nlm = R_n Y_l^m, sum m = 0 and sum l even */
-#define ACE_GROUP_TORUS 1   /* phi_m = e^{i m theta}, sum m = 0; graph only  */
+#define ACE_GROUP_O3    0   /* phi_nlm = R_n Y_l^m, sum m = 0 and sum l even (Sec. 2.4) */
+#define ACE_GROUP_TORUS 1   /* phi_m = e^{i m theta}, sum m = 0 (Sec. 2.3)              */
+#define ACE_GROUP_SO2   2   /* phi_nm = R_n(r) e^{-i m theta}, sum m = 0 (Sec. 2.2)      */
 
 /* ace_basis_spec.build_flags */
 #define ACE_BUILD_HOST_ONLY 1u  /* build the DAG on the host only, no device upload */
@@ -91,7 +92,10 @@ typedef int32_t ace_status;
  *   degree_max  D >= 0: degree cutoff ||k||_p <= D over the element degrees
  *               n_t + l_t (torus: |m_t|); every one-particle function has
  *               n + l <= D
- *   n_max,l_max radial / angular cutoffs (O(3) only), 0 <= l_max <= 16
+ *   n_max,l_max radial / angular cutoffs: O(3) n <= n_max, l <= l_max <= 16;
+ *               SO(2) n <= n_max, |m| <= l_max <= 64; unused for the torus.
+ *               Planar groups read positions as (x, y) (the z entry is
+ *               ignored), theta = atan2(y, x), r = |(x, y)|.
  *   algorithm   1 = Algorithm 1 (Sec. 3.2), 2 = Algorithm 2 (Sec. 3.3)
  *   alg_n       Algorithm 2's parameter n >= 1 (ignored for algorithm 1)
  *   degree_p    ACE_DEGREE_P1 (total degree, also 0), ACE_DEGREE_P2 (sum of

@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "Graph", "basis", "contract", "eval", "eval_grad", "AceEnergy", "AceError",
-    "FLAG_NAIVE", "FLAG_CHECK", "FLAG_LAYERED", "FLAG_UNFOLDED", "FLAG_CONJ_SYMMETRIC", "GROUP_O3", "GROUP_TORUS", "library_path",
+    "FLAG_NAIVE", "FLAG_CHECK", "FLAG_LAYERED", "FLAG_UNFOLDED", "FLAG_CONJ_SYMMETRIC", "GROUP_O3", "GROUP_TORUS", "GROUP_SO2", "library_path",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,6 +31,7 @@ _LIB_PATH = os.path.join(_HERE, "libace.so")
 
 GROUP_O3 = 0
 GROUP_TORUS = 1
+GROUP_SO2 = 2
 BUILD_HOST_ONLY = 1
 FLAG_NAIVE = 1
 FLAG_CHECK = 2
@@ -193,12 +194,12 @@ class Graph:
         return out
 
     def k_degrees(self) -> np.ndarray:
-        """Total degree sum_t (n_t + l_t) of every tuple of K (torus: sum |m|)."""
+        """Total degree sum_t (n_t + l_t) of every tuple of K (SO(2): n + |m|, torus: |m|)."""
         onep = self.export()[0]
-        if self.spec["group"] == GROUP_O3:
-            deg1 = onep[:, 0] + onep[:, 1]
-        else:
+        if self.spec["group"] == GROUP_TORUS:
             deg1 = np.abs(onep[:, 2])
+        else:
+            deg1 = onep[:, 0] + onep[:, 1]   # SO(2): the l column holds |m|
         kt = self.k_tuples()
         d = np.where(kt >= 0, deg1[np.maximum(kt, 0)], 0)
         return d.sum(axis=1)

@@ -179,6 +179,12 @@ void make_ycoef(int L, std::vector<double>& out) {
   }
 }
 
+// largest n and |m| of a planar basis (torus: n = 0, |m| <= D)
+int planar_n(const HostGraph& h) { return h.spec.group == 2 ? std::min(h.spec.n_max, h.spec.degree_max) : 0; }
+int planar_m(const HostGraph& h) {
+  return h.spec.group == 2 ? std::min(h.spec.l_max, h.spec.degree_max) : h.spec.degree_max;
+}
+
 void make_schedule(ace_graph* g) {
   const HostGraph& h = g->h;
   const int64_t V = h.n_nodes();
@@ -274,6 +280,25 @@ void make_schedule(ace_graph* g) {
     g->nstart.assign((size_t)(L + 1) * (N + 1), -1);
     for (int i = 0; i < P1; ++i)
       if (h.on_m[i] == -h.on_l[i]) g->nstart[(size_t)h.on_l[i] * (N + 1) + h.on_n[i]] = i;
+  } else {
+    // planar groups: phi = R_n (Re E, sim Im E), E = u^{|m|}, sim = s sign(m) with
+    // s = +1 (torus, e^{+i m theta}) or -1 (SO(2), e^{-i m theta}); onep_index
+    // holds the planar (n, m) -> i table [(N+1)][(2M+1)]
+    const int N = planar_n(h), M = planar_m(h), W = 2 * M + 1;
+    const int s = h.spec.group == 1 ? 1 : -1;
+    g->onep_index.assign((size_t)(N + 1) * W, (int16_t)-1);
+    for (int i = 0; i < P1; ++i) {
+      const int n = h.on_n[i], m = h.on_m[i];
+      OnepInfo o{};
+      o.n = (int16_t)n;
+      o.am = (int8_t)(m < 0 ? -m : m);
+      o.yoff = o.am;
+      o.sre = 1;
+      o.sim = (int8_t)(m == 0 ? 1 : (m > 0 ? s : -s));
+      o.l = o.am;
+      g->onep.push_back(o);
+      g->onep_index[(size_t)n * W + (m + M)] = (int16_t)i;
+    }
   }
 }
 
@@ -1524,6 +1549,7 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  ACE_HIP(hipFuncSetAttribute((const void*)planar_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   {
     const ace_status fs = upload_forest(g);
     if (fs != ACE_OK) return fs;
@@ -1537,7 +1563,6 @@ bool valid_graph(const ace_graph* g) { return g != nullptr; }
 ace_status need_device(const ace_graph* g) {
   if (!g) return fail(ACE_ERR_INVALID_ARG, "graph is NULL");
   if (!g->on_device) return fail(ACE_ERR_INVALID_ARG, "graph was built with ACE_BUILD_HOST_ONLY");
-  if (g->h.spec.group != 0) return fail(ACE_ERR_UNSUPPORTED, "evaluation is implemented for the O(3) basis only");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != g->device)
     return fail(ACE_ERR_INVALID_ARG, "graph belongs to another HIP device than the current one");
@@ -1623,6 +1648,22 @@ int64_t grid_for(int64_t n_env) { return std::max<int64_t>(1, std::min<int64_t>(
 
 ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offsets, const double* pos, double2* A,
                         hipStream_t s) {
+  if (g->h.spec.group != 0) {
+    BasisArgs a{};
+    a.n_env = n_env;
+    a.offsets = offsets;
+    a.pos = pos;
+    a.A = A;
+    a.onep = g->d_onep;
+    a.P1 = g->P1;
+    a.n_max = planar_n(g->h);
+    a.l_max = planar_m(g->h);
+    a.r_cut = g->h.spec.r_cut;
+    a.group = g->h.spec.group;
+    hipLaunchKernelGGL(planar_basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), 0, s, a);
+    ACE_HIP(hipGetLastError());
+    return ACE_OK;
+  }
   BasisArgs a{};
   a.n_env = n_env;
   a.offsets = offsets;
@@ -1843,6 +1884,25 @@ ace_status launch_naive(const ace_graph* g, const double* coeffs, int64_t n_env,
 
 ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets, const double* pos,
                        const double2* Abar, double* grad, hipStream_t s) {
+  if (g->h.spec.group != 0) {
+    GradArgs a{};
+    a.n_env = n_env;
+    a.offsets = offsets;
+    a.pos = pos;
+    a.Abar = Abar;
+    a.grad = grad;
+    a.P1 = g->P1;
+    a.n_max = planar_n(g->h);
+    a.l_max = planar_m(g->h);
+    a.r_cut = g->h.spec.r_cut;
+    a.group = g->h.spec.group;
+    a.pidx = g->d_onep_index;
+    const size_t lds = (size_t)g->P1 * sizeof(double2);
+    if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
+    hipLaunchKernelGGL(planar_grad_kernel, dim3((unsigned)grid_for(n_env)), dim3(kGradThreads), lds, s, a);
+    ACE_HIP(hipGetLastError());
+    return ACE_OK;
+  }
   GradArgs a{};
   a.n_env = n_env;
   a.offsets = offsets;

@@ -30,7 +30,12 @@ struct BasisArgs {
   const double* ycoef;   // [3][(L+1)*(L+2)/2]: A, B, start (start only at l = m)
   int P1, n_max, l_max;
   double r_cut;
+  int group;             // 0 O(3); planar: 1 torus, 2 SO(2)
 };
+
+// Planar one-particle functions (torus, SO(2)): phi_i = R_n(r) e^{i s m theta}
+// with E_{|m|} = ((x + i y)/r)^{|m|}: phi_i = R_n (Re E, sim Im E) where
+// OnepInfo.sim = s * sign(m) (s = +1 torus, -1 SO(2)); R_n = 1 for the torus.
 
 // Forward / adjoint DAG schedule.  Value slots: one-particle nodes
 // 0..P1-1, stored product nodes (nodes with a child) P1..P1+S-1 in layer
@@ -75,6 +80,8 @@ struct GradArgs {
   const double* ycoef;
   int P1, n_max, l_max;
   double r_cut;
+  int group;                 // 0 O(3); planar: 1 torus, 2 SO(2)
+  const int16_t* pidx;       // planar: [(n_max+1)][(2 m_max+1)] -> i or -1 (m_max = l_max)
 };
 
 }  // namespace ace

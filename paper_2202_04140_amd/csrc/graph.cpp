@@ -187,6 +187,19 @@ void make_onebody(HostGraph& g) {
       if (a.l != b.l) return a.l < b.l;
       return a.m < b.m;
     });
+  } else if (s.group == 2) {
+    // SO(2) (Sec. 2.2): (n, m), n <= n_max, |m| <= m_max (= l_max), degree n + |m|;
+    // the l field holds |m| so that (n, l, -m) is the conjugate function
+    for (int n = 0; n <= s.n_max; ++n)
+      for (int m = -s.l_max; m <= s.l_max; ++m) {
+        const int am = m < 0 ? -m : m;
+        if (n + am <= s.degree_max) v.push_back({n, am, m, n + am});
+      }
+    std::stable_sort(v.begin(), v.end(), [](const T& a, const T& b) {
+      if (a.deg != b.deg) return a.deg < b.deg;
+      if (a.l != b.l) return a.l < b.l;
+      return a.m < b.m;
+    });
   } else {
     for (int m = -s.degree_max; m <= s.degree_max; ++m) v.push_back({0, 0, m, m < 0 ? -m : m});
     std::stable_sort(v.begin(), v.end(), [](const T& a, const T& b) {
@@ -255,12 +268,13 @@ void enumerate_k(HostGraph& g) {
 }  // namespace
 
 void build_graph(const BuildSpec& spec, HostGraph& g) {
-  if (spec.group != 0 && spec.group != 1) throw std::invalid_argument("group must be 0 (O3) or 1 (torus)");
+  if (spec.group < 0 || spec.group > 2) throw std::invalid_argument("group must be 0 (O3), 1 (torus) or 2 (SO2)");
   if (spec.nu_max < 1 || spec.nu_max > 8) throw std::invalid_argument("nu_max must be in 1..8");
   if (spec.degree_max < 0 || spec.degree_max > 64) throw std::invalid_argument("degree_max must be in 0..64");
-  if (spec.group == 0) {
+  if (spec.group == 0 || spec.group == 2) {
     if (spec.n_max < 0 || spec.n_max > 64) throw std::invalid_argument("n_max must be in 0..64");
-    if (spec.l_max < 0 || spec.l_max > 16) throw std::invalid_argument("l_max must be in 0..16");
+    if (spec.l_max < 0 || spec.l_max > (spec.group == 0 ? 16 : 64))
+      throw std::invalid_argument(spec.group == 0 ? "l_max must be in 0..16" : "m_max (l_max) must be in 0..64");
   }
   if (spec.algorithm != 1 && spec.algorithm != 2) throw std::invalid_argument("algorithm must be 1 or 2");
   if (spec.algorithm == 2 && spec.alg_n < 1) throw std::invalid_argument("alg_n must be >= 1");

@@ -7,6 +7,7 @@
 //                  and optionally the reverse pass giving dphi/dA   (Sec. 2.6)
 //   naive_kernel   phi = sum_k c_k prod_t A_{k_t} tuple by tuple     (Eq. (1.1))
 //   grad_kernel    d Re(phi)/d r_j = Re sum_i Abar_i grad(R_n Y_l^m)(r_j)
+//   planar_basis_kernel, planar_grad_kernel  the same for the torus and SO(2)
 //   forest_kernel  the DAG with one-particle and order-2 values resident in
 //                  LDS and the higher nodes walked in registers, forward
 //                  and reverse in one pass (the main schedule)
@@ -490,6 +491,118 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
         p.grad[3 * j + 1] = gy;
         p.grad[3 * j + 2] = gz;
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Planar groups (Sec. 2.2 SO(2), Sec. 2.3 torus).  Positions are read as
+// (x, y); theta = atan2(y, x) enters only through u = (x + i y)/r.
+//   planar_basis_kernel  A_i = sum_j R_{n_i}(r_j) e^{i s m_i theta_j}, one lane
+//                        per one-particle function, u^{|m|} by repeated products
+//   planar_grad_kernel   g_j = Re sum_i Abar_i grad phi_i(r_j), one lane per
+//                        neighbour, looping over (n, |m|) with the recurrences
+//     grad phi = R_n'(r) e r_hat + R_n(r) (i s m) e grad theta,
+//     grad theta = (-y, x) / r^2.
+// A_{n,-m} is computed with the same operations as A_{n,m} and the opposite
+// sign of the imaginary part, so it is exactly conj(A_{n,m}).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void planar_basis_kernel(BasisArgs p) {
+  const bool radial = p.group == 2;
+  const double kr = M_PI / p.r_cut;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    const int j0 = p.offsets[e], j1 = p.offsets[e + 1];
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
+      const OnepInfo o = p.onep[i];
+      double ar = 0.0, ai = 0.0;
+      for (int j = j0; j < j1; ++j) {
+        const double x = p.pos[3 * (int64_t)j], y = p.pos[3 * (int64_t)j + 1];
+        const double r = sqrt(x * x + y * y);
+        const double c = x / r, sn = y / r;
+        double er = 1.0, ei = 0.0;
+        for (int k = 0; k < o.am; ++k) {
+          const double t = er * c - ei * sn;
+          ei = er * sn + ei * c;
+          er = t;
+        }
+        double R = 1.0;
+        if (radial && o.n > 0) {
+          const double X = cos(kr * r);
+          double t0 = 1.0, t1 = X;
+          for (int k = 1; k < o.n; ++k) {
+            const double t2 = 2.0 * X * t1 - t0;
+            t0 = t1;
+            t1 = t2;
+          }
+          R = t1;
+        }
+        ar = fma(R, er, ar);
+        ai = fma(R, (double)o.sim * ei, ai);
+      }
+      p.A[e * p.P1 + i] = make_double2(ar, ai);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void planar_grad_kernel(GradArgs p) {
+  extern __shared__ double2 lds[];
+  double2* Ab = lds;   // [P1]
+  const bool radial = p.group == 2;
+  const double s_exp = radial ? -1.0 : 1.0;
+  const int N = radial ? p.n_max : 0, M = p.l_max, W = 2 * M + 1;
+  const double kr = M_PI / p.r_cut;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) Ab[i] = p.Abar[e * p.P1 + i];
+    __syncthreads();
+    const int j0 = p.offsets[e], j1 = p.offsets[e + 1];
+    for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+      const double x = p.pos[3 * (int64_t)j], y = p.pos[3 * (int64_t)j + 1];
+      const double r2 = x * x + y * y, r = sqrt(r2);
+      const double c = x / r, sn = y / r;
+      const double gtx = -y / r2, gty = x / r2;   // grad theta
+      const double X = cos(kr * r), dX = -kr * sin(kr * r);
+      double gx = 0.0, gy = 0.0;
+      double tm1 = 1.0, t = 1.0, um1 = 0.0, um2 = 0.0;   // T_n, T_{n-1}, U_{n-1}, U_{n-2}
+      for (int n = 0; n <= N; ++n) {
+        if (n == 1) {
+          tm1 = 1.0;
+          t = X;
+          um1 = 1.0;
+          um2 = 0.0;
+        } else if (n >= 2) {
+          const double t2 = 2.0 * X * t - tm1;
+          tm1 = t;
+          t = t2;
+          const double u2 = n == 2 ? 2.0 * X : 2.0 * X * um1 - um2;
+          um2 = um1;
+          um1 = u2;
+        }
+        const double R = radial ? t : 1.0;
+        const double dR = radial ? (double)n * um1 * dX : 0.0;   // T_n' = n U_{n-1}
+        double er = 1.0, ei = 0.0;                                 // u^m
+        for (int m = 0; m <= M; ++m) {
+          for (int sg = 1; sg >= (m == 0 ? 1 : -1); sg -= 2) {
+            const int i = p.pidx[n * W + M + sg * m];
+            if (i < 0) continue;
+            // phi = R (er, s * sg * ei) = R E with E = e^{i s (sg m) theta}
+            const double qr = er, qi = s_exp * (double)sg * ei;
+            const double2 a = Ab[i];
+            const double re = a.x * qr - a.y * qi;         // Re(abar E)
+            const double im = a.x * qi + a.y * qr;         // Im(abar E)
+            // Re(abar * (i s sg m) R E) = -(s sg m) R Im(abar E)
+            const double ang = -(s_exp * (double)(sg * m)) * R * im;
+            gx += dR * re * c + ang * gtx;
+            gy += dR * re * sn + ang * gty;
+          }
+          const double t2 = er * c - ei * sn;
+          ei = er * sn + ei * c;
+          er = t2;
+        }
+      }
+      p.grad[3 * (int64_t)j] = gx;
+      p.grad[3 * (int64_t)j + 1] = gy;
+      p.grad[3 * (int64_t)j + 2] = 0.0;
     }
   }
 }

@@ -302,3 +302,44 @@ def test_folded_remat_matches_oracle_for_conjugate_symmetric_A(spec, alg, n):
     assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
     # for a general A the folded adjoint is not dphi/dA
     assert np.linalg.norm(ab - ar) > 1e-6 * np.linalg.norm(ar)
+
+
+# ---- planar groups: SO(2) builder and schedules ------------------------------------
+@pytest.mark.parametrize("spec,alg,n", [((3, 3, 6, 4), 1, 1), ((4, 4, 8, 3), 2, 2), ((2, 5, 7, 5), 1, 1)])
+def test_builder_bit_exact_so2(spec, alg, n):
+    from oracle.indexsets import group_so2
+    nmax, mmax, D, nu = spec
+    g = ace.Graph(nu, D, nmax, mmax, group=ace.GROUP_SO2, algorithm=alg, alg_n=n, host_only=True)
+    onep, tup, par, k2n = g.export()
+    G, otup, opar, ok2n = oracle_arrays(group_so2(nmax, mmax, D), nu, D, alg, n)
+    assert [(int(a), int(c)) for a, _, c in onep] == G.group.labels
+    np.testing.assert_array_equal(tup, otup)
+    np.testing.assert_array_equal(par, opar)
+    np.testing.assert_array_equal(k2n, ok2n)
+
+
+@pytest.mark.parametrize("group", ["so2", "torus"])
+def test_folded_remat_planar_matches_oracle(group):
+    """Folded remat schedules on pooled planar one-particle values (which satisfy
+    A_{n,-m} = conj(A_{n,m})) against the oracle."""
+    from oracle import contraction as oc
+    from oracle import onebody as ob
+    from oracle.indexsets import all_invariant_tuples, group_so2
+    import workloads as wl
+    if group == "so2":
+        G = ace.Graph(4, 8, 4, 4, group=ace.GROUP_SO2, host_only=True)
+        g = group_so2(4, 4, 8)
+        K = all_invariant_tuples(g, 4, 8)
+    else:
+        G = ace.Graph(5, 8, group=ace.GROUP_TORUS, host_only=True)
+        g = group_torus(8)
+        K = all_invariant_tuples(g, 5, 8)
+    G.set_schedule(schedule="remat")
+    c = np.random.default_rng(4).standard_normal(len(K))
+    off = np.array([0, 6, 13, 20], np.int32)
+    pos = wl.planar_positions(20, 6, circle=group == "torus")
+    A = ob.pooled_A(g.labels, off, pos, 5.0)
+    for folded in (False, True):
+        phi, ab = G.remat_eval_host(c, A, folded=folded)
+        pr = oc.phi_naive(K, c, A)
+        assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)

@@ -41,10 +41,11 @@ class Workload:
     l_max: int
     coeff_power: int
     r_cut: float = 5.0
+    group: int = 0          # 0 O(3) (shell in 3D), 1 torus (unit circle), 2 SO(2) (annulus)
 
     def spec(self) -> dict:
         return dict(nu_max=self.nu_max, degree_max=self.degree_max, n_max=self.n_max,
-                    l_max=self.l_max, r_cut=self.r_cut)
+                    l_max=self.l_max, r_cut=self.r_cut, group=self.group)
 
 
 WORKLOADS = {
@@ -53,6 +54,9 @@ WORKLOADS = {
     3: Workload(3, "phi+forces-4096", 4096, "poisson", 24.0, 4, 64, 4, 12, 6, 6, 2),
     4: Workload(4, "uneven-32768", 32768, "loguniform", 0.0, 2, 96, 5, 14, 8, 8, 2),
     5: Workload(5, "large-basis-8192", 8192, "poisson", 40.0, 1, 128, 6, 16, 10, 10, 2),
+    # planar groups (Sec. 2.2, 2.3): for SO(2) l_max is the largest |m|
+    6: Workload(6, "so2-4096", 4096, "poisson", 24.0, 4, 64, 6, 16, 8, 8, 2, group=2),
+    7: Workload(7, "torus-4096", 4096, "poisson", 24.0, 4, 64, 8, 24, 0, 0, 2, group=1),
 }
 
 
@@ -86,12 +90,28 @@ def positions(n: int, seed_wid: int) -> np.ndarray:
     return d * r[:, None]
 
 
+def planar_positions(n: int, seed_wid: int, circle: bool) -> np.ndarray:
+    """n positions in the plane z = 0: on the unit circle (torus) or uniform in
+    the area of the annulus r_min < r < r_max (SO(2)); [n, 3] float64."""
+    g = _rng(seed_wid, 1)
+    th = g.uniform(-np.pi, np.pi, size=n)
+    if circle:
+        r = np.ones(n)
+    else:
+        u = g.uniform(0.0, 1.0, size=n)
+        r = np.sqrt(R_MIN ** 2 + u * (R_MAX ** 2 - R_MIN ** 2))
+    return np.stack([r * np.cos(th), r * np.sin(th), np.zeros(n)], axis=-1)
+
+
 def batch(w: Workload, n_env: int | None = None):
     """(offsets int32 [E+1], positions float64 [N, 3]) for workload w."""
     J = neighbour_counts(w, n_env)
     offsets = np.zeros(len(J) + 1, dtype=np.int64)
     np.cumsum(J, out=offsets[1:])
-    pos = positions(int(offsets[-1]), w.wid)
+    if w.group == 0:
+        pos = positions(int(offsets[-1]), w.wid)
+    else:
+        pos = planar_positions(int(offsets[-1]), w.wid, circle=w.group == 1)
     return offsets.astype(np.int32), pos
 
 
