@@ -267,6 +267,21 @@ def main():
         wall = time.perf_counter() - t
         return a.elapsed_time(b) / steps, wall
 
+    def distribution(fn, reps, warmup):
+        """Per-replay times (ms) from an event pair around each call: median, p10, p90."""
+        for _ in range(warmup):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in ev])
+        return dict(median=float(np.median(t)), p10=float(np.percentile(t, 10)), p90=float(np.percentile(t, 90)),
+                    replays=reps)
+
     # schedule autotuning on this batch (setup, outside the timed region)
     A = ace.basis(G, toff, tpos)
     tuned = None
@@ -297,6 +312,9 @@ def main():
     ms_dag_eager, _ = timed(step_dag, args.steps, args.warmup)
     ms_dag, wall = (ms_dag_eager, None) if args.eager else timed(graphed(step_dag), args.steps, args.warmup)
     print(f"[bench] DAG phi+forces: {ms_dag:.3f} ms/step (eager {ms_dag_eager:.3f})", file=sys.stderr, flush=True)
+    dist = None
+    if not args.eager:
+        dist = distribution(graphed(step_dag), max(args.steps, 10) if ms_dag < 20 else args.steps, 2)
     phi_dag, grad_dag = phi.clone(), grad.clone()
     ms_naive_eager, _ = timed(step_naive, args.steps, args.warmup)
     ms_naive = ms_naive_eager if args.eager else timed(graphed(step_naive), args.steps, args.warmup)[0]
@@ -377,6 +395,7 @@ def main():
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": profiled_traffic(args.workload), "kernel_ms": ms_kernel, "flops_per_env": fl},
         "eager_ms_per_step": ms_dag_eager,
+        "step_ms_distribution": dist,
         "timing": "eager launches" if args.eager else "hipGraph replays of one captured step",
         "schedule": G.get_schedule(),
         "schedule_kind": kind,

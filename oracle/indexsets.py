@@ -8,6 +8,8 @@ Paper passages followed:
   * torus one-particle index m, invariant tuples sum m = 0  (Sec. 2.3)
   * SO(2) one-particle index (n, m), invariant tuples sum m = 0; degree
     n + |m|  (Sec. 2.2, Sec. 2.5)
+  * O(3) with an invariant feature, index (n, l, m, k), degree n + l + k
+    (Sec. 5.4)
   * total degree p = 1: sum over the tuple of (n_t + l_t), resp. |m_t|
     (Sec. 2.5, Eq. (2.3); Sec. 3 explicit sets K_G(nu, D)); the other
     degree notions of Sec. 2.5, the p-norm of the per-element degrees, for
@@ -18,6 +20,7 @@ Canonical order (the paper leaves it open; fixed reading):
   * O(3): one-particle triples sorted by (n + l, l, m) ascending.
   * torus: m sorted by (|m|, m) ascending, i.e. 0, -1, 1, -2, 2, ...
   * SO(2): pairs (n, m) sorted by (n + |m|, |m|, m) ascending.
+  * O(3) with a feature: (n, l, m, k) sorted by (n + l + k, l, k, m).
   A tuple is the non-decreasing list of positions in that list; sets of
   tuples are ordered by length, then lexicographically.  The element of
   largest degree is therefore the last one.
@@ -47,6 +50,17 @@ def onebody_o3(n_max: int, l_max: int, degree_max: int) -> list[tuple[int, int, 
             for m in range(-l, l + 1):
                 out.append((n, l, m))
     out.sort(key=lambda t: (t[0] + t[1], t[1], t[2]))
+    return out
+
+
+def onebody_o3_features(n_max: int, l_max: int, k_max: int, degree_max: int) -> list[tuple[int, int, int, int]]:
+    """O(3) with one invariant feature (Sec. 5.4): phi_nlmk = R_n Y_l^m T_k(mu),
+    degree n + l + k <= D; quadruples (n, l, m, k) sorted by (n + l + k, l, k, m)
+    (the k tie-break keeps the 2l+1 functions of one (n, l, k) consecutive;
+    with k_max = 0 this is the plain O(3) order)."""
+    out = [(n, l, m, k) for n in range(n_max + 1) for l in range(l_max + 1) for k in range(k_max + 1)
+           if n + l + k <= degree_max for m in range(-l, l + 1)]
+    out.sort(key=lambda t: (t[0] + t[1] + t[3], t[1], t[3], t[2]))
     return out
 
 
@@ -118,6 +132,14 @@ def group_o3(n_max: int, l_max: int, degree_max: int) -> Group:
     lab = onebody_o3(n_max, l_max, degree_max)
     return Group("O3", lab, [n + l for (n, l, m) in lab], [m for (_, _, m) in lab],
                  [l for (_, l, _) in lab], True)
+
+
+def group_o3_features(n_max: int, l_max: int, k_max: int, degree_max: int) -> Group:
+    """Sec. 5.4: the invariance conditions of O(3) (sum m = 0, sum l even); the
+    feature only adds to the degree."""
+    lab = onebody_o3_features(n_max, l_max, k_max, degree_max)
+    return Group("O3f", lab, [n + l + k for (n, l, m, k) in lab], [m for (_, _, m, _) in lab],
+                 [l for (_, l, _, _) in lab], True)
 
 
 def group_so2(n_max: int, m_max: int, degree_max: int) -> Group:

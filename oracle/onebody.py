@@ -86,7 +86,8 @@ def ylm(l: int, m: int, theta, phi):
 
 
 def _planar(labels) -> bool:
-    """Torus labels are integers m, SO(2) labels pairs (n, m), O(3) labels triples."""
+    """Torus labels are integers m, SO(2) labels pairs (n, m), O(3) labels triples
+    (quadruples with a feature)."""
     return len(labels) > 0 and (not isinstance(labels[0], tuple) or len(labels[0]) == 2)
 
 
@@ -133,11 +134,46 @@ def planar_gradients(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
     return out
 
 
+def _features(labels) -> bool:
+    return len(labels) > 0 and isinstance(labels[0], tuple) and len(labels[0]) == 4
+
+
+def feature_values(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """Sec. 5.4: phi_nlmk(r, mu) = R_n(r) Y_l^m(r_hat) T_k(mu); positions carry
+    the feature as a fourth column, pos [J, 4] = (x, y, z, mu); [J, P1]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    base_lab = sorted({(n, l, m) for (n, l, m, _) in labels})
+    base = onebody_values(base_lab, pos[:, :3], r_cut)
+    col = {t: i for i, t in enumerate(base_lab)}
+    Tk = chebyshev_T(max(k for (*_, k) in labels), pos[:, 3])
+    out = np.empty((pos.shape[0], len(labels)), dtype=np.complex128)
+    for i, (n, l, m, k) in enumerate(labels):
+        out[:, i] = base[:, col[(n, l, m)]] * Tk[:, k]
+    return out
+
+
+def feature_gradients(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
+    """grad over the position (the feature is a label): T_k(mu) grad(R_n Y_l^m);
+    complex [J, P1, 3]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    base_lab = sorted({(n, l, m) for (n, l, m, _) in labels})
+    base = onebody_gradients(base_lab, pos[:, :3], r_cut)
+    col = {t: i for i, t in enumerate(base_lab)}
+    Tk = chebyshev_T(max(k for (*_, k) in labels), pos[:, 3])
+    out = np.empty((pos.shape[0], len(labels), 3), dtype=np.complex128)
+    for i, (n, l, m, k) in enumerate(labels):
+        out[:, i, :] = base[:, col[(n, l, m)], :] * Tk[:, k][:, None]
+    return out
+
+
 def onebody_values(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
     """phi_i(r_j) for every one-particle label; [J, P1].  O(3) triples (n, l, m);
-    torus and SO(2) labels go to planar_values."""
+    torus and SO(2) labels go to planar_values, O(3) with a feature (n, l, m, k)
+    to feature_values."""
     if _planar(labels):
         return planar_values(labels, pos, r_cut)
+    if _features(labels):
+        return feature_values(labels, pos, r_cut)
     r, th, ph = spherical_coords(pos)
     nmax = max(n for (n, _, _) in labels)
     R = radial(nmax, r, r_cut)
@@ -155,6 +191,8 @@ def onebody_gradients(labels, pos: np.ndarray, r_cut: float) -> np.ndarray:
     (torus and SO(2) labels go to planar_gradients)."""
     if _planar(labels):
         return planar_gradients(labels, pos, r_cut)
+    if _features(labels):
+        return feature_gradients(labels, pos, r_cut)
     pos = np.asarray(pos, dtype=np.float64)
     r, th, ph = spherical_coords(pos)
     nmax = max(n for (n, _, _) in labels)
