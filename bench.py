@@ -95,7 +95,10 @@ def _worker_init(wid):
     threadpool_limits(1)
     from oracle.indexsets import all_invariant_tuples, group_o3, group_so2, group_torus
     w = wl.WORKLOADS[wid]
-    if w.group == 0:
+    if w.group == 0 and w.k_max > 0:
+        from oracle.indexsets import group_o3_features
+        g = group_o3_features(w.n_max, w.l_max, w.k_max, w.degree_max)
+    elif w.group == 0:
         g = group_o3(w.n_max, w.l_max, w.degree_max)
     elif w.group == 2:
         g = group_so2(w.n_max, w.l_max, w.degree_max)
@@ -237,7 +240,8 @@ def main():
     t0 = time.perf_counter()
     degree_p = {"1": 1, "2": 2, "inf": math.inf}[args.degree_p]
     G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut, algorithm=args.algorithm,
-                  alg_n=args.alg_n if args.algorithm == 2 else 1, degree_p=degree_p, group=w.group)
+                  alg_n=args.alg_n if args.algorithm == 2 else 1, degree_p=degree_p, group=w.group,
+                  k_max=w.k_max)
     t_build = time.perf_counter() - t0
     if args.schedule != "auto":
         G.set_schedule(schedule=args.schedule)
@@ -380,6 +384,7 @@ def main():
                                f"{['O(3)', 'torus', 'SO(2)'][w.group]}, nu<={w.nu_max}, "
                                f"{'total degree' if degree_p == 1 else f'degree p={args.degree_p}'}<={w.degree_max}, "
                                + ("" if w.group == 1 else f"n<={w.n_max}, {'l' if w.group == 0 else '|m|'}<={w.l_max}, ")
+                               + (f"feature k<={w.k_max} (4 species), " if w.k_max else "")
                                + f"Algorithm {args.algorithm}"
                                + (f" (n={args.alg_n})" if args.algorithm == 2 else ""),
                    "n_env": E, "n_nbr": N, "nu_max": w.nu_max, "degree_max": w.degree_max,

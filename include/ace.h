@@ -101,6 +101,11 @@ typedef int32_t ace_status;
  *   degree_p    ACE_DEGREE_P1 (total degree, also 0), ACE_DEGREE_P2 (sum of
  *               squared degrees <= D^2) or ACE_DEGREE_PINF (largest degree <= D)
  *   r_cut       radial scale of R_n (> 0)
+ *   k_max       O(3) only, 0..16: one invariant feature mu per neighbour
+ *               (Sec. 5.4), phi_nlmk = R_n Y_l^m T_k(mu) with Chebyshev T_k,
+ *               k <= k_max, degree n + l + k (0: no feature).  With k_max > 0
+ *               positions are [n_nbr][4] = (x, y, z, mu), mu in [-1, 1]; the
+ *               gradients stay [n_nbr][3].
  */
 #define ACE_DEGREE_P1 1
 #define ACE_DEGREE_P2 2
@@ -116,7 +121,7 @@ typedef struct ace_basis_spec {
   int32_t degree_p;
   double r_cut;
   uint32_t build_flags;
-  uint32_t reserved2;
+  int32_t k_max;
 } ace_basis_spec;
 
 /* Graph statistics (Sec. 3.1: K, D/I split is not computed; A = aux). */
@@ -227,6 +232,10 @@ ace_status ace_graph_export(const ace_graph* g, int32_t* onep, int32_t* node_tup
 
 /* Copy the tuples of K into a caller HOST buffer [|K|][nu_max], -1 padded. */
 ace_status ace_graph_export_k(const ace_graph* g, int32_t* k_tuples);
+
+/* Feature degree k of every one-particle function (host int32 [P1]; all 0
+ * without a feature). */
+ace_status ace_graph_export_feature(const ace_graph* g, int32_t* k);
 
 /*
  * Device workspace (bytes) needed by the evaluation calls below for n_env

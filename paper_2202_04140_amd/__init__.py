@@ -57,7 +57,7 @@ class _Spec(ctypes.Structure):
                 ("l_max", ctypes.c_int32), ("algorithm", ctypes.c_int32),
                 ("alg_n", ctypes.c_int32), ("degree_p", ctypes.c_int32),
                 ("r_cut", ctypes.c_double), ("build_flags", ctypes.c_uint32),
-                ("reserved2", ctypes.c_uint32)]
+                ("k_max", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
@@ -92,6 +92,7 @@ EXPORTED = {
     "ace_graph_info": ([_P, ctypes.POINTER(_Stats)], ctypes.c_int32),
     "ace_graph_export": ([_P, _P, _P, _P, _P], ctypes.c_int32),
     "ace_graph_export_k": ([_P, _P], ctypes.c_int32),
+    "ace_graph_export_feature": ([_P, _P], ctypes.c_int32),
     "ace_workspace_size": ([_P, _I64, _I64, _U32, ctypes.POINTER(_SZ)], ctypes.c_int32),
     "ace_basis": ([_P, _I64, _P, _P, _P, _P], ctypes.c_int32),
     "ace_contract": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
@@ -138,19 +139,22 @@ class Graph:
 
     def __init__(self, nu_max: int, degree_max: int, n_max: int = 0, l_max: int = 0, *,
                  group: int = GROUP_O3, algorithm: int = 1, alg_n: int = 1, r_cut: float = 5.0,
-                 degree_p=1, host_only: bool = False):
+                 degree_p=1, k_max: int = 0, host_only: bool = False):
         """degree_p: 1 (total degree), 2 or math.inf: the p-norm of the element
-        degrees bounded by degree_max (Sec. 2.5)."""
+        degrees bounded by degree_max (Sec. 2.5).  k_max > 0: one invariant
+        feature per neighbour (Sec. 5.4), positions then [n_nbr, 4] = (x, y, z, mu)."""
         code = {1: 1, 2: 2, math.inf: -1}.get(degree_p)
         if code is None:
             raise ValueError(f"degree_p must be 1, 2 or math.inf, got {degree_p!r}")
         spec = _Spec(group=group, nu_max=nu_max, degree_max=degree_max, n_max=n_max, l_max=l_max,
                      algorithm=algorithm, alg_n=alg_n, degree_p=code, r_cut=r_cut,
-                     build_flags=BUILD_HOST_ONLY if host_only else 0, reserved2=0)
+                     build_flags=BUILD_HOST_ONLY if host_only else 0, k_max=k_max)
         self._h = _P()
         _check(lib().ace_graph_build(ctypes.byref(spec), ctypes.byref(self._h)))
         self.spec = dict(group=group, nu_max=nu_max, degree_max=degree_max, n_max=n_max,
-                         l_max=l_max, algorithm=algorithm, alg_n=alg_n, r_cut=r_cut, degree_p=degree_p)
+                         l_max=l_max, algorithm=algorithm, alg_n=alg_n, r_cut=r_cut, degree_p=degree_p,
+                         k_max=k_max)
+        self.pos_cols = 4 if k_max > 0 else 3
         self.host_only = host_only
         st = self.stats()
         self.P1 = st["n_onep"]
@@ -193,13 +197,19 @@ class Graph:
         _check(lib().ace_graph_export_k(self._h, out.ctypes.data))
         return out
 
+    def onep_feature(self) -> np.ndarray:
+        """Feature degree k of every one-particle function (ace_graph_export_feature)."""
+        out = np.zeros(self.P1, dtype=np.int32)
+        _check(lib().ace_graph_export_feature(self._h, out.ctypes.data))
+        return out
+
     def k_degrees(self) -> np.ndarray:
         """Total degree sum_t (n_t + l_t) of every tuple of K (SO(2): n + |m|, torus: |m|)."""
         onep = self.export()[0]
         if self.spec["group"] == GROUP_TORUS:
             deg1 = np.abs(onep[:, 2])
         else:
-            deg1 = onep[:, 0] + onep[:, 1]   # SO(2): the l column holds |m|
+            deg1 = onep[:, 0] + onep[:, 1] + self.onep_feature()   # SO(2): the l column holds |m|
         kt = self.k_tuples()
         d = np.where(kt >= 0, deg1[np.maximum(kt, 0)], 0)
         return d.sum(axis=1)
@@ -304,11 +314,11 @@ def _check_coeffs(g: "Graph", coeffs):
         raise ValueError(f"coeffs must have shape [{g.nK}] (one per tuple of K), got {tuple(coeffs.shape)}")
 
 
-def _check_batch(offsets, pos, check: bool):
+def _check_batch(offsets, pos, check: bool, cols: int = 3):
     if offsets.dim() != 1 or offsets.numel() < 1:
         raise ValueError("offsets must be a 1-d tensor of n_env + 1 entries")
-    if pos.dim() != 2 or pos.shape[1] != 3:
-        raise ValueError(f"pos must have shape [n_nbr, 3], got {tuple(pos.shape)}")
+    if pos.dim() != 2 or pos.shape[1] != cols:
+        raise ValueError(f"pos must have shape [n_nbr, {cols}], got {tuple(pos.shape)}")
     if check and offsets.numel() > 1:
         last = int(offsets[-1].item())
         if last != pos.shape[0]:
@@ -325,7 +335,7 @@ def basis(g: Graph, offsets, pos):
     import torch
     _dev(offsets, torch.int32, "offsets")
     _dev(pos, torch.float64, "pos")
-    _check_batch(offsets, pos, True)
+    _check_batch(offsets, pos, True, g.pos_cols)
     E = offsets.numel() - 1
     A = torch.empty((E, g.P1, 2), dtype=torch.float64, device=pos.device)
     _check(lib().ace_basis(g.handle, E, offsets.data_ptr(), pos.data_ptr(), A.data_ptr(),
@@ -364,7 +374,7 @@ def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = F
     _dev(offsets, torch.int32, "offsets")
     _dev(pos, torch.float64, "pos")
     _check_coeffs(g, coeffs)
-    _check_batch(offsets, pos, check)
+    _check_batch(offsets, pos, check, g.pos_cols)
     E = offsets.numel() - 1
     phi = out if out is not None else torch.empty((E, 2), dtype=torch.float64, device=pos.device)
     flags = ((FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
@@ -383,13 +393,13 @@ def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: boo
     _dev(offsets, torch.int32, "offsets")
     _dev(pos, torch.float64, "pos")
     _check_coeffs(g, coeffs)
-    _check_batch(offsets, pos, check)
+    _check_batch(offsets, pos, check, g.pos_cols)
     E = offsets.numel() - 1
     if out is not None:
         phi, grad = out
     else:
         phi = torch.empty((E, 2), dtype=torch.float64, device=pos.device)
-        grad = torch.empty_like(pos)
+        grad = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
     flags = ((FLAG_NAIVE if naive else 0) | (FLAG_CHECK if check else 0) | (FLAG_LAYERED if layered else 0)
              | (FLAG_UNFOLDED if unfolded else 0))
     ws = g.workspace(E, pos.device, flags)
@@ -405,15 +415,18 @@ def _autograd():
     class AceEnergy(torch.autograd.Function):
         """Re(phi_e) per environment; backward scatters grad_out[e] * g_j.
 
-        forward(pos [N,3] f64, offsets [E+1] i32, coeffs [|K|] f64, graph)
-        The gradient with respect to pos comes from ace_eval_grad; offsets,
-        coeffs and the graph get none.  Double backward is not supported.
+        forward(pos [N,3] f64 (or [N,4] with a feature column), offsets [E+1] i32,
+        coeffs [|K|] f64, graph)
+        The gradient with respect to the positions comes from ace_eval_grad
+        (the feature column gets zero); offsets, coeffs and the graph get
+        none.  Double backward is not supported.
         """
 
         @staticmethod
         def forward(ctx, pos, offsets, coeffs, graph):
             phi, grad = eval_grad(graph, coeffs, offsets, pos.detach().contiguous())
             ctx.save_for_backward(grad, offsets)
+            ctx.pos_cols = pos.shape[1]
             return phi[:, 0].clone()
 
         @staticmethod
@@ -422,7 +435,10 @@ def _autograd():
             grad, offsets = ctx.saved_tensors
             counts = (offsets[1:] - offsets[:-1]).long()
             w = torch.repeat_interleave(grad_out.contiguous(), counts, output_size=grad.shape[0])
-            return grad * w[:, None], None, None, None
+            g = grad * w[:, None]
+            if ctx.pos_cols == 4:
+                g = torch.cat([g, torch.zeros_like(g[:, :1])], dim=1)
+            return g, None, None, None
 
     return AceEnergy
 

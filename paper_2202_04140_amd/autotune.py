@@ -51,6 +51,7 @@ SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 def _key(graph: Graph, n_env: int, device_name: str) -> str:
     s = graph.spec
     p = "" if s.get("degree_p", 1) == 1 else f"|p{s['degree_p']}"
+    p += "" if not s.get("k_max", 0) else f"|k{s['k_max']}"
     return (f"{device_name}|g{s['group']}|nu{s['nu_max']}|D{s['degree_max']}|n{s['n_max']}|l{s['l_max']}"
             f"|alg{s['algorithm']}.{s['alg_n']}{p}|E{n_env}")
 

@@ -271,15 +271,17 @@ void make_schedule(ace_graph* g) {
       o.sim = (int8_t)(m < 0 ? -sgn : 1);
       o.l = (int8_t)l;
       o.am = (int8_t)am;
+      o.k = (int8_t)h.on_k[i];
       g->onep.push_back(o);
-      g->onep_index[(size_t)(n * (L + 1) + l) * W + (m + L)] = (int16_t)i;
+      if (h.on_k[i] == 0) g->onep_index[(size_t)(n * (L + 1) + l) * W + (m + L)] = (int16_t)i;
     }
     make_ycoef(L, g->ycoef);
-    // index of (n, l, -l) per (l, n); the 2l+1 functions of one (n, l) are
-    // consecutive in the canonical order
-    g->nstart.assign((size_t)(L + 1) * (N + 1), -1);
+    // index of (n, l, -l, k) per (l, n, k); the 2l+1 functions of one (n, l, k)
+    // are consecutive in the canonical order
+    const int K1 = h.spec.k_max + 1;
+    g->nstart.assign((size_t)(L + 1) * (N + 1) * K1, -1);
     for (int i = 0; i < P1; ++i)
-      if (h.on_m[i] == -h.on_l[i]) g->nstart[(size_t)h.on_l[i] * (N + 1) + h.on_n[i]] = i;
+      if (h.on_m[i] == -h.on_l[i]) g->nstart[((size_t)h.on_l[i] * (N + 1) + h.on_n[i]) * K1 + h.on_k[i]] = i;
   } else {
     // planar groups: phi = R_n (Re E, sim Im E), E = u^{|m|}, sim = s sign(m) with
     // s = +1 (torus, e^{+i m theta}) or -1 (SO(2), e^{-i m theta}); onep_index
@@ -1169,7 +1171,7 @@ std::vector<int64_t> conj_partners(const HostGraph& h) {
   std::vector<int32_t> cj(P1, -1);
   for (int i = 0; i < P1; ++i)
     for (int j = 0; j < P1; ++j)
-      if (h.on_n[j] == h.on_n[i] && h.on_l[j] == h.on_l[i] && h.on_m[j] == -h.on_m[i]) {
+      if (h.on_n[j] == h.on_n[i] && h.on_l[j] == h.on_l[i] && h.on_m[j] == -h.on_m[i] && h.on_k[j] == h.on_k[i]) {
         cj[i] = j;
         break;
       }
@@ -1660,6 +1662,7 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
     a.l_max = planar_m(g->h);
     a.r_cut = g->h.spec.r_cut;
     a.group = g->h.spec.group;
+    a.pos_stride = 3;
     hipLaunchKernelGGL(planar_basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), 0, s, a);
     ACE_HIP(hipGetLastError());
     return ACE_OK;
@@ -1675,9 +1678,12 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   a.n_max = g->h.spec.n_max;
   a.l_max = g->h.spec.l_max;
   a.r_cut = g->h.spec.r_cut;
+  a.group = 0;
+  a.k_max = g->h.spec.k_max;
+  a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const int chunk = kBasisThreads / (a.l_max + 1);
-  const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * ((a.n_max + 1) + 2 * NY) * 8;
+  const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * ((a.n_max + 1) + (a.k_max + 1) + 2 * NY) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the basis kernel");
   hipLaunchKernelGGL(basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
   ACE_HIP(hipGetLastError());
@@ -1897,6 +1903,7 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
     a.r_cut = g->h.spec.r_cut;
     a.group = g->h.spec.group;
     a.pidx = g->d_onep_index;
+    a.pos_stride = 3;
     const size_t lds = (size_t)g->P1 * sizeof(double2);
     if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
     hipLaunchKernelGGL(planar_grad_kernel, dim3((unsigned)grid_for(n_env)), dim3(kGradThreads), lds, s, a);
@@ -1916,6 +1923,9 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.n_max = g->h.spec.n_max;
   a.l_max = g->h.spec.l_max;
   a.r_cut = g->h.spec.r_cut;
+  a.group = 0;
+  a.k_max = g->h.spec.k_max;
+  a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const int nwb = kGradThreads / 64;
   const size_t lds = (size_t)nwb * g->P1 * 16 + (size_t)3 * NY * 8 + g->nstart.size() * 4;
@@ -1970,6 +1980,7 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out) {
     bs.algorithm = spec->algorithm;
     bs.alg_n = spec->alg_n;
     bs.degree_p = spec->degree_p == 0 ? 1 : spec->degree_p;
+    bs.k_max = spec->k_max;
     bs.r_cut = spec->r_cut;
     build_graph(bs, g->h);
     make_schedule(g);
@@ -2024,6 +2035,12 @@ ace_status ace_graph_export(const ace_graph* g, int32_t* onep, int32_t* node_tup
   if (node_tuple) std::memcpy(node_tuple, h.node_flat.data(), h.node_flat.size() * 4);
   if (parents) std::memcpy(parents, h.par.data(), h.par.size() * 4);
   if (k_to_node) std::memcpy(k_to_node, h.k_to_node.data(), h.k_to_node.size() * 8);
+  return ACE_OK;
+}
+
+ace_status ace_graph_export_feature(const ace_graph* g, int32_t* k) {
+  if (!g || !k) return fail(ACE_ERR_INVALID_ARG, "graph and k must be non-NULL");
+  std::memcpy(k, g->h.on_k.data(), g->h.on_k.size() * 4);
   return ACE_OK;
 }
 

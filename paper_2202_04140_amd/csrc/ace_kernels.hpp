@@ -19,6 +19,7 @@ struct OnepInfo {
   int8_t sim;     // +1 / -1 applied to Im Y_l^{|m|}
   int8_t l;
   int8_t am;      // |m|
+  int8_t k;       // feature degree (Sec. 5.4), 0 without a feature
 };
 
 struct BasisArgs {
@@ -31,6 +32,8 @@ struct BasisArgs {
   int P1, n_max, l_max;
   double r_cut;
   int group;             // 0 O(3); planar: 1 torus, 2 SO(2)
+  int k_max;             // O(3) feature degree; positions then carry mu as a fourth column
+  int pos_stride;        // doubles per position: 3, or 4 with a feature
 };
 
 // Planar one-particle functions (torus, SO(2)): phi_i = R_n(r) e^{i s m theta}
@@ -76,12 +79,14 @@ struct GradArgs {
   const double2* Abar;       // [n_env][P1]
   double* grad;              // [n_nbr][3]
   const int16_t* onep_index; // [(n_max+1)][(l_max+1)][(2 l_max+1)] -> i or -1
-  const int32_t* nstart;     // [(l_max+1)][(n_max+1)]: index of (n, l, -l), or -1
+  const int32_t* nstart;     // [(l_max+1)][(n_max+1)][(k_max+1)]: index of (n, l, -l, k), or -1
   const double* ycoef;
   int P1, n_max, l_max;
   double r_cut;
   int group;                 // 0 O(3); planar: 1 torus, 2 SO(2)
   const int16_t* pidx;       // planar: [(n_max+1)][(2 m_max+1)] -> i or -1 (m_max = l_max)
+  int k_max;                 // O(3) feature degree (nstart is then [l][n][k])
+  int pos_stride;            // doubles per position: 3, or 4 with a feature
 };
 
 }  // namespace ace

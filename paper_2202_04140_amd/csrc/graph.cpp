@@ -174,17 +174,21 @@ struct Builder {
 void make_onebody(HostGraph& g) {
   const BuildSpec& s = g.spec;
   struct T {
-    int n, l, m, deg;
+    int n, l, m, deg, k = 0;
   };
   std::vector<T> v;
   if (s.group == 0) {
+    // with an invariant feature (Sec. 5.4) the degree is n + l + k; the order
+    // (deg, l, k, m) keeps the 2l+1 functions of one (n, l, k) consecutive
     for (int n = 0; n <= s.n_max; ++n)
       for (int l = 0; l <= s.l_max; ++l)
-        if (n + l <= s.degree_max)
-          for (int m = -l; m <= l; ++m) v.push_back({n, l, m, n + l});
+        for (int k = 0; k <= s.k_max; ++k)
+          if (n + l + k <= s.degree_max)
+            for (int m = -l; m <= l; ++m) v.push_back({n, l, m, n + l + k, k});
     std::stable_sort(v.begin(), v.end(), [](const T& a, const T& b) {
       if (a.deg != b.deg) return a.deg < b.deg;
       if (a.l != b.l) return a.l < b.l;
+      if (a.k != b.k) return a.k < b.k;
       return a.m < b.m;
     });
   } else if (s.group == 2) {
@@ -212,6 +216,7 @@ void make_onebody(HostGraph& g) {
     g.on_n.push_back(t.n);
     g.on_l.push_back(t.l);
     g.on_m.push_back(t.m);
+    g.on_k.push_back(t.k);
     g.on_deg.push_back(t.deg);
   }
 }
@@ -278,6 +283,8 @@ void build_graph(const BuildSpec& spec, HostGraph& g) {
   }
   if (spec.algorithm != 1 && spec.algorithm != 2) throw std::invalid_argument("algorithm must be 1 or 2");
   if (spec.algorithm == 2 && spec.alg_n < 1) throw std::invalid_argument("alg_n must be >= 1");
+  if (spec.k_max < 0 || spec.k_max > 16) throw std::invalid_argument("k_max must be in 0..16");
+  if (spec.k_max > 0 && spec.group != 0) throw std::invalid_argument("invariant features need the O(3) group");
   if (spec.degree_p != 1 && spec.degree_p != 2 && spec.degree_p != -1)
     throw std::invalid_argument("degree_p must be 1, 2 or -1 (infinity)");
   if (!(spec.r_cut > 0.0)) throw std::invalid_argument("r_cut must be > 0");

@@ -23,6 +23,7 @@ struct BuildSpec {
   int algorithm = 1;
   int alg_n = 1;
   int degree_p = 1;    // 1, 2, or -1 for p = infinity (Sec. 2.5)
+  int k_max = 0;       // O(3): degree of the invariant-feature polynomials T_k (Sec. 5.4)
   double r_cut = 5.0;
 };
 
@@ -51,7 +52,7 @@ struct HostGraph {
 
   // one-particle list in canonical order (n+l, l, m) (torus: (|m|, m))
   int P1 = 0;
-  std::vector<int32_t> on_n, on_l, on_m, on_deg;
+  std::vector<int32_t> on_n, on_l, on_m, on_k, on_deg;
 
   // K in canonical order: by length, then lexicographic
   int64_t nK = 0;

@@ -88,7 +88,8 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
   extern __shared__ double lds_b[];
   const int L = p.l_max;
   const int NY = (L + 1) * (L + 2) / 2;
-  const int stride = (p.n_max + 1) + 2 * NY;        // doubles per neighbour
+  const int K1 = p.k_max + 1;
+  const int stride = (p.n_max + 1) + K1 + 2 * NY;   // doubles per neighbour: T_n(cos), T_k(mu), Y
   const int chunk = blockDim.x / (L + 1);           // neighbours per chunk
   double2* acc = reinterpret_cast<double2*>(lds_b);  // [P1]
   double* tab = lds_b + 2 * p.P1;                    // [chunk][stride]
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
       __syncthreads();
       const int jj = threadIdx.x / (L + 1), m = threadIdx.x % (L + 1);
       if (jj < nc) {
-        const double* r = p.pos + 3 * (int64_t)(j0 + c0 + jj);
+        const double* r = p.pos + p.pos_stride * (int64_t)(j0 + c0 + jj);
         const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
         const double inv = 1.0 / rr;
         const double x = r[0] * inv, y = r[1] * inv, z = r[2] * inv;
@@ -120,6 +121,18 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
             t0 = t1;
             t1 = t2;
           }
+          // feature polynomials T_k(mu) (Sec. 5.4)
+          double* tk = t + (p.n_max + 1);
+          const double mu = K1 > 1 ? r[3] : 0.0;
+          double k0 = 1.0, k1 = mu;
+          tk[0] = 1.0;
+          if (K1 > 1) tk[1] = mu;
+          for (int k = 2; k < K1; ++k) {
+            const double k2 = 2.0 * mu * k1 - k0;
+            tk[k] = k2;
+            k0 = k1;
+            k1 = k2;
+          }
         }
         double pr = 1.0, pi = 0.0;  // (x + i y)^m
         for (int k = 0; k < m; ++k) {
@@ -127,7 +140,7 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
           pi = pr * y + pi * x;
           pr = nr;
         }
-        double* Y = t + (p.n_max + 1);
+        double* Y = t + (p.n_max + 1) + K1;
         double q2 = 0.0, q1 = cS[(m * (m + 1)) / 2 + m];
         for (int l = m; l <= L; ++l) {
           const int o = (l * (l + 1)) / 2 + m;
@@ -147,8 +160,8 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
         const double sre = (double)o.sre, sim = (double)o.sim;
         for (int k = 0; k < nc; ++k) {
           const double* t = tab + k * stride;
-          const double R = t[o.n];
-          const double* Y = t + (p.n_max + 1) + 2 * o.yoff;
+          const double R = t[o.n] * t[p.n_max + 1 + o.k];
+          const double* Y = t + (p.n_max + 1) + K1 + 2 * o.yoff;
           a.x = fma(R, sre * Y[0], a.x);
           a.y = fma(R, sim * Y[1], a.y);
         }
@@ -330,9 +343,10 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
   const int nwb = blockDim.x >> 6;
   double2* Ab = lds + wid * p.P1;                                    // [nwb][P1]
   double* yc = reinterpret_cast<double*>(lds + nwb * p.P1);           // [3 * NY]
-  int* nst = reinterpret_cast<int*>(yc + 3 * NY);                    // [(L+1)*(N+1)]
+  int* nst = reinterpret_cast<int*>(yc + 3 * NY);                    // [(L+1)*(N+1)*(k_max+1)]
   for (int i = threadIdx.x; i < 3 * NY; i += blockDim.x) yc[i] = p.ycoef[i];
-  for (int i = threadIdx.x; i < (L + 1) * (N + 1); i += blockDim.x) nst[i] = p.nstart[i];
+  const int K1 = p.k_max + 1;
+  for (int i = threadIdx.x; i < (L + 1) * (N + 1) * K1; i += blockDim.x) nst[i] = p.nstart[i];
   const double* cA = yc;
   const double* cB = yc + NY;
   const double* cS = yc + 2 * NY;
@@ -356,7 +370,9 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
     for (int c0 = 0; c0 < J; c0 += per) {
       const int jj = min(c0 + jl, J - 1);   // idle lanes repeat the last neighbour
       const int64_t j = j0 + jj;
-      const double rx = p.pos[3 * j], ry = p.pos[3 * j + 1], rz = p.pos[3 * j + 2];
+      const double* rp = p.pos + p.pos_stride * j;
+      const double rx = rp[0], ry = rp[1], rz = rp[2];
+      const double mu = K1 > 1 ? rp[3] : 0.0;   // invariant feature (Sec. 5.4)
       const double rr = sqrt(rx * rx + ry * ry + rz * rz);
       const double inv = 1.0 / rr;
       const double x = rx * inv, y = ry * inv, z = rz * inv;
@@ -445,18 +461,31 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
               d0 = d1;
               d1 = dT;
             }
-            const int base = nst[l * (N + 1) + n];
-            if (base >= 0) {
-              const double2 ap = Ab[base + l + m];
-              b0pr = fma(ap.x, T, b0pr);
-              b0pi = fma(ap.y, T, b0pi);
-              b1pr = fma(ap.x, dT, b1pr);
-              b1pi = fma(ap.y, dT, b1pi);
-              const double2 am = Ab[base + l - m];
-              b0mr = fma(am.x, T, b0mr);
-              b0mi = fma(am.y, T, b0mi);
-              b1mr = fma(am.x, dT, b1mr);
-              b1mi = fma(am.y, dT, b1mi);
+            // the feature factor T_k(mu) of every (n, l, k), k = 0..k_max
+            double k0 = 1.0, k1 = mu;
+            for (int k = 0; k < K1; ++k) {
+              double Tk = 1.0;
+              if (k == 1) {
+                Tk = mu;
+              } else if (k >= 2) {
+                Tk = 2.0 * mu * k1 - k0;
+                k0 = k1;
+                k1 = Tk;
+              }
+              const int base = nst[(l * (N + 1) + n) * K1 + k];
+              if (base >= 0) {
+                const double w = T * Tk, dw = dT * Tk;
+                const double2 ap = Ab[base + l + m];
+                b0pr = fma(ap.x, w, b0pr);
+                b0pi = fma(ap.y, w, b0pi);
+                b1pr = fma(ap.x, dw, b1pr);
+                b1pi = fma(ap.y, dw, b1pi);
+                const double2 am = Ab[base + l - m];
+                b0mr = fma(am.x, w, b0mr);
+                b0mi = fma(am.y, w, b0mi);
+                b1mr = fma(am.x, dw, b1mr);
+                b1mi = fma(am.y, dw, b1mi);
+              }
             }
           }
           // +m: Y = S; -m: Y_l^{-m} = (-1)^m conj(Y_l^m) (same for the gradient);

@@ -343,3 +343,42 @@ def test_folded_remat_planar_matches_oracle(group):
         phi, ab = G.remat_eval_host(c, A, folded=folded)
         pr = oc.phi_naive(K, c, A)
         assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+
+
+# ---- invariant features (Sec. 5.4) ---------------------------------------------------
+@pytest.mark.parametrize("spec,kmax,alg,n", [((3, 3, 7, 3), 2, 1, 1), ((2, 2, 6, 4), 3, 2, 2)])
+def test_builder_bit_exact_features(spec, kmax, alg, n):
+    from oracle.indexsets import group_o3_features
+    nmax, lmax, D, nu = spec
+    g = ace.Graph(nu, D, nmax, lmax, k_max=kmax, algorithm=alg, alg_n=n, host_only=True)
+    onep, tup, par, k2n = g.export()
+    G, otup, opar, ok2n = oracle_arrays(group_o3_features(nmax, lmax, kmax, D), nu, D, alg, n)
+    assert [(int(a), int(b), int(c), int(k)) for (a, b, c), k in zip(onep, g.onep_feature())] == G.group.labels
+    np.testing.assert_array_equal(tup, otup)
+    np.testing.assert_array_equal(par, opar)
+    np.testing.assert_array_equal(k2n, ok2n)
+    assert np.array_equal(g.k_degrees(), [G.group.degree(k) for k in G.K])
+
+
+def test_features_invalid_and_remat_folded():
+    from oracle import contraction as oc
+    from oracle import onebody as ob
+    from oracle.indexsets import all_invariant_tuples, group_o3_features
+    with pytest.raises(ace.AceError):
+        ace.Graph(3, 6, 2, 2, k_max=17, host_only=True)
+    with pytest.raises(ace.AceError):
+        ace.Graph(3, 6, 2, 2, group=ace.GROUP_SO2, k_max=1, host_only=True)
+    G = ace.Graph(4, 8, 3, 3, k_max=2, host_only=True)
+    G.set_schedule(schedule="remat")
+    g = group_o3_features(3, 3, 2, 8)
+    K = all_invariant_tuples(g, 4, 8)
+    c = np.random.default_rng(2).standard_normal(len(K))
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((15, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pos = np.concatenate([d * rng.uniform(0.5, 5, 15)[:, None], rng.uniform(-1, 1, (15, 1))], axis=1)
+    A = ob.pooled_A(g.labels, np.array([0, 7, 15]), pos, 5.0)
+    for folded in (False, True):
+        phi, _ = G.remat_eval_host(c, A, folded=folded)
+        pr = oc.phi_naive(K, c, A)
+        assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)

@@ -14,7 +14,7 @@ stand in for "atomic environments"):
   * coefficients c_k = N(0, 1) / (1 + deg_k)^q with deg_k = sum_t (n_t + l_t)
     supplied by the caller from its own listing of K;
   * seed = 1000 * workload id + stream (0 counts, 1 positions,
-    2 coefficients).
+    2 coefficients, 3 species features).
 """
 
 from __future__ import annotations
@@ -42,10 +42,11 @@ class Workload:
     coeff_power: int
     r_cut: float = 5.0
     group: int = 0          # 0 O(3) (shell in 3D), 1 torus (unit circle), 2 SO(2) (annulus)
+    k_max: int = 0          # O(3) invariant feature degree (Sec. 5.4); positions get a mu column
 
     def spec(self) -> dict:
         return dict(nu_max=self.nu_max, degree_max=self.degree_max, n_max=self.n_max,
-                    l_max=self.l_max, r_cut=self.r_cut, group=self.group)
+                    l_max=self.l_max, r_cut=self.r_cut, group=self.group, k_max=self.k_max)
 
 
 WORKLOADS = {
@@ -57,6 +58,8 @@ WORKLOADS = {
     # planar groups (Sec. 2.2, 2.3): for SO(2) l_max is the largest |m|
     6: Workload(6, "so2-4096", 4096, "poisson", 24.0, 4, 64, 6, 16, 8, 8, 2, group=2),
     7: Workload(7, "torus-4096", 4096, "poisson", 24.0, 4, 64, 8, 24, 0, 0, 2, group=1),
+    # one invariant feature per neighbour (four species, mu in {-1, -1/3, 1/3, 1})
+    8: Workload(8, "species-4096", 4096, "poisson", 24.0, 4, 64, 4, 12, 6, 6, 2, k_max=3),
 }
 
 
@@ -110,9 +113,18 @@ def batch(w: Workload, n_env: int | None = None):
     np.cumsum(J, out=offsets[1:])
     if w.group == 0:
         pos = positions(int(offsets[-1]), w.wid)
+        if w.k_max > 0:
+            pos = np.concatenate([pos, species_feature(int(offsets[-1]), w.wid)[:, None]], axis=1)
     else:
         pos = planar_positions(int(offsets[-1]), w.wid, circle=w.group == 1)
     return offsets.astype(np.int32), pos
+
+
+def species_feature(n: int, seed_wid: int, n_species: int = 4) -> np.ndarray:
+    """A species label per neighbour, encoded as mu = -1 + 2 s / (n_species - 1)."""
+    g = _rng(seed_wid, 3)
+    s = g.integers(0, n_species, size=n)
+    return -1.0 + 2.0 * s / (n_species - 1)
 
 
 def coefficients(w: Workload, degrees: np.ndarray) -> np.ndarray:
