@@ -1056,12 +1056,16 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     for (int k = 0; k < 4; ++k)
       R.hot[k] = (k < g->opts.hot_columns && k < P1 && freq[ord[k]] * 64 >= npush) ? ord[k] : ONE;
   }
-  auto pack = [&](int32_t node, int from) {
+  // factors of a row node, rotated by `rot`: lanes of a slice start their
+  // factor lists at different positions, so rows that share leading factors
+  // (neighbours in tuple order) do not push to one address in one instruction
+  auto pack = [&](int32_t node, int from, int rot = 0) {
     const int count = h.node_len[node];
     uint64_t w = 0;
     for (int u = 0; u < 4; ++u) {
       const int idx = from + u;
-      const uint64_t sl = 16 * (idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + idx] : (uint64_t)ONE);
+      const uint64_t sl =
+          16 * (idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + (idx + rot) % count] : (uint64_t)ONE);
       w |= sl << (16 * u);
     }
     return w;
@@ -1084,11 +1088,14 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     if (R.fold) R.kbar.resize(P1 + e0 + 64 * (size_t)ncol, -1);
     // per lane: its entries, then their column and factor rotation
     std::vector<std::vector<int64_t>> lane_ents(64);
+    // lanes start their row factor lists at different positions (lane mod nb)
+    int rot[64] = {0};
+    for (int lane = 0; lane < 64; ++lane) rot[lane] = i0 + lane < i1 ? lane % items[i0 + lane].nb : 0;
     for (int lane = 0; lane < 64; ++lane) {
       if (i0 + lane < i1) {
         const Item& it = items[i0 + lane];
-        R.rlo.push_back(pack(it.row, 0));
-        R.rhi.push_back(pack(it.row, 4));
+        R.rlo.push_back(pack(it.row, 0, rot[lane]));
+        R.rhi.push_back(pack(it.row, 4, rot[lane]));
         for (int j = 0; j < it.count; ++j) lane_ents[lane].push_back(it.first + j);
       } else {
         R.rlo.push_back(ones);
