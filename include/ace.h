@@ -307,7 +307,8 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   tree slices, child positions (padded, real), pair-row slices, pair
  *   entries (padded, real), grandchildren, the four hot slots, whether all
  *   resident adjoints fit in LDS, the mean LDS bank cost of pair entries
- *   and of children (x1000).  Remat: LDS value slots, then of the schedule
+ *   and of children (x1000), the real children plus real pair entries of
+ *   the folded forest schedule (0 if it has none).  Remat: LDS value slots, then of the schedule
  *   with the adjoint slices, entry positions (padded, real), items, then of
  *   the forward-only schedule slices, entry positions (padded, real), the
  *   four hot slots, the pair slots of the schedule with the adjoint, the
@@ -328,10 +329,13 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
  *   phi [n_env][2], Abar [n_env][P1][2], all HOST pointers.
  *   ACE_ERR_UNSUPPORTED if the graph has no forest schedule,
  *   ACE_ERR_INTERNAL if an index of the schedule is out of range.
+ *   folded != 0 runs the forest schedule with conjugate pairs folded, with
+ *   the same restriction on A and the same meaning of Abar as for
+ *   ace_debug_remat_eval.
  */
 ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info);
 ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
-                                 double* phi, double* Abar);
+                                 double* phi, double* Abar, int32_t folded);
 ace_status ace_debug_remat_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
                                 double* phi, double* Abar, int32_t folded);
 

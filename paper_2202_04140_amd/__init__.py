@@ -101,7 +101,7 @@ EXPORTED = {
     "ace_graph_get_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_graph_set_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
-    "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int32),
+    "ace_debug_forest_eval": ([_P, _P, _I64, _P, _P, _P, ctypes.c_int32], ctypes.c_int32),
     "ace_debug_remat_eval": ([_P, _P, _I64, _P, _P, _P, ctypes.c_int32], ctypes.c_int32),
 }
 
@@ -253,19 +253,20 @@ class Graph:
         else:
             names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
                      "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",
-                     "bank_cost_rows_x1000", "bank_cost_children_x1000"]
+                     "bank_cost_rows_x1000", "bank_cost_children_x1000", "folded_real"]
         return {"kind": _KIND[k.value], **{n: int(v) for n, v in zip(names, info) if n}}
 
-    def forest_eval_host(self, coeffs: np.ndarray, A: np.ndarray):
+    def forest_eval_host(self, coeffs: np.ndarray, A: np.ndarray, folded: bool = False):
         """Host emulation of the forest kernel (ace_debug_forest_eval):
-        coeffs [|K|] float64, A [E, P1] complex -> (phi [E], Abar [E, P1])."""
+        coeffs [|K|] float64, A [E, P1] complex -> (phi [E], Abar [E, P1]);
+        folded: the schedule with conjugate pairs folded (exact only for conjugate-symmetric A)."""
         c = np.ascontiguousarray(coeffs, dtype=np.float64)
         E = A.shape[0]
         Ar = np.ascontiguousarray(np.stack([A.real, A.imag], -1), dtype=np.float64)
         phi = np.zeros((E, 2))
         ab = np.zeros((E, self.P1, 2))
         _check(lib().ace_debug_forest_eval(self._h, c.ctypes.data, E, Ar.ctypes.data, phi.ctypes.data,
-                                           ab.ctypes.data))
+                                           ab.ctypes.data, int(folded)))
         return phi[:, 0] + 1j * phi[:, 1], ab[..., 0] + 1j * ab[..., 1]
 
     def remat_eval_host(self, coeffs: np.ndarray, A: np.ndarray, folded: bool = False):

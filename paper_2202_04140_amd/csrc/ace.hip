@@ -98,32 +98,37 @@ struct ace_graph {
   bool fwd_xl = false;    // forward-only: value arena in LDS
   bool grad_xl = false;   // forward+reverse: value arena in LDS
   bool grad_al = false;   // forward+reverse: adjoint arena in LDS
-  // forest schedule (forest_kernel); used when forest_ok
-  bool forest_ok = false;
-  std::string forest_why;
-  int N2 = 0, nslot = 0, n_mslices = 0, n_tslices = 0;
-  bool has_gc = false;
-  std::vector<uint32_t> nu2_ab, it_ab;
-  std::vector<int4> mr_slice, tr_slice;
-  std::vector<uint16_t> mr_row, me_col, ch_s, gc_s;
-  std::vector<int2> ch_g;
-  std::vector<int32_t> kmap;
-  int cs_leaf = 0, cs_nu2 = 0, cs_me = 0, cs_it = 0, cs_ch = 0, cs_gc = 0;
+  // forest schedule (forest_kernel): [0] over every tuple of K, [1] over one
+  // tuple of each conjugate pair (coefficients as (Re, Im) weights)
+  struct Forest {
+    bool ok = false;
+    bool fold = false;
+    std::string why;
+    int N2 = 0, nslot = 0, n_mslices = 0, n_tslices = 0;
+    bool has_gc = false;
+    std::vector<uint32_t> nu2_ab, it_ab;
+    std::vector<int4> mr_slice, tr_slice;
+    std::vector<uint16_t> mr_row, me_col, ch_s, gc_s;
+    std::vector<int2> ch_g;
+    std::vector<int32_t> kmap;
+    std::vector<int32_t> kbar;       // folded: conjugate partner of each kmap entry (-1: self)
+    int cs_leaf = 0, cs_nu2 = 0, cs_me = 0, cs_it = 0, cs_ch = 0, cs_gc = 0;
+    uint32_t *d_nu2_ab = nullptr, *d_it_ab = nullptr;
+    int4 *d_mr_slice = nullptr, *d_tr_slice = nullptr;
+    uint16_t *d_mr_row = nullptr, *d_me_col = nullptr, *d_ch_s = nullptr, *d_gc_s = nullptr;
+    int2* d_ch_g = nullptr;
+    int32_t *d_kmap = nullptr, *d_kbar = nullptr;
+    bool fwd_lds = false, grad_lds = false;
+    bool full = false;               // full-adjoint mode fits in LDS
+    int hot_slot[4] = {0, 0, 0, 0};  // most frequent childless-child siblings
+    int n_items = 0;                 // tree items incl. slice padding (= 64 * n_tslices)
+    int cs_hot = 0;                  // coefficients of the hot columns, [4][n_items]
+    std::vector<int32_t> fw_off;     // full-adjoint mode: order-2 -> one-particle forwarding lists
+    std::vector<uint32_t> fw_ent;
+    int32_t* d_fw_off = nullptr;
+    uint32_t* d_fw_ent = nullptr;
+  } fo[2];
   void* fmem = nullptr;
-  uint32_t *d_nu2_ab = nullptr, *d_it_ab = nullptr;
-  int4 *d_mr_slice = nullptr, *d_tr_slice = nullptr;
-  uint16_t *d_mr_row = nullptr, *d_me_col = nullptr, *d_ch_s = nullptr, *d_gc_s = nullptr;
-  int2* d_ch_g = nullptr;
-  int32_t* d_kmap = nullptr;
-  bool forest_fwd_lds = false, forest_grad_lds = false;
-  int hot_slot[4] = {0, 0, 0, 0};  // most frequent childless-child siblings
-  int n_items = 0;                 // tree items incl. slice padding (= 64 * n_tslices)
-  int cs_hot = 0;                  // coefficients of the hot columns, [4][n_items]
-  std::vector<int32_t> fw_off;     // full-adjoint mode: order-2 -> one-particle forwarding lists
-  std::vector<uint32_t> fw_ent;
-  int32_t* d_fw_off = nullptr;
-  uint32_t* d_fw_ent = nullptr;
-  bool forest_full = false;        // full-adjoint mode fits in LDS
   // rematerialising schedule (remat_kernel): [0] forward only (each term in
   // one row), [1] with adjoint (each term in the rows of both parents),
   // [2], [3] the same over one tuple of each conjugate pair
@@ -431,15 +436,37 @@ std::vector<int> plain_lanes(int n) {
   return v;
 }
 
-void make_forest(ace_graph* g) {
+std::vector<int64_t> conj_partners(const HostGraph& h);
+
+// which = 0: every tuple of K carries its coefficient.  which = 1 (folded):
+// only the tuple of smaller index of each conjugate pair does, with the
+// partner recorded beside its coefficient position; the other tuple stays
+// in the schedule only as a parent, with coefficient 0.
+void make_forest(ace_graph* g, int which) {
   const HostGraph& h = g->h;
   const int64_t V = h.n_nodes();
   const int P1 = h.P1;
-  g->forest_ok = false;
-  auto fail_forest = [&](const char* why) { g->forest_why = why; };
+  ace_graph::Forest& F = g->fo[which];
+  F = ace_graph::Forest{};
+  F.fold = which == 1;
+  auto fail_forest = [&](const char* why) { F.why = why; };
+  std::vector<int64_t> kbar;
+  if (F.fold) {
+    try {
+      kbar = conj_partners(h);
+    } catch (const std::logic_error& e) {
+      return fail_forest("no conjugate pairs");
+    }
+  }
+  // tuple of K whose coefficient node v carries, or -1
+  std::vector<int32_t> nk(V, -1);
+  for (int64_t v = 0; v < V; ++v) {
+    const int32_t q = h.node_k[v];
+    nk[v] = q >= 0 && (!F.fold || kbar[q] >= q) ? q : -1;
+  }
   // liveness and live children (parents precede children in insertion order)
   std::vector<uint8_t> live(V, 0);
-  for (int64_t v = 0; v < V; ++v) live[v] = h.node_k[v] >= 0;
+  for (int64_t v = 0; v < V; ++v) live[v] = nk[v] >= 0;
   std::vector<int32_t> nlc(V, 0);
   for (int64_t v = V - 1; v >= P1; --v) {
     if (!live[v]) continue;
@@ -489,33 +516,29 @@ void make_forest(ace_graph* g) {
         for (int32_t gch : kids[c])
           if (!kids[gch].empty()) return fail_forest("trees deeper than two levels");
       }
-  g->has_gc = has_gc;
-  g->N2 = (int)nu2.size();
-  g->nslot = nslot;
+  F.has_gc = has_gc;
+  F.N2 = (int)nu2.size();
+  F.nslot = nslot;
 
   // ---- hot siblings: the most frequent siblings of childless tree children get
   // a fixed column per item, accumulated in registers (no atomics per child) ----
   {
     std::vector<int64_t> freq(nslot, 0);
-    int64_t nchild = 0;
     for (int32_t r : roots)
       for (int32_t c : kids[r])
-        if (kids[c].empty()) {
-          freq[sib[c]] += 1;
-          ++nchild;
-        }
+        if (kids[c].empty()) freq[sib[c]] += 1;
     std::vector<int32_t> order(nslot);
     for (int i = 0; i < nslot; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return freq[x] > freq[y]; });
     for (int h = 0; h < 4; ++h) {
       const int sl = order[h];
-      g->hot_slot[h] = (h < g->opts.hot_columns && sl != P1 && freq[sl] * 16 >= (int64_t)roots.size() &&
+      F.hot_slot[h] = (h < g->opts.hot_columns && sl != P1 && freq[sl] * 16 >= (int64_t)roots.size() &&
                         freq[sl] > 0) ? sl : P1;
     }
   }
   auto hot_col = [&](int slot_) {
     for (int h = 0; h < 4; ++h)
-      if (g->hot_slot[h] != P1 && g->hot_slot[h] == slot_) return h;
+      if (F.hot_slot[h] != P1 && F.hot_slot[h] == slot_) return h;
     return -1;
   };
   // ---- tree items: root + hot columns + a chunk of at most kTreeChunk other children ----
@@ -591,11 +614,11 @@ void make_forest(ace_graph* g) {
   const int nts = (int)slices.size();
   std::vector<int32_t> k_it((size_t)nts * 64, -1), k_ch, k_gc;
   std::vector<int32_t> item_pos(items.size(), -1);   // item -> lane index sl*64 + l
-  g->it_ab.assign((size_t)nts * 64, zz);
-  g->tr_slice.assign(nts, make_int4(0, 0, 0, 0));
-  g->ch_s.clear();
-  g->ch_g.clear();
-  g->gc_s.clear();
+  F.it_ab.assign((size_t)nts * 64, zz);
+  F.tr_slice.assign(nts, make_int4(0, 0, 0, 0));
+  F.ch_s.clear();
+  F.ch_g.clear();
+  F.gc_s.clear();
   // a slot in a given bank group for padding (one-particle slots 0..15)
   auto pad_slot = [&](int bank) { return P1 > 15 ? bank : P1; };
   for (int sl = 0; sl < nts; ++sl) {
@@ -618,55 +641,55 @@ void make_forest(ace_graph* g) {
     const std::vector<std::vector<Ent>> cols =
         g->opts.bank_schedule ? bank_columns(lanes, ncol, pad_slot) : plain_columns(lanes, ncol, P1);
     const int nmax = ncol;
-    const int base = (int)g->ch_s.size();
-    g->tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
-    g->ch_s.resize(base + (size_t)nmax * 64, (uint16_t)P1);
-    g->ch_g.resize(base + (size_t)nmax * 64, make_int2(0, 0));
+    const int base = (int)F.ch_s.size();
+    F.tr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
+    F.ch_s.resize(base + (size_t)nmax * 64, (uint16_t)P1);
+    F.ch_g.resize(base + (size_t)nmax * 64, make_int2(0, 0));
     k_ch.resize(base + (size_t)nmax * 64, -1);
     for (int l = 0; l < nl; ++l) {
       const Item& it = items[slices[sl][l]];
       const int idx = sl * 64 + lane_of_item[l];
       item_pos[slices[sl][l]] = idx;
       const int32_t a = h.par[2 * it.root], b = h.par[2 * it.root + 1];
-      g->it_ab[idx] = (uint32_t)slot[a] | ((uint32_t)slot[b] << 16);
-      k_it[idx] = it.c0 == 0 ? h.node_k[it.root] : -1;
+      F.it_ab[idx] = (uint32_t)slot[a] | ((uint32_t)slot[b] << 16);
+      k_it[idx] = it.c0 == 0 ? nk[it.root] : -1;
     }
     for (int j = 0; j < nmax; ++j)
       for (int l = 0; l < 64; ++l) {
         const Ent& en = cols[j][l];
         const int pos = base + j * 64 + l;
-        g->ch_s[pos] = (uint16_t)en.slot;
+        F.ch_s[pos] = (uint16_t)en.slot;
         if (en.pay < 0) continue;   // padding: coefficient 0
         const int32_t c = en.pay;
-        k_ch[pos] = h.node_k[c];
+        k_ch[pos] = nk[c];
         if (!kids[c].empty()) {
-          const int gb = (int)g->gc_s.size();
+          const int gb = (int)F.gc_s.size();
           for (int32_t gch : kids[c]) {
-            g->gc_s.push_back((uint16_t)sib[gch]);
-            k_gc.push_back(h.node_k[gch]);
+            F.gc_s.push_back((uint16_t)sib[gch]);
+            k_gc.push_back(nk[gch]);
           }
-          g->ch_g[pos] = make_int2(gb, (int)g->gc_s.size());
-        } else if (h.node_k[c] < 0) {
+          F.ch_g[pos] = make_int2(gb, (int)F.gc_s.size());
+        } else if (nk[c] < 0) {
           return fail_forest("childless auxiliary child");
         }
       }
   }
-  g->n_tslices = nts;
-  g->n_items = nts * 64;
+  F.n_tslices = nts;
+  F.n_items = nts * 64;
   std::vector<int32_t> k_hot((size_t)4 * nts * 64, -1);
   for (size_t i = 0; i < items.size(); ++i)
     for (int hc = 0; hc < 4; ++hc)
-      if (items[i].hot[hc] >= 0) k_hot[(size_t)hc * nts * 64 + item_pos[i]] = h.node_k[items[i].hot[hc]];
+      if (items[i].hot[hc] >= 0) k_hot[(size_t)hc * nts * 64 + item_pos[i]] = nk[items[i].hot[hc]];
 
   // ---- resident-pair rows ----
   std::vector<std::vector<std::pair<uint16_t, int32_t>>> rows(nslot);
   // an invariant order-2 node u = a * b contributes c_u x_a x_b: a pair of
   // one-particle slots, so it joins M instead of needing its own pushes
   for (int32_t u : nu2)
-    if (h.node_k[u] >= 0) pairs.push_back(u);
+    if (nk[u] >= 0) pairs.push_back(u);
   for (int32_t w : pairs) {
     const int sa = slot[h.par[2 * w]], sb = slot[h.par[2 * w + 1]];
-    const int32_t k = h.node_k[w];
+    const int32_t k = nk[w];
     if (k < 0) return fail_forest("childless auxiliary pair");
     if (sa == sb) {
       rows[sa].push_back({(uint16_t)sa, -2 - k});  // M_uu = 2 c
@@ -684,9 +707,9 @@ void make_forest(ace_graph* g) {
       rch.push_back({r, e0, std::min((int)rows[r].size(), e0 + g->opts.row_chunk)});
   std::stable_sort(rch.begin(), rch.end(), [](const Row& x, const Row& y) { return x.e1 - x.e0 > y.e1 - y.e0; });
   const int nms = (int)((rch.size() + 63) / 64);
-  g->mr_slice.assign(nms, make_int4(0, 0, 0, 0));
-  g->mr_row.assign((size_t)nms * 64, (uint16_t)P1);
-  g->me_col.clear();
+  F.mr_slice.assign(nms, make_int4(0, 0, 0, 0));
+  F.mr_row.assign((size_t)nms * 64, (uint16_t)P1);
+  F.me_col.clear();
   std::vector<int32_t> k_me;
   for (int sl = 0; sl < nms; ++sl) {
     const int nl = std::min(64, (int)rch.size() - sl * 64);
@@ -704,88 +727,107 @@ void make_forest(ace_graph* g) {
     }
     const std::vector<std::vector<Ent>> cols =
         g->opts.bank_schedule ? bank_columns(lanes, nmax, pad_slot) : plain_columns(lanes, nmax, P1);
-    const int base = (int)g->me_col.size();
-    g->mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
-    g->me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
+    const int base = (int)F.me_col.size();
+    F.mr_slice[sl] = make_int4(sl * 64, base, nmax, 0);
+    F.me_col.resize(base + (size_t)nmax * 64, (uint16_t)P1);
     k_me.resize(base + (size_t)nmax * 64, -1);
-    for (int l = 0; l < nl; ++l) g->mr_row[sl * 64 + lane_of_row[l]] = (uint16_t)rch[sl * 64 + l].row;
+    for (int l = 0; l < nl; ++l) F.mr_row[sl * 64 + lane_of_row[l]] = (uint16_t)rch[sl * 64 + l].row;
     for (int j = 0; j < nmax; ++j)
       for (int l = 0; l < 64; ++l) {
         const int pos = base + j * 64 + l;
-        g->me_col[pos] = (uint16_t)cols[j][l].slot;
+        F.me_col[pos] = (uint16_t)cols[j][l].slot;
         k_me[pos] = cols[j][l].pay;   // padding: -1, coefficient 0
       }
   }
-  g->n_mslices = nms;
+  F.n_mslices = nms;
 
   // ---- order-2 nodes, one-particle coefficients, coefficient map ----
-  g->nu2_ab.resize(nu2.size());
+  F.nu2_ab.resize(nu2.size());
   std::vector<int32_t> k_nu2(nu2.size());
   for (size_t u = 0; u < nu2.size(); ++u) {
     const int32_t v = nu2[u];
-    g->nu2_ab[u] = (uint32_t)slot[h.par[2 * v]] | ((uint32_t)slot[h.par[2 * v + 1]] << 16);
+    F.nu2_ab[u] = (uint32_t)slot[h.par[2 * v]] | ((uint32_t)slot[h.par[2 * v + 1]] << 16);
     if (slot[h.par[2 * v]] >= P1 || slot[h.par[2 * v + 1]] >= P1) return fail_forest("order-2 node without one-particle parents");
     k_nu2[u] = -1;  // carried by the resident-pair matrix
   }
-  g->kmap.clear();
+  F.kmap.clear();
   auto put = [&](const std::vector<int32_t>& part) {
-    const int off = (int)g->kmap.size();
-    g->kmap.insert(g->kmap.end(), part.begin(), part.end());
+    const int off = (int)F.kmap.size();
+    F.kmap.insert(F.kmap.end(), part.begin(), part.end());
     return off;
   };
-  g->cs_it = put(k_it);
-  g->cs_ch = put(k_ch);
-  g->cs_gc = put(k_gc);
-  g->cs_hot = put(k_hot);
-  g->cs_me = put(k_me);
-  g->cs_nu2 = put(k_nu2);
-  std::vector<int32_t> k_leaf(h.node_k.begin(), h.node_k.begin() + P1);
-  g->cs_leaf = put(k_leaf);
+  F.cs_it = put(k_it);
+  F.cs_ch = put(k_ch);
+  F.cs_gc = put(k_gc);
+  F.cs_hot = put(k_hot);
+  F.cs_me = put(k_me);
+  F.cs_nu2 = put(k_nu2);
+  std::vector<int32_t> k_leaf(nk.begin(), nk.begin() + P1);
+  F.cs_leaf = put(k_leaf);
+  if (F.fold) {
+    F.kbar.assign(F.kmap.size(), -1);
+    for (size_t i = 0; i < F.kmap.size(); ++i) {
+      const int32_t k = F.kmap[i];
+      if (k == -1) continue;
+      const int64_t q = k >= 0 ? k : -2 - k;
+      if (kbar[q] != q) F.kbar[i] = (int32_t)kbar[q];
+    }
+  }
   // forwarding lists: one-particle node i receives abar_u x_j from every
   // order-2 node u = i * j (a square u = i * i contributes twice)
   {
     std::vector<std::vector<uint32_t>> fl(P1);
     for (size_t u = 0; u < nu2.size(); ++u) {
-      const uint32_t q = g->nu2_ab[u];
+      const uint32_t q = F.nu2_ab[u];
       const uint32_t a = q & 0xffffu, b = q >> 16;
       const uint32_t us = (uint32_t)(P1 + 1 + u);
       fl[a].push_back(us | (b << 16));
       fl[b].push_back(us | (a << 16));
     }
-    g->fw_off.assign(P1 + 1, 0);
-    g->fw_ent.clear();
+    F.fw_off.assign(P1 + 1, 0);
+    F.fw_ent.clear();
     for (int i = 0; i < P1; ++i) {
-      g->fw_off[i] = (int32_t)g->fw_ent.size();
-      g->fw_ent.insert(g->fw_ent.end(), fl[i].begin(), fl[i].end());
+      F.fw_off[i] = (int32_t)F.fw_ent.size();
+      F.fw_ent.insert(F.fw_ent.end(), fl[i].begin(), fl[i].end());
     }
-    g->fw_off[P1] = (int32_t)g->fw_ent.size();
+    F.fw_off[P1] = (int32_t)F.fw_ent.size();
   }
-  g->forest_ok = true;
+  F.ok = true;
 }
 
 // Host emulation of forest_kernel for one environment, with the same
 // indices, padding and forwarding, every index bounds-checked.  Used by the
-// tests to validate a schedule without a GPU.  Returns false on a bad index.
-bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, double* phi, double* Abar,
+// tests to validate a schedule without a GPU.  Every coefficient is a pair
+// (Re weight, Im weight): (c, c) unfolded, (c_k + c_kbar, c_k - c_kbar)
+// folded; Re phi takes the Re weights, Im phi the Im weights, the adjoint
+// the Re weights.  Returns false on a bad index.
+bool forest_emulate(const ace_graph* g, int which, const double* coeffs, const double* A, double* phi, double* Abar,
                     bool full) {
   using cd = std::complex<double>;
+  const ace_graph::Forest& F = g->fo[which];
   const int P1 = g->P1, ZERO = P1;
-  std::vector<double> cs(g->kmap.size());
-  for (size_t i = 0; i < cs.size(); ++i) {
-    const int k = g->kmap[i];
+  std::vector<double> cr(F.kmap.size(), 0.0), ci(F.kmap.size(), 0.0);
+  for (size_t i = 0; i < cr.size(); ++i) {
+    const int k = F.kmap[i];
     if (k >= g->h.nK || -2 - k >= g->h.nK) return false;
-    cs[i] = k >= 0 ? coeffs[k] : (k == -1 ? 0.0 : 2.0 * coeffs[-2 - k]);
+    if (k == -1) continue;
+    const int q = k >= 0 ? k : -2 - k;
+    const double sc = k >= 0 ? 1.0 : 2.0;
+    const int kb = F.fold ? F.kbar.at(i) : -1;
+    if (kb >= g->h.nK) return false;
+    cr[i] = sc * (kb >= 0 ? coeffs[q] + coeffs[kb] : coeffs[q]);
+    ci[i] = sc * (kb >= 0 ? coeffs[q] - coeffs[kb] : coeffs[q]);
   }
-  std::vector<cd> x(g->nslot), ab(full ? g->nslot : P1 + 1, cd(0.0, 0.0));
+  std::vector<cd> x(F.nslot), ab(full ? F.nslot : P1 + 1, cd(0.0, 0.0));
   auto X = [&](int s) -> cd& {
-    if (s < 0 || s >= g->nslot) throw std::out_of_range("slot");
+    if (s < 0 || s >= F.nslot) throw std::out_of_range("slot");
     return x[s];
   };
   auto push = [&](int s, cd d) {
     if (full || s <= P1) {
       ab.at(s) += d;
     } else {
-      const uint32_t q = g->nu2_ab.at(s - P1 - 1);
+      const uint32_t q = F.nu2_ab.at(s - P1 - 1);
       const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
       ab.at(a) += d * X(b);
       ab.at(b) += d * X(a);
@@ -794,92 +836,101 @@ bool forest_emulate(const ace_graph* g, const double* coeffs, const double* A, d
   try {
     for (int i = 0; i < P1; ++i) {
       x[i] = cd(A[2 * i], A[2 * i + 1]);
-      ab[i] = cd(cs.at(g->cs_leaf + i), 0.0);
+      ab[i] = cd(cr.at(F.cs_leaf + i), 0.0);
     }
     x[ZERO] = 0.0;
     ab[ZERO] = 0.0;
-    cd acc = 0.0;
-    for (int i = 0; i < P1; ++i) acc += cs.at(g->cs_leaf + i) * x[i];
-    for (int u = 0; u < g->N2; ++u) {
-      const uint32_t q = g->nu2_ab.at(u);
+    cd accr = 0.0, acci = 0.0;   // phi = Re accr + i Im acci
+    for (int i = 0; i < P1; ++i) {
+      accr += cr.at(F.cs_leaf + i) * x[i];
+      acci += ci.at(F.cs_leaf + i) * x[i];
+    }
+    for (int u = 0; u < F.N2; ++u) {
+      const uint32_t q = F.nu2_ab.at(u);
       const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
       if (a >= P1 || b >= P1) return false;
       const cd xu = X(a) * X(b);
       X(P1 + 1 + u) = xu;
-      const double c = cs.at(g->cs_nu2 + u);
-      acc += c * xu;
-      ab.at(a) += c * X(b);
-      ab.at(b) += c * X(a);
+      accr += cr.at(F.cs_nu2 + u) * xu;
+      acci += ci.at(F.cs_nu2 + u) * xu;
+      ab.at(a) += cr.at(F.cs_nu2 + u) * X(b);
+      ab.at(b) += cr.at(F.cs_nu2 + u) * X(a);
     }
-    for (int s = 0; s < g->n_mslices; ++s) {
-      const int4 sl = g->mr_slice.at(s);
+    for (int s = 0; s < F.n_mslices; ++s) {
+      const int4 sl = F.mr_slice.at(s);
       for (int lane = 0; lane < 64; ++lane) {
-        const int row = g->mr_row.at(sl.x + lane);
+        const int row = F.mr_row.at(sl.x + lane);
         const cd xu = X(row);
-        cd y = 0.0;
+        cd yr = 0.0, yi = 0.0;
         for (int j = 0; j < sl.z; ++j) {
           const int pos = sl.y + j * 64 + lane;
-          y += cs.at(g->cs_me + pos) * X(g->me_col.at(pos));
+          yr += cr.at(F.cs_me + pos) * X(F.me_col.at(pos));
+          yi += ci.at(F.cs_me + pos) * X(F.me_col.at(pos));
         }
-        acc += 0.5 * xu * y;
-        if (row != ZERO) push(row, y);
+        accr += 0.5 * xu * yr;
+        acci += 0.5 * xu * yi;
+        if (row != ZERO) push(row, yr);
       }
     }
     cd hacc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int s = 0; s < g->n_tslices; ++s) {
-      const int4 sl = g->tr_slice.at(s);
+    for (int s = 0; s < F.n_tslices; ++s) {
+      const int4 sl = F.tr_slice.at(s);
       for (int lane = 0; lane < 64; ++lane) {
         const int item = sl.x + lane;
-        const uint32_t q = g->it_ab.at(item);
+        const uint32_t q = F.it_ab.at(item);
         const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
         const cd xa = X(a), xb = X(b), xv = xa * xb;
-        cd t = cs.at(g->cs_it + item), asum = 0.0;
+        cd tr = cr.at(F.cs_it + item), ti = ci.at(F.cs_it + item), asum = 0.0;
         for (int hc = 0; hc < 4; ++hc) {
-          const double k = cs.at((size_t)g->cs_hot + (size_t)hc * g->n_items + item);
-          t += k * X(g->hot_slot[hc]);
-          hacc[hc] += k * xv;
+          const size_t hp = (size_t)F.cs_hot + (size_t)hc * F.n_items + item;
+          tr += cr.at(hp) * X(F.hot_slot[hc]);
+          ti += ci.at(hp) * X(F.hot_slot[hc]);
+          hacc[hc] += cr.at(hp) * xv;
         }
         for (int j = 0; j < sl.z; ++j) {
           const int pos = sl.y + j * 64 + lane;
-          const int sidx = g->ch_s.at(pos);
-          const double c = cs.at(g->cs_ch + pos);
+          const int sidx = F.ch_s.at(pos);
+          const double c = cr.at(F.cs_ch + pos), c2 = ci.at(F.cs_ch + pos);
           const cd xs = X(sidx);
-          const int2 gg = g->ch_g.at(pos);
+          const int2 gg = F.ch_g.at(pos);
           if (gg.x == gg.y) {
-            t += c * xs;
+            tr += c * xs;
+            ti += c2 * xs;
             if (c != 0.0) push(sidx, c * xv);
           } else {
             const cd xw = xv * xs;
-            cd aw = c;
+            cd awr = c, awi = c2;
             for (int k = gg.x; k < gg.y; ++k) {
-              const int sg = g->gc_s.at(k);
-              const double cg = cs.at(g->cs_gc + k);
-              aw += cg * X(sg);
-              push(sg, cg * xw);
+              const int sg = F.gc_s.at(k);
+              awr += cr.at(F.cs_gc + k) * X(sg);
+              awi += ci.at(F.cs_gc + k) * X(sg);
+              push(sg, cr.at(F.cs_gc + k) * xw);
             }
-            acc += xw * aw;
-            push(sidx, aw * xv);
-            asum += aw * xs;
+            accr += xw * awr;
+            acci += xw * awi;
+            push(sidx, awr * xv);
+            asum += awr * xs;
           }
         }
-        acc += xv * t;
+        accr += xv * tr;
+        acci += xv * ti;
         if (q != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
-          const cd av = t + asum;
+          const cd av = tr + asum;
           push(a, av * xb);
           push(b, av * xa);
         }
       }
     }
     for (int hc = 0; hc < 4; ++hc)
-      if (g->hot_slot[hc] != ZERO) push(g->hot_slot[hc], hacc[hc]);
+      if (F.hot_slot[hc] != ZERO) push(F.hot_slot[hc], hacc[hc]);
     if (full)
       for (int i = 0; i < P1; ++i)
-        for (int q = g->fw_off.at(i); q < g->fw_off.at(i + 1); ++q) {
-          const uint32_t en = g->fw_ent.at(q);
+        for (int q = F.fw_off.at(i); q < F.fw_off.at(i + 1); ++q) {
+          const uint32_t en = F.fw_ent.at(q);
           ab.at(i) += ab.at(en & 0xffffu) * X(en >> 16);
         }
-    phi[0] = acc.real();
-    phi[1] = acc.imag();
+    phi[0] = accr.real();
+    phi[1] = acci.imag();
     for (int i = 0; i < P1; ++i) {
       Abar[2 * i] = ab[i].real();
       Abar[2 * i + 1] = ab[i].imag();
@@ -1385,10 +1436,10 @@ void make_stats(ace_graph* g) {
 
 // LDS of forest_kernel: values of every resident slot, one-particle
 // adjoints (reverse pass), the order-2 parent table, reduction scratch.
-size_t forest_lds_bytes(const ace_graph* g, bool grad, bool full) {
-  size_t b = (size_t)g->nslot * 16;
-  if (grad && full) b += (size_t)g->nslot * 16;
-  if (grad && !full) b += (size_t)(g->P1 + 1) * 16 + ((size_t)g->N2 * 4 + 15) / 16 * 16;
+size_t forest_lds_bytes(const ace_graph::Forest& F, int P1, bool grad, bool full) {
+  size_t b = (size_t)F.nslot * 16;
+  if (grad && full) b += (size_t)F.nslot * 16;
+  if (grad && !full) b += (size_t)(P1 + 1) * 16 + ((size_t)F.N2 * 4 + 15) / 16 * 16;
   return b + (kForestThreads / 64) * sizeof(double2);
 }
 
@@ -1415,50 +1466,66 @@ ace_status upload_forest(ace_graph* g) {
   }
   auto put = [](void* d, const void* s, size_t n) { return n ? hipMemcpy(d, s, n, hipMemcpyHostToDevice) : hipSuccess; };
   const int maxl = (int)g->max_lds;
-  if (g->forest_ok) {
-    size_t fb = 0;
-    fb += align_up(g->nu2_ab.size() * 4) + align_up(g->it_ab.size() * 4);
-    fb += align_up(g->mr_slice.size() * sizeof(int4)) + align_up(g->tr_slice.size() * sizeof(int4));
-    fb += align_up(g->mr_row.size() * 2) + align_up(g->me_col.size() * 2) + align_up(g->ch_s.size() * 2);
-    fb += align_up(g->gc_s.size() * 2) + align_up(g->ch_g.size() * sizeof(int2)) + align_up(g->kmap.size() * 4);
-    fb += align_up(g->fw_off.size() * 4) + align_up(g->fw_ent.size() * 4);
-    fb += kAlign;
+  size_t fb = kAlign;
+  for (const ace_graph::Forest& F : g->fo) {
+    if (!F.ok) continue;
+    fb += align_up(F.nu2_ab.size() * 4) + align_up(F.it_ab.size() * 4);
+    fb += align_up(F.mr_slice.size() * sizeof(int4)) + align_up(F.tr_slice.size() * sizeof(int4));
+    fb += align_up(F.mr_row.size() * 2) + align_up(F.me_col.size() * 2) + align_up(F.ch_s.size() * 2);
+    fb += align_up(F.gc_s.size() * 2) + align_up(F.ch_g.size() * sizeof(int2)) + align_up(F.kmap.size() * 4);
+    fb += align_up(F.kbar.size() * 4) + align_up(F.fw_off.size() * 4) + align_up(F.fw_ent.size() * 4);
+  }
+  if (g->fo[0].ok || g->fo[1].ok) {
     if (hipMalloc(&g->fmem, fb) != hipSuccess) {
       g->fmem = nullptr;
       (void)hipGetLastError();
       return fail(ACE_ERR_OUT_OF_MEMORY, "hipMalloc of the forest schedule failed");
     }
     char* q = static_cast<char*>(g->fmem);
-    g->d_nu2_ab = carve<uint32_t>(q, g->nu2_ab.size());
-    g->d_it_ab = carve<uint32_t>(q, g->it_ab.size());
-    g->d_mr_slice = carve<int4>(q, g->mr_slice.size());
-    g->d_tr_slice = carve<int4>(q, g->tr_slice.size());
-    g->d_mr_row = carve<uint16_t>(q, g->mr_row.size());
-    g->d_me_col = carve<uint16_t>(q, g->me_col.size());
-    g->d_ch_s = carve<uint16_t>(q, g->ch_s.size());
-    g->d_gc_s = carve<uint16_t>(q, g->gc_s.size());
-    g->d_ch_g = carve<int2>(q, g->ch_g.size());
-    g->d_kmap = carve<int32_t>(q, g->kmap.size());
-    g->d_fw_off = carve<int32_t>(q, g->fw_off.size());
-    g->d_fw_ent = carve<uint32_t>(q, g->fw_ent.size());
-    ACE_HIP(put(g->d_nu2_ab, g->nu2_ab.data(), g->nu2_ab.size() * 4));
-    ACE_HIP(put(g->d_it_ab, g->it_ab.data(), g->it_ab.size() * 4));
-    ACE_HIP(put(g->d_mr_slice, g->mr_slice.data(), g->mr_slice.size() * sizeof(int4)));
-    ACE_HIP(put(g->d_tr_slice, g->tr_slice.data(), g->tr_slice.size() * sizeof(int4)));
-    ACE_HIP(put(g->d_mr_row, g->mr_row.data(), g->mr_row.size() * 2));
-    ACE_HIP(put(g->d_me_col, g->me_col.data(), g->me_col.size() * 2));
-    ACE_HIP(put(g->d_ch_s, g->ch_s.data(), g->ch_s.size() * 2));
-    ACE_HIP(put(g->d_gc_s, g->gc_s.data(), g->gc_s.size() * 2));
-    ACE_HIP(put(g->d_ch_g, g->ch_g.data(), g->ch_g.size() * sizeof(int2)));
-    ACE_HIP(put(g->d_kmap, g->kmap.data(), g->kmap.size() * 4));
-    ACE_HIP(put(g->d_fw_off, g->fw_off.data(), g->fw_off.size() * 4));
-    ACE_HIP(put(g->d_fw_ent, g->fw_ent.data(), g->fw_ent.size() * 4));
-    g->forest_fwd_lds = forest_lds_bytes(g, false, false) <= g->max_lds;
-    g->forest_full = forest_lds_bytes(g, true, true) <= g->max_lds;
-    g->forest_grad_lds = g->forest_full || forest_lds_bytes(g, true, false) <= g->max_lds;
-    const void* fk[] = {(const void*)forest_kernel<false, false, false>, (const void*)forest_kernel<false, true, false>,
-                        (const void*)forest_kernel<true, false, false>, (const void*)forest_kernel<true, true, false>,
-                        (const void*)forest_kernel<true, false, true>, (const void*)forest_kernel<true, true, true>};
+    for (ace_graph::Forest& F : g->fo) {
+      if (!F.ok) continue;
+      F.d_nu2_ab = carve<uint32_t>(q, F.nu2_ab.size());
+      F.d_it_ab = carve<uint32_t>(q, F.it_ab.size());
+      F.d_mr_slice = carve<int4>(q, F.mr_slice.size());
+      F.d_tr_slice = carve<int4>(q, F.tr_slice.size());
+      F.d_mr_row = carve<uint16_t>(q, F.mr_row.size());
+      F.d_me_col = carve<uint16_t>(q, F.me_col.size());
+      F.d_ch_s = carve<uint16_t>(q, F.ch_s.size());
+      F.d_gc_s = carve<uint16_t>(q, F.gc_s.size());
+      F.d_ch_g = carve<int2>(q, F.ch_g.size());
+      F.d_kmap = carve<int32_t>(q, F.kmap.size());
+      F.d_kbar = carve<int32_t>(q, F.kbar.size());
+      F.d_fw_off = carve<int32_t>(q, F.fw_off.size());
+      F.d_fw_ent = carve<uint32_t>(q, F.fw_ent.size());
+      ACE_HIP(put(F.d_nu2_ab, F.nu2_ab.data(), F.nu2_ab.size() * 4));
+      ACE_HIP(put(F.d_it_ab, F.it_ab.data(), F.it_ab.size() * 4));
+      ACE_HIP(put(F.d_mr_slice, F.mr_slice.data(), F.mr_slice.size() * sizeof(int4)));
+      ACE_HIP(put(F.d_tr_slice, F.tr_slice.data(), F.tr_slice.size() * sizeof(int4)));
+      ACE_HIP(put(F.d_mr_row, F.mr_row.data(), F.mr_row.size() * 2));
+      ACE_HIP(put(F.d_me_col, F.me_col.data(), F.me_col.size() * 2));
+      ACE_HIP(put(F.d_ch_s, F.ch_s.data(), F.ch_s.size() * 2));
+      ACE_HIP(put(F.d_gc_s, F.gc_s.data(), F.gc_s.size() * 2));
+      ACE_HIP(put(F.d_ch_g, F.ch_g.data(), F.ch_g.size() * sizeof(int2)));
+      ACE_HIP(put(F.d_kmap, F.kmap.data(), F.kmap.size() * 4));
+      ACE_HIP(put(F.d_kbar, F.kbar.data(), F.kbar.size() * 4));
+      ACE_HIP(put(F.d_fw_off, F.fw_off.data(), F.fw_off.size() * 4));
+      ACE_HIP(put(F.d_fw_ent, F.fw_ent.data(), F.fw_ent.size() * 4));
+      F.fwd_lds = forest_lds_bytes(F, g->P1, false, false) <= g->max_lds;
+      F.full = forest_lds_bytes(F, g->P1, true, true) <= g->max_lds;
+      F.grad_lds = F.full || forest_lds_bytes(F, g->P1, true, false) <= g->max_lds;
+    }
+    const void* fk[] = {(const void*)forest_kernel<false, false, false, false>,
+                        (const void*)forest_kernel<false, true, false, false>,
+                        (const void*)forest_kernel<true, false, false, false>,
+                        (const void*)forest_kernel<true, true, false, false>,
+                        (const void*)forest_kernel<true, false, true, false>,
+                        (const void*)forest_kernel<true, true, true, false>,
+                        (const void*)forest_kernel<false, false, false, true>,
+                        (const void*)forest_kernel<false, true, false, true>,
+                        (const void*)forest_kernel<true, false, false, true>,
+                        (const void*)forest_kernel<true, true, false, true>,
+                        (const void*)forest_kernel<true, false, true, true>,
+                        (const void*)forest_kernel<true, true, true, true>};
     for (const void* f : fk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
   if (g->rmem) {
@@ -1593,7 +1660,15 @@ int arena_blocks(int64_t n_env) { return (int)std::max<int64_t>(1, std::min<int6
 enum class Sched { Layered, Forest, Remat };
 
 bool use_forest(const ace_graph* g, bool grad) {
-  return g->forest_ok && (grad ? g->forest_grad_lds : g->forest_fwd_lds);
+  const ace_graph::Forest& F = g->fo[0];
+  return F.ok && (grad ? F.grad_lds : F.fwd_lds);
+}
+
+// The folded forest schedule serves A with the conjugate symmetry when it
+// fits; it never holds more resident slots than the unfolded one.
+bool use_folded_forest(const ace_graph* g, bool grad) {
+  const ace_graph::Forest& F = g->fo[1];
+  return F.ok && (grad ? F.grad_lds : F.fwd_lds);
 }
 
 // The kernel that evaluates the DAG: the requested schedule when it is
@@ -1634,7 +1709,9 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char
   const size_t arena = (size_t)arena_blocks(n_env) * g->slots * sizeof(double2);
   if (layered && (!g->fwd_xl || !g->grad_xl)) w.arena_x = take(arena);
   if (layered && !g->grad_al) w.arena_ab = take(arena);
-  size_t ncs = g->forest_ok ? g->kmap.size() : 0;
+  size_t ncs = 0;
+  for (const auto& F : g->fo)
+    if (F.ok) ncs = std::max(ncs, F.kmap.size() * (F.fold ? 2 : 1));
   if (g->remat_ok)
     for (const auto& R : g->rm) ncs = std::max(ncs, R.kmap.size() * (R.fold ? 2 : 1));
   if (ncs) w.cs = reinterpret_cast<double*>(take(ncs * sizeof(double)));
@@ -1698,14 +1775,26 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
 }
 
 ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                         double2* Abar, const Workspace& w, hipStream_t s) {
-  PrepArgs pa{};
-  pa.kmap = g->d_kmap;
-  pa.coeffs = coeffs;
-  pa.cs = w.cs;
-  pa.n = (int64_t)g->kmap.size();
-  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((pa.n + 255) / 256, 1024));
-  hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+                         double2* Abar, const Workspace& w, hipStream_t s, bool fold) {
+  const ace_graph::Forest& F = g->fo[fold ? 1 : 0];
+  const int64_t nk = (int64_t)F.kmap.size();
+  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nk + 255) / 256, 1024));
+  if (fold) {
+    PrepFoldArgs pa{};
+    pa.kmap = F.d_kmap;
+    pa.kbar = F.d_kbar;
+    pa.coeffs = coeffs;
+    pa.cs = reinterpret_cast<double2*>(w.cs);
+    pa.n = nk;
+    hipLaunchKernelGGL(prep_fold_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  } else {
+    PrepArgs pa{};
+    pa.kmap = F.d_kmap;
+    pa.coeffs = coeffs;
+    pa.cs = w.cs;
+    pa.n = nk;
+    hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  }
   ACE_HIP(hipGetLastError());
   ForestArgs a{};
   a.n_env = n_env;
@@ -1713,47 +1802,47 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.phi = phi;
   a.Abar = Abar;
   a.cs = w.cs;
-  a.nu2_ab = g->d_nu2_ab;
-  a.mr_slice = g->d_mr_slice;
-  a.mr_row = g->d_mr_row;
-  a.me_col = g->d_me_col;
-  a.tr_slice = g->d_tr_slice;
-  a.it_ab = g->d_it_ab;
-  a.ch_s = g->d_ch_s;
-  a.ch_g = g->has_gc ? g->d_ch_g : nullptr;
-  a.gc_s = g->d_gc_s;
-  a.cs_leaf = g->cs_leaf;
-  a.cs_nu2 = g->cs_nu2;
-  a.cs_me = g->cs_me;
-  a.cs_it = g->cs_it;
-  a.cs_ch = g->cs_ch;
-  a.cs_gc = g->cs_gc;
-  a.cs_hot = g->cs_hot;
-  a.n_items = g->n_items;
-  a.hot = make_int4(g->hot_slot[0], g->hot_slot[1], g->hot_slot[2], g->hot_slot[3]);
+  a.nu2_ab = F.d_nu2_ab;
+  a.mr_slice = F.d_mr_slice;
+  a.mr_row = F.d_mr_row;
+  a.me_col = F.d_me_col;
+  a.tr_slice = F.d_tr_slice;
+  a.it_ab = F.d_it_ab;
+  a.ch_s = F.d_ch_s;
+  a.ch_g = F.has_gc ? F.d_ch_g : nullptr;
+  a.gc_s = F.d_gc_s;
+  a.cs_leaf = F.cs_leaf;
+  a.cs_nu2 = F.cs_nu2;
+  a.cs_me = F.cs_me;
+  a.cs_it = F.cs_it;
+  a.cs_ch = F.cs_ch;
+  a.cs_gc = F.cs_gc;
+  a.cs_hot = F.cs_hot;
+  a.n_items = F.n_items;
+  a.hot = make_int4(F.hot_slot[0], F.hot_slot[1], F.hot_slot[2], F.hot_slot[3]);
   a.P1 = g->P1;
-  a.N2 = g->N2;
-  a.nslot = g->nslot;
-  a.n_mslices = g->n_mslices;
-  a.n_tslices = g->n_tslices;
-  a.fw_off = g->d_fw_off;
-  a.fw_ent = g->d_fw_ent;
+  a.N2 = F.N2;
+  a.nslot = F.nslot;
+  a.n_mslices = F.n_mslices;
+  a.n_tslices = F.n_tslices;
+  a.fw_off = F.d_fw_off;
+  a.fw_ent = F.d_fw_ent;
   const bool grad = Abar != nullptr;
-  const bool full = grad && g->forest_full;
-  const size_t lds = forest_lds_bytes(g, grad, full);
+  const bool full = grad && F.full;
+  const size_t lds = forest_lds_bytes(F, g->P1, grad, full);
   const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
-  if (full && g->has_gc)
-    hipLaunchKernelGGL((forest_kernel<true, true, true>), grid, block, lds, s, a);
-  else if (full)
-    hipLaunchKernelGGL((forest_kernel<true, false, true>), grid, block, lds, s, a);
-  else if (grad && g->has_gc)
-    hipLaunchKernelGGL((forest_kernel<true, true, false>), grid, block, lds, s, a);
-  else if (grad)
-    hipLaunchKernelGGL((forest_kernel<true, false, false>), grid, block, lds, s, a);
-  else if (g->has_gc)
-    hipLaunchKernelGGL((forest_kernel<false, true, false>), grid, block, lds, s, a);
-  else
-    hipLaunchKernelGGL((forest_kernel<false, false, false>), grid, block, lds, s, a);
+  // kernel variant: forward / reverse with one-particle adjoints / reverse
+  // with every resident adjoint, with or without grandchildren, folded or not
+  using K = void (*)(ForestArgs);
+  static const K table[2][3][2] = {
+      {{forest_kernel<false, false, false, false>, forest_kernel<false, true, false, false>},
+       {forest_kernel<true, false, false, false>, forest_kernel<true, true, false, false>},
+       {forest_kernel<true, false, true, false>, forest_kernel<true, true, true, false>}},
+      {{forest_kernel<false, false, false, true>, forest_kernel<false, true, false, true>},
+       {forest_kernel<true, false, false, true>, forest_kernel<true, true, false, true>},
+       {forest_kernel<true, false, true, true>, forest_kernel<true, true, true, true>}}};
+  const K k = table[fold ? 1 : 0][full ? 2 : grad ? 1 : 0][F.has_gc ? 1 : 0];
+  hipLaunchKernelGGL(k, grid, block, lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
@@ -1818,7 +1907,8 @@ ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, c
                       double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags, bool conj_ok) {
   switch (pick_schedule(g, Abar != nullptr, flags)) {
     case Sched::Forest:
-      return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s);
+      return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s,
+                           conj_ok && !(flags & ACE_FLAG_UNFOLDED) && use_folded_forest(g, Abar != nullptr));
     case Sched::Remat:
       return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s, conj_ok && !(flags & ACE_FLAG_UNFOLDED));
     default:
@@ -1991,7 +2081,8 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out) {
     bs.r_cut = spec->r_cut;
     build_graph(bs, g->h);
     make_schedule(g);
-    make_forest(g);
+    make_forest(g, 0);
+    make_forest(g, 1);
     make_remat(g);
     make_stats(g);
   } catch (const std::invalid_argument& e) {
@@ -2165,15 +2256,16 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   g->opts.term_chunk = o->term_chunk;
   g->opts.pair_slots = o->pair_slots;
   try {
-    make_forest(g);
+    make_forest(g, 0);
+    make_forest(g, 1);
     make_remat(g);
   } catch (const std::bad_alloc&) {
     g->opts = old;
     return fail(ACE_ERR_OUT_OF_MEMORY, "host allocation failed while rebuilding the schedule");
   }
-  if (o->schedule == ACE_SCHEDULE_FOREST && !g->forest_ok) {
+  if (o->schedule == ACE_SCHEDULE_FOREST && !g->fo[0].ok) {
     g->opts.schedule = old.schedule;
-    return fail(ACE_ERR_UNSUPPORTED, "no forest schedule for this graph: " + g->forest_why);
+    return fail(ACE_ERR_UNSUPPORTED, "no forest schedule for this graph: " + g->fo[0].why);
   }
   if (o->schedule == ACE_SCHEDULE_REMAT && !g->remat_ok) {
     g->opts.schedule = old.schedule;
@@ -2196,7 +2288,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
   } else {
     // host-only graph: what a device with 160 KiB of LDS per block would pick
     const size_t lds = 160 * 1024;
-    const bool f = g->forest_ok && forest_lds_bytes(g, true, false) <= lds;
+    const bool f = g->fo[0].ok && forest_lds_bytes(g->fo[0], g->P1, true, false) <= lds;
     const bool r = g->remat_ok && remat_lds_bytes(g, 1) <= lds && remat_lds_bytes(g, 3) <= lds;
     const int want = g->opts.schedule;
     if (want == ACE_SCHEDULE_LAYERED) sc = Sched::Layered;
@@ -2206,7 +2298,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
     else sc = Sched::Layered;
   }
   *kind = sc == Sched::Forest ? 1 : sc == Sched::Remat ? 2 : 0;
-  if (sc != Sched::Forest) g_error = g->forest_ok ? "forest schedule not selected" : g->forest_why;
+  if (sc != Sched::Forest) g_error = g->fo[0].ok ? "forest schedule not selected" : g->fo[0].why;
   if (info) {
     for (int i = 0; i < 16; ++i) info[i] = 0;
     if (sc == Sched::Remat) {
@@ -2259,20 +2351,21 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       info[14] = real3;
     }
     if (sc == Sched::Forest) {
-      info[0] = g->nslot;
-      info[1] = g->n_tslices;
-      info[2] = (int64_t)g->ch_s.size();
+      const ace_graph::Forest& F = g->fo[0];
+      info[0] = F.nslot;
+      info[1] = F.n_tslices;
+      info[2] = (int64_t)F.ch_s.size();
       int64_t realc = 0;
-      for (uint16_t v : g->ch_s) realc += v != (uint16_t)g->P1;
+      for (uint16_t v : F.ch_s) realc += v != (uint16_t)g->P1;
       info[3] = realc;
-      info[4] = g->n_mslices;
-      info[5] = (int64_t)g->me_col.size();
+      info[4] = F.n_mslices;
+      info[5] = (int64_t)F.me_col.size();
       int64_t reale = 0;
-      for (int32_t k : std::vector<int32_t>(g->kmap.begin() + g->cs_me, g->kmap.begin() + g->cs_nu2)) reale += k != -1;
+      for (int32_t k : std::vector<int32_t>(F.kmap.begin() + F.cs_me, F.kmap.begin() + F.cs_nu2)) reale += k != -1;
       info[6] = reale;
-      info[7] = (int64_t)g->gc_s.size();
-      for (int h = 0; h < 4; ++h) info[8 + h] = g->hot_slot[h];
-      info[12] = g->forest_full ? 1 : 0;
+      info[7] = (int64_t)F.gc_s.size();
+      for (int h = 0; h < 4; ++h) info[8 + h] = F.hot_slot[h];
+      info[12] = F.full ? 1 : 0;
       // LDS bank cost of the 16-byte gathers: sum over gathers and quarters of
       // the largest number of lanes sharing a bank group (ideal: 1 each)
       auto cost = [](const uint16_t* sl) {   // distinct slots per bank group (same slot: broadcast)
@@ -2295,24 +2388,32 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
         return c;
       };
       int64_t cm = 0, ct = 0, nm = 0, nt = 0;
-      for (size_t pos = 0; pos + 64 <= g->me_col.size(); pos += 64, ++nm) cm += cost(&g->me_col[pos]);
-      for (size_t pos = 0; pos + 64 <= g->ch_s.size(); pos += 64, ++nt) ct += cost(&g->ch_s[pos]);
+      for (size_t pos = 0; pos + 64 <= F.me_col.size(); pos += 64, ++nm) cm += cost(&F.me_col[pos]);
+      for (size_t pos = 0; pos + 64 <= F.ch_s.size(); pos += 64, ++nt) ct += cost(&F.ch_s[pos]);
       info[13] = nm ? (1000 * cm) / (4 * nm) : 0;   // mean per quarter, x1000
       info[14] = nt ? (1000 * ct) / (4 * nt) : 0;
+      int64_t realf = 0;   // real tree children and pair entries of the folded schedule
+      const ace_graph::Forest& F1 = g->fo[1];
+      if (F1.ok) {
+        for (uint16_t v : F1.ch_s) realf += v != (uint16_t)g->P1;
+        for (int i = F1.cs_me; i < F1.cs_nu2; ++i) realf += F1.kmap[i] != -1;
+      }
+      info[15] = realf;
     }
   }
   return ACE_OK;
 }
 
 ace_status ace_debug_forest_eval(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A,
-                                 double* phi, double* Abar) {
+                                 double* phi, double* Abar, int32_t folded) {
   if (!g || !coeffs || !A || !phi || !Abar || n_env < 0) return fail(ACE_ERR_INVALID_ARG, "NULL argument");
-  if (!g->forest_ok) return fail(ACE_ERR_UNSUPPORTED, "no forest schedule: " + g->forest_why);
+  const int which = folded ? 1 : 0;
+  if (!g->fo[which].ok) return fail(ACE_ERR_UNSUPPORTED, "no forest schedule: " + g->fo[which].why);
   std::vector<double> phi2(2), ab2(2 * (size_t)g->P1);
   for (int64_t e = 0; e < n_env; ++e) {
     // both adjoint modes; they must agree
-    if (!forest_emulate(g, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1, true) ||
-        !forest_emulate(g, coeffs, A + 2 * e * g->P1, phi2.data(), ab2.data(), false))
+    if (!forest_emulate(g, which, coeffs, A + 2 * e * g->P1, phi + 2 * e, Abar + 2 * e * g->P1, true) ||
+        !forest_emulate(g, which, coeffs, A + 2 * e * g->P1, phi2.data(), ab2.data(), false))
       return fail(ACE_ERR_INTERNAL, "forest schedule index out of range");
     double num = 0.0, den = 0.0;
     for (int i = 0; i < 2 * g->P1; ++i) {

@@ -102,7 +102,7 @@ struct ForestArgs {
   const double2* A;          // [n_env][P1]
   double2* phi;              // [n_env]
   double2* Abar;             // [n_env][P1], or nullptr for the forward pass only
-  const double* cs;          // prepared coefficients
+  const double* cs;          // prepared coefficients (double2 pairs for a folded schedule)
   const uint32_t* nu2_ab;    // [N2] parent one-particle slots, a | b << 16
   const int4* mr_slice;      // [n_mslices] {first row, first entry, entries per row, 0}
   const uint16_t* mr_row;    // [64 * n_mslices] row slot of each resident-pair row

@@ -688,9 +688,57 @@ __device__ __forceinline__ void push_r(int P1, const uint32_t* n2, const double2
     push_adj(P1, n2, x, ab, slot, d);
 }
 
+// A coefficient of the forest or remat schedules: c (plain), or (c', c'')
+// for a folded conjugate pair (Re and Im weights).
+template <bool FOLD>
+struct RCoef;
+template <>
+struct RCoef<false> {
+  double c;
+};
+template <>
+struct RCoef<true> {
+  double2 c;
+};
+
+template <bool FOLD>
+__device__ __forceinline__ RCoef<FOLD> load_coef(const double* cs, unsigned i) {
+  RCoef<FOLD> r;
+  if constexpr (FOLD)
+    r.c = reinterpret_cast<const double2*>(cs)[i];
+  else
+    r.c = cs[i];
+  return r;
+}
+
+// y1 += c' x (and y2 += c'' x when folded)
+template <bool FOLD>
+__device__ __forceinline__ void coef_fma(const RCoef<FOLD>& k, double2 v, double2& y1, double2& y2) {
+  if constexpr (FOLD) {
+    y1 = rfma(k.c.x, v, y1);
+    y2 = rfma(k.c.y, v, y2);
+  } else {
+    y1 = rfma(k.c, v, y1);
+  }
+}
+
+// The Re weight (the one the adjoint takes).
+template <bool FOLD>
+__device__ __forceinline__ double re_w(const RCoef<FOLD>& k) {
+  if constexpr (FOLD)
+    return k.c.x;
+  else
+    return k.c;
+}
+
 constexpr int kForestBlock = 512;
 
-template <bool GRAD, bool GC, bool FULL>
+// FOLD: the folded schedule (one tuple of each conjugate pair, with
+// (Re, Im) weights).  Every sum sum_j c_j x_j of the unfolded kernel is then
+// kept twice, with the Re weights (t, y, aw: Re phi and the adjoint) and
+// with the Im weights (ti, yi, awi: Im phi only), since
+// c' Re(u w) + i c'' Im(u w) = Re(u sum c' w) + i Im(u sum c'' w).
+template <bool GRAD, bool GC, bool FULL, bool FOLD>
 __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
   extern __shared__ double2 lds[];
   // values of the resident slots; adjoints of all resident slots (FULL) or of
@@ -714,7 +762,7 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
     const double2* Ae = p.A + e * P1;
     for (int i = threadIdx.x; i < P1; i += blockDim.x) {
       x[i] = Ae[i];
-      if (GRAD) ab[i] = make_double2(cs[p.cs_leaf + i], 0.0);
+      if (GRAD) ab[i] = make_double2(re_w(load_coef<FOLD>(cs, p.cs_leaf + i)), 0.0);
     }
     if (threadIdx.x == 0) {
       x[ZERO] = make_double2(0.0, 0.0);
@@ -723,17 +771,19 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
     if (GRAD && FULL)
       for (int u = threadIdx.x; u < p.N2; u += blockDim.x) ab[P1 + 1 + u] = make_double2(0.0, 0.0);
     __syncthreads();
-    double2 acc = make_double2(0.0, 0.0);
+    // phi = acc (unfolded); Re acc + i Im acci (folded)
+    double2 acc = make_double2(0.0, 0.0), acci = acc;
     // phase 1: order-2 nodes, their own and the one-particle coefficients
-    for (int i = threadIdx.x; i < P1; i += blockDim.x) acc = rfma(cs[p.cs_leaf + i], x[i], acc);
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) coef_fma(load_coef<FOLD>(cs, p.cs_leaf + i), x[i], acc, acci);
     for (int u = threadIdx.x; u < p.N2; u += blockDim.x) {
       const uint32_t q = p.nu2_ab[u];
       const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
       const double2 xa = x[a], xb = x[b];
       const double2 xu = cmul(xa, xb);
       x[P1 + 1 + u] = xu;
-      const double c = cs[p.cs_nu2 + u];
-      acc = rfma(c, xu, acc);
+      const RCoef<FOLD> k = load_coef<FOLD>(cs, p.cs_nu2 + u);
+      coef_fma(k, xu, acc, acci);
+      const double c = re_w(k);
       if (GRAD && c != 0.0) {
         atomic_cadd(&ab[a], make_double2(c * xb.x, c * xb.y));
         atomic_cadd(&ab[b], make_double2(c * xa.x, c * xa.y));
@@ -744,28 +794,33 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
     for (int s = wid; s < p.n_mslices; s += nw) {
       const int4 sl = p.mr_slice[s];
       const int row = p.mr_row[sl.x + lane];
-      const double* ce = cs + p.cs_me;
-      double2 y0 = make_double2(0.0, 0.0), y1 = make_double2(0.0, 0.0);
+      double2 y0 = make_double2(0.0, 0.0), y1 = y0, y0i = y0, y1i = y0;
       const int z4 = sl.z & ~3;
       for (int j = z4; j < sl.z; ++j) {
         const int pos = sl.y + j * 64 + lane;
-        y0 = rfma(ce[pos], x[p.me_col[pos]], y0);
+        coef_fma(load_coef<FOLD>(cs, p.cs_me + pos), x[p.me_col[pos]], y0, y0i);
       }
       for (int j = 0; j < z4; j += 4) {
         const int pos = sl.y + j * 64 + lane;
         const int c0 = p.me_col[pos], c1 = p.me_col[pos + 64];
         const int c2 = p.me_col[pos + 128], c3 = p.me_col[pos + 192];
-        const double k0 = ce[pos], k1 = ce[pos + 64], k2 = ce[pos + 128], k3 = ce[pos + 192];
+        const RCoef<FOLD> k0 = load_coef<FOLD>(cs, p.cs_me + pos), k1 = load_coef<FOLD>(cs, p.cs_me + pos + 64);
+        const RCoef<FOLD> k2 = load_coef<FOLD>(cs, p.cs_me + pos + 128), k3 = load_coef<FOLD>(cs, p.cs_me + pos + 192);
         const double2 x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-        y0 = rfma(k0, x0, y0);
-        y1 = rfma(k1, x1, y1);
-        y0 = rfma(k2, x2, y0);
-        y1 = rfma(k3, x3, y1);
+        coef_fma(k0, x0, y0, y0i);
+        coef_fma(k1, x1, y1, y1i);
+        coef_fma(k2, x2, y0, y0i);
+        coef_fma(k3, x3, y1, y1i);
       }
       const double2 y = make_double2(y0.x + y1.x, y0.y + y1.y);
-      const double2 h = cmul(x[row], y);
+      const double2 xr = x[row];
+      const double2 h = cmul(xr, y);
       acc.x = fma(0.5, h.x, acc.x);
       acc.y = fma(0.5, h.y, acc.y);
+      if (FOLD) {
+        const double2 hi = cmul(xr, make_double2(y0i.x + y1i.x, y0i.y + y1i.y));
+        acci.y = fma(0.5, hi.y, acci.y);
+      }
       if (GRAD && row != ZERO) push_r<FULL>(P1, n2, x, ab, row, y);
     }
     // phase 2b: trees.  Children whose sibling is one of the four hot slots
@@ -780,69 +835,79 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
       const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
       const double2 xa = x[a], xb = x[b];
       const double2 xv = cmul(xa, xb);
-      double2 t = make_double2(cs[p.cs_it + item], 0.0);  // abar_v from childless children
+      // abar_v from childless children (t, and ti for Im phi when folded)
+      double2 t = make_double2(0.0, 0.0), ti = t;
+      coef_fma(load_coef<FOLD>(cs, p.cs_it + item), make_double2(1.0, 0.0), t, ti);
       double2 asum = make_double2(0.0, 0.0);              // abar_v from children with children
       {
-        const double* ch = cs + p.cs_hot + item;
-        const double k0 = ch[0], k1 = ch[p.n_items], k2 = ch[2 * p.n_items], k3 = ch[3 * p.n_items];
-        t = rfma(k0, xh0, t);
-        t = rfma(k1, xh1, t);
-        t = rfma(k2, xh2, t);
-        t = rfma(k3, xh3, t);
+        const int hp = p.cs_hot + item;
+        const RCoef<FOLD> k0 = load_coef<FOLD>(cs, hp), k1 = load_coef<FOLD>(cs, hp + p.n_items);
+        const RCoef<FOLD> k2 = load_coef<FOLD>(cs, hp + 2 * p.n_items), k3 = load_coef<FOLD>(cs, hp + 3 * p.n_items);
+        coef_fma(k0, xh0, t, ti);
+        coef_fma(k1, xh1, t, ti);
+        coef_fma(k2, xh2, t, ti);
+        coef_fma(k3, xh3, t, ti);
         if (GRAD) {
-          hacc0 = rfma(k0, xv, hacc0);
-          hacc1 = rfma(k1, xv, hacc1);
-          hacc2 = rfma(k2, xv, hacc2);
-          hacc3 = rfma(k3, xv, hacc3);
+          hacc0 = rfma(re_w(k0), xv, hacc0);
+          hacc1 = rfma(re_w(k1), xv, hacc1);
+          hacc2 = rfma(re_w(k2), xv, hacc2);
+          hacc3 = rfma(re_w(k3), xv, hacc3);
         }
       }
-      const double* cc = cs + p.cs_ch;
+      const int cc = p.cs_ch;
       if (!GC) {
         // four children at a time, then the remainder (padding: sibling ZERO, coefficient 0)
         const int z4 = sl.z & ~3;
         for (int j = z4; j < sl.z; ++j) {
           const int pos = sl.y + j * 64 + lane;
           const int s0 = p.ch_s[pos];
-          const double k0 = cc[pos];
-          t = rfma(k0, x[s0], t);
-          if (GRAD && k0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
+          const RCoef<FOLD> k0 = load_coef<FOLD>(cs, cc + pos);
+          coef_fma(k0, x[s0], t, ti);
+          const double r0 = re_w(k0);
+          if (GRAD && r0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(r0 * xv.x, r0 * xv.y));
         }
         for (int j = 0; j < z4; j += 4) {
           const int pos = sl.y + j * 64 + lane;
           const int s0 = p.ch_s[pos], s1 = p.ch_s[pos + 64], s2 = p.ch_s[pos + 128], s3 = p.ch_s[pos + 192];
-          const double k0 = cc[pos], k1 = cc[pos + 64], k2 = cc[pos + 128], k3 = cc[pos + 192];
+          const RCoef<FOLD> k0 = load_coef<FOLD>(cs, cc + pos), k1 = load_coef<FOLD>(cs, cc + pos + 64);
+          const RCoef<FOLD> k2 = load_coef<FOLD>(cs, cc + pos + 128), k3 = load_coef<FOLD>(cs, cc + pos + 192);
           const double2 x0 = x[s0], x1 = x[s1], x2 = x[s2], x3 = x[s3];
-          t = rfma(k0, x0, t);
-          t = rfma(k1, x1, t);
-          t = rfma(k2, x2, t);
-          t = rfma(k3, x3, t);
+          coef_fma(k0, x0, t, ti);
+          coef_fma(k1, x1, t, ti);
+          coef_fma(k2, x2, t, ti);
+          coef_fma(k3, x3, t, ti);
           if (GRAD) {
-            if (k0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(k0 * xv.x, k0 * xv.y));
-            if (k1 != 0.0) push_r<FULL>(P1, n2, x, ab, s1, make_double2(k1 * xv.x, k1 * xv.y));
-            if (k2 != 0.0) push_r<FULL>(P1, n2, x, ab, s2, make_double2(k2 * xv.x, k2 * xv.y));
-            if (k3 != 0.0) push_r<FULL>(P1, n2, x, ab, s3, make_double2(k3 * xv.x, k3 * xv.y));
+            const double r0 = re_w(k0), r1 = re_w(k1), r2 = re_w(k2), r3 = re_w(k3);
+            if (r0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(r0 * xv.x, r0 * xv.y));
+            if (r1 != 0.0) push_r<FULL>(P1, n2, x, ab, s1, make_double2(r1 * xv.x, r1 * xv.y));
+            if (r2 != 0.0) push_r<FULL>(P1, n2, x, ab, s2, make_double2(r2 * xv.x, r2 * xv.y));
+            if (r3 != 0.0) push_r<FULL>(P1, n2, x, ab, s3, make_double2(r3 * xv.x, r3 * xv.y));
           }
         }
       } else {
         for (int j = 0; j < sl.z; ++j) {
           const int pos = sl.y + j * 64 + lane;
           const int sidx = p.ch_s[pos];
-          const double c = cc[pos];
+          const RCoef<FOLD> k = load_coef<FOLD>(cs, cc + pos);
+          const double c = re_w(k);
           const int2 g = p.ch_g[pos];
           const double2 xs = x[sidx];
           if (g.x == g.y) {
-            t = rfma(c, xs, t);
+            coef_fma(k, xs, t, ti);
             if (GRAD && c != 0.0) push_r<FULL>(P1, n2, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
           } else {
             const double2 xw = cmul(xv, xs);
-            double2 aw = make_double2(c, 0.0);
-            for (int k = g.x; k < g.y; ++k) {
-              const int sg = p.gc_s[k];
-              const double cg = cs[p.cs_gc + k];
-              aw = rfma(cg, x[sg], aw);
+            double2 aw = make_double2(0.0, 0.0), awi = aw;
+            coef_fma(k, make_double2(1.0, 0.0), aw, awi);
+            for (int kk = g.x; kk < g.y; ++kk) {
+              const int sg = p.gc_s[kk];
+              const RCoef<FOLD> kg = load_coef<FOLD>(cs, p.cs_gc + kk);
+              coef_fma(kg, x[sg], aw, awi);
+              const double cg = re_w(kg);
               if (GRAD) push_r<FULL>(P1, n2, x, ab, sg, make_double2(cg * xw.x, cg * xw.y));
             }
             acc = cfma(xw, aw, acc);
+            if (FOLD) acci = cfma(xw, awi, acci);
             if (GRAD) {
               push_r<FULL>(P1, n2, x, ab, sidx, cmul(aw, xv));
               asum = cfma(aw, xs, asum);
@@ -851,6 +916,7 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
         }
       }
       acc = cfma(xv, t, acc);
+      if (FOLD) acci = cfma(xv, ti, acci);
       if (GRAD && q != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
         const double2 av = make_double2(t.x + asum.x, t.y + asum.y);
         push_r<FULL>(P1, n2, x, ab, a, cmul(av, xb));
@@ -879,6 +945,7 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
       }
       __syncthreads();
     }
+    if (FOLD) acc.y = acci.y;
     const double2 phi = block_sum(acc, red);
     if (threadIdx.x == 0) p.phi[e] = phi;
     if (GRAD) {
@@ -958,40 +1025,6 @@ __device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo,
 #pragma unroll
   for (int u = 1; u < SIG; ++u) v = cmul(v, lds_at(x, slot16(lo, hi, u)));
   return v;
-}
-
-// Coefficients of a remat entry: c (plain), or (c', c'') for a folded
-// conjugate pair (Re and Im weights).
-template <bool FOLD>
-struct RCoef;
-template <>
-struct RCoef<false> {
-  double c;
-};
-template <>
-struct RCoef<true> {
-  double2 c;
-};
-
-template <bool FOLD>
-__device__ __forceinline__ RCoef<FOLD> load_coef(const double* cs, unsigned i) {
-  RCoef<FOLD> r;
-  if constexpr (FOLD)
-    r.c = reinterpret_cast<const double2*>(cs)[i];
-  else
-    r.c = cs[i];
-  return r;
-}
-
-// y1 += c' x (and y2 += c'' x when folded)
-template <bool FOLD>
-__device__ __forceinline__ void coef_fma(const RCoef<FOLD>& k, double2 v, double2& y1, double2& y2) {
-  if constexpr (FOLD) {
-    y1 = rfma(k.c.x, v, y1);
-    y2 = rfma(k.c.y, v, y2);
-  } else {
-    y1 = rfma(k.c, v, y1);
-  }
 }
 
 template <bool GRAD, int SIG, bool FOLD>
@@ -1167,11 +1200,17 @@ __global__ __launch_bounds__(256) void prep_fold_kernel(PrepFoldArgs p) {
   }
 }
 
-template __global__ void forest_kernel<false, false, false>(ForestArgs);
-template __global__ void forest_kernel<false, true, false>(ForestArgs);
-template __global__ void forest_kernel<true, false, false>(ForestArgs);
-template __global__ void forest_kernel<true, true, false>(ForestArgs);
-template __global__ void forest_kernel<true, false, true>(ForestArgs);
-template __global__ void forest_kernel<true, true, true>(ForestArgs);
+template __global__ void forest_kernel<false, false, false, false>(ForestArgs);
+template __global__ void forest_kernel<false, true, false, false>(ForestArgs);
+template __global__ void forest_kernel<true, false, false, false>(ForestArgs);
+template __global__ void forest_kernel<true, true, false, false>(ForestArgs);
+template __global__ void forest_kernel<true, false, true, false>(ForestArgs);
+template __global__ void forest_kernel<true, true, true, false>(ForestArgs);
+template __global__ void forest_kernel<false, false, false, true>(ForestArgs);
+template __global__ void forest_kernel<false, true, false, true>(ForestArgs);
+template __global__ void forest_kernel<true, false, false, true>(ForestArgs);
+template __global__ void forest_kernel<true, true, false, true>(ForestArgs);
+template __global__ void forest_kernel<true, false, true, true>(ForestArgs);
+template __global__ void forest_kernel<true, true, true, true>(ForestArgs);
 
 }  // namespace ace

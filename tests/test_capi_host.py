@@ -304,6 +304,80 @@ def test_folded_remat_matches_oracle_for_conjugate_symmetric_A(spec, alg, n):
     assert np.linalg.norm(ab - ar) > 1e-6 * np.linalg.norm(ar)
 
 
+# ---- folded forest schedule (conjugate pairs) --------------------------------------
+@pytest.mark.parametrize("spec,alg,n", [((4, 4, 8, 3), 1, 1), ((6, 6, 12, 4), 1, 1), ((6, 6, 12, 4), 2, 2),
+                                        ((3, 2, 9, 5), 1, 1)])
+def test_folded_forest_matches_oracle_for_conjugate_symmetric_A(spec, alg, n):
+    """The forest over one tuple of each conjugate pair: phi exact for
+    conjugate-symmetric A, and Re sum_i Abar'_i dA_i equal to the oracle's
+    d Re(phi) along conjugate-symmetric directions dA."""
+    from oracle import contraction as oc
+    from oracle.indexsets import all_invariant_tuples
+    import workloads as wl
+    nmax, lmax, D, nu = spec
+    G = ace.Graph(nu, D, nmax, lmax, algorithm=alg, alg_n=n, host_only=True)
+    if G.schedule_kind() != "forest":
+        pytest.skip("graph uses another schedule")
+    info = G.schedule_info()
+    assert 0 < info["folded_real"] < 0.9 * (info["child_real"] + info["entry_real"])
+    g = group_o3(nmax, lmax, D)
+    K = all_invariant_tuples(g, nu, D)
+    c = np.random.default_rng(13).standard_normal(len(K))
+    A = wl.random_A_conj(3, g.labels, 33) * 0.5
+    dA = wl.random_A_conj(3, g.labels, 34)
+    phi, ab = G.forest_eval_host(c, A, folded=True)
+    pr, ar = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+    lhs = np.real(np.sum(ab * dA, axis=1))
+    rhs = np.real(np.sum(ar * dA, axis=1))
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+    assert np.linalg.norm(ab - ar) > 1e-6 * np.linalg.norm(ar)
+    # the unfolded forest is exact for any A
+    A2 = wl.random_A(2, len(g), 35) * 0.5
+    phi2, ab2 = G.forest_eval_host(c, A2, folded=False)
+    assert np.linalg.norm(phi2 - oc.phi_naive(K, c, A2)) <= 1e-13 * np.linalg.norm(phi2)
+    assert np.linalg.norm(ab2 - oc.abar_naive(K, c, A2)) <= 1e-13 * np.linalg.norm(ab2)
+
+
+@pytest.mark.parametrize("group", ["so2", "torus", "features"])
+def test_folded_forest_other_groups_matches_oracle(group):
+    """Folded forest on pooled one-particle values of the planar groups and of
+    an O(3) basis with an invariant feature."""
+    from oracle import contraction as oc
+    from oracle import onebody as ob
+    from oracle.indexsets import all_invariant_tuples, group_o3_features, group_so2
+    import workloads as wl
+    if group == "so2":
+        G = ace.Graph(4, 8, 4, 4, group=ace.GROUP_SO2, host_only=True)
+        g = group_so2(4, 4, 8)
+        K = all_invariant_tuples(g, 4, 8)
+        off = np.array([0, 6, 13, 20], np.int32)
+        pos = wl.planar_positions(20, 6, circle=False)
+    elif group == "torus":
+        G = ace.Graph(5, 8, group=ace.GROUP_TORUS, host_only=True)
+        g = group_torus(8)
+        K = all_invariant_tuples(g, 5, 8)
+        off = np.array([0, 6, 13, 20], np.int32)
+        pos = wl.planar_positions(20, 7, circle=True)
+    else:
+        G = ace.Graph(4, 8, 3, 3, k_max=2, host_only=True)
+        g = group_o3_features(3, 3, 2, 8)
+        K = all_invariant_tuples(g, 4, 8)
+        rng = np.random.default_rng(3)
+        d = rng.standard_normal((15, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        pos = np.concatenate([d * rng.uniform(0.5, 5, 15)[:, None], rng.uniform(-1, 1, (15, 1))], axis=1)
+        off = np.array([0, 7, 15], np.int32)
+    if G.schedule_kind() != "forest":
+        pytest.skip("graph uses another schedule")
+    c = np.random.default_rng(4).standard_normal(len(K))
+    A = ob.pooled_A(g.labels, off, pos, 5.0)
+    pr = oc.phi_naive(K, c, A)
+    for folded in (False, True):
+        phi, _ = G.forest_eval_host(c, A, folded=folded)
+        assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+
+
 # ---- planar groups: SO(2) builder and schedules ------------------------------------
 @pytest.mark.parametrize("spec,alg,n", [((3, 3, 6, 4), 1, 1), ((4, 4, 8, 3), 2, 2), ((2, 5, 7, 5), 1, 1)])
 def test_builder_bit_exact_so2(spec, alg, n):

@@ -341,14 +341,15 @@ def test_large_basis_eval_grad(device, wid, n_env):
     assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
 
 
-# ---- conjugate-pair folding (remat schedule) -----------------------------------------
-@pytest.mark.parametrize("wid,n_env", [(4, 24), (5, 4)])
-def test_folded_and_unfolded_eval_grad_agree(device, wid, n_env):
-    """ace_eval_grad folds conjugate pairs on the remat schedule; the flag
-    ACE_FLAG_UNFOLDED evaluates every tuple.  Both match, and the oracle."""
+# ---- conjugate-pair folding (remat and forest schedules) -----------------------------
+@pytest.mark.parametrize("sched", ["remat", None])
+@pytest.mark.parametrize("wid,n_env", [(3, 40), (4, 24), (5, 4)])
+def test_folded_and_unfolded_eval_grad_agree(device, wid, n_env, sched):
+    """ace_eval_grad folds conjugate pairs on the remat and forest schedules;
+    the flag ACE_FLAG_UNFOLDED evaluates every tuple.  Both match, and the oracle."""
     import paper_2202_04140_amd as ace
-    print(f"folded wid={wid} n_env={n_env}", flush=True)
-    G = graph(wid, device, "remat")
+    print(f"folded wid={wid} n_env={n_env} sched={sched}", flush=True)
+    G = graph(wid, device, sched)
     g, K, c = oracle_basis(wid)
     off, pos = problem(wid, n_env)
     tc, toff, tpos = to_dev(device, c, off, pos)
@@ -358,7 +359,7 @@ def test_folded_and_unfolded_eval_grad_agree(device, wid, n_env):
     assert rel(grad_f.cpu().numpy(), grad_u.cpu().numpy()) <= TOL_GRAD
     phi_e = ace.eval(G, tc, toff, tpos)
     assert rel(cplx(phi_e), cplx(phi_u)) <= TOL_PHI
-    if wid == 4:
+    if wid in (3, 4):
         phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
         assert rel(cplx(phi_f), phi_ref) <= TOL_PHI
         assert rel(grad_f.cpu().numpy(), g_ref) <= TOL_GRAD
