@@ -41,7 +41,8 @@ constexpr int kDagThreads = 256;
 constexpr int kForestThreads = 512;
 constexpr int kNaiveThreads = 256;
 constexpr int kBasisThreads = 256;
-constexpr int kGradThreads = 256;
+constexpr int kGradThreads = 256;   // planar gradient kernel
+constexpr int kGradWave = 64;       // O(3) gradient kernel: one wave per block
 constexpr int kArenaBlocks = 1024;
 constexpr int kRematMaxSlots = 4096;   // remat factor fields are 16-bit LDS byte offsets
 constexpr size_t kAlign = 256;
@@ -83,14 +84,14 @@ struct ace_graph {
   std::vector<int16_t> naive_tup;
   std::vector<OnepInfo> onep;
   std::vector<int16_t> onep_index;
-  std::vector<int32_t> nstart;
+  std::vector<int32_t> gsrc;
   std::vector<double> ycoef;
   // device copies (one allocation)
   void* dmem = nullptr;
   int2 *d_st_ab = nullptr, *d_cl_ab = nullptr;
   int32_t *d_st_k = nullptr, *d_cl_k = nullptr, *d_leaf_k = nullptr;
   int16_t *d_naive_tup = nullptr, *d_onep_index = nullptr;
-  int32_t* d_nstart = nullptr;
+  int32_t* d_gsrc = nullptr;
   OnepInfo* d_onep = nullptr;
   double* d_ycoef = nullptr;
   // LDS plan
@@ -260,7 +261,7 @@ void make_schedule(ace_graph* g) {
   // one-particle tables (O(3) only)
   g->onep.clear();
   g->onep_index.clear();
-  g->nstart.clear();
+  g->gsrc.clear();
   g->ycoef.clear();
   if (h.spec.group == 0) {
     const int L = h.spec.l_max, N = h.spec.n_max, W = 2 * L + 1;
@@ -281,12 +282,14 @@ void make_schedule(ace_graph* g) {
       if (h.on_k[i] == 0) g->onep_index[(size_t)(n * (L + 1) + l) * W + (m + L)] = (int16_t)i;
     }
     make_ycoef(L, g->ycoef);
-    // index of (n, l, -l, k) per (l, n, k); the 2l+1 functions of one (n, l, k)
-    // are consecutive in the canonical order
+    // the gradient kernel's layout of Abar: position ((l^2 + l + m) (N+1) + n) K1 + k
+    // holds one-particle function (n, l, m, k), or -1 (absent: zero)
     const int K1 = h.spec.k_max + 1;
-    g->nstart.assign((size_t)(L + 1) * (N + 1) * K1, -1);
-    for (int i = 0; i < P1; ++i)
-      if (h.on_m[i] == -h.on_l[i]) g->nstart[((size_t)h.on_l[i] * (N + 1) + h.on_n[i]) * K1 + h.on_k[i]] = i;
+    g->gsrc.assign((size_t)(L + 1) * (L + 1) * (N + 1) * K1, -1);
+    for (int i = 0; i < P1; ++i) {
+      const int l = h.on_l[i];
+      g->gsrc[((size_t)(l * l + l + h.on_m[i]) * (N + 1) + h.on_n[i]) * K1 + h.on_k[i]] = i;
+    }
   } else {
     // planar groups: phi = R_n (Re E, sim Im E), E = u^{|m|}, sim = s sign(m) with
     // s = +1 (torus, e^{+i m theta}) or -1 (SO(2), e^{-i m theta}); onep_index
@@ -1584,7 +1587,7 @@ ace_status upload(ace_graph* g) {
   bytes += align_up(g->cl_ab.size() * sizeof(int2)) + align_up(g->cl_k.size() * 4);
   bytes += align_up(g->leaf_k.size() * 4) + align_up(g->naive_tup.size() * 2);
   bytes += align_up(g->onep.size() * sizeof(OnepInfo)) + align_up(g->onep_index.size() * 2);
-  bytes += align_up(g->ycoef.size() * 8) + align_up(g->nstart.size() * 4) + kAlign;
+  bytes += align_up(g->ycoef.size() * 8) + align_up(g->gsrc.size() * 4) + kAlign;
   if (hipMalloc(&g->dmem, bytes) != hipSuccess) {
     g->dmem = nullptr;
     (void)hipGetLastError();
@@ -1600,7 +1603,7 @@ ace_status upload(ace_graph* g) {
   g->d_onep = carve<OnepInfo>(p, g->onep.size());
   g->d_onep_index = carve<int16_t>(p, g->onep_index.size());
   g->d_ycoef = carve<double>(p, g->ycoef.size());
-  g->d_nstart = carve<int32_t>(p, g->nstart.size());
+  g->d_gsrc = carve<int32_t>(p, g->gsrc.size());
   auto put = [](void* d, const void* s, size_t n) { return n ? hipMemcpy(d, s, n, hipMemcpyHostToDevice) : hipSuccess; };
   ACE_HIP(put(g->d_st_ab, g->st_ab.data(), g->st_ab.size() * sizeof(int2)));
   ACE_HIP(put(g->d_st_k, g->st_k.data(), g->st_k.size() * 4));
@@ -1611,7 +1614,7 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(put(g->d_onep, g->onep.data(), g->onep.size() * sizeof(OnepInfo)));
   ACE_HIP(put(g->d_onep_index, g->onep_index.data(), g->onep_index.size() * 2));
   ACE_HIP(put(g->d_ycoef, g->ycoef.data(), g->ycoef.size() * 8));
-  ACE_HIP(put(g->d_nstart, g->nstart.data(), g->nstart.size() * 4));
+  ACE_HIP(put(g->d_gsrc, g->gsrc.data(), g->gsrc.size() * 4));
 
   // LDS plan for the DAG kernel
   const size_t red = (kDagThreads / 64) * sizeof(double2);
@@ -1624,7 +1627,8 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-  ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)planar_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   {
     const ace_status fs = upload_forest(g);
@@ -2014,7 +2018,7 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.Abar = Abar;
   a.grad = grad;
   a.onep_index = g->d_onep_index;
-  a.nstart = g->d_nstart;
+  a.gsrc = g->d_gsrc;
   a.ycoef = g->d_ycoef;
   a.P1 = g->P1;
   a.n_max = g->h.spec.n_max;
@@ -2024,11 +2028,12 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.k_max = g->h.spec.k_max;
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
-  const int nwb = kGradThreads / 64;
-  const size_t lds = (size_t)nwb * g->P1 * 16 + (size_t)3 * NY * 8 + g->nstart.size() * 4;
+  const size_t lds = g->gsrc.size() * sizeof(double2) + (size_t)3 * NY * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
-  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_env + nwb - 1) / nwb, (int64_t)1 << 20));
-  hipLaunchKernelGGL(grad_kernel, dim3((unsigned)blocks), dim3(kGradThreads), lds, s, a);
+  if (a.k_max > 0)
+    hipLaunchKernelGGL(grad_kernel<true>, dim3((unsigned)grid_for(n_env)), dim3(kGradWave), lds, s, a);
+  else
+    hipLaunchKernelGGL(grad_kernel<false>, dim3((unsigned)grid_for(n_env)), dim3(kGradWave), lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }

@@ -328,41 +328,39 @@ template __global__ void naive_kernel<8>(NaiveArgs);
 // where Q follows the same recurrence as q with the constant term scaled
 // by rho, differentiated in z and rho alongside (no pole singularity).
 //
-// One wave per environment, its adjoint Abar in LDS.  Lanes are
-// (neighbour, group) pairs: group g of G handles m = g, g + G, ... and the
-// G partial gradients of a neighbour are summed by lane shuffles; G is the
-// largest power of two with G * J <= 64 (at most 16).
+// One wave (one block) per environment, its adjoint Abar in LDS in (l, m, n,
+// k) order with zeros for absent functions, so the inner loop over n reads
+// two affine addresses.  Lanes are (neighbour, group) pairs: group g of G
+// handles m = g, g + G, ... and the G partial gradients of a neighbour are
+// summed by lane shuffles; G is the largest power of two with G * J <= 64
+// (at most 16).  FEAT: a feature factor T_k(mu) per function (Sec. 5.4).
 // ---------------------------------------------------------------------------
-constexpr int kGradBlock = 256;
-
-__global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
+template <bool FEAT>
+__global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
   extern __shared__ double2 lds[];
   const int L = p.l_max, N = p.n_max;
+  const int K1 = FEAT ? p.k_max + 1 : 1;
   const int NY = (L + 1) * (L + 2) / 2;
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nwb = blockDim.x >> 6;
-  double2* Ab = lds + wid * p.P1;                                    // [nwb][P1]
-  double* yc = reinterpret_cast<double*>(lds + nwb * p.P1);           // [3 * NY]
-  int* nst = reinterpret_cast<int*>(yc + 3 * NY);                    // [(L+1)*(N+1)*(k_max+1)]
-  for (int i = threadIdx.x; i < 3 * NY; i += blockDim.x) yc[i] = p.ycoef[i];
-  const int K1 = p.k_max + 1;
-  for (int i = threadIdx.x; i < (L + 1) * (N + 1) * K1; i += blockDim.x) nst[i] = p.nstart[i];
+  const int NB = (N + 1) * K1;                 // entries per (l, m)
+  const int ND = (L + 1) * (L + 1) * NB;
+  const int lane = threadIdx.x;
+  double2* Ab = lds;                                           // [ND]
+  double* yc = reinterpret_cast<double*>(lds + ND);            // [3 * NY]
+  for (int i = lane; i < 3 * NY; i += 64) yc[i] = p.ycoef[i];
   const double* cA = yc;
   const double* cB = yc + NY;
   const double* cS = yc + 2 * NY;
-  const int64_t rounds = (p.n_env + (int64_t)gridDim.x * nwb - 1) / ((int64_t)gridDim.x * nwb);
-  for (int64_t it = 0; it < rounds; ++it) {
-    const int64_t e = (it * gridDim.x + blockIdx.x) * nwb + wid;   // wave-uniform
-    __syncthreads();
-    if (e < p.n_env) {
-      const double2* Be = p.Abar + e * p.P1;
-      for (int i = lane; i < p.P1; i += 64) Ab[i] = Be[i];
-    }
-    __syncthreads();
-    if (e >= p.n_env) continue;
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
-    if (J <= 0) continue;
+    if (J <= 0) continue;   // block-uniform
+    __syncthreads();
+    const double2* Be = p.Abar + e * p.P1;
+    for (int d = lane; d < ND; d += 64) {
+      const int src = p.gsrc[d];
+      Ab[d] = src >= 0 ? Be[src] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
     int G = 1;
     while (G < 16 && 2 * G * J <= 64) G *= 2;
     const int per = 64 / G;              // neighbours per pass
@@ -372,7 +370,7 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
       const int64_t j = j0 + jj;
       const double* rp = p.pos + p.pos_stride * j;
       const double rx = rp[0], ry = rp[1], rz = rp[2];
-      const double mu = K1 > 1 ? rp[3] : 0.0;   // invariant feature (Sec. 5.4)
+      const double mu = FEAT ? rp[3] : 0.0;   // invariant feature (Sec. 5.4)
       const double rr = sqrt(rx * rx + ry * ry + rz * rz);
       const double inv = 1.0 / rr;
       const double x = rx * inv, y = ry * inv, z = rz * inv;
@@ -380,16 +378,12 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
       const double c = cos(arg);
       const double dcdr = -(M_PI / p.r_cut) * sin(arg);
       double gx = 0.0, gy = 0.0, gz = 0.0;
-      // (x + i y)^g, (x + i y)^G, (x + i y)^(G-1)
-      double pr = 1.0, pi = 0.0, pGr = 1.0, pGi = 0.0, pG1r = 1.0, pG1i = 0.0;
+      // (x + i y)^g, (x + i y)^G
+      double pr = 1.0, pi = 0.0, pGr = 1.0, pGi = 0.0;
       for (int k = 0; k < G; ++k) {
         if (k == g) {
           pr = pGr;
           pi = pGi;
-        }
-        if (k == G - 1) {
-          pG1r = pGr;
-          pG1i = pGi;
         }
         const double nr = pGr * x - pGi * y;
         pGi = pGr * y + pGi * x;
@@ -409,13 +403,59 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
         double Q2 = 0.0, Qz2 = 0.0, Qp2 = 0.0;
         double Q1 = cS[(m * (m + 1)) / 2 + m], Qz1 = 0.0, Qp1 = 0.0;
         for (int l = m; l <= L; ++l) {
-          const int o = (l * (l + 1)) / 2 + m;
+          // B0 = sum_{n,k} Abar_{n l (+/-m) k} T_n T_k, B1 = the same with T_n'
+          const double2* bp = Ab + (l * l + l + m) * NB;
+          const double2* bm = Ab + (l * l + l - m) * NB;
+          double b0pr = 0.0, b0pi = 0.0, b1pr = 0.0, b1pi = 0.0;   // +m
+          double b0mr = 0.0, b0mi = 0.0, b1mr = 0.0, b1mi = 0.0;   // -m
+          double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
+          for (int n = 0; n <= N; ++n) {
+            double T, dT;
+            if (n == 0) {
+              T = 1.0;
+              dT = 0.0;
+            } else if (n == 1) {
+              T = c;
+              dT = 1.0;
+            } else {
+              T = 2.0 * c * t1 - t0;
+              dT = 2.0 * t1 + 2.0 * c * d1 - d0;
+              t0 = t1;
+              t1 = T;
+              d0 = d1;
+              d1 = dT;
+            }
+            double k0 = 1.0, k1 = mu;
+            for (int k = 0; k < K1; ++k) {
+              double Tk = 1.0;
+              if (FEAT) {
+                if (k == 1) {
+                  Tk = mu;
+                } else if (k >= 2) {
+                  Tk = 2.0 * mu * k1 - k0;
+                  k0 = k1;
+                  k1 = Tk;
+                }
+              }
+              const double w = T * Tk, dw = dT * Tk;
+              const double2 ap = bp[n * K1 + k], am = bm[n * K1 + k];
+              b0pr = fma(ap.x, w, b0pr);
+              b0pi = fma(ap.y, w, b0pi);
+              b1pr = fma(ap.x, dw, b1pr);
+              b1pi = fma(ap.y, dw, b1pi);
+              b0mr = fma(am.x, w, b0mr);
+              b0mi = fma(am.y, w, b0mi);
+              b1mr = fma(am.x, dw, b1mr);
+              b1mi = fma(am.y, dw, b1mi);
+            }
+          }
           double Q, Qz, Qp;
           if (l == m) {
             Q = Q1;
             Qz = 0.0;
             Qp = 0.0;
           } else {
+            const int o = (l * (l + 1)) / 2 + m;
             const double a = cA[o], b = cB[o];
             Q = a * z * Q1 - b * Q2;
             Qz = a * (Q1 + z * Qz1) - b * Qz2;
@@ -441,53 +481,6 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
           const double gYxr = (dxr - lf * Sr * x) * inv, gYxi = (dxi - lf * Si * x) * inv;
           const double gYyr = (dyr - lf * Sr * y) * inv, gYyi = (dyi - lf * Si * y) * inv;
           const double gYzr = (dzr - lf * Sr * z) * inv, gYzi = (dzi - lf * Si * z) * inv;
-          // B0 = sum_n Abar_{n l (+/-m)} T_n, B1 = sum_n Abar_{n l (+/-m)} T_n'
-          double b0pr = 0.0, b0pi = 0.0, b1pr = 0.0, b1pi = 0.0;   // +m
-          double b0mr = 0.0, b0mi = 0.0, b1mr = 0.0, b1mi = 0.0;   // -m
-          double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
-          for (int n = 0; n <= N; ++n) {
-            double T, dT;
-            if (n == 0) {
-              T = 1.0;
-              dT = 0.0;
-            } else if (n == 1) {
-              T = c;
-              dT = 1.0;
-            } else {
-              T = 2.0 * c * t1 - t0;
-              dT = 2.0 * t1 + 2.0 * c * d1 - d0;
-              t0 = t1;
-              t1 = T;
-              d0 = d1;
-              d1 = dT;
-            }
-            // the feature factor T_k(mu) of every (n, l, k), k = 0..k_max
-            double k0 = 1.0, k1 = mu;
-            for (int k = 0; k < K1; ++k) {
-              double Tk = 1.0;
-              if (k == 1) {
-                Tk = mu;
-              } else if (k >= 2) {
-                Tk = 2.0 * mu * k1 - k0;
-                k0 = k1;
-                k1 = Tk;
-              }
-              const int base = nst[(l * (N + 1) + n) * K1 + k];
-              if (base >= 0) {
-                const double w = T * Tk, dw = dT * Tk;
-                const double2 ap = Ab[base + l + m];
-                b0pr = fma(ap.x, w, b0pr);
-                b0pi = fma(ap.y, w, b0pi);
-                b1pr = fma(ap.x, dw, b1pr);
-                b1pi = fma(ap.y, dw, b1pi);
-                const double2 am = Ab[base + l - m];
-                b0mr = fma(am.x, w, b0mr);
-                b0mi = fma(am.y, w, b0mi);
-                b1mr = fma(am.x, dw, b1mr);
-                b1mi = fma(am.y, dw, b1mi);
-              }
-            }
-          }
           // +m: Y = S; -m: Y_l^{-m} = (-1)^m conj(Y_l^m) (same for the gradient);
           // for m = 0 both read the same entry, so count it once
           const double fm = (m & 1) ? -1.0 : 1.0;
@@ -497,10 +490,15 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
           gy += rad * y + (b0pr * gYyr - b0pi * gYyi) + w0 * fm * (b0mr * gYyr + b0mi * gYyi);
           gz += rad * z + (b0pr * gYzr - b0pi * gYzi) + w0 * fm * (b0mr * gYzr + b0mi * gYzi);
         }
-        // step m -> m + G
+        // step m -> m + G: (x + i y)^(m + G - 1)
         if (m == 0) {
-          qr = pG1r;
-          qi = pG1i;
+          qr = 1.0;
+          qi = 0.0;
+          for (int k = 1; k < G; ++k) {
+            const double nr = qr * x - qi * y;
+            qi = qr * y + qi * x;
+            qr = nr;
+          }
         } else {
           const double nr = qr * pGr - qi * pGi;
           qi = qr * pGi + qi * pGr;
@@ -523,6 +521,9 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(GradArgs p) {
     }
   }
 }
+
+template __global__ void grad_kernel<false>(GradArgs);
+template __global__ void grad_kernel<true>(GradArgs);
 
 // ---------------------------------------------------------------------------
 // Planar groups (Sec. 2.2 SO(2), Sec. 2.3 torus).  Positions are read as
