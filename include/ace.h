@@ -181,6 +181,10 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *                  precomputed in LDS per environment and used as factors,
  *                  0..8192 (the most frequent pairs are taken), or -1: as
  *                  many as fit without lowering the kernel's occupancy
+ *   env_per_block  forest schedule: environments one block evaluates
+ *                  together, sharing every schedule and coefficient load,
+ *                  1 or 2 (2 falls back to 1 where two environments'
+ *                  values do not fit in LDS)
  * hot_columns also sets the number of one-particle slots whose adjoints
  * the remat kernel sums in registers.
  */
@@ -198,6 +202,7 @@ typedef struct ace_schedule_opts {
   int32_t schedule;
   int32_t term_chunk;
   int32_t pair_slots;
+  int32_t env_per_block;
 } ace_schedule_opts;
 
 /* Current schedule options of a graph (host). */

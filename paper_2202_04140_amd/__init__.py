@@ -64,7 +64,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("row_chunk", ctypes.c_int32), ("tree_chunk", ctypes.c_int32),
                 ("hot_columns", ctypes.c_int32), ("bank_schedule", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("term_chunk", ctypes.c_int32), ("pair_slots", ctypes.c_int32)]
+                ("term_chunk", ctypes.c_int32), ("pair_slots", ctypes.c_int32),
+                ("env_per_block", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -215,7 +216,7 @@ class Graph:
         return d.sum(axis=1)
 
     SCHEDULE_KEYS = ("row_chunk", "tree_chunk", "hot_columns", "bank_schedule", "block_threads",
-                     "schedule", "term_chunk", "pair_slots")
+                     "schedule", "term_chunk", "pair_slots", "env_per_block")
 
     def get_schedule(self) -> dict:
         """Schedule options (ace_graph_get_schedule); "schedule" is a name of SCHEDULES."""

@@ -4,7 +4,8 @@ The DAG (node list) is fixed by the insertion heuristic; how its evaluation
 is laid out on the GPU is not: which kernel runs it (forest or remat), how
 many pair-row entries, tree children or terms a lane takes per item, how
 many hot slots get register accumulators, whether lanes and columns are
-ordered by LDS bank group, and the block size of the DAG kernel.  tune()
+ordered by LDS bank group, the block size of the DAG kernel and how many
+environments a forest block evaluates together.  tune()
 searches these by coordinate descent for every available kernel, timing the
 fused forward + reverse DAG launch (ace_contract with an adjoint) on the
 caller's one-particle values, applies the fastest schedule to the graph and
@@ -30,6 +31,7 @@ SPACE = {
         "hot_columns": [0, 2, 4],
         "bank_schedule": [0, 1],
         "block_threads": [256, 512],
+        "env_per_block": [1, 2],
     },
     "remat": {
         "term_chunk": [16, 32, 64, 128, 256],

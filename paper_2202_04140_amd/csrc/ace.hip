@@ -67,6 +67,7 @@ struct ScheduleOpts {
   int schedule = 0;        // ACE_SCHEDULE_*
   int term_chunk = 64;     // remat: terms per lane item at most
   int pair_slots = -1;     // remat: precomputed one-particle pair products at most (-1: fill LDS)
+  int env_per_block = 1;   // forest: environments per block (1 or 2)
 };
 
 struct ace_graph {
@@ -1439,11 +1440,38 @@ void make_stats(ace_graph* g) {
 
 // LDS of forest_kernel: values of every resident slot, one-particle
 // adjoints (reverse pass), the order-2 parent table, reduction scratch.
-size_t forest_lds_bytes(const ace_graph::Forest& F, int P1, bool grad, bool full) {
+size_t forest_lds_bytes(const ace_graph::Forest& F, int P1, bool grad, bool full, int ne = 1) {
   size_t b = (size_t)F.nslot * 16;
   if (grad && full) b += (size_t)F.nslot * 16;
-  if (grad && !full) b += (size_t)(P1 + 1) * 16 + ((size_t)F.N2 * 4 + 15) / 16 * 16;
+  if (grad && !full) b += (size_t)(P1 + 1) * 16;
+  b *= (size_t)ne;
+  if (grad && !full) b += ((size_t)F.N2 * 4 + 15) / 16 * 16;
   return b + (kForestThreads / 64) * sizeof(double2);
+}
+
+// forest_kernel variants: [environments per block - 1][folded][forward /
+// reverse with one-particle adjoints / reverse with every resident
+// adjoint][grandchildren]
+using ForestKernel = void (*)(ForestArgs);
+template <int NE, bool FOLD>
+constexpr ForestKernel forest_row[3][2] = {
+    {forest_kernel<false, false, false, FOLD, NE>, forest_kernel<false, true, false, FOLD, NE>},
+    {forest_kernel<true, false, false, FOLD, NE>, forest_kernel<true, true, false, FOLD, NE>},
+    {forest_kernel<true, false, true, FOLD, NE>, forest_kernel<true, true, true, FOLD, NE>}};
+
+ForestKernel forest_variant(int ne, bool fold, int mode, bool gc) {
+  const int g = gc ? 1 : 0;
+  if (ne == 2) return fold ? forest_row<2, true>[mode][g] : forest_row<2, false>[mode][g];
+  return fold ? forest_row<1, true>[mode][g] : forest_row<1, false>[mode][g];
+}
+
+std::vector<const void*> forest_variants() {
+  std::vector<const void*> v;
+  for (int ne = 1; ne <= 2; ++ne)
+    for (int f = 0; f < 2; ++f)
+      for (int mode = 0; mode < 3; ++mode)
+        for (int gc = 0; gc < 2; ++gc) v.push_back((const void*)forest_variant(ne, f == 1, mode, gc == 1));
+  return v;
 }
 
 template <typename T>
@@ -1517,19 +1545,8 @@ ace_status upload_forest(ace_graph* g) {
       F.full = forest_lds_bytes(F, g->P1, true, true) <= g->max_lds;
       F.grad_lds = F.full || forest_lds_bytes(F, g->P1, true, false) <= g->max_lds;
     }
-    const void* fk[] = {(const void*)forest_kernel<false, false, false, false>,
-                        (const void*)forest_kernel<false, true, false, false>,
-                        (const void*)forest_kernel<true, false, false, false>,
-                        (const void*)forest_kernel<true, true, false, false>,
-                        (const void*)forest_kernel<true, false, true, false>,
-                        (const void*)forest_kernel<true, true, true, false>,
-                        (const void*)forest_kernel<false, false, false, true>,
-                        (const void*)forest_kernel<false, true, false, true>,
-                        (const void*)forest_kernel<true, false, false, true>,
-                        (const void*)forest_kernel<true, true, false, true>,
-                        (const void*)forest_kernel<true, false, true, true>,
-                        (const void*)forest_kernel<true, true, true, true>};
-    for (const void* f : fk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+    for (const void* f : forest_variants())
+      ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
   if (g->rmem) {
     (void)hipFree(g->rmem);
@@ -1832,20 +1849,17 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.fw_off = F.d_fw_off;
   a.fw_ent = F.d_fw_ent;
   const bool grad = Abar != nullptr;
-  const bool full = grad && F.full;
-  const size_t lds = forest_lds_bytes(F, g->P1, grad, full);
-  const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
-  // kernel variant: forward / reverse with one-particle adjoints / reverse
-  // with every resident adjoint, with or without grandchildren, folded or not
-  using K = void (*)(ForestArgs);
-  static const K table[2][3][2] = {
-      {{forest_kernel<false, false, false, false>, forest_kernel<false, true, false, false>},
-       {forest_kernel<true, false, false, false>, forest_kernel<true, true, false, false>},
-       {forest_kernel<true, false, true, false>, forest_kernel<true, true, true, false>}},
-      {{forest_kernel<false, false, false, true>, forest_kernel<false, true, false, true>},
-       {forest_kernel<true, false, false, true>, forest_kernel<true, true, false, true>},
-       {forest_kernel<true, false, true, true>, forest_kernel<true, true, true, true>}}};
-  const K k = table[fold ? 1 : 0][full ? 2 : grad ? 1 : 0][F.has_gc ? 1 : 0];
+  // two environments per block where their values fit in LDS
+  int ne = g->opts.env_per_block;
+  bool full = grad && forest_lds_bytes(F, g->P1, true, true, ne) <= g->max_lds;
+  if (ne > 1 && forest_lds_bytes(F, g->P1, grad, full, ne) > g->max_lds) {
+    ne = 1;
+    full = grad && F.full;
+  }
+  const size_t lds = forest_lds_bytes(F, g->P1, grad, full, ne);
+  const int64_t blocks = (n_env + ne - 1) / ne;
+  const dim3 grid((unsigned)grid_for(blocks)), block((unsigned)g->opts.block_threads);
+  const ForestKernel k = forest_variant(ne, fold, full ? 2 : grad ? 1 : 0, F.has_gc);
   hipLaunchKernelGGL(k, grid, block, lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
@@ -2240,6 +2254,7 @@ ace_status ace_graph_get_schedule(const ace_graph* g, ace_schedule_opts* o) {
   o->schedule = g->opts.schedule;
   o->term_chunk = g->opts.term_chunk;
   o->pair_slots = g->opts.pair_slots;
+  o->env_per_block = g->opts.env_per_block;
   return ACE_OK;
 }
 
@@ -2249,7 +2264,7 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
       o->hot_columns > 4 || (o->bank_schedule != 0 && o->bank_schedule != 1) || o->block_threads < 64 ||
       o->block_threads > 512 || o->block_threads % 64 != 0 || o->schedule < ACE_SCHEDULE_AUTO ||
       o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256 ||
-      o->pair_slots < -1 || o->pair_slots > 8192)
+      o->pair_slots < -1 || o->pair_slots > 8192 || o->env_per_block < 1 || o->env_per_block > 2)
     return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");
   const ScheduleOpts old = g->opts;
   g->opts.row_chunk = o->row_chunk;
@@ -2260,6 +2275,7 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   g->opts.schedule = o->schedule;
   g->opts.term_chunk = o->term_chunk;
   g->opts.pair_slots = o->pair_slots;
+  g->opts.env_per_block = o->env_per_block;
   try {
     make_forest(g, 0);
     make_forest(g, 1);

@@ -739,16 +739,26 @@ constexpr int kForestBlock = 512;
 // kept twice, with the Re weights (t, y, aw: Re phi and the adjoint) and
 // with the Im weights (ti, yi, awi: Im phi only), since
 // c' Re(u w) + i c'' Im(u w) = Re(u sum c' w) + i Im(u sum c'' w).
-template <bool GRAD, bool GC, bool FULL, bool FOLD>
-__global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
+// NE environments per block share every schedule and coefficient load
+// (each has its own values and adjoints in LDS); a missing last
+// environment computes on zeros and writes nothing.
+template <bool GRAD, bool GC, bool FULL, bool FOLD, int NE>
+__global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(ForestArgs p) {
   extern __shared__ double2 lds[];
-  // values of the resident slots; adjoints of all resident slots (FULL) or of
-  // the one-particle slots only, with the order-2 parent table (!FULL)
+  // per environment: values of the resident slots, then adjoints of all
+  // resident slots (FULL) or of the one-particle slots only (!FULL); then the
+  // order-2 parent table (!FULL) and the reduction scratch
   constexpr bool TAB = GRAD && !FULL;
-  double2* x = lds;
-  double2* ab = lds + p.nslot;
   const int nab = GRAD ? (FULL ? p.nslot : p.P1 + 1) : 0;
-  uint32_t* n2 = reinterpret_cast<uint32_t*>(ab + nab);
+  const int per_env = p.nslot + nab;
+  double2* x[NE];
+  double2* ab[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    x[q] = lds + q * per_env;
+    ab[q] = x[q] + p.nslot;
+  }
+  uint32_t* n2 = reinterpret_cast<uint32_t*>(lds + NE * per_env);
   double2* red = reinterpret_cast<double2*>(n2) + (TAB ? (p.N2 + 3) / 4 : 0);
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -756,38 +766,55 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
   const int P1 = p.P1;
   const int ZERO = P1;
   const double* cs = p.cs;
+  const double2 z2 = make_double2(0.0, 0.0);
   if (TAB)
     for (int u = threadIdx.x; u < p.N2; u += blockDim.x) n2[u] = p.nu2_ab[u];
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+  for (int64_t e0 = (int64_t)blockIdx.x * NE; e0 < p.n_env; e0 += (int64_t)gridDim.x * NE) {
     // phase 0: one-particle values and adjoint accumulators
-    const double2* Ae = p.A + e * P1;
     for (int i = threadIdx.x; i < P1; i += blockDim.x) {
-      x[i] = Ae[i];
-      if (GRAD) ab[i] = make_double2(re_w(load_coef<FOLD>(cs, p.cs_leaf + i)), 0.0);
+      const double leaf = GRAD ? re_w(load_coef<FOLD>(cs, p.cs_leaf + i)) : 0.0;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        x[q][i] = e0 + q < p.n_env ? p.A[(e0 + q) * P1 + i] : z2;
+        if (GRAD) ab[q][i] = make_double2(leaf, 0.0);
+      }
     }
-    if (threadIdx.x == 0) {
-      x[ZERO] = make_double2(0.0, 0.0);
-      if (GRAD) ab[ZERO] = make_double2(0.0, 0.0);
-    }
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        x[q][ZERO] = z2;
+        if (GRAD) ab[q][ZERO] = z2;
+      }
     if (GRAD && FULL)
-      for (int u = threadIdx.x; u < p.N2; u += blockDim.x) ab[P1 + 1 + u] = make_double2(0.0, 0.0);
+      for (int u = threadIdx.x; u < p.N2; u += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < NE; ++q) ab[q][P1 + 1 + u] = z2;
     __syncthreads();
     // phi = acc (unfolded); Re acc + i Im acci (folded)
-    double2 acc = make_double2(0.0, 0.0), acci = acc;
+    double2 acc[NE], acci[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) acc[q] = acci[q] = z2;
     // phase 1: order-2 nodes, their own and the one-particle coefficients
-    for (int i = threadIdx.x; i < P1; i += blockDim.x) coef_fma(load_coef<FOLD>(cs, p.cs_leaf + i), x[i], acc, acci);
+    for (int i = threadIdx.x; i < P1; i += blockDim.x) {
+      const RCoef<FOLD> k = load_coef<FOLD>(cs, p.cs_leaf + i);
+#pragma unroll
+      for (int q = 0; q < NE; ++q) coef_fma(k, x[q][i], acc[q], acci[q]);
+    }
     for (int u = threadIdx.x; u < p.N2; u += blockDim.x) {
-      const uint32_t q = p.nu2_ab[u];
-      const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
-      const double2 xa = x[a], xb = x[b];
-      const double2 xu = cmul(xa, xb);
-      x[P1 + 1 + u] = xu;
+      const uint32_t qq = p.nu2_ab[u];
+      const int a = (int)(qq & 0xffffu), b = (int)(qq >> 16);
       const RCoef<FOLD> k = load_coef<FOLD>(cs, p.cs_nu2 + u);
-      coef_fma(k, xu, acc, acci);
       const double c = re_w(k);
-      if (GRAD && c != 0.0) {
-        atomic_cadd(&ab[a], make_double2(c * xb.x, c * xb.y));
-        atomic_cadd(&ab[b], make_double2(c * xa.x, c * xa.y));
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const double2 xa = x[q][a], xb = x[q][b];
+        const double2 xu = cmul(xa, xb);
+        x[q][P1 + 1 + u] = xu;
+        coef_fma(k, xu, acc[q], acci[q]);
+        if (GRAD && c != 0.0) {
+          atomic_cadd(&ab[q][a], make_double2(c * xb.x, c * xb.y));
+          atomic_cadd(&ab[q][b], make_double2(c * xa.x, c * xa.y));
+        }
       }
     }
     __syncthreads();
@@ -795,11 +822,16 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
     for (int s = wid; s < p.n_mslices; s += nw) {
       const int4 sl = p.mr_slice[s];
       const int row = p.mr_row[sl.x + lane];
-      double2 y0 = make_double2(0.0, 0.0), y1 = y0, y0i = y0, y1i = y0;
+      double2 y0[NE], y1[NE], y0i[NE], y1i[NE];
+#pragma unroll
+      for (int q = 0; q < NE; ++q) y0[q] = y1[q] = y0i[q] = y1i[q] = z2;
       const int z4 = sl.z & ~3;
       for (int j = z4; j < sl.z; ++j) {
         const int pos = sl.y + j * 64 + lane;
-        coef_fma(load_coef<FOLD>(cs, p.cs_me + pos), x[p.me_col[pos]], y0, y0i);
+        const int c0 = p.me_col[pos];
+        const RCoef<FOLD> k0 = load_coef<FOLD>(cs, p.cs_me + pos);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) coef_fma(k0, x[q][c0], y0[q], y0i[q]);
       }
       for (int j = 0; j < z4; j += 4) {
         const int pos = sl.y + j * 64 + lane;
@@ -807,52 +839,75 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
         const int c2 = p.me_col[pos + 128], c3 = p.me_col[pos + 192];
         const RCoef<FOLD> k0 = load_coef<FOLD>(cs, p.cs_me + pos), k1 = load_coef<FOLD>(cs, p.cs_me + pos + 64);
         const RCoef<FOLD> k2 = load_coef<FOLD>(cs, p.cs_me + pos + 128), k3 = load_coef<FOLD>(cs, p.cs_me + pos + 192);
-        const double2 x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-        coef_fma(k0, x0, y0, y0i);
-        coef_fma(k1, x1, y1, y1i);
-        coef_fma(k2, x2, y0, y0i);
-        coef_fma(k3, x3, y1, y1i);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          const double2 x0 = x[q][c0], x1 = x[q][c1], x2 = x[q][c2], x3 = x[q][c3];
+          coef_fma(k0, x0, y0[q], y0i[q]);
+          coef_fma(k1, x1, y1[q], y1i[q]);
+          coef_fma(k2, x2, y0[q], y0i[q]);
+          coef_fma(k3, x3, y1[q], y1i[q]);
+        }
       }
-      const double2 y = make_double2(y0.x + y1.x, y0.y + y1.y);
-      const double2 xr = x[row];
-      const double2 h = cmul(xr, y);
-      acc.x = fma(0.5, h.x, acc.x);
-      acc.y = fma(0.5, h.y, acc.y);
-      if (FOLD) {
-        const double2 hi = cmul(xr, make_double2(y0i.x + y1i.x, y0i.y + y1i.y));
-        acci.y = fma(0.5, hi.y, acci.y);
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const double2 y = make_double2(y0[q].x + y1[q].x, y0[q].y + y1[q].y);
+        const double2 xr = x[q][row];
+        const double2 h = cmul(xr, y);
+        acc[q].x = fma(0.5, h.x, acc[q].x);
+        acc[q].y = fma(0.5, h.y, acc[q].y);
+        if (FOLD) {
+          const double2 hi = cmul(xr, make_double2(y0i[q].x + y1i[q].x, y0i[q].y + y1i[q].y));
+          acci[q].y = fma(0.5, hi.y, acci[q].y);
+        }
+        if (GRAD && row != ZERO) push_r<FULL>(P1, n2, x[q], ab[q], row, y);
       }
-      if (GRAD && row != ZERO) push_r<FULL>(P1, n2, x, ab, row, y);
     }
     // phase 2b: trees.  Children whose sibling is one of the four hot slots
     // sit in fixed columns; their adjoint contributions are summed in
     // registers and pushed once per wave at the end.
-    const double2 xh0 = x[p.hot.x], xh1 = x[p.hot.y], xh2 = x[p.hot.z], xh3 = x[p.hot.w];
-    double2 hacc0 = make_double2(0.0, 0.0), hacc1 = hacc0, hacc2 = hacc0, hacc3 = hacc0;
+    double2 xh0[NE], xh1[NE], xh2[NE], xh3[NE];
+    double2 hacc0[NE], hacc1[NE], hacc2[NE], hacc3[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      xh0[q] = x[q][p.hot.x];
+      xh1[q] = x[q][p.hot.y];
+      xh2[q] = x[q][p.hot.z];
+      xh3[q] = x[q][p.hot.w];
+      hacc0[q] = hacc1[q] = hacc2[q] = hacc3[q] = z2;
+    }
     for (int s = wid; s < p.n_tslices; s += nw) {
       const int4 sl = p.tr_slice[s];
       const int item = sl.x + lane;
-      const uint32_t q = p.it_ab[item];
-      const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
-      const double2 xa = x[a], xb = x[b];
-      const double2 xv = cmul(xa, xb);
+      const uint32_t qab = p.it_ab[item];
+      const int a = (int)(qab & 0xffffu), b = (int)(qab >> 16);
+      double2 xa[NE], xb[NE], xv[NE];
       // abar_v from childless children (t, and ti for Im phi when folded)
-      double2 t = make_double2(0.0, 0.0), ti = t;
-      coef_fma(load_coef<FOLD>(cs, p.cs_it + item), make_double2(1.0, 0.0), t, ti);
-      double2 asum = make_double2(0.0, 0.0);              // abar_v from children with children
+      double2 t[NE], ti[NE], asum[NE];   // asum: abar_v from children with children
+      const RCoef<FOLD> kit = load_coef<FOLD>(cs, p.cs_it + item);
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        xa[q] = x[q][a];
+        xb[q] = x[q][b];
+        xv[q] = cmul(xa[q], xb[q]);
+        t[q] = ti[q] = asum[q] = z2;
+        coef_fma(kit, make_double2(1.0, 0.0), t[q], ti[q]);
+      }
       {
         const int hp = p.cs_hot + item;
         const RCoef<FOLD> k0 = load_coef<FOLD>(cs, hp), k1 = load_coef<FOLD>(cs, hp + p.n_items);
         const RCoef<FOLD> k2 = load_coef<FOLD>(cs, hp + 2 * p.n_items), k3 = load_coef<FOLD>(cs, hp + 3 * p.n_items);
-        coef_fma(k0, xh0, t, ti);
-        coef_fma(k1, xh1, t, ti);
-        coef_fma(k2, xh2, t, ti);
-        coef_fma(k3, xh3, t, ti);
-        if (GRAD) {
-          hacc0 = rfma(re_w(k0), xv, hacc0);
-          hacc1 = rfma(re_w(k1), xv, hacc1);
-          hacc2 = rfma(re_w(k2), xv, hacc2);
-          hacc3 = rfma(re_w(k3), xv, hacc3);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          coef_fma(k0, xh0[q], t[q], ti[q]);
+          coef_fma(k1, xh1[q], t[q], ti[q]);
+          coef_fma(k2, xh2[q], t[q], ti[q]);
+          coef_fma(k3, xh3[q], t[q], ti[q]);
+          if (GRAD) {
+            hacc0[q] = rfma(re_w(k0), xv[q], hacc0[q]);
+            hacc1[q] = rfma(re_w(k1), xv[q], hacc1[q]);
+            hacc2[q] = rfma(re_w(k2), xv[q], hacc2[q]);
+            hacc3[q] = rfma(re_w(k3), xv[q], hacc3[q]);
+          }
         }
       }
       const int cc = p.cs_ch;
@@ -863,26 +918,33 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
           const int pos = sl.y + j * 64 + lane;
           const int s0 = p.ch_s[pos];
           const RCoef<FOLD> k0 = load_coef<FOLD>(cs, cc + pos);
-          coef_fma(k0, x[s0], t, ti);
           const double r0 = re_w(k0);
-          if (GRAD && r0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(r0 * xv.x, r0 * xv.y));
+#pragma unroll
+          for (int q = 0; q < NE; ++q) {
+            coef_fma(k0, x[q][s0], t[q], ti[q]);
+            if (GRAD && r0 != 0.0) push_r<FULL>(P1, n2, x[q], ab[q], s0, make_double2(r0 * xv[q].x, r0 * xv[q].y));
+          }
         }
         for (int j = 0; j < z4; j += 4) {
           const int pos = sl.y + j * 64 + lane;
           const int s0 = p.ch_s[pos], s1 = p.ch_s[pos + 64], s2 = p.ch_s[pos + 128], s3 = p.ch_s[pos + 192];
           const RCoef<FOLD> k0 = load_coef<FOLD>(cs, cc + pos), k1 = load_coef<FOLD>(cs, cc + pos + 64);
           const RCoef<FOLD> k2 = load_coef<FOLD>(cs, cc + pos + 128), k3 = load_coef<FOLD>(cs, cc + pos + 192);
-          const double2 x0 = x[s0], x1 = x[s1], x2 = x[s2], x3 = x[s3];
-          coef_fma(k0, x0, t, ti);
-          coef_fma(k1, x1, t, ti);
-          coef_fma(k2, x2, t, ti);
-          coef_fma(k3, x3, t, ti);
-          if (GRAD) {
-            const double r0 = re_w(k0), r1 = re_w(k1), r2 = re_w(k2), r3 = re_w(k3);
-            if (r0 != 0.0) push_r<FULL>(P1, n2, x, ab, s0, make_double2(r0 * xv.x, r0 * xv.y));
-            if (r1 != 0.0) push_r<FULL>(P1, n2, x, ab, s1, make_double2(r1 * xv.x, r1 * xv.y));
-            if (r2 != 0.0) push_r<FULL>(P1, n2, x, ab, s2, make_double2(r2 * xv.x, r2 * xv.y));
-            if (r3 != 0.0) push_r<FULL>(P1, n2, x, ab, s3, make_double2(r3 * xv.x, r3 * xv.y));
+          const double r0 = re_w(k0), r1 = re_w(k1), r2 = re_w(k2), r3 = re_w(k3);
+#pragma unroll
+          for (int q = 0; q < NE; ++q) {
+            const double2 x0 = x[q][s0], x1 = x[q][s1], x2 = x[q][s2], x3 = x[q][s3];
+            coef_fma(k0, x0, t[q], ti[q]);
+            coef_fma(k1, x1, t[q], ti[q]);
+            coef_fma(k2, x2, t[q], ti[q]);
+            coef_fma(k3, x3, t[q], ti[q]);
+            if (GRAD) {
+              const double2 v = xv[q];
+              if (r0 != 0.0) push_r<FULL>(P1, n2, x[q], ab[q], s0, make_double2(r0 * v.x, r0 * v.y));
+              if (r1 != 0.0) push_r<FULL>(P1, n2, x[q], ab[q], s1, make_double2(r1 * v.x, r1 * v.y));
+              if (r2 != 0.0) push_r<FULL>(P1, n2, x[q], ab[q], s2, make_double2(r2 * v.x, r2 * v.y));
+              if (r3 != 0.0) push_r<FULL>(P1, n2, x[q], ab[q], s3, make_double2(r3 * v.x, r3 * v.y));
+            }
           }
         }
       } else {
@@ -892,67 +954,98 @@ __global__ __launch_bounds__(kForestBlock) void forest_kernel(ForestArgs p) {
           const RCoef<FOLD> k = load_coef<FOLD>(cs, cc + pos);
           const double c = re_w(k);
           const int2 g = p.ch_g[pos];
-          const double2 xs = x[sidx];
           if (g.x == g.y) {
-            coef_fma(k, xs, t, ti);
-            if (GRAD && c != 0.0) push_r<FULL>(P1, n2, x, ab, sidx, make_double2(c * xv.x, c * xv.y));
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+              coef_fma(k, x[q][sidx], t[q], ti[q]);
+              if (GRAD && c != 0.0)
+                push_r<FULL>(P1, n2, x[q], ab[q], sidx, make_double2(c * xv[q].x, c * xv[q].y));
+            }
           } else {
-            const double2 xw = cmul(xv, xs);
-            double2 aw = make_double2(0.0, 0.0), awi = aw;
-            coef_fma(k, make_double2(1.0, 0.0), aw, awi);
+            double2 xs[NE], xw[NE], aw[NE], awi[NE];
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+              xs[q] = x[q][sidx];
+              xw[q] = cmul(xv[q], xs[q]);
+              aw[q] = awi[q] = z2;
+              coef_fma(k, make_double2(1.0, 0.0), aw[q], awi[q]);
+            }
             for (int kk = g.x; kk < g.y; ++kk) {
               const int sg = p.gc_s[kk];
               const RCoef<FOLD> kg = load_coef<FOLD>(cs, p.cs_gc + kk);
-              coef_fma(kg, x[sg], aw, awi);
               const double cg = re_w(kg);
-              if (GRAD) push_r<FULL>(P1, n2, x, ab, sg, make_double2(cg * xw.x, cg * xw.y));
+#pragma unroll
+              for (int q = 0; q < NE; ++q) {
+                coef_fma(kg, x[q][sg], aw[q], awi[q]);
+                if (GRAD) push_r<FULL>(P1, n2, x[q], ab[q], sg, make_double2(cg * xw[q].x, cg * xw[q].y));
+              }
             }
-            acc = cfma(xw, aw, acc);
-            if (FOLD) acci = cfma(xw, awi, acci);
-            if (GRAD) {
-              push_r<FULL>(P1, n2, x, ab, sidx, cmul(aw, xv));
-              asum = cfma(aw, xs, asum);
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+              acc[q] = cfma(xw[q], aw[q], acc[q]);
+              if (FOLD) acci[q] = cfma(xw[q], awi[q], acci[q]);
+              if (GRAD) {
+                push_r<FULL>(P1, n2, x[q], ab[q], sidx, cmul(aw[q], xv[q]));
+                asum[q] = cfma(aw[q], xs[q], asum[q]);
+              }
             }
           }
         }
       }
-      acc = cfma(xv, t, acc);
-      if (FOLD) acci = cfma(xv, ti, acci);
-      if (GRAD && q != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
-        const double2 av = make_double2(t.x + asum.x, t.y + asum.y);
-        push_r<FULL>(P1, n2, x, ab, a, cmul(av, xb));
-        push_r<FULL>(P1, n2, x, ab, b, cmul(av, xa));
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        acc[q] = cfma(xv[q], t[q], acc[q]);
+        if (FOLD) acci[q] = cfma(xv[q], ti[q], acci[q]);
+        if (GRAD && qab != ((uint32_t)ZERO | ((uint32_t)ZERO << 16))) {
+          const double2 av = make_double2(t[q].x + asum[q].x, t[q].y + asum[q].y);
+          push_r<FULL>(P1, n2, x[q], ab[q], a, cmul(av, xb[q]));
+          push_r<FULL>(P1, n2, x[q], ab[q], b, cmul(av, xa[q]));
+        }
       }
     }
     if (GRAD) {
-      const double2 h0 = wave_sum(hacc0), h1 = wave_sum(hacc1), h2 = wave_sum(hacc2), h3 = wave_sum(hacc3);
-      if (lane == 0) {
-        if (p.hot.x != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.x, h0);
-        if (p.hot.y != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.y, h1);
-        if (p.hot.z != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.z, h2);
-        if (p.hot.w != ZERO) push_r<FULL>(P1, n2, x, ab, p.hot.w, h3);
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const double2 h0 = wave_sum(hacc0[q]), h1 = wave_sum(hacc1[q]);
+        const double2 h2 = wave_sum(hacc2[q]), h3 = wave_sum(hacc3[q]);
+        if (lane == 0) {
+          if (p.hot.x != ZERO) push_r<FULL>(P1, n2, x[q], ab[q], p.hot.x, h0);
+          if (p.hot.y != ZERO) push_r<FULL>(P1, n2, x[q], ab[q], p.hot.y, h1);
+          if (p.hot.z != ZERO) push_r<FULL>(P1, n2, x[q], ab[q], p.hot.z, h2);
+          if (p.hot.w != ZERO) push_r<FULL>(P1, n2, x[q], ab[q], p.hot.w, h3);
+        }
       }
     }
     __syncthreads();
     if (GRAD && FULL) {
       // order-2 adjoints to the one-particle adjoints: abar_a += abar_u x_b
       for (int i = threadIdx.x; i < P1; i += blockDim.x) {
-        double2 s2 = ab[i];
-        for (int q = p.fw_off[i]; q < p.fw_off[i + 1]; ++q) {
-          const uint32_t en = p.fw_ent[q];
-          s2 = cfma(ab[en & 0xffffu], x[en >> 16], s2);
+        double2 s2[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) s2[q] = ab[q][i];
+        for (int f = p.fw_off[i]; f < p.fw_off[i + 1]; ++f) {
+          const uint32_t en = p.fw_ent[f];
+#pragma unroll
+          for (int q = 0; q < NE; ++q) s2[q] = cfma(ab[q][en & 0xffffu], x[q][en >> 16], s2[q]);
         }
-        ab[i] = s2;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) ab[q][i] = s2[q];
       }
       __syncthreads();
     }
-    if (FOLD) acc.y = acci.y;
-    const double2 phi = block_sum(acc, red);
-    if (threadIdx.x == 0) p.phi[e] = phi;
-    if (GRAD) {
-      double2* Be = p.Abar + e * P1;
-      for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      if (FOLD) acc[q].y = acci[q].y;
+      const double2 phi = block_sum(acc[q], red);
+      if (threadIdx.x == 0 && e0 + q < p.n_env) p.phi[e0 + q] = phi;
     }
+    if (GRAD)
+#pragma unroll
+      for (int q = 0; q < NE; ++q)
+        if (e0 + q < p.n_env) {
+          double2* Be = p.Abar + (e0 + q) * P1;
+          for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[q][i];
+        }
     __syncthreads();
   }
 }
@@ -1201,17 +1294,29 @@ __global__ __launch_bounds__(256) void prep_fold_kernel(PrepFoldArgs p) {
   }
 }
 
-template __global__ void forest_kernel<false, false, false, false>(ForestArgs);
-template __global__ void forest_kernel<false, true, false, false>(ForestArgs);
-template __global__ void forest_kernel<true, false, false, false>(ForestArgs);
-template __global__ void forest_kernel<true, true, false, false>(ForestArgs);
-template __global__ void forest_kernel<true, false, true, false>(ForestArgs);
-template __global__ void forest_kernel<true, true, true, false>(ForestArgs);
-template __global__ void forest_kernel<false, false, false, true>(ForestArgs);
-template __global__ void forest_kernel<false, true, false, true>(ForestArgs);
-template __global__ void forest_kernel<true, false, false, true>(ForestArgs);
-template __global__ void forest_kernel<true, true, false, true>(ForestArgs);
-template __global__ void forest_kernel<true, false, true, true>(ForestArgs);
-template __global__ void forest_kernel<true, true, true, true>(ForestArgs);
+template __global__ void forest_kernel<false, false, false, false, 1>(ForestArgs);
+template __global__ void forest_kernel<false, true, false, false, 1>(ForestArgs);
+template __global__ void forest_kernel<true, false, false, false, 1>(ForestArgs);
+template __global__ void forest_kernel<true, true, false, false, 1>(ForestArgs);
+template __global__ void forest_kernel<true, false, true, false, 1>(ForestArgs);
+template __global__ void forest_kernel<true, true, true, false, 1>(ForestArgs);
+template __global__ void forest_kernel<false, false, false, true, 1>(ForestArgs);
+template __global__ void forest_kernel<false, true, false, true, 1>(ForestArgs);
+template __global__ void forest_kernel<true, false, false, true, 1>(ForestArgs);
+template __global__ void forest_kernel<true, true, false, true, 1>(ForestArgs);
+template __global__ void forest_kernel<true, false, true, true, 1>(ForestArgs);
+template __global__ void forest_kernel<true, true, true, true, 1>(ForestArgs);
+template __global__ void forest_kernel<false, false, false, false, 2>(ForestArgs);
+template __global__ void forest_kernel<false, true, false, false, 2>(ForestArgs);
+template __global__ void forest_kernel<true, false, false, false, 2>(ForestArgs);
+template __global__ void forest_kernel<true, true, false, false, 2>(ForestArgs);
+template __global__ void forest_kernel<true, false, true, false, 2>(ForestArgs);
+template __global__ void forest_kernel<true, true, true, false, 2>(ForestArgs);
+template __global__ void forest_kernel<false, false, false, true, 2>(ForestArgs);
+template __global__ void forest_kernel<false, true, false, true, 2>(ForestArgs);
+template __global__ void forest_kernel<true, false, false, true, 2>(ForestArgs);
+template __global__ void forest_kernel<true, true, false, true, 2>(ForestArgs);
+template __global__ void forest_kernel<true, false, true, true, 2>(ForestArgs);
+template __global__ void forest_kernel<true, true, true, true, 2>(ForestArgs);
 
 }  // namespace ace

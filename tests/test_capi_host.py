@@ -241,7 +241,8 @@ def test_schedule_kinds():
     g2 = ace.Graph(3, 8, 4, 4, host_only=True)
     g2.set_schedule(schedule="remat", term_chunk=3)
     assert g2.schedule_kind() == "remat" and g2.get_schedule()["term_chunk"] == 3
-    for bad in (dict(term_chunk=0), dict(term_chunk=257), dict(schedule=4)):
+    for bad in (dict(term_chunk=0), dict(term_chunk=257), dict(schedule=4), dict(env_per_block=0),
+                dict(env_per_block=3)):
         with pytest.raises(ace.AceError):
             g2.set_schedule(**bad)
 

@@ -137,6 +137,46 @@ def test_schedule_in_use(device):
     assert graph(2, device, "remat").schedule_kind() == "remat"
 
 
+# ---- two environments per forest block ----------------------------------------------
+@pytest.mark.parametrize("wid,n_env", [(1, 15), (2, 33), (3, 17), (4, 5)])
+def test_forest_two_envs_per_block(device, wid, n_env):
+    """env_per_block = 2 (two environments share every schedule and coefficient
+    load; an odd count leaves the last block half empty; a basis whose two
+    environments do not fit in LDS falls back to one): contract with and without
+    folding, forward only, and the full path, against the oracle."""
+    import paper_2202_04140_amd as ace
+    print(f"forest two envs wid={wid} n_env={n_env}", flush=True)
+    w = wl.WORKLOADS[wid]
+    G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
+    G.set_schedule(schedule="forest", env_per_block=2)
+    assert G.schedule_kind() == "forest" and G.get_schedule()["env_per_block"] == 2
+    g, K, c = oracle_basis(wid)
+    A = wl.random_A(n_env, len(g), seed=400 + wid) * 0.5
+    tc, tA = to_dev(device, c, np.stack([A.real, A.imag], -1))
+    phi_ref, ab_ref = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    phi, Ab = ace.contract(G, tc, tA, with_grad=True)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(cplx(Ab), ab_ref) <= TOL_ABAR
+    assert rel(cplx(ace.contract(G, tc, tA, with_grad=False)), phi_ref) <= TOL_PHI
+    As = wl.random_A_conj(n_env, g.labels, 500 + wid) * 0.5
+    dA = wl.random_A_conj(n_env, g.labels, 600 + wid)
+    (tAs,) = to_dev(device, np.stack([As.real, As.imag], -1))
+    phis_ref, abs_ref = oc.phi_naive(K, c, As), oc.abar_naive(K, c, As)
+    phi, Ab = ace.contract(G, tc, tAs, with_grad=True, conj_symmetric=True)
+    assert rel(cplx(phi), phis_ref) <= TOL_PHI
+    lhs = np.real(np.sum(cplx(Ab) * dA, axis=1))
+    rhs = np.real(np.sum(abs_ref * dA, axis=1))
+    assert rel(lhs, rhs) <= TOL_ABAR
+    assert rel(cplx(ace.contract(G, tc, tAs, with_grad=False, conj_symmetric=True)), phis_ref) <= TOL_PHI
+    if wid in (1, 3):
+        off, pos = problem(wid, n_env)
+        tc, toff, tpos = to_dev(device, c, off, pos)
+        phi, grad = ace.eval_grad(G, tc, toff, tpos)
+        phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, w.r_cut)
+        assert rel(cplx(phi), phi_ref) <= TOL_PHI
+        assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+
+
 # ---- full path ---------------------------------------------------------------------
 @pytest.mark.parametrize("naive", [False, True])
 @pytest.mark.parametrize("wid,n_env", [(1, None), (2, 96)])
