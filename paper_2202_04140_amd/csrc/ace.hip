@@ -86,6 +86,7 @@ struct ace_graph {
   std::vector<OnepInfo> onep;
   std::vector<int16_t> onep_index;
   std::vector<int32_t> gsrc;
+  int grad_nb = 0;                 // gradient kernel: Abar entries per (l, m), padded to odd
   std::vector<double> ycoef;
   // device copies (one allocation)
   void* dmem = nullptr;
@@ -283,13 +284,16 @@ void make_schedule(ace_graph* g) {
       if (h.on_k[i] == 0) g->onep_index[(size_t)(n * (L + 1) + l) * W + (m + L)] = (int16_t)i;
     }
     make_ycoef(L, g->ycoef);
-    // the gradient kernel's layout of Abar: position ((l^2 + l + m) (N+1) + n) K1 + k
-    // holds one-particle function (n, l, m, k), or -1 (absent: zero)
+    // the gradient kernel's layout of Abar: position (l^2 + l + m) NB + n K1 + k
+    // holds one-particle function (n, l, m, k), or -1 (absent: zero); the block
+    // of one (l, m) is padded to an odd length NB, so that lanes reading
+    // different (l, m) spread over the LDS bank groups
     const int K1 = h.spec.k_max + 1;
-    g->gsrc.assign((size_t)(L + 1) * (L + 1) * (N + 1) * K1, -1);
+    g->grad_nb = ((N + 1) * K1) | 1;
+    g->gsrc.assign((size_t)(L + 1) * (L + 1) * g->grad_nb, -1);
     for (int i = 0; i < P1; ++i) {
       const int l = h.on_l[i];
-      g->gsrc[((size_t)(l * l + l + h.on_m[i]) * (N + 1) + h.on_n[i]) * K1 + h.on_k[i]] = i;
+      g->gsrc[(size_t)(l * l + l + h.on_m[i]) * g->grad_nb + h.on_n[i] * K1 + h.on_k[i]] = i;
     }
   } else {
     // planar groups: phi = R_n (Re E, sim Im E), E = u^{|m|}, sim = s sign(m) with
@@ -1788,7 +1792,7 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const int chunk = kBasisThreads / (a.l_max + 1);
-  const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * ((a.n_max + 1) + (a.k_max + 1) + 2 * NY) * 8;
+  const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * (((a.n_max + 1) + (a.k_max + 1) + 2 * NY) | 1) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the basis kernel");
   hipLaunchKernelGGL(basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
   ACE_HIP(hipGetLastError());
@@ -2042,8 +2046,9 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.k_max = g->h.spec.k_max;
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
-  const size_t lds = g->gsrc.size() * sizeof(double2) + (size_t)3 * NY * 8;
+  const size_t lds = g->gsrc.size() * sizeof(double2) + (size_t)3 * NY * 8 + (size_t)kGradChunk * (kGradNbr + 3) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
+  a.nb = g->grad_nb;
   if (a.k_max > 0)
     hipLaunchKernelGGL(grad_kernel<true>, dim3((unsigned)grid_for(n_env)), dim3(kGradWave), lds, s, a);
   else

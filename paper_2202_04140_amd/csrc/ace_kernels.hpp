@@ -79,7 +79,7 @@ struct GradArgs {
   const double2* Abar;       // [n_env][P1]
   double* grad;              // [n_nbr][3]
   const int16_t* onep_index; // [(n_max+1)][(l_max+1)][(2 l_max+1)] -> i or -1
-  const int32_t* gsrc;       // [(l_max+1)^2][(n_max+1)][(k_max+1)]: (n, l, m, k) at ((l^2+l+m)(n_max+1)+n)(k_max+1)+k -> i or -1
+  const int32_t* gsrc;       // [(l_max+1)^2][nb]: (n, l, m, k) at (l^2+l+m) nb + n (k_max+1) + k -> i or -1
   const double* ycoef;
   int P1, n_max, l_max;
   double r_cut;
@@ -87,6 +87,7 @@ struct GradArgs {
   const int16_t* pidx;       // planar: [(n_max+1)][(2 m_max+1)] -> i or -1 (m_max = l_max)
   int k_max;                 // O(3) feature degree
   int pos_stride;            // doubles per position: 3, or 4 with a feature
+  int nb;                    // O(3): entries per (l, m) of the staged Abar (odd, >= (n_max+1)(k_max+1))
 };
 
 }  // namespace ace

@@ -89,7 +89,9 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
   const int L = p.l_max;
   const int NY = (L + 1) * (L + 2) / 2;
   const int K1 = p.k_max + 1;
-  const int stride = (p.n_max + 1) + K1 + 2 * NY;   // doubles per neighbour: T_n(cos), T_k(mu), Y
+  // doubles per neighbour: T_n(cos), T_k(mu), Y; odd, so that lanes writing
+  // different neighbours' rows spread over the LDS banks
+  const int stride = ((p.n_max + 1) + K1 + 2 * NY) | 1;
   const int chunk = blockDim.x / (L + 1);           // neighbours per chunk
   double2* acc = reinterpret_cast<double2*>(lds_b);  // [P1]
   double* tab = lds_b + 2 * p.P1;                    // [chunk][stride]
@@ -330,22 +332,33 @@ template __global__ void naive_kernel<8>(NaiveArgs);
 //
 // One wave (one block) per environment, its adjoint Abar in LDS in (l, m, n,
 // k) order with zeros for absent functions, so the inner loop over n reads
-// two affine addresses.  Lanes are (neighbour, group) pairs: group g of G
-// handles m = g, g + G, ... and the G partial gradients of a neighbour are
-// summed by lane shuffles; G is the largest power of two with G * J <= 64
-// (at most 16).  FEAT: a feature factor T_k(mu) per function (Sec. 5.4).
+// two affine addresses; the block of one (l, m) has an odd length nb.
+//
+// Work is balanced over the lanes: the neighbours are taken in chunks of
+// kGradChunk; the (neighbour, m >= 0, l) units of a chunk, neighbour-major
+// and m-major, are cut into 64 contiguous ranges, one per lane.  A lane
+// walks its range with the Legendre recurrence in l (restarted on a new m,
+// warmed up when its range starts inside an m line) and adds its partial
+// gradient of each neighbour to an LDS accumulator when it leaves that
+// neighbour.  Per-neighbour quantities are computed once per chunk into LDS.
+// FEAT: a feature factor T_k(mu) per function (Sec. 5.4).
 // ---------------------------------------------------------------------------
+constexpr int kGradChunk = 32;   // neighbours per chunk
+constexpr int kGradNbr = 7;      // doubles per neighbour: x, y, z, 1/r, cos, dcos/dr, mu
+
 template <bool FEAT>
 __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
   extern __shared__ double2 lds[];
   const int L = p.l_max, N = p.n_max;
   const int K1 = FEAT ? p.k_max + 1 : 1;
-  const int NY = (L + 1) * (L + 2) / 2;
-  const int NB = (N + 1) * K1;                 // entries per (l, m)
+  const int NY = (L + 1) * (L + 2) / 2;        // (l, m >= 0) units per neighbour
+  const int NB = p.nb;                         // entries per (l, m)
   const int ND = (L + 1) * (L + 1) * NB;
   const int lane = threadIdx.x;
   double2* Ab = lds;                                           // [ND]
   double* yc = reinterpret_cast<double*>(lds + ND);            // [3 * NY]
+  double* nbr = yc + 3 * NY;                                   // [kGradChunk][kGradNbr]
+  double* gacc = nbr + kGradChunk * kGradNbr;                  // [kGradChunk][3]
   for (int i = lane; i < 3 * NY; i += 64) yc[i] = p.ycoef[i];
   const double* cA = yc;
   const double* cB = yc + NY;
@@ -360,55 +373,82 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
       const int src = p.gsrc[d];
       Ab[d] = src >= 0 ? Be[src] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    int G = 1;
-    while (G < 16 && 2 * G * J <= 64) G *= 2;
-    const int per = 64 / G;              // neighbours per pass
-    const int g = lane % G, jl = lane / G;
-    for (int c0 = 0; c0 < J; c0 += per) {
-      const int jj = min(c0 + jl, J - 1);   // idle lanes repeat the last neighbour
-      const int64_t j = j0 + jj;
-      const double* rp = p.pos + p.pos_stride * j;
-      const double rx = rp[0], ry = rp[1], rz = rp[2];
-      const double mu = FEAT ? rp[3] : 0.0;   // invariant feature (Sec. 5.4)
-      const double rr = sqrt(rx * rx + ry * ry + rz * rz);
-      const double inv = 1.0 / rr;
-      const double x = rx * inv, y = ry * inv, z = rz * inv;
-      const double arg = M_PI * rr / p.r_cut;
-      const double c = cos(arg);
-      const double dcdr = -(M_PI / p.r_cut) * sin(arg);
-      double gx = 0.0, gy = 0.0, gz = 0.0;
-      // (x + i y)^g, (x + i y)^G
-      double pr = 1.0, pi = 0.0, pGr = 1.0, pGi = 0.0;
-      for (int k = 0; k < G; ++k) {
-        if (k == g) {
-          pr = pGr;
-          pi = pGi;
-        }
-        const double nr = pGr * x - pGi * y;
-        pGi = pGr * y + pGi * x;
-        pGr = nr;
+    for (int c0 = 0; c0 < J; c0 += kGradChunk) {
+      const int nc = min(kGradChunk, J - c0);
+      __syncthreads();
+      if (lane < nc) {
+        const double* rp = p.pos + p.pos_stride * (int64_t)(j0 + c0 + lane);
+        const double rx = rp[0], ry = rp[1], rz = rp[2];
+        const double rr = sqrt(rx * rx + ry * ry + rz * rz);
+        const double inv = 1.0 / rr;
+        const double arg = M_PI * rr / p.r_cut;
+        double* nd = nbr + lane * kGradNbr;
+        nd[0] = rx * inv;
+        nd[1] = ry * inv;
+        nd[2] = rz * inv;
+        nd[3] = inv;
+        nd[4] = cos(arg);
+        nd[5] = -(M_PI / p.r_cut) * sin(arg);
+        nd[6] = FEAT ? rp[3] : 0.0;   // invariant feature (Sec. 5.4)
+        gacc[3 * lane] = gacc[3 * lane + 1] = gacc[3 * lane + 2] = 0.0;
       }
-      // (x + i y)^(m-1) for m = g >= 1
-      double qr = 0.0, qi = 0.0;
-      if (g >= 1) {
-        qr = 1.0;
-        for (int k = 1; k < g; ++k) {
-          const double nr = qr * x - qi * y;
-          qi = qr * y + qi * x;
-          qr = nr;
+      __syncthreads();
+      const int U = nc * NY;
+      const int u0 = (lane * U) >> 6, u1 = ((lane + 1) * U) >> 6;
+      if (u0 < u1) {
+        // first unit: neighbour jj, line m, degree l
+        int jj = u0 / NY, r = u0 - jj * NY, m = 0;
+        while (r >= L + 1 - m) {
+          r -= L + 1 - m;
+          ++m;
         }
-      }
-      for (int m = g; m <= L; m += G) {
-        double Q2 = 0.0, Qz2 = 0.0, Qp2 = 0.0;
-        double Q1 = cS[(m * (m + 1)) / 2 + m], Qz1 = 0.0, Qp1 = 0.0;
-        for (int l = m; l <= L; ++l) {
+        int l = m + r;
+        double x, y, z, inv, c, dcdr, mu;
+        auto load_nbr = [&](int q) {
+          const double* nd = nbr + q * kGradNbr;
+          x = nd[0];
+          y = nd[1];
+          z = nd[2];
+          inv = nd[3];
+          c = nd[4];
+          dcdr = nd[5];
+          mu = nd[6];
+        };
+        load_nbr(jj);
+        // p = (x + i y)^m, q = (x + i y)^(m-1) (0 for m = 0)
+        double pr = 1.0, pi = 0.0, qr = 0.0, qi = 0.0;
+        for (int k = 0; k < m; ++k) {
+          qr = pr;
+          qi = pi;
+          const double nr = pr * x - pi * y;
+          pi = pr * y + pi * x;
+          pr = nr;
+        }
+        // Q, Qz, Qp at l and at l - 1 (Qm, Qzm, Qpm), from l = m
+        double Q = cS[(m * (m + 1)) / 2 + m], Qz = 0.0, Qp = 0.0, Qm = 0.0, Qzm = 0.0, Qpm = 0.0;
+        auto step_l = [&](int lnew) {
+          const int o = (lnew * (lnew + 1)) / 2 + m;
+          const double a = cA[o], b = cB[o];
+          const double Qn = a * z * Q - b * Qm;
+          const double Qzn = a * (Q + z * Qz) - b * Qzm;
+          const double Qpn = a * z * Qp - b * (Qm + Qpm);
+          Qm = Q;
+          Qzm = Qz;
+          Qpm = Qp;
+          Q = Qn;
+          Qz = Qzn;
+          Qp = Qpn;
+        };
+        for (int ll = m + 1; ll <= l; ++ll) step_l(ll);
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int u = u0; u < u1; ++u) {
           // B0 = sum_{n,k} Abar_{n l (+/-m) k} T_n T_k, B1 = the same with T_n'
           const double2* bp = Ab + (l * l + l + m) * NB;
           const double2* bm = Ab + (l * l + l - m) * NB;
           double b0pr = 0.0, b0pi = 0.0, b1pr = 0.0, b1pi = 0.0;   // +m
           double b0mr = 0.0, b0mi = 0.0, b1mr = 0.0, b1mi = 0.0;   // -m
           double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
+#pragma unroll 2
           for (int n = 0; n <= N; ++n) {
             double T, dT;
             if (n == 0) {
@@ -449,24 +489,7 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
               b1mi = fma(am.y, dw, b1mi);
             }
           }
-          double Q, Qz, Qp;
-          if (l == m) {
-            Q = Q1;
-            Qz = 0.0;
-            Qp = 0.0;
-          } else {
-            const int o = (l * (l + 1)) / 2 + m;
-            const double a = cA[o], b = cB[o];
-            Q = a * z * Q1 - b * Q2;
-            Qz = a * (Q1 + z * Qz1) - b * Qz2;
-            Qp = a * z * Qp1 - b * (Q2 + Qp2);
-            Q2 = Q1;
-            Qz2 = Qz1;
-            Qp2 = Qp1;
-            Q1 = Q;
-            Qz1 = Qz;
-            Qp1 = Qp;
-          }
+          // S = p Q = r^l Y_l^m at the unit vector, and its gradient
           const double Sr = pr * Q, Si = pi * Q;
           double dxr = 2.0 * x * Qp * pr, dxi = 2.0 * x * Qp * pi;
           double dyr = 2.0 * y * Qp * pr, dyi = 2.0 * y * Qp * pi;
@@ -489,34 +512,47 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
           gx += rad * x + (b0pr * gYxr - b0pi * gYxi) + w0 * fm * (b0mr * gYxr + b0mi * gYxi);
           gy += rad * y + (b0pr * gYyr - b0pi * gYyi) + w0 * fm * (b0mr * gYyr + b0mi * gYyi);
           gz += rad * z + (b0pr * gYzr - b0pi * gYzi) + w0 * fm * (b0mr * gYzr + b0mi * gYzi);
-        }
-        // step m -> m + G: (x + i y)^(m + G - 1)
-        if (m == 0) {
-          qr = 1.0;
-          qi = 0.0;
-          for (int k = 1; k < G; ++k) {
-            const double nr = qr * x - qi * y;
-            qi = qr * y + qi * x;
-            qr = nr;
+          // next unit
+          if (l < L) {
+            ++l;
+            step_l(l);
+          } else if (m < L) {
+            ++m;
+            l = m;
+            qr = pr;
+            qi = pi;
+            const double nr = pr * x - pi * y;
+            pi = pr * y + pi * x;
+            pr = nr;
+            Q = cS[(m * (m + 1)) / 2 + m];
+            Qz = Qp = Qm = Qzm = Qpm = 0.0;
+          } else {
+            atomicAdd(&gacc[3 * jj], gx);
+            atomicAdd(&gacc[3 * jj + 1], gy);
+            atomicAdd(&gacc[3 * jj + 2], gz);
+            gx = gy = gz = 0.0;
+            ++jj;
+            m = 0;
+            l = 0;
+            if (jj < nc) load_nbr(jj);
+            pr = 1.0;
+            pi = qr = qi = 0.0;
+            Q = cS[0];
+            Qz = Qp = Qm = Qzm = Qpm = 0.0;
           }
-        } else {
-          const double nr = qr * pGr - qi * pGi;
-          qi = qr * pGi + qi * pGr;
-          qr = nr;
         }
-        const double nr = pr * pGr - pi * pGi;
-        pi = pr * pGi + pi * pGr;
-        pr = nr;
+        if (jj < nc) {
+          atomicAdd(&gacc[3 * jj], gx);
+          atomicAdd(&gacc[3 * jj + 1], gy);
+          atomicAdd(&gacc[3 * jj + 2], gz);
+        }
       }
-      for (int off = 1; off < G; off <<= 1) {
-        gx += __shfl_xor(gx, off, 64);
-        gy += __shfl_xor(gy, off, 64);
-        gz += __shfl_xor(gz, off, 64);
-      }
-      if (g == 0 && c0 + jl < J) {
-        p.grad[3 * j] = gx;
-        p.grad[3 * j + 1] = gy;
-        p.grad[3 * j + 2] = gz;
+      __syncthreads();
+      if (lane < nc) {
+        double* gout = p.grad + 3 * (int64_t)(j0 + c0 + lane);
+        gout[0] = gacc[3 * lane];
+        gout[1] = gacc[3 * lane + 1];
+        gout[2] = gacc[3 * lane + 2];
       }
     }
   }
