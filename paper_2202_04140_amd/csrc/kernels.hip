@@ -156,17 +156,31 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
         }
       }
       __syncthreads();
+      // two neighbours per step into two partial sums (more loads in flight);
+      // sre, sim = +-1 are applied to the sums
       for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
         const OnepInfo o = p.onep[i];
-        double2 a = acc[i];
-        const double sre = (double)o.sre, sim = (double)o.sim;
-        for (int k = 0; k < nc; ++k) {
-          const double* t = tab + k * stride;
-          const double R = t[o.n] * t[p.n_max + 1 + o.k];
-          const double* Y = t + (p.n_max + 1) + K1 + 2 * o.yoff;
-          a.x = fma(R, sre * Y[0], a.x);
-          a.y = fma(R, sim * Y[1], a.y);
+        const int ro = o.n, ko = p.n_max + 1 + o.k, yo = (p.n_max + 1) + K1 + 2 * o.yoff;
+        double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
+        int k = 0;
+        for (; k + 1 < nc; k += 2) {
+          const double* t0 = tab + k * stride;
+          const double* t1 = t0 + stride;
+          const double R0 = t0[ro] * t0[ko], R1 = t1[ro] * t1[ko];
+          ax0 = fma(R0, t0[yo], ax0);
+          ay0 = fma(R0, t0[yo + 1], ay0);
+          ax1 = fma(R1, t1[yo], ax1);
+          ay1 = fma(R1, t1[yo + 1], ay1);
         }
+        if (k < nc) {
+          const double* t0 = tab + k * stride;
+          const double R0 = t0[ro] * t0[ko];
+          ax0 = fma(R0, t0[yo], ax0);
+          ay0 = fma(R0, t0[yo + 1], ay0);
+        }
+        double2 a = acc[i];
+        a.x = fma((double)o.sre, ax0 + ax1, a.x);
+        a.y = fma((double)o.sim, ay0 + ay1, a.y);
         acc[i] = a;
       }
     }
