@@ -1651,6 +1651,7 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)planar_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  ACE_HIP(hipFuncSetAttribute((const void*)planar_basis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   {
     const ace_status fs = upload_forest(g);
     if (fs != ACE_OK) return fs;
@@ -1772,7 +1773,9 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
     a.r_cut = g->h.spec.r_cut;
     a.group = g->h.spec.group;
     a.pos_stride = 3;
-    hipLaunchKernelGGL(planar_basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), 0, s, a);
+    const size_t lds = (size_t)g->P1 * 16 + (size_t)kPlanarChunk * (((a.n_max + 1) + 2 * (a.l_max + 1)) | 1) * 8;
+    if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the basis kernel");
+    hipLaunchKernelGGL(planar_basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
     ACE_HIP(hipGetLastError());
     return ACE_OK;
   }
@@ -2023,7 +2026,9 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
     a.group = g->h.spec.group;
     a.pidx = g->d_onep_index;
     a.pos_stride = 3;
-    const size_t lds = (size_t)g->P1 * sizeof(double2);
+    const int NR = g->h.spec.group == 2 ? a.n_max : 0;
+    const size_t lds = (size_t)g->P1 * sizeof(double2) +
+                       (size_t)kPlanarChunk * (((kPlanarNbr + 2 * (NR + 1) + 2 * (a.l_max + 1)) | 1) + 2) * 8;
     if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
     hipLaunchKernelGGL(planar_grad_kernel, dim3((unsigned)grid_for(n_env)), dim3(kGradThreads), lds, s, a);
     ACE_HIP(hipGetLastError());

@@ -578,111 +578,201 @@ template __global__ void grad_kernel<true>(GradArgs);
 // ---------------------------------------------------------------------------
 // Planar groups (Sec. 2.2 SO(2), Sec. 2.3 torus).  Positions are read as
 // (x, y); theta = atan2(y, x) enters only through u = (x + i y)/r.
-//   planar_basis_kernel  A_i = sum_j R_{n_i}(r_j) e^{i s m_i theta_j}, one lane
-//                        per one-particle function, u^{|m|} by repeated products
-//   planar_grad_kernel   g_j = Re sum_i Abar_i grad phi_i(r_j), one lane per
-//                        neighbour, looping over (n, |m|) with the recurrences
+//   planar_basis_kernel  A_i = sum_j R_{n_i}(r_j) e^{i s m_i theta_j}: per
+//                        chunk of neighbours a table of T_n(cos(pi r / r_cut))
+//                        and u^{|m|} (repeated products) in LDS, one lane per
+//                        neighbour; then one lane per one-particle function
+//   planar_grad_kernel   g_j = Re sum_i Abar_i grad phi_i(r_j): per chunk a
+//                        table of R_n, R_n', u^{|m|} and grad theta per
+//                        neighbour, then the (neighbour, n, |m|) units cut
+//                        into contiguous ranges over the block's threads,
+//                        partial gradients added to LDS accumulators
 //     grad phi = R_n'(r) e r_hat + R_n(r) (i s m) e grad theta,
 //     grad theta = (-y, x) / r^2.
 // A_{n,-m} is computed with the same operations as A_{n,m} and the opposite
 // sign of the imaginary part, so it is exactly conj(A_{n,m}).
 // ---------------------------------------------------------------------------
+constexpr int kPlanarChunk = 64;   // neighbours per table
+
 __global__ __launch_bounds__(256) void planar_basis_kernel(BasisArgs p) {
+  extern __shared__ double lds_p[];
   const bool radial = p.group == 2;
+  const int N = p.n_max, M = p.l_max;
+  const int stride = ((N + 1) + 2 * (M + 1)) | 1;   // per neighbour: T_n, then (Re, Im) u^m
   const double kr = M_PI / p.r_cut;
+  double2* acc = reinterpret_cast<double2*>(lds_p);   // [P1]
+  double* tab = lds_p + 2 * p.P1;                      // [kPlanarChunk][stride]
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
-    const int j0 = p.offsets[e], j1 = p.offsets[e + 1];
-    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
-      const OnepInfo o = p.onep[i];
-      double ar = 0.0, ai = 0.0;
-      for (int j = j0; j < j1; ++j) {
-        const double x = p.pos[3 * (int64_t)j], y = p.pos[3 * (int64_t)j + 1];
+    const int j0 = p.offsets[e];
+    const int J = p.offsets[e + 1] - j0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) acc[i] = make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < J; c0 += kPlanarChunk) {
+      const int nc = min(kPlanarChunk, J - c0);
+      __syncthreads();
+      if ((int)threadIdx.x < nc) {
+        const int64_t j = j0 + c0 + threadIdx.x;
+        const double x = p.pos[3 * j], y = p.pos[3 * j + 1];
         const double r = sqrt(x * x + y * y);
         const double c = x / r, sn = y / r;
-        double er = 1.0, ei = 0.0;
-        for (int k = 0; k < o.am; ++k) {
-          const double t = er * c - ei * sn;
-          ei = er * sn + ei * c;
-          er = t;
-        }
-        double R = 1.0;
-        if (radial && o.n > 0) {
+        double* t = tab + threadIdx.x * stride;
+        t[0] = 1.0;
+        if (radial && N >= 1) {
           const double X = cos(kr * r);
           double t0 = 1.0, t1 = X;
-          for (int k = 1; k < o.n; ++k) {
+          t[1] = X;
+          for (int n = 2; n <= N; ++n) {
             const double t2 = 2.0 * X * t1 - t0;
             t0 = t1;
             t1 = t2;
+            t[n] = t2;
           }
-          R = t1;
         }
-        ar = fma(R, er, ar);
-        ai = fma(R, (double)o.sim * ei, ai);
-      }
-      p.A[e * p.P1 + i] = make_double2(ar, ai);
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void planar_grad_kernel(GradArgs p) {
-  extern __shared__ double2 lds[];
-  double2* Ab = lds;   // [P1]
-  const bool radial = p.group == 2;
-  const double s_exp = radial ? -1.0 : 1.0;
-  const int N = radial ? p.n_max : 0, M = p.l_max, W = 2 * M + 1;
-  const double kr = M_PI / p.r_cut;
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) Ab[i] = p.Abar[e * p.P1 + i];
-    __syncthreads();
-    const int j0 = p.offsets[e], j1 = p.offsets[e + 1];
-    for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-      const double x = p.pos[3 * (int64_t)j], y = p.pos[3 * (int64_t)j + 1];
-      const double r2 = x * x + y * y, r = sqrt(r2);
-      const double c = x / r, sn = y / r;
-      const double gtx = -y / r2, gty = x / r2;   // grad theta
-      const double X = cos(kr * r), dX = -kr * sin(kr * r);
-      double gx = 0.0, gy = 0.0;
-      double tm1 = 1.0, t = 1.0, um1 = 0.0, um2 = 0.0;   // T_n, T_{n-1}, U_{n-1}, U_{n-2}
-      for (int n = 0; n <= N; ++n) {
-        if (n == 1) {
-          tm1 = 1.0;
-          t = X;
-          um1 = 1.0;
-          um2 = 0.0;
-        } else if (n >= 2) {
-          const double t2 = 2.0 * X * t - tm1;
-          tm1 = t;
-          t = t2;
-          const double u2 = n == 2 ? 2.0 * X : 2.0 * X * um1 - um2;
-          um2 = um1;
-          um1 = u2;
-        }
-        const double R = radial ? t : 1.0;
-        const double dR = radial ? (double)n * um1 * dX : 0.0;   // T_n' = n U_{n-1}
-        double er = 1.0, ei = 0.0;                                 // u^m
-        for (int m = 0; m <= M; ++m) {
-          for (int sg = 1; sg >= (m == 0 ? 1 : -1); sg -= 2) {
-            const int i = p.pidx[n * W + M + sg * m];
-            if (i < 0) continue;
-            // phi = R (er, s * sg * ei) = R E with E = e^{i s (sg m) theta}
-            const double qr = er, qi = s_exp * (double)sg * ei;
-            const double2 a = Ab[i];
-            const double re = a.x * qr - a.y * qi;         // Re(abar E)
-            const double im = a.x * qi + a.y * qr;         // Im(abar E)
-            // Re(abar * (i s sg m) R E) = -(s sg m) R Im(abar E)
-            const double ang = -(s_exp * (double)(sg * m)) * R * im;
-            gx += dR * re * c + ang * gtx;
-            gy += dR * re * sn + ang * gty;
-          }
+        double er = 1.0, ei = 0.0;
+        double* E = t + (N + 1);
+        E[0] = 1.0;
+        E[1] = 0.0;
+        for (int m = 1; m <= M; ++m) {
           const double t2 = er * c - ei * sn;
           ei = er * sn + ei * c;
           er = t2;
+          E[2 * m] = er;
+          E[2 * m + 1] = ei;
         }
       }
-      p.grad[3 * (int64_t)j] = gx;
-      p.grad[3 * (int64_t)j + 1] = gy;
-      p.grad[3 * (int64_t)j + 2] = 0.0;
+      __syncthreads();
+      for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
+        const OnepInfo o = p.onep[i];
+        const int ro = radial ? o.n : 0, eo = (N + 1) + 2 * o.am;
+        double ar = 0.0, ai = 0.0;
+        for (int k = 0; k < nc; ++k) {
+          const double* t = tab + k * stride;
+          const double R = t[ro];
+          ar = fma(R, t[eo], ar);
+          ai = fma(R, (double)o.sim * t[eo + 1], ai);
+        }
+        double2 a = acc[i];
+        a.x += ar;
+        a.y += ai;
+        acc[i] = a;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) p.A[e * p.P1 + i] = acc[i];
+  }
+}
+
+constexpr int kPlanarNbr = 4;   // doubles per neighbour before the R_n table: cos, sin, grad theta
+
+__global__ __launch_bounds__(256) void planar_grad_kernel(GradArgs p) {
+  extern __shared__ double2 lds[];
+  const bool radial = p.group == 2;
+  const double s_exp = radial ? -1.0 : 1.0;
+  const int N = radial ? p.n_max : 0, M = p.l_max, W = 2 * M + 1;
+  const int stride = (kPlanarNbr + 2 * (N + 1) + 2 * (M + 1)) | 1;   // cos, sin, grad theta, R, R', u^m
+  const double kr = M_PI / p.r_cut;
+  double2* Ab = lds;                                               // [P1]
+  double* tab = reinterpret_cast<double*>(Ab + p.P1);              // [kPlanarChunk][stride]
+  double* gacc = tab + kPlanarChunk * stride;                      // [kPlanarChunk][2]
+  const int NU = (N + 1) * (M + 1);                                // (n, |m|) units per neighbour
+  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+    const int j0 = p.offsets[e];
+    const int J = p.offsets[e + 1] - j0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < p.P1; i += blockDim.x) Ab[i] = p.Abar[e * p.P1 + i];
+    for (int c0 = 0; c0 < J; c0 += kPlanarChunk) {
+      const int nc = min(kPlanarChunk, J - c0);
+      __syncthreads();
+      if ((int)threadIdx.x < nc) {
+        const int64_t j = j0 + c0 + threadIdx.x;
+        const double x = p.pos[3 * j], y = p.pos[3 * j + 1];
+        const double r2 = x * x + y * y, r = sqrt(r2);
+        double* t = tab + threadIdx.x * stride;
+        t[0] = x / r;
+        t[1] = y / r;
+        t[2] = -y / r2;   // grad theta
+        t[3] = x / r2;
+        double* R = t + kPlanarNbr;          // R_n
+        double* dR = R + (N + 1);            // R_n' = n U_{n-1}(X) dX/dr
+        R[0] = 1.0;
+        dR[0] = 0.0;
+        if (radial && N >= 1) {
+          const double X = cos(kr * r), dX = -kr * sin(kr * r);
+          double tm1 = 1.0, tc = X, um2 = 0.0, um1 = 1.0;   // T_{n-1}, T_n, U_{n-2}, U_{n-1}
+          R[1] = X;
+          dR[1] = dX;
+          for (int n = 2; n <= N; ++n) {
+            const double t2 = 2.0 * X * tc - tm1;
+            tm1 = tc;
+            tc = t2;
+            const double u2 = n == 2 ? 2.0 * X : 2.0 * X * um1 - um2;
+            um2 = um1;
+            um1 = u2;
+            R[n] = tc;
+            dR[n] = (double)n * um1 * dX;
+          }
+        }
+        double* E = dR + (N + 1);
+        const double c = t[0], sn = t[1];
+        double er = 1.0, ei = 0.0;
+        E[0] = 1.0;
+        E[1] = 0.0;
+        for (int m = 1; m <= M; ++m) {
+          const double t2 = er * c - ei * sn;
+          ei = er * sn + ei * c;
+          er = t2;
+          E[2 * m] = er;
+          E[2 * m + 1] = ei;
+        }
+        gacc[2 * threadIdx.x] = gacc[2 * threadIdx.x + 1] = 0.0;
+      }
+      __syncthreads();
+      const int U = nc * NU;
+      const int u0 = (int)(((int64_t)threadIdx.x * U) / blockDim.x);
+      const int u1 = (int)(((int64_t)(threadIdx.x + 1) * U) / blockDim.x);
+      int jj = -1;
+      double gx = 0.0, gy = 0.0;
+      for (int u = u0; u < u1; ++u) {
+        const int q = u / NU, r = u - q * NU, n = r / (M + 1), m = r - n * (M + 1);
+        if (q != jj) {
+          if (jj >= 0) {
+            atomicAdd(&gacc[2 * jj], gx);
+            atomicAdd(&gacc[2 * jj + 1], gy);
+          }
+          jj = q;
+          gx = gy = 0.0;
+        }
+        const double* t = tab + q * stride;
+        const double c = t[0], sn = t[1], gtx = t[2], gty = t[3];
+        const double Rn = radial ? t[kPlanarNbr + n] : 1.0;
+        const double dRn = radial ? t[kPlanarNbr + (N + 1) + n] : 0.0;
+        const double* E = t + kPlanarNbr + 2 * (N + 1);
+        const double er = E[2 * m], ei = E[2 * m + 1];
+        for (int sg = 1; sg >= (m == 0 ? 1 : -1); sg -= 2) {
+          const int i = p.pidx[n * W + M + sg * m];
+          if (i < 0) continue;
+          // phi = R (er, s * sg * ei) = R E with E = e^{i s (sg m) theta}
+          const double qr = er, qi = s_exp * (double)sg * ei;
+          const double2 a = Ab[i];
+          const double re = a.x * qr - a.y * qi;         // Re(abar E)
+          const double im = a.x * qi + a.y * qr;         // Im(abar E)
+          // Re(abar * (i s sg m) R E) = -(s sg m) R Im(abar E)
+          const double ang = -(s_exp * (double)(sg * m)) * Rn * im;
+          gx += dRn * re * c + ang * gtx;
+          gy += dRn * re * sn + ang * gty;
+        }
+      }
+      if (jj >= 0) {
+        atomicAdd(&gacc[2 * jj], gx);
+        atomicAdd(&gacc[2 * jj + 1], gy);
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < nc) {
+        const int64_t j = j0 + c0 + threadIdx.x;
+        p.grad[3 * j] = gacc[2 * threadIdx.x];
+        p.grad[3 * j + 1] = gacc[2 * threadIdx.x + 1];
+        p.grad[3 * j + 2] = 0.0;
+      }
     }
   }
 }
