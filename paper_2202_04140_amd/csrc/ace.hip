@@ -2051,7 +2051,8 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.k_max = g->h.spec.k_max;
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
-  const size_t lds = g->gsrc.size() * sizeof(double2) + (size_t)3 * NY * 8 + (size_t)kGradChunk * (kGradNbr + 3) * 8;
+  const size_t lds = g->gsrc.size() * sizeof(double2) + (size_t)((3 * NY + 1) & ~1) * 8 +
+                     (size_t)kGradChunk * (grad_nbr_doubles(a.n_max) + 3) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
   a.nb = g->grad_nb;
   if (a.k_max > 0)

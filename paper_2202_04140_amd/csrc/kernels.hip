@@ -354,11 +354,13 @@ template __global__ void naive_kernel<8>(NaiveArgs);
 // walks its range with the Legendre recurrence in l (restarted on a new m,
 // warmed up when its range starts inside an m line) and adds its partial
 // gradient of each neighbour to an LDS accumulator when it leaves that
-// neighbour.  Per-neighbour quantities are computed once per chunk into LDS.
+// neighbour.  Per-neighbour quantities, T_n and T_n' among them, are
+// computed once per chunk into LDS.
 // FEAT: a feature factor T_k(mu) per function (Sec. 5.4).
 // ---------------------------------------------------------------------------
-constexpr int kGradChunk = 32;   // neighbours per chunk
-constexpr int kGradNbr = 7;      // doubles per neighbour: x, y, z, 1/r, cos, dcos/dr, mu
+constexpr int kGradChunk = 16;   // neighbours per chunk
+// doubles per neighbour: x, y, z, 1/r, cos, dcos/dr, mu, pad, then (T_n, T_n') for n = 0..n_max
+__host__ __device__ constexpr int grad_nbr_doubles(int n_max) { return 8 + 2 * (n_max + 1); }
 
 template <bool FEAT>
 __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
@@ -370,9 +372,10 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
   const int ND = (L + 1) * (L + 1) * NB;
   const int lane = threadIdx.x;
   double2* Ab = lds;                                           // [ND]
+  const int NR = grad_nbr_doubles(N);
   double* yc = reinterpret_cast<double*>(lds + ND);            // [3 * NY]
-  double* nbr = yc + 3 * NY;                                   // [kGradChunk][kGradNbr]
-  double* gacc = nbr + kGradChunk * kGradNbr;                  // [kGradChunk][3]
+  double* nbr = yc + ((3 * NY + 1) & ~1);                      // [kGradChunk][NR], 16-byte aligned
+  double* gacc = nbr + kGradChunk * NR;                        // [kGradChunk][3]
   for (int i = lane; i < 3 * NY; i += 64) yc[i] = p.ycoef[i];
   const double* cA = yc;
   const double* cB = yc + NY;
@@ -396,14 +399,35 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
         const double rr = sqrt(rx * rx + ry * ry + rz * rz);
         const double inv = 1.0 / rr;
         const double arg = M_PI * rr / p.r_cut;
-        double* nd = nbr + lane * kGradNbr;
+        double* nd = nbr + lane * NR;
+        const double c = cos(arg);
         nd[0] = rx * inv;
         nd[1] = ry * inv;
         nd[2] = rz * inv;
         nd[3] = inv;
-        nd[4] = cos(arg);
+        nd[4] = c;
         nd[5] = -(M_PI / p.r_cut) * sin(arg);
         nd[6] = FEAT ? rp[3] : 0.0;   // invariant feature (Sec. 5.4)
+        nd[7] = 0.0;
+        // T_n(c) and T_n'(c) by the Chebyshev recurrence
+        double* tt = nd + 8;
+        double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
+        tt[0] = 1.0;
+        tt[1] = 0.0;
+        if (N >= 1) {
+          tt[2] = c;
+          tt[3] = 1.0;
+        }
+        for (int n = 2; n <= N; ++n) {
+          const double T = 2.0 * c * t1 - t0;
+          const double dT = 2.0 * t1 + 2.0 * c * d1 - d0;
+          t0 = t1;
+          t1 = T;
+          d0 = d1;
+          d1 = dT;
+          tt[2 * n] = T;
+          tt[2 * n + 1] = dT;
+        }
         gacc[3 * lane] = gacc[3 * lane + 1] = gacc[3 * lane + 2] = 0.0;
       }
       __syncthreads();
@@ -417,14 +441,14 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
           ++m;
         }
         int l = m + r;
-        double x, y, z, inv, c, dcdr, mu;
+        double x, y, z, inv, dcdr, mu;
+        const double* nd = nbr;
         auto load_nbr = [&](int q) {
-          const double* nd = nbr + q * kGradNbr;
+          nd = nbr + q * NR;
           x = nd[0];
           y = nd[1];
           z = nd[2];
           inv = nd[3];
-          c = nd[4];
           dcdr = nd[5];
           mu = nd[6];
         };
@@ -461,24 +485,11 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
           const double2* bm = Ab + (l * l + l - m) * NB;
           double b0pr = 0.0, b0pi = 0.0, b1pr = 0.0, b1pi = 0.0;   // +m
           double b0mr = 0.0, b0mi = 0.0, b1mr = 0.0, b1mi = 0.0;   // -m
-          double t0 = 1.0, t1 = c, d0 = 0.0, d1 = 1.0;
+          const double2* tt = reinterpret_cast<const double2*>(nd + 8);   // (T_n, T_n')
 #pragma unroll 2
           for (int n = 0; n <= N; ++n) {
-            double T, dT;
-            if (n == 0) {
-              T = 1.0;
-              dT = 0.0;
-            } else if (n == 1) {
-              T = c;
-              dT = 1.0;
-            } else {
-              T = 2.0 * c * t1 - t0;
-              dT = 2.0 * t1 + 2.0 * c * d1 - d0;
-              t0 = t1;
-              t1 = T;
-              d0 = d1;
-              d1 = dT;
-            }
+            const double2 td = tt[n];
+            const double T = td.x, dT = td.y;
             double k0 = 1.0, k1 = mu;
             for (int k = 0; k < K1; ++k) {
               double Tk = 1.0;
@@ -503,29 +514,24 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
               b1mi = fma(am.y, dw, b1mi);
             }
           }
-          // S = p Q = r^l Y_l^m at the unit vector, and its gradient
-          const double Sr = pr * Q, Si = pi * Q;
-          double dxr = 2.0 * x * Qp * pr, dxi = 2.0 * x * Qp * pi;
-          double dyr = 2.0 * y * Qp * pr, dyi = 2.0 * y * Qp * pi;
-          const double dzr = (Qz + 2.0 * z * Qp) * pr, dzi = (Qz + 2.0 * z * Qp) * pi;
-          if (m > 0) {
-            dxr += m * qr * Q;
-            dxi += m * qi * Q;
-            dyr -= m * qi * Q;
-            dyi += m * qr * Q;
-          }
-          const double lf = (double)l;
-          const double gYxr = (dxr - lf * Sr * x) * inv, gYxi = (dxi - lf * Si * x) * inv;
-          const double gYyr = (dyr - lf * Sr * y) * inv, gYyi = (dyi - lf * Si * y) * inv;
-          const double gYzr = (dzr - lf * Sr * z) * inv, gYzi = (dzi - lf * Si * z) * inv;
-          // +m: Y = S; -m: Y_l^{-m} = (-1)^m conj(Y_l^m) (same for the gradient);
-          // for m = 0 both read the same entry, so count it once
-          const double fm = (m & 1) ? -1.0 : 1.0;
-          const double w0 = m == 0 ? 0.0 : 1.0;
-          const double rad = dcdr * ((b1pr * Sr - b1pi * Si) + w0 * fm * (b1mr * Sr + b1mi * Si));
-          gx += rad * x + (b0pr * gYxr - b0pi * gYxi) + w0 * fm * (b0mr * gYxr + b0mi * gYxi);
-          gy += rad * y + (b0pr * gYyr - b0pi * gYyi) + w0 * fm * (b0mr * gYyr + b0mi * gYyi);
-          gz += rad * z + (b0pr * gYzr - b0pi * gYzi) + w0 * fm * (b0mr * gYzr + b0mi * gYzi);
+          // The +m and -m terms (Y_l^{-m} = (-1)^m conj(Y_l^m), likewise its
+          // gradient; m = 0 counted once) sum to Br Re(g) + Bi Im(g) for g = Y
+          // or grad Y, with Br = b.re(+m) + s b.re(-m), Bi = s b.im(-m) - b.im(+m),
+          // s = (-1)^m (0 for m = 0).  With S = p Q, p = (x + i y)^m,
+          // q = (x + i y)^(m-1) at the unit vector u:
+          //   grad S = 2 Qp p u + m Q q (1, i, 0) + Qz p e_z,
+          //   grad Y = (grad S - l S u) / |r|,  d/dr of the radial part: T_n' dcos/dr,
+          // so everything pairs (Br, Bi) with p (P) or q.
+          const double sgn = m == 0 ? 0.0 : ((m & 1) ? -1.0 : 1.0);
+          const double Br = fma(sgn, b0mr, b0pr), Bi = fma(sgn, b0mi, -b0pi);
+          const double B1r = fma(sgn, b1mr, b1pr), B1i = fma(sgn, b1mi, -b1pi);
+          const double P = fma(Br, pr, Bi * pi);
+          const double P1 = fma(B1r, pr, B1i * pi);
+          const double cu = fma(dcdr * Q, P1, inv * P * (2.0 * Qp - (double)l * Q));
+          const double mq = inv * (double)m * Q;
+          gx = fma(x, cu, fma(mq, fma(Br, qr, Bi * qi), gx));
+          gy = fma(y, cu, fma(mq, fma(Bi, qr, -(Br * qi)), gy));
+          gz = fma(z, cu, fma(inv * Qz, P, gz));
           // next unit
           if (l < L) {
             ++l;
