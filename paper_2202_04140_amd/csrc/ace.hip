@@ -1647,7 +1647,8 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)dag_kernel<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
-  ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
+  ACE_HIP(hipFuncSetAttribute((const void*)basis_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)grad_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   ACE_HIP(hipFuncSetAttribute((const void*)planar_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
@@ -1797,7 +1798,10 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   const int chunk = kBasisThreads / (a.l_max + 1);
   const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * (((a.n_max + 1) + (a.k_max + 1) + 2 * NY) | 1) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the basis kernel");
-  hipLaunchKernelGGL(basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
+  if (a.k_max > 0)
+    hipLaunchKernelGGL(basis_kernel<true>, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL(basis_kernel<false>, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }

@@ -84,11 +84,14 @@ constexpr int kBasisBlock = 256;
 // Condon-Shortley phase are folded into the coefficients on the host; the
 // form has no division by sin(theta)).  Then one lane per one-particle
 // index i accumulates R_{n_i} Y_{l_i}^{m_i} over the chunk.
+// FEAT: a feature factor T_k(mu) per function (Sec. 5.4); without it the
+// radial factor is T_n alone.
+template <bool FEAT>
 __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
   extern __shared__ double lds_b[];
   const int L = p.l_max;
   const int NY = (L + 1) * (L + 2) / 2;
-  const int K1 = p.k_max + 1;
+  const int K1 = FEAT ? p.k_max + 1 : 1;
   // doubles per neighbour: T_n(cos), T_k(mu), Y; odd, so that lanes writing
   // different neighbours' rows spread over the LDS banks
   const int stride = ((p.n_max + 1) + K1 + 2 * NY) | 1;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
         for (; k + 1 < nc; k += 2) {
           const double* t0 = tab + k * stride;
           const double* t1 = t0 + stride;
-          const double R0 = t0[ro] * t0[ko], R1 = t1[ro] * t1[ko];
+          const double R0 = FEAT ? t0[ro] * t0[ko] : t0[ro], R1 = FEAT ? t1[ro] * t1[ko] : t1[ro];
           ax0 = fma(R0, t0[yo], ax0);
           ay0 = fma(R0, t0[yo + 1], ay0);
           ax1 = fma(R1, t1[yo], ax1);
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
         }
         if (k < nc) {
           const double* t0 = tab + k * stride;
-          const double R0 = t0[ro] * t0[ko];
+          const double R0 = FEAT ? t0[ro] * t0[ko] : t0[ro];
           ax0 = fma(R0, t0[yo], ax0);
           ay0 = fma(R0, t0[yo + 1], ay0);
         }
@@ -190,6 +193,9 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
     __syncthreads();
   }
 }
+
+template __global__ void basis_kernel<false>(BasisArgs);
+template __global__ void basis_kernel<true>(BasisArgs);
 
 // ---------------------------------------------------------------------------
 // DAG forward + reverse pass
