@@ -92,3 +92,23 @@ def test_planar_gradient_central_differences(device):
             fd[rows, d] = (fp[envs] - fm[envs]) / (2 * h)
     assert rel(grad, fd) <= 1e-6
     assert np.all(grad[:, 2] == 0)
+
+
+@pytest.mark.parametrize("wid", [6, 7])
+def test_planar_long_and_empty_environments(device, wid):
+    """Neighbour counts across the kernels' 64-neighbour table chunks (0, 1, 63,
+    64, 65, 150): basis, phi and forces against the oracle."""
+    print(f"planar long/empty wid={wid}", flush=True)
+    ace, G, g, K, c, _, _ = setup(wid, 1)
+    counts = np.array([0, 1, 63, 64, 65, 150])
+    off = np.zeros(len(counts) + 1, np.int32)
+    off[1:] = np.cumsum(counts)
+    pos = wl.planar_positions(int(off[-1]), 60 + wid, circle=wid == 7)
+    tc, toff, tpos = dev(device, c, off, pos)
+    A = cplx(ace.basis(G, toff, tpos))
+    assert rel(A, ob.pooled_A(g.labels, off, pos, 5.0)) <= TOL_A
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, 5.0)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+    assert cplx(phi)[0] == 0
