@@ -27,7 +27,7 @@ from . import Graph, contract
 SPACE = {
     "forest": {
         "row_chunk": [16, 32, 64],
-        "tree_chunk": [8, 16, 32],
+        "tree_chunk": [4, 8, 16, 32],
         "hot_columns": [0, 2, 4],
         "bank_schedule": [0, 1],
         "block_threads": [256, 512],
