@@ -812,9 +812,11 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs p) {
 // each lane gathers one row chunk y = M x, which gives both the forward
 // contribution (phi += x.y / 2) and the adjoint (abar += y) with no atomics.
 //
-// Adjoints of order-2 nodes are never stored: a contribution d to abar_u,
-// u = a * b, is forwarded at once to the one-particle adjoints
-// (abar_a += d x_b, abar_b += d x_a).  One-particle adjoints are LDS
+// Where LDS has room (FULL), every resident slot has an adjoint accumulator
+// and the order-2 adjoints reach the one-particle ones by one gather per
+// one-particle node at the end.  Otherwise order-2 adjoints are not stored:
+// a contribution d to abar_u, u = a * b, is forwarded at once to the
+// one-particle adjoints (abar_a += d x_b, abar_b += d x_a).  Adjoints are LDS
 // accumulators updated with atomics, so the reverse pass is not bitwise
 // deterministic (the forward pass is).
 // ---------------------------------------------------------------------------
