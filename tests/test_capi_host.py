@@ -457,3 +457,27 @@ def test_features_invalid_and_remat_folded():
         phi, _ = G.remat_eval_host(c, A, folded=folded)
         pr = oc.phi_naive(K, c, A)
         assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+
+
+# ---- Sec. 3.4 numerical tests regenerated with the library builder -------------------
+def test_aux_ratio_trends_of_sec_3_4():
+    """The trends the paper reports for #A/#V: torus, nu = 3: both heuristics insert
+    the same auxiliary nodes; nu = 4, 5 at larger D: Algorithm 2 (n = 2) inserts
+    fewer.  O(3): for p = 1 Algorithm 2 is slightly worse pre-asymptotically, for
+    p = 2 and p = infinity it inserts fewer."""
+    import math
+    from paper_2202_04140_amd import counts
+    for D in (8, 16, 24):
+        r = counts.sizes(ace.GROUP_TORUS, 3, D, 1, 1), counts.sizes(ace.GROUP_TORUS, 3, D, 1, 2)
+        assert r[0] == r[1]
+    for nu in (4, 5):
+        a1, a2 = counts.sizes(ace.GROUP_TORUS, nu, 32, 1, 1), counts.sizes(ace.GROUP_TORUS, nu, 32, 1, 2)
+        assert a1["K"] == a2["K"] and a2["A"] < a1["A"]
+    a1, a2 = counts.sizes(ace.GROUP_O3, 4, 10, 1, 1), counts.sizes(ace.GROUP_O3, 4, 10, 1, 2)
+    assert a2["A"] > a1["A"]
+    a1, a2 = counts.sizes(ace.GROUP_O3, 4, 8, 2, 1), counts.sizes(ace.GROUP_O3, 4, 8, 2, 2)
+    assert a2["A"] < a1["A"]
+    a1, a2 = counts.sizes(ace.GROUP_O3, 3, 6, math.inf, 1), counts.sizes(ace.GROUP_O3, 3, 6, math.inf, 2)
+    assert a2["A"] < a1["A"]
+    rows = counts.table(ace.GROUP_TORUS, 1, [4], [8, 12])
+    assert [r[:2] for r in rows] == [(4, 8), (4, 12)] and all(0 < r[5] < 1 for r in rows)
