@@ -39,6 +39,7 @@ ace_status fail(ace_status code, const std::string& msg) {
 
 constexpr int kDagThreads = 256;
 constexpr int kForestThreads = 512;
+constexpr int kForwardChunk = 8;   // forest, full-adjoint mode: forwarding entries per chunk
 constexpr int kNaiveThreads = 256;
 constexpr int kBasisThreads = 256;
 constexpr int kGradThreads = 256;   // planar gradient kernel
@@ -126,9 +127,12 @@ struct ace_graph {
     int hot_slot[4] = {0, 0, 0, 0};  // most frequent childless-child siblings
     int n_items = 0;                 // tree items incl. slice padding (= 64 * n_tslices)
     int cs_hot = 0;                  // coefficients of the hot columns, [4][n_items]
-    std::vector<int32_t> fw_off;     // full-adjoint mode: order-2 -> one-particle forwarding lists
+    // full-adjoint mode: order-2 -> one-particle forwarding lists, cut into
+    // chunks {one-particle slot, first entry, end entry, 0} of at most
+    // kForwardChunk entries each
+    std::vector<int4> fw_ck;
     std::vector<uint32_t> fw_ent;
-    int32_t* d_fw_off = nullptr;
+    int4* d_fw_ck = nullptr;
     uint32_t* d_fw_ent = nullptr;
   } fo[2];
   void* fmem = nullptr;
@@ -792,13 +796,16 @@ void make_forest(ace_graph* g, int which) {
       fl[a].push_back(us | (b << 16));
       fl[b].push_back(us | (a << 16));
     }
-    F.fw_off.assign(P1 + 1, 0);
+    // chunks: a one-particle node that is a parent of many order-2 nodes
+    // would otherwise hold one lane in a long serial loop
+    F.fw_ck.clear();
     F.fw_ent.clear();
     for (int i = 0; i < P1; ++i) {
-      F.fw_off[i] = (int32_t)F.fw_ent.size();
+      const int b0 = (int)F.fw_ent.size();
       F.fw_ent.insert(F.fw_ent.end(), fl[i].begin(), fl[i].end());
+      const int b1 = (int)F.fw_ent.size();
+      for (int c = b0; c < b1; c += kForwardChunk) F.fw_ck.push_back(make_int4(i, c, std::min(b1, c + kForwardChunk), 0));
     }
-    F.fw_off[P1] = (int32_t)F.fw_ent.size();
   }
   F.ok = true;
 }
@@ -932,11 +939,15 @@ bool forest_emulate(const ace_graph* g, int which, const double* coeffs, const d
     for (int hc = 0; hc < 4; ++hc)
       if (F.hot_slot[hc] != ZERO) push(F.hot_slot[hc], hacc[hc]);
     if (full)
-      for (int i = 0; i < P1; ++i)
-        for (int q = F.fw_off.at(i); q < F.fw_off.at(i + 1); ++q) {
+      for (const int4& ck : F.fw_ck) {
+        if (ck.x < 0 || ck.x >= P1) return false;
+        cd s = 0.0;
+        for (int q = ck.y; q < ck.z; ++q) {
           const uint32_t en = F.fw_ent.at(q);
-          ab.at(i) += ab.at(en & 0xffffu) * X(en >> 16);
+          s += ab.at(en & 0xffffu) * X(en >> 16);
         }
+        ab.at(ck.x) += s;
+      }
     phi[0] = accr.real();
     phi[1] = acci.imag();
     for (int i = 0; i < P1; ++i) {
@@ -1508,7 +1519,7 @@ ace_status upload_forest(ace_graph* g) {
     fb += align_up(F.mr_slice.size() * sizeof(int4)) + align_up(F.tr_slice.size() * sizeof(int4));
     fb += align_up(F.mr_row.size() * 2) + align_up(F.me_col.size() * 2) + align_up(F.ch_s.size() * 2);
     fb += align_up(F.gc_s.size() * 2) + align_up(F.ch_g.size() * sizeof(int2)) + align_up(F.kmap.size() * 4);
-    fb += align_up(F.kbar.size() * 4) + align_up(F.fw_off.size() * 4) + align_up(F.fw_ent.size() * 4);
+    fb += align_up(F.kbar.size() * 4) + align_up(F.fw_ck.size() * sizeof(int4)) + align_up(F.fw_ent.size() * 4);
   }
   if (g->fo[0].ok || g->fo[1].ok) {
     if (hipMalloc(&g->fmem, fb) != hipSuccess) {
@@ -1530,7 +1541,7 @@ ace_status upload_forest(ace_graph* g) {
       F.d_ch_g = carve<int2>(q, F.ch_g.size());
       F.d_kmap = carve<int32_t>(q, F.kmap.size());
       F.d_kbar = carve<int32_t>(q, F.kbar.size());
-      F.d_fw_off = carve<int32_t>(q, F.fw_off.size());
+      F.d_fw_ck = carve<int4>(q, F.fw_ck.size());
       F.d_fw_ent = carve<uint32_t>(q, F.fw_ent.size());
       ACE_HIP(put(F.d_nu2_ab, F.nu2_ab.data(), F.nu2_ab.size() * 4));
       ACE_HIP(put(F.d_it_ab, F.it_ab.data(), F.it_ab.size() * 4));
@@ -1543,7 +1554,7 @@ ace_status upload_forest(ace_graph* g) {
       ACE_HIP(put(F.d_ch_g, F.ch_g.data(), F.ch_g.size() * sizeof(int2)));
       ACE_HIP(put(F.d_kmap, F.kmap.data(), F.kmap.size() * 4));
       ACE_HIP(put(F.d_kbar, F.kbar.data(), F.kbar.size() * 4));
-      ACE_HIP(put(F.d_fw_off, F.fw_off.data(), F.fw_off.size() * 4));
+      ACE_HIP(put(F.d_fw_ck, F.fw_ck.data(), F.fw_ck.size() * sizeof(int4)));
       ACE_HIP(put(F.d_fw_ent, F.fw_ent.data(), F.fw_ent.size() * 4));
       F.fwd_lds = forest_lds_bytes(F, g->P1, false, false) <= g->max_lds;
       F.full = forest_lds_bytes(F, g->P1, true, true) <= g->max_lds;
@@ -1857,7 +1868,8 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.nslot = F.nslot;
   a.n_mslices = F.n_mslices;
   a.n_tslices = F.n_tslices;
-  a.fw_off = F.d_fw_off;
+  a.fw_ck = F.d_fw_ck;
+  a.n_fwck = (int)F.fw_ck.size();
   a.fw_ent = F.d_fw_ent;
   const bool grad = Abar != nullptr;
   // two environments per block where their values fit in LDS

@@ -118,8 +118,10 @@ struct ForestArgs {
   int n_items;   // 64 * n_tslices
   int4 hot;      // slots of the four hot-sibling columns (P1 = unused)
   // full-adjoint mode: abar for every resident slot in LDS, order-2
-  // adjoints forwarded at the end by a gather per one-particle node
-  const int32_t* fw_off;   // [P1 + 1] CSR offsets
+  // adjoints forwarded at the end: each chunk {one-particle slot i, first,
+  // end} gathers sum abar_u x_other over its entries and adds it to abar_i
+  const int4* fw_ck;       // [n_fwck]
+  int n_fwck;
   const uint32_t* fw_ent;  // entries: order-2 slot | (other parent slot << 16)
 };
 

@@ -1172,18 +1172,22 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
     }
     __syncthreads();
     if (GRAD && FULL) {
-      // order-2 adjoints to the one-particle adjoints: abar_a += abar_u x_b
-      for (int i = threadIdx.x; i < P1; i += blockDim.x) {
+      // order-2 adjoints to the one-particle adjoints, abar_a += abar_u x_b, in
+      // chunks of a few entries per lane (a one-particle node can be a parent
+      // of hundreds of order-2 nodes); the chunk sums are added atomically,
+      // and no order-2 adjoint changes in this phase
+      for (int c = threadIdx.x; c < p.n_fwck; c += blockDim.x) {
+        const int4 ck = p.fw_ck[c];
         double2 s2[NE];
 #pragma unroll
-        for (int q = 0; q < NE; ++q) s2[q] = ab[q][i];
-        for (int f = p.fw_off[i]; f < p.fw_off[i + 1]; ++f) {
+        for (int q = 0; q < NE; ++q) s2[q] = z2;
+        for (int f = ck.y; f < ck.z; ++f) {
           const uint32_t en = p.fw_ent[f];
 #pragma unroll
           for (int q = 0; q < NE; ++q) s2[q] = cfma(ab[q][en & 0xffffu], x[q][en >> 16], s2[q]);
         }
 #pragma unroll
-        for (int q = 0; q < NE; ++q) ab[q][i] = s2[q];
+        for (int q = 0; q < NE; ++q) atomic_cadd(&ab[q][ck.x], s2[q]);
       }
       __syncthreads();
     }
