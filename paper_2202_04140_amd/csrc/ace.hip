@@ -126,6 +126,8 @@ struct ace_graph {
     bool full = false;               // full-adjoint mode fits in LDS
     int hot_slot[4] = {0, 0, 0, 0};  // most frequent childless-child siblings
     int n_items = 0;                 // tree items incl. slice padding (= 64 * n_tslices)
+    int mr_wave[kMaxForestWaves + 1] = {0};   // wave w takes pair-row slices [mr_wave[w], mr_wave[w + 1])
+    int tr_wave[kMaxForestWaves + 1] = {0};   // and tree slices [tr_wave[w], tr_wave[w + 1])
     int cs_hot = 0;                  // coefficients of the hot columns, [4][n_items]
     // full-adjoint mode: order-2 -> one-particle forwarding lists, cut into
     // chunks {one-particle slot, first entry, end entry, 0} of at most
@@ -752,6 +754,53 @@ void make_forest(ace_graph* g, int which) {
       }
   }
   F.n_mslices = nms;
+
+  // ---- slices to waves: longest first to the least loaded wave (cost
+  // estimates in units of one pair-row entry), then each wave's pair-row and
+  // tree slices made contiguous, so that the block's waves finish together ----
+  {
+    const int nw = std::max(1, std::min(kMaxForestWaves, g->opts.block_threads / 64));
+    struct SC {
+      double cost;
+      int tree, idx;
+    };
+    std::vector<SC> sc;
+    for (int s = 0; s < nms; ++s) sc.push_back({1.0 + F.mr_slice[s].z, 0, s});
+    for (int s = 0; s < nts; ++s) {
+      const int4 d = F.tr_slice[s];
+      int gcmax = 0;
+      if (!F.gc_s.empty())
+        for (int l = 0; l < 64; ++l) {
+          int n = 0;
+          for (int j = 0; j < d.z; ++j) {
+            const int2 r = F.ch_g[d.y + j * 64 + l];
+            n += r.y - r.x;
+          }
+          gcmax = std::max(gcmax, n);
+        }
+      sc.push_back({6.0 + 3.0 * d.z + 3.0 * gcmax, 1, s});
+    }
+    std::stable_sort(sc.begin(), sc.end(), [](const SC& a, const SC& b) { return a.cost > b.cost; });
+    std::vector<double> load(nw, 0.0);
+    std::vector<std::vector<int>> rows_of(nw), trees_of(nw);
+    for (const SC& c : sc) {
+      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[w] += c.cost;
+      (c.tree ? trees_of : rows_of)[w].push_back(c.idx);
+    }
+    std::vector<int4> mr(F.mr_slice), tr(F.tr_slice);
+    int im = 0, it = 0;
+    for (int w = 0; w < nw; ++w) {
+      F.mr_wave[w] = im;
+      F.tr_wave[w] = it;
+      for (int s : rows_of[w]) F.mr_slice[im++] = mr[s];
+      for (int s : trees_of[w]) F.tr_slice[it++] = tr[s];
+    }
+    for (int w = nw; w <= kMaxForestWaves; ++w) {
+      F.mr_wave[w] = im;
+      F.tr_wave[w] = it;
+    }
+  }
 
   // ---- order-2 nodes, one-particle coefficients, coefficient map ----
   F.nu2_ab.resize(nu2.size());
@@ -1862,6 +1911,10 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.cs_gc = F.cs_gc;
   a.cs_hot = F.cs_hot;
   a.n_items = F.n_items;
+  for (int w = 0; w <= kMaxForestWaves; ++w) {
+    a.mr_wave[w] = F.mr_wave[w];
+    a.tr_wave[w] = F.tr_wave[w];
+  }
   a.hot = make_int4(F.hot_slot[0], F.hot_slot[1], F.hot_slot[2], F.hot_slot[3]);
   a.P1 = g->P1;
   a.N2 = F.N2;

@@ -94,6 +94,8 @@ struct GradArgs {
 
 namespace ace {
 
+constexpr int kMaxForestWaves = 8;   // forest kernel: waves per block at most (512 threads)
+
 // Forest schedule (see forest_kernel).  Value slots: one-particle nodes
 // 0..P1-1, a constant-zero slot P1, then the order-2 nodes P1+1..P1+N2.
 // Slot numbers fit in 16 bits.  Coefficients are read from `cs`, the
@@ -117,6 +119,10 @@ struct ForestArgs {
   int P1, N2, nslot, n_mslices, n_tslices;
   int n_items;   // 64 * n_tslices
   int4 hot;      // slots of the four hot-sibling columns (P1 = unused)
+  // wave w of a block takes pair-row slices [mr_wave[w], mr_wave[w + 1]) and
+  // tree slices [tr_wave[w], tr_wave[w + 1]) (balanced on the host)
+  int mr_wave[kMaxForestWaves + 1];
+  int tr_wave[kMaxForestWaves + 1];
   // full-adjoint mode: abar for every resident slot in LDS, order-2
   // adjoints forwarded at the end: each chunk {one-particle slot i, first,
   // end} gathers sum abar_u x_other over its entries and adds it to abar_i

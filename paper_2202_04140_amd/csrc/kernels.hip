@@ -916,7 +916,6 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
   double2* red = reinterpret_cast<double2*>(n2) + (TAB ? (p.N2 + 3) / 4 : 0);
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  const int nw = blockDim.x >> 6;
   const int P1 = p.P1;
   const int ZERO = P1;
   const double* cs = p.cs;
@@ -973,7 +972,7 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
     }
     __syncthreads();
     // phase 2a: resident-pair rows, y = M x (entry count padded to 4)
-    for (int s = wid; s < p.n_mslices; s += nw) {
+    for (int s = p.mr_wave[wid]; s < p.mr_wave[wid + 1]; ++s) {
       const int4 sl = p.mr_slice[s];
       const int row = p.mr_row[sl.x + lane];
       double2 y0[NE], y1[NE], y0i[NE], y1i[NE];
@@ -1029,7 +1028,7 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
       xh3[q] = x[q][p.hot.w];
       hacc0[q] = hacc1[q] = hacc2[q] = hacc3[q] = z2;
     }
-    for (int s = wid; s < p.n_tslices; s += nw) {
+    for (int s = p.tr_wave[wid]; s < p.tr_wave[wid + 1]; ++s) {
       const int4 sl = p.tr_slice[s];
       const int item = sl.x + lane;
       const uint32_t qab = p.it_ab[item];
