@@ -947,26 +947,28 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
     double2 acc[NE], acci[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) acc[q] = acci[q] = z2;
-    // phase 1: order-2 nodes, their own and the one-particle coefficients
+    // phase 1: the one-particle coefficients, and the order-2 values (an
+    // invariant order-2 node's own term is an entry of the pair matrix, so
+    // it has no coefficient here); four parent loads in flight per thread
     for (int i = threadIdx.x; i < P1; i += blockDim.x) {
       const RCoef<FOLD> k = load_coef<FOLD>(cs, p.cs_leaf + i);
 #pragma unroll
       for (int q = 0; q < NE; ++q) coef_fma(k, x[q][i], acc[q], acci[q]);
     }
-    for (int u = threadIdx.x; u < p.N2; u += blockDim.x) {
-      const uint32_t qq = p.nu2_ab[u];
-      const int a = (int)(qq & 0xffffu), b = (int)(qq >> 16);
-      const RCoef<FOLD> k = load_coef<FOLD>(cs, p.cs_nu2 + u);
-      const double c = re_w(k);
+    for (int u0 = threadIdx.x; u0 < p.N2; u0 += 4 * blockDim.x) {
+      uint32_t qq[4];
 #pragma unroll
-      for (int q = 0; q < NE; ++q) {
-        const double2 xa = x[q][a], xb = x[q][b];
-        const double2 xu = cmul(xa, xb);
-        x[q][P1 + 1 + u] = xu;
-        coef_fma(k, xu, acc[q], acci[q]);
-        if (GRAD && c != 0.0) {
-          atomic_cadd(&ab[q][a], make_double2(c * xb.x, c * xb.y));
-          atomic_cadd(&ab[q][b], make_double2(c * xa.x, c * xa.y));
+      for (int r = 0; r < 4; ++r) {
+        const int u = u0 + r * (int)blockDim.x;
+        qq[r] = u < p.N2 ? p.nu2_ab[u] : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int u = u0 + r * (int)blockDim.x;
+        if (u < p.N2) {
+          const int a = (int)(qq[r] & 0xffffu), b = (int)(qq[r] >> 16);
+#pragma unroll
+          for (int q = 0; q < NE; ++q) x[q][P1 + 1 + u] = cmul(x[q][a], x[q][b]);
         }
       }
     }
