@@ -392,9 +392,18 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
     if (J <= 0) continue;   // block-uniform
     __syncthreads();
     const double2* Be = p.Abar + e * p.P1;
-    for (int d = lane; d < ND; d += 64) {
-      const int src = p.gsrc[d];
-      Ab[d] = src >= 0 ? Be[src] : make_double2(0.0, 0.0);
+    // four entries per lane at a time: the table loads, then the Abar loads,
+    // are all in flight together
+    for (int d0 = lane; d0 < ND; d0 += 4 * 64) {
+      int src[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) src[r] = d0 + 64 * r < ND ? p.gsrc[d0 + 64 * r] : -1;
+      double2 v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = src[r] >= 0 ? Be[src[r]] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (d0 + 64 * r < ND) Ab[d0 + 64 * r] = v[r];
     }
     for (int c0 = 0; c0 < J; c0 += kGradChunk) {
       const int nc = min(kGradChunk, J - c0);
