@@ -915,10 +915,8 @@ bool forest_emulate(const ace_graph* g, int which, const double* coeffs, const d
       if (a >= P1 || b >= P1) return false;
       const cd xu = X(a) * X(b);
       X(P1 + 1 + u) = xu;
-      accr += cr.at(F.cs_nu2 + u) * xu;
-      acci += ci.at(F.cs_nu2 + u) * xu;
-      ab.at(a) += cr.at(F.cs_nu2 + u) * X(b);
-      ab.at(b) += cr.at(F.cs_nu2 + u) * X(a);
+      // an invariant order-2 node's own term is a pair-matrix entry
+      if (F.kmap.at(F.cs_nu2 + u) != -1) return false;
     }
     for (int s = 0; s < F.n_mslices; ++s) {
       const int4 sl = F.mr_slice.at(s);
@@ -1904,7 +1902,6 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.ch_g = F.has_gc ? F.d_ch_g : nullptr;
   a.gc_s = F.d_gc_s;
   a.cs_leaf = F.cs_leaf;
-  a.cs_nu2 = F.cs_nu2;
   a.cs_me = F.cs_me;
   a.cs_it = F.cs_it;
   a.cs_ch = F.cs_ch;

@@ -115,7 +115,7 @@ struct ForestArgs {
   const uint16_t* ch_s;      // children, 64-interleaved per slice: resident sibling slot
   const int2* ch_g;          // children: grandchild range [x, y) (nullptr if none exist)
   const uint16_t* gc_s;      // grandchildren: resident sibling slot
-  int cs_leaf, cs_nu2, cs_me, cs_it, cs_ch, cs_gc, cs_hot;
+  int cs_leaf, cs_me, cs_it, cs_ch, cs_gc, cs_hot;
   int P1, N2, nslot, n_mslices, n_tslices;
   int n_items;   // 64 * n_tslices
   int4 hot;      // slots of the four hot-sibling columns (P1 = unused)
