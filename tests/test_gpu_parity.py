@@ -232,6 +232,41 @@ def test_full_size_sampled_and_dag_vs_naive(device):
     assert rel(grad[rows], g_ref) <= TOL_GRAD
 
 
+@pytest.mark.parametrize("wid,n_sample", [(3, 24), (4, 8), (5, 3)])
+def test_full_size_in_benchmark_schedule(device, wid, n_sample, tmp_path, monkeypatch):
+    """Every environment of the 4096-, 32768- and 8192-environment workloads in one
+    ace_eval_grad call, in the schedule the benchmark applies to that batch (the
+    shipped autotuned choice: an empty user cache, as on a fresh machine); sampled
+    environments (the smallest and largest neighbour counts among them) against the
+    oracle, all of them against the naive kernel."""
+    import paper_2202_04140_amd as ace
+    from paper_2202_04140_amd import autotune
+    monkeypatch.setenv("ACE_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    w = wl.WORKLOADS[wid]
+    G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid)
+    print(f"full size wid={wid} n_env={len(off) - 1} n_nbr={len(pos)}", flush=True)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    tuned = autotune.tune(G, tc, ace.basis(G, toff, tpos))
+    assert tuned["cached"], "no shipped schedule for this workload"
+    assert G.schedule_kind() == tuned["opts"]["schedule"]
+    phi, grad = ace.eval_grad(G, tc, toff, tpos)
+    phi_n, grad_n = ace.eval_grad(G, tc, toff, tpos, naive=True)
+    phi, grad, phi_n, grad_n = cplx(phi), grad.cpu().numpy(), cplx(phi_n), grad_n.cpu().numpy()
+    assert np.isfinite(phi).all() and np.isfinite(grad).all()
+    assert rel(phi, phi_n) <= TOL_PHI
+    assert rel(grad, grad_n) <= TOL_GRAD
+    envs = wl.subset(off, n_sample)
+    J = np.diff(off)
+    assert J[envs].min() == J.min() and J[envs].max() == J.max()
+    so, sp_ = wl.gather(off, pos, envs)
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, so, sp_, w.r_cut)
+    rows = np.concatenate([np.arange(off[e], off[e + 1]) for e in envs])
+    assert rel(phi[envs], phi_ref) <= TOL_PHI
+    assert rel(grad[rows], g_ref) <= TOL_GRAD
+
+
 # ---- edge cases ----------------------------------------------------------------------
 def test_edge_cases_empty_ragged(device):
     import paper_2202_04140_amd as ace
