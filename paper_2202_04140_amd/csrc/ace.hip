@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cstdint>
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -86,6 +88,7 @@ struct ace_graph {
   std::vector<int16_t> naive_tup;
   std::vector<OnepInfo> onep;
   std::vector<int16_t> onep_index;
+  std::vector<int16_t> basis_prim;   // O(3): the functions with m >= 0
   std::vector<int32_t> gsrc;
   int grad_nb = 0;                 // gradient kernel: Abar entries per (l, m), padded to odd
   std::vector<double> ycoef;
@@ -93,7 +96,7 @@ struct ace_graph {
   void* dmem = nullptr;
   int2 *d_st_ab = nullptr, *d_cl_ab = nullptr;
   int32_t *d_st_k = nullptr, *d_cl_k = nullptr, *d_leaf_k = nullptr;
-  int16_t *d_naive_tup = nullptr, *d_onep_index = nullptr;
+  int16_t *d_naive_tup = nullptr, *d_onep_index = nullptr, *d_basis_prim = nullptr;
   int32_t* d_gsrc = nullptr;
   OnepInfo* d_onep = nullptr;
   double* d_ycoef = nullptr;
@@ -269,6 +272,7 @@ void make_schedule(ace_graph* g) {
   // one-particle tables (O(3) only)
   g->onep.clear();
   g->onep_index.clear();
+  g->basis_prim.clear();
   g->gsrc.clear();
   g->ycoef.clear();
   if (h.spec.group == 0) {
@@ -286,8 +290,22 @@ void make_schedule(ace_graph* g) {
       o.l = (int8_t)l;
       o.am = (int8_t)am;
       o.k = (int8_t)h.on_k[i];
+      o.neg = -1;
       g->onep.push_back(o);
       if (h.on_k[i] == 0) g->onep_index[(size_t)(n * (L + 1) + l) * W + (m + L)] = (int16_t)i;
+    }
+    // the basis kernel sums the m >= 0 functions only; an m > 0 function also
+    // writes its -m partner (same n, l, k), a sign-flipped copy of its sums
+    std::map<std::array<int, 4>, int> where;
+    for (int i = 0; i < P1; ++i) where[{h.on_n[i], h.on_l[i], h.on_m[i], h.on_k[i]}] = i;
+    for (int i = 0; i < P1; ++i) {
+      if (h.on_m[i] < 0) continue;
+      g->basis_prim.push_back((int16_t)i);
+      if (h.on_m[i] > 0) {
+        const auto it = where.find({h.on_n[i], h.on_l[i], -h.on_m[i], h.on_k[i]});
+        if (it == where.end()) throw std::runtime_error("one-particle set without the -m partner of a function");
+        g->onep[i].neg = (int16_t)it->second;
+      }
     }
     make_ycoef(L, g->ycoef);
     // the gradient kernel's layout of Abar: position (l^2 + l + m) NB + n K1 + k
@@ -317,6 +335,7 @@ void make_schedule(ace_graph* g) {
       o.sre = 1;
       o.sim = (int8_t)(m == 0 ? 1 : (m > 0 ? s : -s));
       o.l = o.am;
+      o.neg = -1;
       g->onep.push_back(o);
       g->onep_index[(size_t)n * W + (m + M)] = (int16_t)i;
     }
@@ -1666,6 +1685,7 @@ ace_status upload(ace_graph* g) {
   bytes += align_up(g->cl_ab.size() * sizeof(int2)) + align_up(g->cl_k.size() * 4);
   bytes += align_up(g->leaf_k.size() * 4) + align_up(g->naive_tup.size() * 2);
   bytes += align_up(g->onep.size() * sizeof(OnepInfo)) + align_up(g->onep_index.size() * 2);
+  bytes += align_up(g->basis_prim.size() * 2);
   bytes += align_up(g->ycoef.size() * 8) + align_up(g->gsrc.size() * 4) + kAlign;
   if (hipMalloc(&g->dmem, bytes) != hipSuccess) {
     g->dmem = nullptr;
@@ -1681,6 +1701,7 @@ ace_status upload(ace_graph* g) {
   g->d_naive_tup = carve<int16_t>(p, g->naive_tup.size());
   g->d_onep = carve<OnepInfo>(p, g->onep.size());
   g->d_onep_index = carve<int16_t>(p, g->onep_index.size());
+  g->d_basis_prim = carve<int16_t>(p, g->basis_prim.size());
   g->d_ycoef = carve<double>(p, g->ycoef.size());
   g->d_gsrc = carve<int32_t>(p, g->gsrc.size());
   auto put = [](void* d, const void* s, size_t n) { return n ? hipMemcpy(d, s, n, hipMemcpyHostToDevice) : hipSuccess; };
@@ -1692,6 +1713,7 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(put(g->d_naive_tup, g->naive_tup.data(), g->naive_tup.size() * 2));
   ACE_HIP(put(g->d_onep, g->onep.data(), g->onep.size() * sizeof(OnepInfo)));
   ACE_HIP(put(g->d_onep_index, g->onep_index.data(), g->onep_index.size() * 2));
+  ACE_HIP(put(g->d_basis_prim, g->basis_prim.data(), g->basis_prim.size() * 2));
   ACE_HIP(put(g->d_ycoef, g->ycoef.data(), g->ycoef.size() * 8));
   ACE_HIP(put(g->d_gsrc, g->gsrc.data(), g->gsrc.size() * 4));
 
@@ -1852,6 +1874,8 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   a.group = 0;
   a.k_max = g->h.spec.k_max;
   a.pos_stride = a.k_max > 0 ? 4 : 3;
+  a.prim = g->d_basis_prim;
+  a.n_prim = (int)g->basis_prim.size();
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const int chunk = kBasisThreads / (a.l_max + 1);
   const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * (((a.n_max + 1) + (a.k_max + 1) + 2 * NY) | 1) * 8;

@@ -20,6 +20,7 @@ struct OnepInfo {
   int8_t l;
   int8_t am;      // |m|
   int8_t k;       // feature degree (Sec. 5.4), 0 without a feature
+  int16_t neg;    // O(3), m > 0: index of the (n, l, -m, k) function; else -1
 };
 
 struct BasisArgs {
@@ -34,6 +35,8 @@ struct BasisArgs {
   int group;             // 0 O(3); planar: 1 torus, 2 SO(2)
   int k_max;             // O(3) feature degree; positions then carry mu as a fourth column
   int pos_stride;        // doubles per position: 3, or 4 with a feature
+  const int16_t* prim;   // O(3): [n_prim] indices of the functions with m >= 0
+  int n_prim;
 };
 
 // Planar one-particle functions (torus, SO(2)): phi_i = R_n(r) e^{i s m theta}

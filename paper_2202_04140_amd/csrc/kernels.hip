@@ -159,9 +159,12 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
         }
       }
       __syncthreads();
-      // two neighbours per step into two partial sums (more loads in flight);
-      // sre, sim = +-1 are applied to the sums
-      for (int i = threadIdx.x; i < p.P1; i += blockDim.x) {
+      // one lane per function with m >= 0; two neighbours per step into two
+      // partial sums (more loads in flight).  The -m partner of an m > 0
+      // function gets the same sums with the signs of Y_l^{-m} =
+      // (-1)^m conj(Y_l^m) (its own sre, sim) applied.
+      for (int q = threadIdx.x; q < p.n_prim; q += blockDim.x) {
+        const int i = p.prim[q];
         const OnepInfo o = p.onep[i];
         const int ro = o.n, ko = p.n_max + 1 + o.k, yo = (p.n_max + 1) + K1 + 2 * o.yoff;
         double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
@@ -181,10 +184,18 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
           ax0 = fma(R0, t0[yo], ax0);
           ay0 = fma(R0, t0[yo + 1], ay0);
         }
+        const double sx = ax0 + ax1, sy = ay0 + ay1;
         double2 a = acc[i];
-        a.x = fma((double)o.sre, ax0 + ax1, a.x);
-        a.y = fma((double)o.sim, ay0 + ay1, a.y);
+        a.x = fma((double)o.sre, sx, a.x);
+        a.y = fma((double)o.sim, sy, a.y);
         acc[i] = a;
+        if (o.neg >= 0) {
+          const OnepInfo on = p.onep[o.neg];
+          double2 b = acc[o.neg];
+          b.x = fma((double)on.sre, sx, b.x);
+          b.y = fma((double)on.sim, sy, b.y);
+          acc[o.neg] = b;
+        }
       }
     }
     __syncthreads();
