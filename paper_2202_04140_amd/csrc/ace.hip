@@ -308,16 +308,23 @@ void make_schedule(ace_graph* g) {
       }
     }
     make_ycoef(L, g->ycoef);
-    // the gradient kernel's layout of Abar: position (l^2 + l + m) NB + n K1 + k
-    // holds one-particle function (n, l, m, k), or -1 (absent: zero); the block
-    // of one (l, m) is padded to an odd length NB, so that lanes reading
-    // different (l, m) spread over the LDS bank groups
+    // the gradient kernel's staged adjoint: position (l (l + 1) / 2 + m) NB +
+    // n K1 + k, m >= 0, combines the functions (n, l, +-m, k); its pair of
+    // sources is (index of +m or -1, index of -m encoded as i for even m and
+    // -2 - i for odd m, or -1: absent or m = 0).  The block of one (l, m) is
+    // padded to an odd length NB, so that lanes reading different (l, m)
+    // spread over the LDS bank groups.
     const int K1 = h.spec.k_max + 1;
+    const int NY = (L + 1) * (L + 2) / 2;
     g->grad_nb = ((N + 1) * K1) | 1;
-    g->gsrc.assign((size_t)(L + 1) * (L + 1) * g->grad_nb, -1);
+    g->gsrc.assign((size_t)NY * g->grad_nb * 2, -1);
     for (int i = 0; i < P1; ++i) {
-      const int l = h.on_l[i];
-      g->gsrc[(size_t)(l * l + l + h.on_m[i]) * g->grad_nb + h.on_n[i] * K1 + h.on_k[i]] = i;
+      const int l = h.on_l[i], m = h.on_m[i], am = m < 0 ? -m : m;
+      const size_t slot = (size_t)((l * (l + 1)) / 2 + am) * g->grad_nb + h.on_n[i] * K1 + h.on_k[i];
+      if (m >= 0)
+        g->gsrc[2 * slot] = i;
+      else
+        g->gsrc[2 * slot + 1] = (am & 1) ? -2 - i : i;
     }
   } else {
     // planar groups: phi = R_n (Re E, sim Im E), E = u^{|m|}, sim = s sign(m) with
@@ -1839,9 +1846,50 @@ ace_status check_offsets(const int32_t* offsets, int64_t n_env, int64_t n_nbr, h
 
 int64_t grid_for(int64_t n_env) { return std::max<int64_t>(1, std::min<int64_t>(n_env, (int64_t)1 << 30)); }
 
+// The coefficients of a DAG launch in its schedule order: a separate launch.
+ace_status launch_prep(const CoefPrep& c, hipStream_t s) {
+  const int64_t nk = c.mode == CoefPrep::kFold ? c.fold.n : c.mode == CoefPrep::kPlain ? c.plain.n : 0;
+  if (nk == 0) return ACE_OK;
+  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nk + 255) / 256, 1024));
+  if (c.mode == CoefPrep::kFold)
+    hipLaunchKernelGGL(prep_fold_kernel, dim3(pgrid), dim3(256), 0, s, c.fold);
+  else
+    hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, c.plain);
+  ACE_HIP(hipGetLastError());
+  return ACE_OK;
+}
+
+// The preparation of coefficients for a schedule with the given kmap (and
+// kbar when folded) into the workspace.
+CoefPrep coef_prep(const double* coeffs, const Workspace& w, const int32_t* kmap, const int32_t* kbar, int64_t nk,
+                   bool fold) {
+  CoefPrep c{};
+  if (fold) {
+    c.mode = CoefPrep::kFold;
+    c.fold.kmap = kmap;
+    c.fold.kbar = kbar;
+    c.fold.coeffs = coeffs;
+    c.fold.cs = reinterpret_cast<double2*>(w.cs);
+    c.fold.n = nk;
+  } else {
+    c.mode = CoefPrep::kPlain;
+    c.plain.kmap = kmap;
+    c.plain.coeffs = coeffs;
+    c.plain.cs = w.cs;
+    c.plain.n = nk;
+  }
+  return c;
+}
+
+// prep (may be NULL): a DAG launch's coefficient preparation, done on the
+// basis kernel's grid (O(3)) or launched before the planar basis kernel.
 ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offsets, const double* pos, double2* A,
-                        hipStream_t s) {
+                        hipStream_t s, const CoefPrep* prep) {
   if (g->h.spec.group != 0) {
+    if (prep) {
+      const ace_status st = launch_prep(*prep, s);
+      if (st != ACE_OK) return st;
+    }
     BasisArgs a{};
     a.n_env = n_env;
     a.offsets = offsets;
@@ -1876,6 +1924,7 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   a.prim = g->d_basis_prim;
   a.n_prim = (int)g->basis_prim.size();
+  if (prep) a.prep = *prep;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const int chunk = kBasisThreads / (a.l_max + 1);
   const size_t lds = (size_t)g->P1 * 16 + (size_t)chunk * (((a.n_max + 1) + (a.k_max + 1) + 2 * NY) | 1) * 8;
@@ -1888,28 +1937,19 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   return ACE_OK;
 }
 
-ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                         double2* Abar, const Workspace& w, hipStream_t s, bool fold) {
+CoefPrep forest_prep(const ace_graph* g, const double* coeffs, const Workspace& w, bool fold) {
   const ace_graph::Forest& F = g->fo[fold ? 1 : 0];
-  const int64_t nk = (int64_t)F.kmap.size();
-  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nk + 255) / 256, 1024));
-  if (fold) {
-    PrepFoldArgs pa{};
-    pa.kmap = F.d_kmap;
-    pa.kbar = F.d_kbar;
-    pa.coeffs = coeffs;
-    pa.cs = reinterpret_cast<double2*>(w.cs);
-    pa.n = nk;
-    hipLaunchKernelGGL(prep_fold_kernel, dim3(pgrid), dim3(256), 0, s, pa);
-  } else {
-    PrepArgs pa{};
-    pa.kmap = F.d_kmap;
-    pa.coeffs = coeffs;
-    pa.cs = w.cs;
-    pa.n = nk;
-    hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  return coef_prep(coeffs, w, F.d_kmap, F.d_kbar, (int64_t)F.kmap.size(), fold);
+}
+
+// prepped: the coefficients are already in schedule order in the workspace
+ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
+                         double2* Abar, const Workspace& w, hipStream_t s, bool fold, bool prepped) {
+  const ace_graph::Forest& F = g->fo[fold ? 1 : 0];
+  if (!prepped) {
+    const ace_status st = launch_prep(forest_prep(g, coeffs, w, fold), s);
+    if (st != ACE_OK) return st;
   }
-  ACE_HIP(hipGetLastError());
   ForestArgs a{};
   a.n_env = n_env;
   a.A = A;
@@ -1962,30 +2002,20 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   return ACE_OK;
 }
 
+CoefPrep remat_prep(const ace_graph* g, const double* coeffs, const Workspace& w, bool grad, bool fold) {
+  const ace_graph::Remat& R = g->rm[(fold ? 2 : 0) + (grad ? 1 : 0)];
+  return coef_prep(coeffs, w, R.d_kmap, R.d_kbar, (int64_t)R.kmap.size(), fold);
+}
+
 ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                        double2* Abar, const Workspace& w, hipStream_t s, bool fold) {
+                        double2* Abar, const Workspace& w, hipStream_t s, bool fold, bool prepped) {
   const bool grad = Abar != nullptr;
   const int which = (fold ? 2 : 0) + (grad ? 1 : 0);
   const ace_graph::Remat& R = g->rm[which];
-  const int64_t nk = (int64_t)R.kmap.size();
-  const int pgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nk + 255) / 256, 1024));
-  if (fold) {
-    PrepFoldArgs pa{};
-    pa.kmap = R.d_kmap;
-    pa.kbar = R.d_kbar;
-    pa.coeffs = coeffs;
-    pa.cs = reinterpret_cast<double2*>(w.cs);
-    pa.n = nk;
-    hipLaunchKernelGGL(prep_fold_kernel, dim3(pgrid), dim3(256), 0, s, pa);
-  } else {
-    PrepArgs pa{};
-    pa.kmap = R.d_kmap;
-    pa.coeffs = coeffs;
-    pa.cs = w.cs;
-    pa.n = nk;
-    hipLaunchKernelGGL(prep_kernel, dim3(pgrid), dim3(256), 0, s, pa);
+  if (!prepped) {
+    const ace_status st = launch_prep(remat_prep(g, coeffs, w, grad, fold), s);
+    if (st != ACE_OK) return st;
   }
-  ACE_HIP(hipGetLastError());
   RematArgs a{};
   a.n_env = n_env;
   a.A = A;
@@ -2018,14 +2048,31 @@ ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env,
 
 // conj_ok: A satisfies A_{n,l,-m} = (-1)^m conj(A_{n,l,m}) (it comes from
 // the basis kernel), so schedules with folded conjugate pairs may be used.
+// The coefficient preparation launch_dag needs for these arguments (mode
+// kNone for the layered schedule, which reads c directly).
+CoefPrep dag_prep(const ace_graph* g, const double* coeffs, const Workspace& w, bool grad, uint32_t flags,
+                  bool conj_ok) {
+  switch (pick_schedule(g, grad, flags)) {
+    case Sched::Forest:
+      return forest_prep(g, coeffs, w, conj_ok && !(flags & ACE_FLAG_UNFOLDED) && use_folded_forest(g, grad));
+    case Sched::Remat:
+      return remat_prep(g, coeffs, w, grad, conj_ok && !(flags & ACE_FLAG_UNFOLDED));
+    default:
+      return CoefPrep{};
+  }
+}
+
+// prepped: dag_prep's preparation for the same arguments has been done
 ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                      double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags, bool conj_ok) {
+                      double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags, bool conj_ok,
+                      bool prepped = false) {
   switch (pick_schedule(g, Abar != nullptr, flags)) {
     case Sched::Forest:
       return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s,
-                           conj_ok && !(flags & ACE_FLAG_UNFOLDED) && use_folded_forest(g, Abar != nullptr));
+                           conj_ok && !(flags & ACE_FLAG_UNFOLDED) && use_folded_forest(g, Abar != nullptr),
+                           prepped);
     case Sched::Remat:
-      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s, conj_ok && !(flags & ACE_FLAG_UNFOLDED));
+      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s, conj_ok && !(flags & ACE_FLAG_UNFOLDED), prepped);
     default:
       break;
   }
@@ -2131,7 +2178,7 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.Abar = Abar;
   a.grad = grad;
   a.onep_index = g->d_onep_index;
-  a.gsrc = g->d_gsrc;
+  a.gsrc = reinterpret_cast<const int2*>(g->d_gsrc);
   a.ycoef = g->d_ycoef;
   a.P1 = g->P1;
   a.n_max = g->h.spec.n_max;
@@ -2141,7 +2188,7 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.k_max = g->h.spec.k_max;
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
-  const size_t lds = g->gsrc.size() * sizeof(double2) + (size_t)((3 * NY + 1) & ~1) * 8 +
+  const size_t lds = (g->gsrc.size() / 2) * sizeof(double2) + (size_t)((3 * NY + 1) & ~1) * 8 +
                      (size_t)kGradChunk * (grad_nbr_doubles(a.n_max) + 3) * 8;
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the gradient kernel");
   a.nb = g->grad_nb;
@@ -2284,7 +2331,7 @@ ace_status ace_basis(const ace_graph* g, int64_t n_env, const int32_t* offsets, 
   if (n_env < 0) return fail(ACE_ERR_INVALID_ARG, "n_env must be >= 0");
   if (n_env == 0) return ACE_OK;
   if (!offsets || !pos || !A) return fail(ACE_ERR_INVALID_ARG, "offsets, pos and A must be non-NULL");
-  return launch_basis(g, n_env, offsets, pos, reinterpret_cast<double2*>(A), (hipStream_t)stream);
+  return launch_basis(g, n_env, offsets, pos, reinterpret_cast<double2*>(A), (hipStream_t)stream, nullptr);
 }
 
 ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env, const double* A, double* phi,
@@ -2314,10 +2361,16 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
     if (st != ACE_OK) return st;
   }
   const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
-  st = launch_basis(g, n_env, offsets, pos, w.A, s);
+  if (flags & ACE_FLAG_NAIVE) {
+    st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr);
+    if (st != ACE_OK) return st;
+    return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
+  }
+  // the DAG launch's coefficients are prepared on the basis kernel's grid
+  const CoefPrep prep = dag_prep(g, coeffs, w, false, flags, true);
+  st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep);
   if (st != ACE_OK) return st;
-  if (flags & ACE_FLAG_NAIVE) return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
-  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags, true);
+  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags, true, true);
 }
 
 ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
@@ -2334,12 +2387,17 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
     if (st != ACE_OK) return st;
   }
   const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
-  st = launch_basis(g, n_env, offsets, pos, w.A, s);
-  if (st != ACE_OK) return st;
-  if (flags & ACE_FLAG_NAIVE)
+  if (flags & ACE_FLAG_NAIVE) {
+    st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr);
+    if (st != ACE_OK) return st;
     st = launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, s);
-  else
-    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags, true);
+  } else {
+    // the DAG launch's coefficients are prepared on the basis kernel's grid
+    const CoefPrep prep = dag_prep(g, coeffs, w, true, flags, true);
+    st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep);
+    if (st != ACE_OK) return st;
+    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags, true, true);
+  }
   if (st != ACE_OK) return st;
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
 }

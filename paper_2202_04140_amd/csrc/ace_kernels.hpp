@@ -23,6 +23,30 @@ struct OnepInfo {
   int16_t neg;    // O(3), m > 0: index of the (n, l, -m, k) function; else -1
 };
 
+struct PrepFoldArgs {
+  const int32_t* kmap;   // k >= 0: c_k;  -1: 0;  k <= -2: doubled c_{-2-k}
+  const int32_t* kbar;   // conjugate partner of k, or -1 if k is self-conjugate
+  const double* coeffs;  // [|K|]
+  double2* cs;           // output (Re weight, Im weight)
+  int64_t n;
+};
+
+struct PrepArgs {
+  const int32_t* kmap;   // k >= 0: c_k;  -1: 0;  k <= -2: 2 c_{-2-k}
+  const double* coeffs;  // [|K|]
+  double* cs;            // output
+  int64_t n;
+};
+
+// The coefficient preparation of one DAG launch, done by another kernel
+// of the same step (the basis kernel): none, plain or folded.
+struct CoefPrep {
+  enum { kNone = 0, kPlain = 1, kFold = 2 };
+  int mode;
+  PrepArgs plain;
+  PrepFoldArgs fold;
+};
+
 struct BasisArgs {
   int64_t n_env;
   const int32_t* offsets;
@@ -37,6 +61,7 @@ struct BasisArgs {
   int pos_stride;        // doubles per position: 3, or 4 with a feature
   const int16_t* prim;   // O(3): [n_prim] indices of the functions with m >= 0
   int n_prim;
+  CoefPrep prep;         // O(3): the next DAG launch's coefficients, prepared on this grid
 };
 
 // Planar one-particle functions (torus, SO(2)): phi_i = R_n(r) e^{i s m theta}
@@ -82,7 +107,8 @@ struct GradArgs {
   const double2* Abar;       // [n_env][P1]
   double* grad;              // [n_nbr][3]
   const int16_t* onep_index; // [(n_max+1)][(l_max+1)][(2 l_max+1)] -> i or -1
-  const int32_t* gsrc;       // [(l_max+1)^2][nb]: (n, l, m, k) at (l^2+l+m) nb + n (k_max+1) + k -> i or -1
+  const int2* gsrc;          // [(l_max+1)(l_max+2)/2][nb]: at (l(l+1)/2+m) nb + n (k_max+1) + k, m >= 0, the
+                             // functions (n, l, +-m, k): (i of +m or -1, i of -m as i (m even) or -2-i (m odd), or -1)
   const double* ycoef;
   int P1, n_max, l_max;
   double r_cut;
@@ -154,21 +180,6 @@ struct RematArgs {
   int cs_leaf, cs_ent;
   int P1, n_slices, n_pairs;
   int4 hot;                  // one-particle slots whose adjoints are summed in registers (P1 = unused)
-};
-
-struct PrepFoldArgs {
-  const int32_t* kmap;   // k >= 0: c_k;  -1: 0;  k <= -2: doubled c_{-2-k}
-  const int32_t* kbar;   // conjugate partner of k, or -1 if k is self-conjugate
-  const double* coeffs;  // [|K|]
-  double2* cs;           // output (Re weight, Im weight)
-  int64_t n;
-};
-
-struct PrepArgs {
-  const int32_t* kmap;   // k >= 0: c_k;  -1: 0;  k <= -2: 2 c_{-2-k}
-  const double* coeffs;  // [|K|]
-  double* cs;            // output
-  int64_t n;
 };
 
 }  // namespace ace

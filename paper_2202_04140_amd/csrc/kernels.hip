@@ -72,6 +72,45 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
 }
 
 // ---------------------------------------------------------------------------
+// coefficients in schedule order, once per call (the DAG launches read them
+// at the positions of their schedules)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void prep_range(const PrepArgs& p, int64_t i0, int64_t stride) {
+  for (int64_t i = i0; i < p.n; i += stride) {
+    const int k = p.kmap[i];
+    p.cs[i] = k >= 0 ? p.coeffs[k] : (k == -1 ? 0.0 : 2.0 * p.coeffs[-2 - k]);
+  }
+}
+
+// Folded coefficients of a conjugate pair {k, kbar} (Re and Im weights):
+// (c_k + c_kbar, c_k - c_kbar); a self-conjugate tuple gives (c_k, c_k).
+// kmap: k >= 0, -1 (padding: 0), or -2-k (doubled diagonal); kbar < 0: self.
+__device__ __forceinline__ void prep_fold_range(const PrepFoldArgs& p, int64_t i0, int64_t stride) {
+  for (int64_t i = i0; i < p.n; i += stride) {
+    const int k = p.kmap[i], kb = p.kbar[i];
+    double2 r = make_double2(0.0, 0.0);
+    if (k != -1) {
+      const int q = k >= 0 ? k : -2 - k;
+      const double sc = k >= 0 ? 1.0 : 2.0;
+      const double a = p.coeffs[q];
+      const double b = kb >= 0 ? p.coeffs[kb] : a;
+      r = kb >= 0 ? make_double2(sc * (a + b), sc * (a - b)) : make_double2(sc * a, sc * a);
+    }
+    p.cs[i] = r;
+  }
+}
+
+// the preparation a DAG launch needs, spread over every thread of a grid
+__device__ __forceinline__ void prep_on_grid(const CoefPrep& c) {
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (c.mode == CoefPrep::kFold)
+    prep_fold_range(c.fold, i0, stride);
+  else if (c.mode == CoefPrep::kPlain)
+    prep_range(c.plain, i0, stride);
+}
+
+// ---------------------------------------------------------------------------
 // one-particle basis
 // ---------------------------------------------------------------------------
 constexpr int kBasisBlock = 256;
@@ -101,6 +140,9 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
   const double* cA = p.ycoef;
   const double* cB = p.ycoef + NY;
   const double* cS = p.ycoef + 2 * NY;
+  // the coefficient preparation of the DAG launch that follows (independent
+  // of this kernel's own work; one launch fewer per step)
+  prep_on_grid(p.prep);
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
@@ -361,9 +403,11 @@ template __global__ void naive_kernel<8>(NaiveArgs);
 // where Q follows the same recurrence as q with the constant term scaled
 // by rho, differentiated in z and rho alongside (no pole singularity).
 //
-// One wave (one block) per environment, its adjoint Abar in LDS in (l, m, n,
-// k) order with zeros for absent functions, so the inner loop over n reads
-// two affine addresses; the block of one (l, m) has an odd length nb.
+// One wave (one block) per environment.  Its adjoint is staged in LDS per
+// (l, m >= 0) with the +m and -m functions already combined into the two
+// real weights the gradient needs (see below), in (l, m, n, k) order with
+// zeros for absent functions, so the inner loop over n reads one affine
+// address; the block of one (l, m) has an odd length nb.
 //
 // Work is balanced over the lanes: the neighbours are taken in chunks of
 // kGradChunk; the (neighbour, m >= 0, l) units of a chunk, neighbour-major
@@ -386,7 +430,7 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
   const int K1 = FEAT ? p.k_max + 1 : 1;
   const int NY = (L + 1) * (L + 2) / 2;        // (l, m >= 0) units per neighbour
   const int NB = p.nb;                         // entries per (l, m)
-  const int ND = (L + 1) * (L + 1) * NB;
+  const int ND = NY * NB;
   const int lane = threadIdx.x;
   double2* Ab = lds;                                           // [ND]
   const int NR = grad_nbr_doubles(N);
@@ -403,18 +447,29 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
     if (J <= 0) continue;   // block-uniform
     __syncthreads();
     const double2* Be = p.Abar + e * p.P1;
-    // four entries per lane at a time: the table loads, then the Abar loads,
-    // are all in flight together
+    // The +m and -m terms of one (n, l, m, k) (Y_l^{-m} = (-1)^m conj(Y_l^m),
+    // likewise its gradient; m = 0 counted once) sum to Br Re(g) + Bi Im(g)
+    // for g = Y or grad Y with Br = abar.re(+m) + s abar.re(-m),
+    // Bi = s abar.im(-m) - abar.im(+m), s = (-1)^m: the staged entry is
+    // (Br, Bi).  Four entries per lane at a time: the table loads, then the
+    // Abar loads, are all in flight together.
     for (int d0 = lane; d0 < ND; d0 += 4 * 64) {
-      int src[4];
+      int2 src[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) src[r] = d0 + 64 * r < ND ? p.gsrc[d0 + 64 * r] : -1;
-      double2 v[4];
+      for (int r = 0; r < 4; ++r) src[r] = d0 + 64 * r < ND ? p.gsrc[d0 + 64 * r] : make_int2(-1, -1);
+      double2 vp[4], vm[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = src[r] >= 0 ? Be[src[r]] : make_double2(0.0, 0.0);
+      for (int r = 0; r < 4; ++r) {
+        const int im = src[r].y >= 0 ? src[r].y : -2 - src[r].y;
+        vp[r] = src[r].x >= 0 ? Be[src[r].x] : make_double2(0.0, 0.0);
+        vm[r] = src[r].y != -1 ? Be[im] : make_double2(0.0, 0.0);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (d0 + 64 * r < ND) Ab[d0 + 64 * r] = v[r];
+        if (d0 + 64 * r < ND) {
+          const double sg = src[r].y >= 0 ? 1.0 : -1.0;   // vm is 0 where there is no -m
+          Ab[d0 + 64 * r] = make_double2(fma(sg, vm[r].x, vp[r].x), fma(sg, vm[r].y, -vp[r].y));
+        }
     }
     for (int c0 = 0; c0 < J; c0 += kGradChunk) {
       const int nc = min(kGradChunk, J - c0);
@@ -506,11 +561,9 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
         for (int ll = m + 1; ll <= l; ++ll) step_l(ll);
         double gx = 0.0, gy = 0.0, gz = 0.0;
         for (int u = u0; u < u1; ++u) {
-          // B0 = sum_{n,k} Abar_{n l (+/-m) k} T_n T_k, B1 = the same with T_n'
-          const double2* bp = Ab + (l * l + l + m) * NB;
-          const double2* bm = Ab + (l * l + l - m) * NB;
-          double b0pr = 0.0, b0pi = 0.0, b1pr = 0.0, b1pi = 0.0;   // +m
-          double b0mr = 0.0, b0mi = 0.0, b1mr = 0.0, b1mi = 0.0;   // -m
+          // (Br, Bi) = sum_{n,k} (staged entry) T_n T_k, (B1r, B1i) the same with T_n'
+          const double2* bc = Ab + ((l * (l + 1)) / 2 + m) * NB;
+          double Br = 0.0, Bi = 0.0, B1r = 0.0, B1i = 0.0;
           const double2* tt = reinterpret_cast<const double2*>(nd + 8);   // (T_n, T_n')
 #pragma unroll 2
           for (int n = 0; n <= N; ++n) {
@@ -529,28 +582,18 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
                 }
               }
               const double w = T * Tk, dw = dT * Tk;
-              const double2 ap = bp[n * K1 + k], am = bm[n * K1 + k];
-              b0pr = fma(ap.x, w, b0pr);
-              b0pi = fma(ap.y, w, b0pi);
-              b1pr = fma(ap.x, dw, b1pr);
-              b1pi = fma(ap.y, dw, b1pi);
-              b0mr = fma(am.x, w, b0mr);
-              b0mi = fma(am.y, w, b0mi);
-              b1mr = fma(am.x, dw, b1mr);
-              b1mi = fma(am.y, dw, b1mi);
+              const double2 cc = bc[n * K1 + k];
+              Br = fma(cc.x, w, Br);
+              Bi = fma(cc.y, w, Bi);
+              B1r = fma(cc.x, dw, B1r);
+              B1i = fma(cc.y, dw, B1i);
             }
           }
-          // The +m and -m terms (Y_l^{-m} = (-1)^m conj(Y_l^m), likewise its
-          // gradient; m = 0 counted once) sum to Br Re(g) + Bi Im(g) for g = Y
-          // or grad Y, with Br = b.re(+m) + s b.re(-m), Bi = s b.im(-m) - b.im(+m),
-          // s = (-1)^m (0 for m = 0).  With S = p Q, p = (x + i y)^m,
-          // q = (x + i y)^(m-1) at the unit vector u:
+          // With S = p Q, p = (x + i y)^m, q = (x + i y)^(m-1) at the unit
+          // vector u:
           //   grad S = 2 Qp p u + m Q q (1, i, 0) + Qz p e_z,
           //   grad Y = (grad S - l S u) / |r|,  d/dr of the radial part: T_n' dcos/dr,
           // so everything pairs (Br, Bi) with p (P) or q.
-          const double sgn = m == 0 ? 0.0 : ((m & 1) ? -1.0 : 1.0);
-          const double Br = fma(sgn, b0mr, b0pr), Bi = fma(sgn, b0mi, -b0pi);
-          const double B1r = fma(sgn, b1mr, b1pr), B1i = fma(sgn, b1mi, -b1pi);
           const double P = fma(Br, pr, Bi * pi);
           const double P1 = fma(B1r, pr, B1i * pi);
           const double cu = fma(dcdr * Q, P1, inv * P * (2.0 * Qp - (double)l * Q));
@@ -813,10 +856,7 @@ __global__ __launch_bounds__(256) void planar_grad_kernel(GradArgs p) {
 // Coefficients in schedule order, once per call.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void prep_kernel(PrepArgs p) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int k = p.kmap[i];
-    p.cs[i] = k >= 0 ? p.coeffs[k] : (k == -1 ? 0.0 : 2.0 * p.coeffs[-2 - k]);
-  }
+  prep_range(p, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1455,22 +1495,8 @@ template __global__ void remat_kernel<true, false>(RematArgs);
 template __global__ void remat_kernel<false, true>(RematArgs);
 template __global__ void remat_kernel<true, true>(RematArgs);
 
-// Folded coefficients of a conjugate pair {k, kbar} (Re and Im weights):
-// (c_k + c_kbar, c_k - c_kbar); a self-conjugate tuple gives (c_k, c_k).
-// kmap: k >= 0, -1 (padding: 0), or -2-k (doubled diagonal); kbar < 0: self.
 __global__ __launch_bounds__(256) void prep_fold_kernel(PrepFoldArgs p) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int k = p.kmap[i], kb = p.kbar[i];
-    double2 r = make_double2(0.0, 0.0);
-    if (k != -1) {
-      const int q = k >= 0 ? k : -2 - k;
-      const double sc = k >= 0 ? 1.0 : 2.0;
-      const double a = p.coeffs[q];
-      const double b = kb >= 0 ? p.coeffs[kb] : a;
-      r = kb >= 0 ? make_double2(sc * (a + b), sc * (a - b)) : make_double2(sc * a, sc * a);
-    }
-    p.cs[i] = r;
-  }
+  prep_fold_range(p, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 template __global__ void forest_kernel<false, false, false, false, 1>(ForestArgs);
