@@ -207,7 +207,7 @@ def main():
                     help="after timing, copy a buffer of this many MiB once (scale for HBM counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="reduce two rocprofv3 counter databases (FETCH_SIZE, WRITE_SIZE runs made with "
-                         "--calibrate-copy) to profiles/forest_kernel_traffic.json and exit")
+                         "--calibrate-copy) to profiles/dag_kernel_traffic_w<workload>.json and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         out = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy or 512, args.workload,
