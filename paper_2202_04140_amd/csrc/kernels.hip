@@ -122,7 +122,9 @@ constexpr int kBasisBlock = 256;
 // q_l^m = A_lm z q_{l-1}^m - B_lm q_{l-2}^m; normalisation and
 // Condon-Shortley phase are folded into the coefficients on the host; the
 // form has no division by sin(theta)).  Then one lane per one-particle
-// index i accumulates R_{n_i} Y_{l_i}^{m_i} over the chunk.
+// function i with m_i >= 0 accumulates R_{n_i} Y_{l_i}^{m_i} over the chunk
+// and also adds the sums, with the signs of Y_l^{-m} = (-1)^m conj(Y_l^m),
+// to its -m partner.
 // FEAT: a feature factor T_k(mu) per function (Sec. 5.4); without it the
 // radial factor is T_n alone.
 template <bool FEAT>
