@@ -192,6 +192,28 @@ def test_eval_parity(device, wid, n_env, naive):
     assert rel(phi, ref) <= TOL_PHI
 
 
+@pytest.mark.parametrize("unfolded", [False, True])
+@pytest.mark.parametrize("mode", ["dag", "remat", "layered"])
+@pytest.mark.parametrize("wid,n_env", [(3, 40), (4, 10)])
+def test_forward_only_every_schedule(device, wid, n_env, mode, unfolded):
+    """ace_eval (no reverse pass) in each schedule, conjugate pairs folded or not.
+    Its coefficients are gathered on the basis kernel's grid for the forward-only
+    schedule (another gather map than the one with the reverse pass); phi matches
+    the oracle and the phi of ace_eval_grad."""
+    import paper_2202_04140_amd as ace
+    print(f"forward only wid={wid} n_env={n_env} mode={mode} unfolded={unfolded}", flush=True)
+    kw, sched = MODES[mode]
+    G = graph(wid, device, sched)
+    g, K, c = oracle_basis(wid)
+    off, pos = problem(wid, n_env)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi = cplx(ace.eval(G, tc, toff, tpos, unfolded=unfolded, **kw))
+    phi_g, _ = ace.eval_grad(G, tc, toff, tpos, unfolded=unfolded, **kw)
+    ref = oc.eval_naive(g.labels, K, c, off, pos, wl.WORKLOADS[wid].r_cut)
+    assert rel(phi, ref) <= TOL_PHI
+    assert rel(phi, cplx(phi_g)) <= TOL_PHI
+
+
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("wid,n_env", [(1, None), (3, 64), (4, 12)])
 def test_eval_grad_parity(device, wid, n_env, mode):
