@@ -1881,6 +1881,19 @@ CoefPrep coef_prep(const double* coeffs, const Workspace& w, const int32_t* kmap
   return c;
 }
 
+// Whether two preparations write the same coefficients (same schedule map,
+// same coefficients, same output).
+bool same_prep(const CoefPrep& a, const CoefPrep& b) {
+  if (a.mode != b.mode) return false;
+  if (a.mode == CoefPrep::kFold)
+    return a.fold.kmap == b.fold.kmap && a.fold.kbar == b.fold.kbar && a.fold.coeffs == b.fold.coeffs &&
+           a.fold.cs == b.fold.cs && a.fold.n == b.fold.n;
+  if (a.mode == CoefPrep::kPlain)
+    return a.plain.kmap == b.plain.kmap && a.plain.coeffs == b.plain.coeffs && a.plain.cs == b.plain.cs &&
+           a.plain.n == b.plain.n;
+  return true;
+}
+
 // prep (may be NULL): a DAG launch's coefficient preparation, done on the
 // basis kernel's grid (O(3)) or launched before the planar basis kernel.
 ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offsets, const double* pos, double2* A,
@@ -1942,12 +1955,14 @@ CoefPrep forest_prep(const ace_graph* g, const double* coeffs, const Workspace& 
   return coef_prep(coeffs, w, F.d_kmap, F.d_kbar, (int64_t)F.kmap.size(), fold);
 }
 
-// prepped: the coefficients are already in schedule order in the workspace
+// done (may be NULL): a preparation already on the stream; this launch
+// prepares its coefficients itself unless that is the one it needs
 ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                         double2* Abar, const Workspace& w, hipStream_t s, bool fold, bool prepped) {
+                         double2* Abar, const Workspace& w, hipStream_t s, bool fold, const CoefPrep* done) {
   const ace_graph::Forest& F = g->fo[fold ? 1 : 0];
-  if (!prepped) {
-    const ace_status st = launch_prep(forest_prep(g, coeffs, w, fold), s);
+  const CoefPrep need = forest_prep(g, coeffs, w, fold);
+  if (!done || !same_prep(*done, need)) {
+    const ace_status st = launch_prep(need, s);
     if (st != ACE_OK) return st;
   }
   ForestArgs a{};
@@ -2008,12 +2023,13 @@ CoefPrep remat_prep(const ace_graph* g, const double* coeffs, const Workspace& w
 }
 
 ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                        double2* Abar, const Workspace& w, hipStream_t s, bool fold, bool prepped) {
+                        double2* Abar, const Workspace& w, hipStream_t s, bool fold, const CoefPrep* done) {
   const bool grad = Abar != nullptr;
   const int which = (fold ? 2 : 0) + (grad ? 1 : 0);
   const ace_graph::Remat& R = g->rm[which];
-  if (!prepped) {
-    const ace_status st = launch_prep(remat_prep(g, coeffs, w, grad, fold), s);
+  const CoefPrep need = remat_prep(g, coeffs, w, grad, fold);
+  if (!done || !same_prep(*done, need)) {
+    const ace_status st = launch_prep(need, s);
     if (st != ACE_OK) return st;
   }
   RematArgs a{};
@@ -2062,17 +2078,17 @@ CoefPrep dag_prep(const ace_graph* g, const double* coeffs, const Workspace& w, 
   }
 }
 
-// prepped: dag_prep's preparation for the same arguments has been done
+// done (may be NULL): a coefficient preparation already on the stream
+// (dag_prep's for the same arguments, normally)
 ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
                       double2* Abar, const Workspace& w, hipStream_t s, uint32_t flags, bool conj_ok,
-                      bool prepped = false) {
+                      const CoefPrep* done = nullptr) {
   switch (pick_schedule(g, Abar != nullptr, flags)) {
     case Sched::Forest:
       return launch_forest(g, coeffs, n_env, A, phi, Abar, w, s,
-                           conj_ok && !(flags & ACE_FLAG_UNFOLDED) && use_folded_forest(g, Abar != nullptr),
-                           prepped);
+                           conj_ok && !(flags & ACE_FLAG_UNFOLDED) && use_folded_forest(g, Abar != nullptr), done);
     case Sched::Remat:
-      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s, conj_ok && !(flags & ACE_FLAG_UNFOLDED), prepped);
+      return launch_remat(g, coeffs, n_env, A, phi, Abar, w, s, conj_ok && !(flags & ACE_FLAG_UNFOLDED), done);
     default:
       break;
   }
@@ -2370,7 +2386,7 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
   const CoefPrep prep = dag_prep(g, coeffs, w, false, flags, true);
   st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep);
   if (st != ACE_OK) return st;
-  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags, true, true);
+  return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags, true, &prep);
 }
 
 ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
@@ -2396,7 +2412,7 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
     const CoefPrep prep = dag_prep(g, coeffs, w, true, flags, true);
     st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep);
     if (st != ACE_OK) return st;
-    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags, true, true);
+    st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags, true, &prep);
   }
   if (st != ACE_OK) return st;
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
