@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput of phi + forces by recursive DAG contraction on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 5]
 
 One step = one pass of the whole path over the batch (one-particle basis,
 DAG forward with the coefficient contraction, reverse pass, dA/dr chain)
@@ -87,12 +87,14 @@ def profiled_traffic(workload: int):
 # ---------------------------------------------------------------------------
 # CPU baseline (oracle) -- runs before any GPU initialisation
 # ---------------------------------------------------------------------------
+# Worker processes at most: the host share of one GPU on the machines this
+# runs on is 16 cores, whatever the affinity mask shows.
+MAX_WORKERS = 16
 _W = {}
 
 
-def _worker_init(wid):
-    from threadpoolctl import threadpool_limits
-    threadpool_limits(1)
+def _oracle_setup(wid):
+    """The oracle's own listing of K and the coefficients drawn from it."""
     from oracle.indexsets import all_invariant_tuples, group_o3, group_so2, group_torus
     w = wl.WORKLOADS[wid]
     if w.group == 0 and w.k_max > 0:
@@ -109,6 +111,11 @@ def _worker_init(wid):
     _W.update(w=w, g=g, K=K, c=c)
 
 
+def _worker_init():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
 def _worker_run(args):
     off, pos = args
     from oracle.contraction import grad_naive
@@ -116,25 +123,48 @@ def _worker_run(args):
     return grad_naive(g.labels, K, c, off, pos, w.r_cut)
 
 
-def cpu_baseline(wid: int, off: np.ndarray, pos: np.ndarray, n_sample: int, chunk: int = 32):
+def default_cpu_sample(wid: int) -> int:
+    """Whole batch for the small workloads, a 512-environment subset (smallest
+    and largest neighbour count included) for the 32768- and 8192-environment ones."""
+    return 512 if wl.WORKLOADS[wid].n_env > 4096 else wl.WORKLOADS[wid].n_env
+
+
+def cpu_baseline(wid: int, off: np.ndarray, pos: np.ndarray, n_sample: int, chunk: int = 8,
+                 one_core_envs: int = 4):
+    """The oracle on a seeded subset of the batch, on every core of the
+    affinity mask (at most MAX_WORKERS single-threaded processes), and on a
+    few environments of it on one core."""
     import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    t0 = time.perf_counter()
+    _oracle_setup(wid)                      # inherited by the forked workers
+    t_setup = time.perf_counter() - t0
     envs = wl.subset(off, n_sample)
-    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    affinity = len(os.sched_getaffinity(0))
+    cores = max(1, min(affinity, MAX_WORKERS))
     jobs = [wl.gather(off, pos, envs[i:i + chunk]) for i in range(0, len(envs), chunk)]
     ctx = mp.get_context("fork")
-    with ctx.Pool(cores, initializer=_worker_init, initargs=(wid,)) as pool:
-        pool.map(_worker_run, jobs[:cores], chunksize=1)   # warm (K listing done)
+    with ctx.Pool(cores, initializer=_worker_init) as pool:
         t0 = time.perf_counter()
         res = pool.map(_worker_run, jobs, chunksize=1)
         dt = time.perf_counter() - t0
     phi = np.concatenate([r[0] for r in res])
     grad = np.concatenate([r[1] for r in res])
+    # one core: the first few environments of the subset in this process
+    n1 = min(one_core_envs, len(envs))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        _worker_run(wl.gather(off, pos, envs[:n1]))
+        dt1 = time.perf_counter() - t0
     cpu = open("/proc/cpuinfo").read()
     model = next((ln.split(":", 1)[1].strip() for ln in cpu.splitlines() if ln.startswith("model name")), "?")
     return envs, phi, grad, dict(value=len(envs) / dt, unit="environments/s", cores=cores, kind="oracle",
-                                 sample=f"{len(envs)} environments of the same workload (smallest and largest "
-                                        f"neighbour count included), phi + forces, {dt:.1f} s wall on {cores} "
-                                        f"single-threaded processes ({model})")
+                                 sample=f"{len(envs)} environments of the same workload (seeded subset with the "
+                                        f"smallest and largest neighbour count), phi + forces, {dt:.1f} s wall on "
+                                        f"{cores} single-threaded processes ({model}, {affinity} cores in the "
+                                        f"affinity mask); K listed once beforehand in {t_setup:.1f} s",
+                                 one_core={"value": n1 / dt1, "unit": "environments/s", "envs": n1,
+                                           "seconds": dt1})
 
 
 # ---------------------------------------------------------------------------
@@ -150,6 +180,25 @@ def _per_dispatch(db_path: str, counter: str):
         k = (d, name)
         acc[k] = acc.get(k, 0.0) + float(v)
     return acc
+
+
+def pmc_table(dbs) -> dict:
+    """{kernel: {counter: mean value per dispatch, "dispatches": n}} over rocprofv3 counter databases."""
+    import sqlite3
+    out = {}
+    for db in dbs:
+        cur = sqlite3.connect(db).cursor()
+        rows = cur.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
+        acc = {}
+        for d, name, cname, v in rows:
+            k = (name, cname)
+            acc.setdefault(k, {}).setdefault(d, 0.0)
+            acc[k][d] += float(v)
+        for (name, cname), per in acc.items():
+            e = out.setdefault(name, {})
+            e[cname] = sum(per.values()) / len(per)
+            e["dispatches"] = max(e.get("dispatches", 0), len(per))
+    return out
 
 
 def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, out_path: str) -> dict:
@@ -185,13 +234,91 @@ def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, ou
 
 
 # ---------------------------------------------------------------------------
+def per_env_errors(phi, phi_ref, grad, grad_ref, offsets) -> dict:
+    """Largest per-environment norm-wise relative errors: |phi_e - ref_e| / |ref_e|
+    over the environments whose |ref_e| is at least 1e-6 of the RMS (the others
+    are counted as flagged), and ||g_e - ref_e|| / ||ref_e|| over each
+    environment's gradient rows."""
+    phi, phi_ref = np.asarray(phi), np.asarray(phi_ref)
+    mag = np.abs(phi_ref)
+    rms = float(np.sqrt(np.mean(mag ** 2))) if len(mag) else 0.0
+    ok = mag >= 1e-6 * rms
+    e_phi = np.abs(phi - phi_ref)[ok] / mag[ok]
+    off = np.asarray(offsets, dtype=np.int64)
+    d2 = np.add.reduceat(np.sum((grad - grad_ref) ** 2, axis=1), off[:-1]) if len(grad) else np.zeros(0)
+    r2 = np.add.reduceat(np.sum(grad_ref ** 2, axis=1), off[:-1]) if len(grad) else np.zeros(0)
+    has = (np.diff(off) > 0) & (r2 > 0)
+    e_g = np.sqrt(d2[has] / r2[has])
+    return dict(phi_max=float(e_phi.max()) if len(e_phi) else 0.0, phi_flagged=int((~ok).sum()),
+                grad_max=float(e_g.max()) if len(e_g) else 0.0)
+
+
+def dag_kernel_ms(ace, torch, G, tc, A, timed, steps, warmup) -> float:
+    """The dominant kernel alone: the fused forward + reverse DAG launch
+    (ace_contract on the basis output, conjugate pairs folded as in
+    ace_eval_grad), timed with events on the stream it is launched on."""
+    dev = A.device
+    E = A.shape[0]
+    phi = torch.empty((E, 2), dtype=torch.float64, device=dev)
+    Abar = torch.empty_like(A)
+    ws = G.workspace(E, dev)
+    lib = ace.lib()
+    stream = torch.cuda.current_stream(dev)
+
+    def launch():
+        st = lib.ace_contract(G.handle, tc.data_ptr(), E, A.data_ptr(), phi.data_ptr(), Abar.data_ptr(),
+                              ws.data_ptr(), ws.numel(), ace.FLAG_CONJ_SYMMETRIC, ace._stream(dev))
+        if st != 0:
+            raise RuntimeError(lib.ace_last_error().decode())
+
+    with torch.cuda.stream(stream):
+        ms, _ = timed(launch, steps, warmup)
+    return ms
+
+
+def small_workload_figures(ace, torch, dev, timed, graphed, args) -> dict:
+    """phi + forces on the 4096-environment nu <= 4 workload, beside the headline."""
+    w = wl.WORKLOADS[3]
+    off, pos = wl.batch(w)
+    E = len(off) - 1
+    G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
+    tc = torch.from_numpy(wl.coefficients(w, G.k_degrees())).to(dev)
+    toff = torch.from_numpy(off).to(dev)
+    tpos = torch.from_numpy(pos).to(dev)
+    phi = torch.empty((E, 2), dtype=torch.float64, device=dev)
+    grad = torch.empty((len(pos), 3), dtype=torch.float64, device=dev)
+    A = ace.basis(G, toff, tpos)
+    if not args.no_tune:
+        from paper_2202_04140_amd import autotune
+        autotune.tune(G, tc, A, use_cache=not args.retune)
+    ms, _ = timed(graphed(lambda: ace.eval_grad(G, tc, toff, tpos, out=(phi, grad))), 20, 5)
+    ms_k = dag_kernel_ms(ace, torch, G, tc, A, timed, 20, 5)
+    fl = dag_flops_per_env(G.stats())["total"]
+    return {"workload": f"{w.name}: {E} environments, {len(pos)} neighbour vectors, O(3), nu<={w.nu_max}, "
+                        f"total degree<={w.degree_max}, n<={w.n_max}, l<={w.l_max}",
+            "value": E / (ms * 1e-3), "ms_per_step": ms, "schedule_kind": G.schedule_kind(),
+            "kernel_ms": ms_k, "frac": fl * E / (ms_k * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--workload", type=int, default=5,
+                    help="workload id (default 5: 8192 environments, nu<=6, D<=16, the largest basis)")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="environments of the oracle's CPU baseline and parity sample "
+                         "(default: the whole batch up to 4096 environments, else 512)")
+    ap.add_argument("--naive-steps", type=int, default=3,
+                    help="timed steps of the naive baseline when one of its steps takes over 50 ms")
+    ap.add_argument("--no-naive", action="store_true",
+                    help="skip the naive baseline (for profiling runs)")
+    ap.add_argument("--pmc-table", nargs="+", metavar="DB",
+                    help="print the mean per dispatch of every counter in these rocprofv3 databases, "
+                         "per kernel, as JSON, and exit")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 4096-environment phi+forces figures reported beside a larger workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--algorithm", type=int, default=1, choices=[1, 2],
                     help="insertion heuristic of the DAG (Algorithm 1 or 2)")
@@ -209,6 +336,9 @@ def main():
                     help="reduce two rocprofv3 counter databases (FETCH_SIZE, WRITE_SIZE runs made with "
                          "--calibrate-copy) to profiles/dag_kernel_traffic_w<workload>.json and exit")
     args = ap.parse_args()
+    if args.pmc_table:
+        print(json.dumps(pmc_table(args.pmc_table), indent=1))
+        return
     if args.pmc_summary:
         out = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy or 512, args.workload,
                             traffic_path(args.workload))
@@ -227,6 +357,8 @@ def main():
     cpu = None
     if args.degree_p != "1":
         args.no_cpu_baseline = True   # the oracle baseline lists the total-degree set
+    if args.cpu_sample is None:
+        args.cpu_sample = default_cpu_sample(args.workload)
     if not args.no_cpu_baseline:
         print(f"[bench] oracle CPU baseline on a {args.cpu_sample}-environment sample ...", file=sys.stderr,
               flush=True)
@@ -320,27 +452,21 @@ def main():
     if not args.eager:
         dist = distribution(graphed(step_dag), max(args.steps, 10) if ms_dag < 20 else args.steps, 2)
     phi_dag, grad_dag = phi.clone(), grad.clone()
-    ms_naive_eager, _ = timed(step_naive, args.steps, args.warmup)
-    ms_naive = ms_naive_eager if args.eager else timed(graphed(step_naive), args.steps, args.warmup)[0]
-    print(f"[bench] naive phi+forces: {ms_naive:.3f} ms/step", file=sys.stderr, flush=True)
-    phi_naive, grad_naive = phi.clone(), grad.clone()
+    # the naive baseline: fewer steps where one takes long (the same hipGraph timing)
+    ms_naive = None
+    if not args.no_naive:
+        t = time.perf_counter()
+        step_naive()
+        torch.cuda.synchronize()
+        slow = time.perf_counter() - t > 0.05
+        n_steps, n_warm = (args.naive_steps, 1) if slow else (args.steps, args.warmup)
+        ms_naive_eager, _ = timed(step_naive, n_steps, 0 if slow else n_warm)
+        ms_naive = ms_naive_eager if args.eager else timed(graphed(step_naive), n_steps, n_warm)[0]
+        print(f"[bench] naive phi+forces: {ms_naive:.3f} ms/step ({n_steps} steps)", file=sys.stderr, flush=True)
+        phi_naive, grad_naive = phi.clone(), grad.clone()
     ms_fwd, _ = timed(lambda: ace.eval(G, tc, toff, tpos, out=phi), args.steps, args.warmup)
 
-    # dominant kernel alone: the fused forward + reverse DAG launch, timed with
-    # events on the stream it is launched on (torch's current stream)
-    Abar = torch.empty_like(A)
-    ws = G.workspace(E, dev)
-    stream = torch.cuda.current_stream(dev)
-    lib = ace.lib()
-
-    def dag_launch():
-        st = lib.ace_contract(G.handle, tc.data_ptr(), E, A.data_ptr(), phi.data_ptr(), Abar.data_ptr(),
-                              ws.data_ptr(), ws.numel(), ace.FLAG_CONJ_SYMMETRIC, ace._stream(dev))
-        if st != 0:
-            raise RuntimeError(lib.ace_last_error().decode())
-
-    with torch.cuda.stream(stream):
-        ms_kernel, _ = timed(dag_launch, args.steps, args.warmup)
+    ms_kernel = dag_kernel_ms(ace, torch, G, tc, A, timed, args.steps, args.warmup)
     fl = dag_flops_per_env(stats)
     kind = G.schedule_kind()
     kernel_name = {"forest": "forest_kernel", "remat": "remat_kernel", "layered": "dag_kernel"}[kind] + \
@@ -351,14 +477,24 @@ def main():
     def rel(a, b):
         return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
-    pd, pn = phi_dag.cpu().numpy(), phi_naive.cpu().numpy()
-    gd, gn = grad_dag.cpu().numpy(), grad_naive.cpu().numpy()
-    parity = dict(dag_vs_naive_phi=rel(pd, pn), dag_vs_naive_grad=rel(gd, gn))
+    pd, gd = phi_dag.cpu().numpy(), grad_dag.cpu().numpy()
+    parity = {}
+    if ms_naive is not None:
+        pn, gn = phi_naive.cpu().numpy(), grad_naive.cpu().numpy()
+        parity = dict(dag_vs_naive_phi=rel(pd, pn), dag_vs_naive_grad=rel(gd, gn),
+                      dag_vs_naive_per_env=per_env_errors(pd[:, 0] + 1j * pd[:, 1], pn[:, 0] + 1j * pn[:, 1],
+                                                          gd, gn, off))
     if cpu is not None:
         rows = np.concatenate([np.arange(off[e], off[e + 1]) for e in s_envs])
         pc = pd[s_envs, 0] + 1j * pd[s_envs, 1]
+        sub_off = np.zeros(len(s_envs) + 1, dtype=np.int64)
+        np.cumsum(np.diff(off.astype(np.int64))[s_envs], out=sub_off[1:])
         parity.update(oracle_phi=rel(pc, s_phi), oracle_grad=rel(gd[rows], s_grad),
-                      oracle_sample=int(len(s_envs)))
+                      oracle_sample=int(len(s_envs)),
+                      oracle_per_env=per_env_errors(pc, s_phi, gd[rows], s_grad, sub_off))
+    extra = None
+    if not args.no_extra and args.workload != 3:
+        extra = small_workload_figures(ace, torch, dev, timed, graphed, args)
 
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
@@ -389,8 +525,8 @@ def main():
                                + (f" (n={args.alg_n})" if args.algorithm == 2 else ""),
                    "n_env": E, "n_nbr": N, "nu_max": w.nu_max, "degree_max": w.degree_max,
                    "n_max": w.n_max, "l_max": w.l_max},
-        "naive": {"value": E / (ms_naive * 1e-3), "ms_per_step": ms_naive},
-        "dag_vs_naive": ms_naive / ms_dag,
+        "naive": None if ms_naive is None else {"value": E / (ms_naive * 1e-3), "ms_per_step": ms_naive},
+        "dag_vs_naive": None if ms_naive is None else ms_naive / ms_dag,
         "forces_per_s": N / (ms_dag * 1e-3),
         "phi_only_env_per_s": E / (ms_fwd * 1e-3),
         "roofline": {"bound": "alu", "kernel": kernel_name, "achieved": achieved,
@@ -407,6 +543,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "graph_build_s": t_build,
+        "w3": extra,
         "dag": {"V": stats["n_nodes"], "K": stats["n_k"], "aux": stats["n_aux"], "stored": stats["n_stored"],
                 "childless": stats["n_childless"]},
     }

@@ -2441,7 +2441,41 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
       o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256 ||
       o->pair_slots < -1 || o->pair_slots > 8192 || o->env_per_block < 1 || o->env_per_block > 2)
     return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");
+  if (g->on_device) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device)
+      return fail(ACE_ERR_INVALID_ARG, "graph belongs to another HIP device than the current one");
+  }
+  // The current schedules (host layouts and the device copies their pointers
+  // name) stay intact until the new ones are built and uploaded; any failure
+  // puts them back together with every option.
   const ScheduleOpts old = g->opts;
+  ace_graph::Forest old_fo[2];
+  ace_graph::Remat old_rm[4];
+  for (int i = 0; i < 2; ++i) {
+    old_fo[i] = std::move(g->fo[i]);
+    g->fo[i] = ace_graph::Forest{};
+  }
+  for (int i = 0; i < 4; ++i) {
+    old_rm[i] = std::move(g->rm[i]);
+    g->rm[i] = ace_graph::Remat{};
+  }
+  const bool old_remat_ok = g->remat_ok, old_remat_lds = g->remat_lds;
+  std::string old_remat_why = g->remat_why;
+  void* old_fmem = g->fmem;
+  void* old_rmem = g->rmem;
+  auto restore = [&]() {
+    if (g->fmem != old_fmem && g->fmem) (void)hipFree(g->fmem);
+    if (g->rmem != old_rmem && g->rmem) (void)hipFree(g->rmem);
+    g->fmem = old_fmem;
+    g->rmem = old_rmem;
+    g->opts = old;
+    for (int i = 0; i < 2; ++i) g->fo[i] = std::move(old_fo[i]);
+    for (int i = 0; i < 4; ++i) g->rm[i] = std::move(old_rm[i]);
+    g->remat_ok = old_remat_ok;
+    g->remat_lds = old_remat_lds;
+    g->remat_why = old_remat_why;
+  };
   g->opts.row_chunk = o->row_chunk;
   g->opts.tree_chunk = o->tree_chunk;
   g->opts.hot_columns = o->hot_columns;
@@ -2456,22 +2490,32 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
     make_forest(g, 1);
     make_remat(g);
   } catch (const std::bad_alloc&) {
-    g->opts = old;
+    restore();
     return fail(ACE_ERR_OUT_OF_MEMORY, "host allocation failed while rebuilding the schedule");
   }
   if (o->schedule == ACE_SCHEDULE_FOREST && !g->fo[0].ok) {
-    g->opts.schedule = old.schedule;
-    return fail(ACE_ERR_UNSUPPORTED, "no forest schedule for this graph: " + g->fo[0].why);
+    const std::string why = g->fo[0].why;
+    restore();
+    return fail(ACE_ERR_UNSUPPORTED, "no forest schedule for this graph: " + why);
   }
   if (o->schedule == ACE_SCHEDULE_REMAT && !g->remat_ok) {
-    g->opts.schedule = old.schedule;
-    return fail(ACE_ERR_UNSUPPORTED, "no remat schedule for this graph: " + g->remat_why);
+    const std::string why = g->remat_why;
+    restore();
+    return fail(ACE_ERR_UNSUPPORTED, "no remat schedule for this graph: " + why);
   }
   if (g->on_device) {
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != g->device)
-      return fail(ACE_ERR_INVALID_ARG, "graph belongs to another HIP device than the current one");
-    return upload_forest(g);
+    // upload_forest allocates fresh device blocks; the old ones are freed
+    // only once the new ones are in place
+    g->fmem = nullptr;
+    g->rmem = nullptr;
+    const ace_status st = upload_forest(g);
+    if (st != ACE_OK) {
+      const std::string msg = ace_last_error();
+      restore();
+      return fail(st, msg);
+    }
+    if (old_fmem) (void)hipFree(old_fmem);
+    if (old_rmem) (void)hipFree(old_rmem);
   }
   return ACE_OK;
 }

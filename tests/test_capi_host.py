@@ -247,6 +247,34 @@ def test_schedule_kinds():
             g2.set_schedule(**bad)
 
 
+def test_failed_set_schedule_leaves_every_option_and_layout_unchanged():
+    """A set_schedule call that fails (here: a forest on a graph that has none)
+    must leave the options and the schedules as they were, including the
+    options it would have changed along the way."""
+    from oracle import contraction as oc
+    from oracle.indexsets import all_invariant_tuples
+    import workloads as wl
+    g = ace.Graph(6, 6, 2, 2, host_only=True)
+    g.set_schedule(schedule="remat", term_chunk=64, pair_slots=100, hot_columns=2)
+    before = (g.get_schedule(), g.schedule_info())
+    with pytest.raises(ace.AceError) as ei:
+        g.set_schedule(schedule="forest", term_chunk=16, pair_slots=0, hot_columns=4, row_chunk=8)
+    assert ei.value.status == 2
+    assert (g.get_schedule(), g.schedule_info()) == before
+    gr = group_o3(2, 2, 6)
+    K = all_invariant_tuples(gr, 6, 6)
+    c = np.random.default_rng(3).standard_normal(len(K))
+    A = wl.random_A(2, len(gr), 5) * 0.5
+    phi, ab = g.remat_eval_host(c, A)
+    pr, ar = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    assert np.linalg.norm(phi - pr) <= 1e-13 * np.linalg.norm(pr)
+    assert np.linalg.norm(ab - ar) <= 1e-13 * np.linalg.norm(ar)
+    # an out-of-range option is rejected before anything is touched
+    with pytest.raises(ace.AceError):
+        g.set_schedule(term_chunk=0)
+    assert (g.get_schedule(), g.schedule_info()) == before
+
+
 # ---- remat schedule: host emulation of the kernel's exact index logic -------------
 @pytest.mark.parametrize("spec,alg,n,chunk,pairs", [((4, 4, 8, 3), 1, 1, 16, 0), ((6, 6, 12, 4), 1, 1, 5, 64),
                                                     ((6, 6, 12, 4), 2, 2, 16, 2048), ((3, 2, 9, 5), 1, 1, 1, 7),
