@@ -299,6 +299,24 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
                          uint32_t flags, void* stream);
 
 /*
+ * ace_eval_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Arguments and results as for
+ * ace_eval_grad; ACE_FLAG_CHECK is not accepted.  The workspace is a fixed
+ * device array of 64 MiB inside the library, one per device, set up when a
+ * graph is built on that device and held until the process ends; the call
+ * allocates nothing.  Batches whose ace_workspace_size exceeds 64 MiB fail
+ * with ACE_ERR_INVALID_ARG (split them: 4096 environments of the
+ * 343-function basis n, l <= 6 fit, 8192 do not).  Every call on a device
+ * shares that device's array, so calls that overlap in time on one device
+ * (on any streams, from any threads) race and give wrong results: serialise
+ * them.  No result depends on what an earlier call left in the array.
+ */
+ace_status ace_eval_grad_noalloc(const ace_graph* g, const double* coeffs, int64_t n_env,
+                                 const int32_t* offsets, const double* pos, double* phi,
+                                 double* grad, uint32_t flags, void* stream);
+
+/*
  * Introspection for tests (host only, no device work).
  *
  * ace_debug_schedule: the schedule ace_eval_grad uses without flags:

@@ -22,7 +22,7 @@ import threading
 import numpy as np
 
 __all__ = [
-    "Graph", "basis", "contract", "eval", "eval_grad", "AceEnergy", "AceError",
+    "Graph", "basis", "contract", "eval", "eval_grad", "eval_grad_noalloc", "AceEnergy", "AceError",
     "FLAG_NAIVE", "FLAG_CHECK", "FLAG_LAYERED", "FLAG_UNFOLDED", "FLAG_CONJ_SYMMETRIC", "GROUP_O3", "GROUP_TORUS", "GROUP_SO2", "library_path",
 ]
 
@@ -99,6 +99,7 @@ EXPORTED = {
     "ace_contract": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval_grad": ([_P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
+    "ace_eval_grad_noalloc": ([_P, _P, _I64, _P, _P, _P, _P, _U32, _P], ctypes.c_int32),
     "ace_graph_get_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_graph_set_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
@@ -408,6 +409,26 @@ def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: boo
     _check(lib().ace_eval_grad(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                                phi.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), flags,
                                _stream(pos.device)))
+    return phi, grad
+
+
+def eval_grad_noalloc(g: Graph, coeffs, offsets, pos, phi, grad, *, naive: bool = False):
+    """ace_eval_grad_noalloc into caller-allocated phi [E, 2] and grad [N, 3]:
+    the library's fixed device workspace, no allocation in the call."""
+    import torch
+    _dev(coeffs, torch.float64, "coeffs")
+    _dev(offsets, torch.int32, "offsets")
+    _dev(pos, torch.float64, "pos")
+    _dev(phi, torch.float64, "phi")
+    _dev(grad, torch.float64, "grad")
+    _check_coeffs(g, coeffs)
+    _check_batch(offsets, pos, False, g.pos_cols)
+    E = offsets.numel() - 1
+    if tuple(phi.shape) != (E, 2) or tuple(grad.shape) != (pos.shape[0], 3):
+        raise ValueError("phi must be [n_env, 2] and grad [n_nbr, 3]")
+    _check(lib().ace_eval_grad_noalloc(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
+                                       phi.data_ptr(), grad.data_ptr(), FLAG_NAIVE if naive else 0,
+                                       _stream(pos.device)))
     return phi, grad
 
 

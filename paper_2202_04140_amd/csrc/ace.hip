@@ -11,6 +11,7 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -54,6 +55,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 }  // namespace
 }  // namespace ace
+
+// Workspace of ace_eval_grad_noalloc: a fixed device array, one copy on each
+// device the library runs on, held until the process ends.  In host code its
+// name is a stand-in, not a device address; host code uses only the address
+// hipGetSymbolAddress returns for the current device (scratch_address below).
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 using namespace ace;
 
@@ -1680,10 +1688,37 @@ ace_status upload_forest(ace_graph* g) {
   return ACE_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device), looked up
+// once per device.
+ace_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ACE_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(ACE_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return ACE_OK;
+}
+
 ace_status upload(ace_graph* g) {
   int dev = 0;
   ACE_HIP(hipGetDevice(&dev));
   g->device = dev;
+  {
+    // the fixed workspace of ace_eval_grad_noalloc is located on every
+    // device a graph is built on
+    void* unused = nullptr;
+    const ace_status sst = scratch_address(dev, &unused);
+    if (sst != ACE_OK) return sst;
+  }
   int lds = 0;
   ACE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   g->max_lds = (size_t)lds;
@@ -2416,6 +2451,28 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
   }
   if (st != ACE_OK) return st;
   return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
+}
+
+ace_status ace_eval_grad_noalloc(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,
+                                 const double* pos, double* phi, double* grad, uint32_t flags, void* stream) {
+  ace_status st = need_device(g);
+  if (st != ACE_OK) return st;
+  if (n_env < 0) return fail(ACE_ERR_INVALID_ARG, "n_env must be >= 0");
+  if (n_env > ((int64_t)1 << 30)) return fail(ACE_ERR_INVALID_ARG, "n_env too large");
+  if (flags & ACE_FLAG_CHECK)
+    return fail(ACE_ERR_INVALID_ARG, "ace_eval_grad_noalloc does not take ACE_FLAG_CHECK");
+  if (flags & ~(ACE_FLAG_NAIVE | ACE_FLAG_LAYERED | ACE_FLAG_UNFOLDED))
+    return fail(ACE_ERR_INVALID_ARG, "unknown flag bits");
+  if (n_env == 0) return ACE_OK;
+  const size_t need = plan_workspace(g, n_env, flags, nullptr).bytes;
+  if (need > kNoallocScratchBytes)
+    return fail(ACE_ERR_INVALID_ARG, "ace_eval_grad_noalloc: " + std::to_string(n_env) + " environments need " +
+                                         std::to_string(need) + " bytes of workspace, more than its fixed " +
+                                         std::to_string(kNoallocScratchBytes) + "; split the batch");
+  void* ws = nullptr;
+  st = scratch_address(g->device, &ws);
+  if (st != ACE_OK) return st;
+  return ace_eval_grad(g, coeffs, n_env, offsets, pos, phi, grad, ws, kNoallocScratchBytes, flags, stream);
 }
 
 ace_status ace_graph_get_schedule(const ace_graph* g, ace_schedule_opts* o) {
