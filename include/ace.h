@@ -168,7 +168,8 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *                  accumulators instead of per-child atomics, 0..4
  *   bank_schedule  1: order work so that a quarter-wave's LDS gathers hit
  *                  distinct bank groups; 0: plain order
- *   block_threads  threads per block of the DAG kernel, 64..512, multiple of 64
+ *   block_threads  threads per block of the DAG kernel, 64..1024, multiple
+ *                  of 64 (the forest kernel takes at most 512)
  *   schedule       which DAG kernel evaluates the graph (ACE_SCHEDULE_*):
  *                  AUTO takes the forest schedule when its resident set
  *                  fits in LDS, else the remat schedule, else the layered
@@ -181,12 +182,13 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *                  precomputed in LDS per environment and used as factors,
  *                  0..8192 (the most frequent pairs are taken), or -1: as
  *                  many as fit without lowering the kernel's occupancy
- *   env_per_block  forest schedule: environments one block evaluates
- *                  together, sharing every schedule and coefficient load,
- *                  1 or 2 (2 falls back to 1 where two environments'
- *                  values do not fit in LDS)
+ *   env_per_block  forest and remat schedules: environments one block
+ *                  evaluates together, sharing every schedule and
+ *                  coefficient load, 1 or 2 (2 falls back to 1 where two
+ *                  environments' values do not fit in LDS)
  * hot_columns also sets the number of one-particle slots whose adjoints
- * the remat kernel sums in registers.
+ * the remat kernel sums in registers (at most 2 with two environments per
+ * block).
  */
 #define ACE_SCHEDULE_AUTO 0
 #define ACE_SCHEDULE_FOREST 1   /* one-particle and order-2 values resident in LDS */

@@ -5,7 +5,7 @@ is laid out on the GPU is not: which kernel runs it (forest or remat), how
 many pair-row entries, tree children or terms a lane takes per item, how
 many hot slots get register accumulators, whether lanes and columns are
 ordered by LDS bank group, the block size of the DAG kernel and how many
-environments a forest block evaluates together.  tune()
+environments a block evaluates together.  tune()
 searches these by coordinate descent for every available kernel, timing the
 fused forward + reverse DAG launch (ace_contract with an adjoint) on the
 caller's one-particle values, applies the fastest schedule to the graph and
@@ -34,10 +34,12 @@ SPACE = {
         "env_per_block": [1, 2],
     },
     "remat": {
+        # searched jointly: two environments per block pay off only with the
+        # 1024-thread blocks whose register bound keeps 16 waves per CU
+        ("env_per_block", "block_threads"): [(1, 256), (1, 512), (1, 1024), (2, 512), (2, 1024)],
         "term_chunk": [16, 32, 64, 128, 256],
         "pair_slots": [-1, 0, 512, 1024, 2048],
         "hot_columns": [0, 2, 4],
-        "block_threads": [256, 512],
     },
 }
 
@@ -138,11 +140,13 @@ def tune(graph: Graph, coeffs, A, *, reps: int = 5, use_cache: bool = True, verb
         kbest, kms = start, _time(graph, coeffs, A, reps)
         tried.append((dict(kbest), kms))
         for name_, values in SPACE[kind].items():
+            names = name_ if isinstance(name_, tuple) else (name_,)
             for v in values:
-                if v == kbest[name_]:
+                vals = v if isinstance(name_, tuple) else (v,)
+                if all(kbest[n] == x for n, x in zip(names, vals)):
                     continue
                 cand = dict(kbest)
-                cand[name_] = v
+                cand.update(zip(names, vals))
                 graph.set_schedule(**cand)
                 ms = _time(graph, coeffs, A, reps)
                 tried.append((cand, ms))

@@ -74,11 +74,11 @@ struct ScheduleOpts {
   int tree_chunk = 16;     // regular children per tree item at most
   int hot_columns = 4;     // hot-sibling register columns (0..4)
   int bank_schedule = 1;   // order lanes and columns by LDS bank group
-  int block_threads = 512; // forest / remat kernel block size
+  int block_threads = 512; // remat kernel block size; the forest kernel takes at most 512
   int schedule = 0;        // ACE_SCHEDULE_*
   int term_chunk = 64;     // remat: terms per lane item at most
   int pair_slots = -1;     // remat: precomputed one-particle pair products at most (-1: fill LDS)
-  int env_per_block = 1;   // forest: environments per block (1 or 2)
+  int env_per_block = 1;   // forest and remat: environments per block (1 or 2)
 };
 
 struct ace_graph {
@@ -1130,17 +1130,19 @@ void compress_others(const HostGraph& h, const std::vector<REnt>& ents, int budg
   }
 }
 
-// Pair slots that fit beside the one-particle values (and adjoints) without
-// lowering the number of resident waves below what the kernel's registers
-// allow: remat_kernel<true> holds 4 waves per SIMD, <false> 5 (gfx950,
-// 512 VGPRs per lane), i.e. 16 and 20 waves per CU of 160 KiB LDS.
+// Pair slots that fit beside the one-particle values (and adjoints) of the
+// block's environments without lowering the number of resident waves below
+// what the kernel's registers allow: remat_kernel<true> holds 4 waves per
+// SIMD, <false> 5 (gfx950, 512 VGPRs per lane, at most 128 per lane at the
+// kernel's 1024-thread bound), i.e. 16 and 20 waves per CU of 160 KiB LDS.
 int auto_pair_slots(const ace_graph* g, bool grad) {
+  const int ne = std::max(1, g->opts.env_per_block);
   const int wave_per_block = std::max(1, g->opts.block_threads / 64);
   const int waves_cu = grad ? 16 : 20;
   const int blocks = std::max(1, waves_cu / wave_per_block);
   const size_t per_block = (size_t)160 * 1024 / blocks;
-  const size_t base = (size_t)(g->P1 + 1) * 16 * (grad ? 2 : 1) + 8 * 16 + 256;
-  return per_block > base ? (int)std::min<size_t>(8192, (per_block - base) / 16) : 0;
+  const size_t base = (size_t)ne * (g->P1 + 1) * 16 * (grad ? 2 : 1) + 16 * 16 + 256;
+  return per_block > base ? (int)std::min<size_t>(8192, (per_block - base) / (16 * (size_t)ne)) : 0;
 }
 
 void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool grad) {
@@ -1578,11 +1580,22 @@ T* carve(char*& p, size_t n) {
 }
 
 // LDS of remat_kernel: one-particle values and adjoints, reduction scratch.
-size_t remat_lds_bytes(const ace_graph* g, int which) {
+size_t remat_lds_bytes(const ace_graph* g, int which, int ne = 1) {
   const bool grad = which & 1;
   const size_t np = g->rm[which].pairs.size();
-  return (size_t)(g->P1 + 1 + np) * 16 + (grad ? (size_t)(g->P1 + 1) * 16 : 0) + (kRematBlock / 64) * sizeof(double2);
+  return (size_t)ne * ((g->P1 + 1 + np) * 16 + (grad ? (size_t)(g->P1 + 1) * 16 : 0)) +
+         (kRematBlock / 64) * sizeof(double2);
 }
+
+// Environments one remat block evaluates: the requested number where their
+// values fit in LDS, else one.
+int remat_env_per_block(const ace_graph* g, int which) {
+  return g->opts.env_per_block >= 2 && remat_lds_bytes(g, which, 2) <= g->max_lds ? 2 : 1;
+}
+
+// Block size of the forest kernel (its schedule spreads over at most
+// kMaxForestWaves waves).
+int forest_threads(const ace_graph* g) { return std::min(g->opts.block_threads, 64 * kMaxForestWaves); }
 
 // Upload the forest and remat schedules (replacing previous ones) and plan
 // their LDS.
@@ -1681,8 +1694,15 @@ ace_status upload_forest(ace_graph* g) {
     }
     g->remat_lds = true;
     for (int which = 0; which < 4; ++which) g->remat_lds &= remat_lds_bytes(g, which) <= g->max_lds;
-    const void* rk[] = {(const void*)remat_kernel<false, false>, (const void*)remat_kernel<true, false>,
-                        (const void*)remat_kernel<false, true>, (const void*)remat_kernel<true, true>};
+    const void* rk[] = {
+        (const void*)remat_kernel<false, false, 1, false>, (const void*)remat_kernel<true, false, 1, false>,
+        (const void*)remat_kernel<false, true, 1, false>,  (const void*)remat_kernel<true, true, 1, false>,
+        (const void*)remat_kernel<false, false, 2, false>, (const void*)remat_kernel<true, false, 2, false>,
+        (const void*)remat_kernel<false, true, 2, false>,  (const void*)remat_kernel<true, true, 2, false>,
+        (const void*)remat_kernel<false, false, 1, true>,  (const void*)remat_kernel<true, false, 1, true>,
+        (const void*)remat_kernel<false, true, 1, true>,   (const void*)remat_kernel<true, true, 1, true>,
+        (const void*)remat_kernel<false, false, 2, true>,  (const void*)remat_kernel<true, false, 2, true>,
+        (const void*)remat_kernel<false, true, 2, true>,   (const void*)remat_kernel<true, true, 2, true>};
     for (const void* f : rk) ACE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxl));
   }
   return ACE_OK;
@@ -2045,7 +2065,7 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   }
   const size_t lds = forest_lds_bytes(F, g->P1, grad, full, ne);
   const int64_t blocks = (n_env + ne - 1) / ne;
-  const dim3 grid((unsigned)grid_for(blocks)), block((unsigned)g->opts.block_threads);
+  const dim3 grid((unsigned)grid_for(blocks)), block((unsigned)forest_threads(g));
   const ForestKernel k = forest_variant(ne, fold, full ? 2 : grad ? 1 : 0, F.has_gc);
   hipLaunchKernelGGL(k, grid, block, lds, s, a);
   ACE_HIP(hipGetLastError());
@@ -2085,14 +2105,30 @@ ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env,
   a.pairs = R.d_pairs;
   a.n_pairs = (int)R.pairs.size();
   a.hot = make_int4(R.hot[0], R.hot[1], R.hot[2], R.hot[3]);
-  const size_t lds = remat_lds_bytes(g, which);
-  const dim3 grid((unsigned)grid_for(n_env)), block((unsigned)g->opts.block_threads);
-  switch (which) {
-    case 0: hipLaunchKernelGGL((remat_kernel<false, false>), grid, block, lds, s, a); break;
-    case 1: hipLaunchKernelGGL((remat_kernel<true, false>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((remat_kernel<false, true>), grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL((remat_kernel<true, true>), grid, block, lds, s, a); break;
+  const int ne = remat_env_per_block(g, which);
+  const size_t lds = remat_lds_bytes(g, which, ne);
+  const dim3 grid((unsigned)grid_for((n_env + ne - 1) / ne)), block((unsigned)g->opts.block_threads);
+  const bool big = g->opts.block_threads > kRematBlock / 2;
+#define ACE_REMAT_LAUNCH(G_, F_, N_, B_) hipLaunchKernelGGL((remat_kernel<G_, F_, N_, B_>), grid, block, lds, s, a)
+  switch (which + 4 * (ne - 1) + 8 * (big ? 1 : 0)) {
+    case 0: ACE_REMAT_LAUNCH(false, false, 1, false); break;
+    case 1: ACE_REMAT_LAUNCH(true, false, 1, false); break;
+    case 2: ACE_REMAT_LAUNCH(false, true, 1, false); break;
+    case 3: ACE_REMAT_LAUNCH(true, true, 1, false); break;
+    case 4: ACE_REMAT_LAUNCH(false, false, 2, false); break;
+    case 5: ACE_REMAT_LAUNCH(true, false, 2, false); break;
+    case 6: ACE_REMAT_LAUNCH(false, true, 2, false); break;
+    case 7: ACE_REMAT_LAUNCH(true, true, 2, false); break;
+    case 8: ACE_REMAT_LAUNCH(false, false, 1, true); break;
+    case 9: ACE_REMAT_LAUNCH(true, false, 1, true); break;
+    case 10: ACE_REMAT_LAUNCH(false, true, 1, true); break;
+    case 11: ACE_REMAT_LAUNCH(true, true, 1, true); break;
+    case 12: ACE_REMAT_LAUNCH(false, false, 2, true); break;
+    case 13: ACE_REMAT_LAUNCH(true, false, 2, true); break;
+    case 14: ACE_REMAT_LAUNCH(false, true, 2, true); break;
+    default: ACE_REMAT_LAUNCH(true, true, 2, true); break;
   }
+#undef ACE_REMAT_LAUNCH
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
@@ -2494,7 +2530,7 @@ ace_status ace_graph_set_schedule(ace_graph* g, const ace_schedule_opts* o) {
   if (!g || !o) return fail(ACE_ERR_INVALID_ARG, "graph and opts must be non-NULL");
   if (o->row_chunk < 4 || o->row_chunk > 256 || o->tree_chunk < 1 || o->tree_chunk > 256 || o->hot_columns < 0 ||
       o->hot_columns > 4 || (o->bank_schedule != 0 && o->bank_schedule != 1) || o->block_threads < 64 ||
-      o->block_threads > 512 || o->block_threads % 64 != 0 || o->schedule < ACE_SCHEDULE_AUTO ||
+      o->block_threads > 1024 || o->block_threads % 64 != 0 || o->schedule < ACE_SCHEDULE_AUTO ||
       o->schedule > ACE_SCHEDULE_LAYERED || o->term_chunk < 1 || o->term_chunk > 256 ||
       o->pair_slots < -1 || o->pair_slots > 8192 || o->env_per_block < 1 || o->env_per_block > 2)
     return fail(ACE_ERR_INVALID_ARG, "schedule option out of range");

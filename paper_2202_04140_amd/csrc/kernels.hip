@@ -1306,23 +1306,25 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
 // weight, which gives d Re(phi)/dA in the form Re sum_i abar_i dA_i (the
 // adjoint itself differs from the unfolded one).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const int4& hot, double2& h0, double2& h1,
-                                         double2& h2, double2& h3) {
-  if (s == hot.x) {
-    h0.x += d.x;
-    h0.y += d.y;
-  } else if (s == hot.y) {
-    h1.x += d.x;
-    h1.y += d.y;
-  } else if (s == hot.z) {
-    h2.x += d.x;
-    h2.y += d.y;
-  } else if (s == hot.w) {
-    h3.x += d.x;
-    h3.y += d.y;
+// d added to abar_s: in the register accumulator of s if s is one of the
+// NH hot slots, else atomically in LDS (every index into h is a constant).
+template <int K, int NH>
+__device__ __forceinline__ void push_hot_from(double2* ab, int s, double2 d, const int4& hot, double2 (&h)[NH]) {
+  if constexpr (K < NH) {
+    const int hk = K == 0 ? hot.x : K == 1 ? hot.y : K == 2 ? hot.z : hot.w;
+    if (s == hk) {
+      h[K].x += d.x;
+      h[K].y += d.y;
+    } else {
+      push_hot_from<K + 1, NH>(ab, s, d, hot, h);
+    }
   } else {
     atomic_cadd(&ab[s], d);
   }
+}
+template <int NH>
+__device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const int4& hot, double2 (&h)[NH]) {
+  push_hot_from<0, NH>(ab, s, d, hot, h);
 }
 
 // Field i of a packed factor list: the LDS byte offset of a 16-byte slot.
@@ -1342,26 +1344,36 @@ __device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo,
   return v;
 }
 
-template <bool GRAD, int SIG, bool FOLD>
-__device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x, double2* ab, const int4& sl, int lane,
-                                           double2& acc, double2& h0, double2& h1, double2& h2, double2& h3) {
-  const int ONE_OFF = 16 * p.P1;
-  const int nb = sl.w & 0xff;
-  const int item = sl.x + lane;
-  const uint64_t blo = p.row_lo[item], bhi = p.row_hi[item];
-  // row value (its factors are read again for the adjoint at the end, so
-  // that they hold no registers during the entry loop)
-  double2 xb = lds_at(x, slot16(blo, bhi, 0));
-#pragma unroll
-  for (int i = 1; i < 8; ++i)
-    if (i < nb) xb = cmul(xb, lds_at(x, slot16(blo, bhi, i)));
+// One lane item is a chunk of a row: the terms that share one parent (the
+// row's base, a product of NB one-particle values) for NE environments,
+// which share every metadata and coefficient load; environment e's values
+// and adjoints sit xs and as double2 slots after those of environment e - 1.
+//
+// remat_entries: y1 = sum_j c'_j x_j (and y2 = sum_j c''_j x_j when
+// folded) over the item's entries, x_j the other parent of term j, a
+// product of SIG factors (one-particle values or pair products).
+template <int SIG, bool FOLD, int NE>
+__device__ __forceinline__ void remat_entries(const RematArgs& p, const double2* x, int xs, const int4& sl, int lane,
+                                              double2 (&y1)[NE], double2 (&y2)[NE]) {
   // entry metadata of this slice, prefetched one entry ahead of its use in
   // two register sets (the loop is unrolled by two)
   const uint64_t* olo_p = p.oth_lo + sl.y + lane;
   const uint64_t* ohi_p = p.oth_hi + sl.y + lane;
   const unsigned c0 = (unsigned)(p.cs_ent + sl.y + lane);
   const int n = sl.z;
-  double2 y1 = make_double2(0.0, 0.0), y2 = y1;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) y1[e] = y2[e] = make_double2(0.0, 0.0);
+  if constexpr (NE > 1 && SIG > 4) {
+    // long products of several environments: one entry in flight (registers)
+    for (int j = 0; j < n; ++j) {
+      const unsigned o = (unsigned)j * 64u;
+      const uint64_t lo = olo_p[o], hi = ohi_p[o];
+      const RCoef<FOLD> c = load_coef<FOLD>(p.cs, c0 + o);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) coef_fma<FOLD>(c, factor_product<SIG>(x + e * xs, lo, hi), y1[e], y2[e]);
+    }
+    return;
+  }
   uint64_t a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
   RCoef<FOLD> a_c{}, b_c{};
   if (n > 0) {
@@ -1375,127 +1387,193 @@ __device__ __forceinline__ void remat_item(const RematArgs& p, const double2* x,
     b_lo = olo_p[o1];
     if (SIG > 4) b_hi = ohi_p[o1];
     b_c = load_coef<FOLD>(p.cs, c0 + o1);
-    coef_fma<FOLD>(a_c, factor_product<SIG>(x, a_lo, a_hi), y1, y2);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) coef_fma<FOLD>(a_c, factor_product<SIG>(x + e * xs, a_lo, a_hi), y1[e], y2[e]);
     if (j + 2 < n) {
       const unsigned o2 = (unsigned)(j + 2) * 64u;
       a_lo = olo_p[o2];
       if (SIG > 4) a_hi = ohi_p[o2];
       a_c = load_coef<FOLD>(p.cs, c0 + o2);
     }
-    coef_fma<FOLD>(b_c, factor_product<SIG>(x, b_lo, b_hi), y1, y2);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) coef_fma<FOLD>(b_c, factor_product<SIG>(x + e * xs, b_lo, b_hi), y1[e], y2[e]);
   }
-  if (j < n) coef_fma<FOLD>(a_c, factor_product<SIG>(x, a_lo, a_hi), y1, y2);
-  // phi: Re from the c' sums, Im from the c'' sums when folded
+  if (j < n) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) coef_fma<FOLD>(a_c, factor_product<SIG>(x + e * xs, a_lo, a_hi), y1[e], y2[e]);
+  }
+}
+
+// remat_row: the row value x_b (product of the NB row factors, whose
+// packed offsets blo, bhi were loaded before the entries; the values are
+// read after them so that they hold no registers there), phi += x_b y
+// (halved with the adjoint: every term sits in two rows), and with GRAD the
+// adjoint y pushed to the row's factors by prefix and suffix products.  NH
+// hot one-particle slots per environment are summed in registers.
+template <bool GRAD, int NB, bool FOLD, int NE, int NH>
+__device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, double2* ab, int xs, int as,
+                                          uint64_t blo, uint64_t bhi, const double2 (&y1)[NE],
+                                          const double2 (&y2)[NE], double2 (&acc)[NE], double2 (&hot)[NE][NH]) {
   const double w = GRAD ? 0.5 : 1.0;
-  if constexpr (FOLD) {
-    acc.x = fma(w, xb.x * y1.x - xb.y * y1.y, acc.x);
-    acc.y = fma(w, xb.x * y2.y + xb.y * y2.x, acc.y);
-  } else {
-    const double2 h = cmul(xb, y1);
-    acc.x = fma(w, h.x, acc.x);
-    acc.y = fma(w, h.y, acc.y);
-  }
-  if (!GRAD) return;
-  if (slot16(blo, bhi, 0) != ONE_OFF) {
-    double2 pre[8];
-    double2 run = make_double2(1.0, 0.0);
+  const bool push = GRAD && slot16(blo, bhi, 0) != 16 * p.P1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (i < nb) {
-        pre[i] = run;
-        run = i == 0 ? lds_at(x, slot16(blo, bhi, 0)) : cmul(run, lds_at(x, slot16(blo, bhi, i)));
-      }
-    double2 suf = y1;
+  for (int e = 0; e < NE; ++e) {
+    const double2* xe = x + e * xs;
+    double2 pre[NB];
+    double2 xb = lds_at(xe, slot16(blo, bhi, 0));
+    pre[0] = make_double2(1.0, 0.0);
 #pragma unroll
-    for (int i = 7; i >= 0; --i) {
-      if (i < nb) {
-        push_hot(ab, slot16(blo, bhi, i) >> 4, i == 0 ? suf : cmul(pre[i], suf), p.hot, h0, h1, h2, h3);
-        if (i > 0) suf = cmul(suf, lds_at(x, slot16(blo, bhi, i)));
+    for (int i = 1; i < NB; ++i) {
+      pre[i] = xb;
+      xb = cmul(xb, lds_at(xe, slot16(blo, bhi, i)));
+    }
+    if constexpr (FOLD) {
+      acc[e].x = fma(w, xb.x * y1[e].x - xb.y * y1[e].y, acc[e].x);
+      acc[e].y = fma(w, xb.x * y2[e].y + xb.y * y2[e].x, acc[e].y);
+    } else {
+      const double2 h = cmul(xb, y1[e]);
+      acc[e].x = fma(w, h.x, acc[e].x);
+      acc[e].y = fma(w, h.y, acc[e].y);
+    }
+    if (push) {
+      double2 suf = y1[e];
+#pragma unroll
+      for (int i = NB - 1; i >= 0; --i) {
+        push_hot<NH>(ab + e * as, slot16(blo, bhi, i) >> 4, i == 0 ? suf : cmul(pre[i], suf), p.hot, hot[e]);
+        if (i > 0) suf = cmul(suf, lds_at(xe, slot16(blo, bhi, i)));
       }
     }
   }
 }
 
-constexpr int kRematBlock = 512;
+constexpr int kRematBlock = 1024;
 
-template <bool GRAD, bool FOLD>
-__global__ __launch_bounds__(kRematBlock) void remat_kernel(RematArgs p) {
+// NE environments per block (1 or 2): the block's slices are walked once,
+// each lane item evaluating its terms for every environment of the block
+// from the same metadata; a missing last environment computes on zeros and
+// writes nothing.  BIG: blocks of up to 1024 threads (at most 128 VGPRs),
+// else up to 512.
+template <bool GRAD, bool FOLD, int NE, bool BIG>
+__global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_kernel(RematArgs p) {
+  constexpr int NH = NE == 1 ? 4 : 2;
   extern __shared__ double2 lds[];
   const int P1 = p.P1;
   const int ONE = P1;
-  double2* x = lds;             // [P1 + 1 + n_pairs] one-particle values, constant one, pair products
-  double2* ab = lds + P1 + 1 + p.n_pairs;   // [P1 + 1] one-particle adjoints (GRAD)
-  double2* red = ab + (GRAD ? P1 + 1 : 0);
+  const int xs = P1 + 1 + p.n_pairs;   // values per environment: one-particle, constant one, pair products
+  const int as = GRAD ? P1 + 1 : 0;    // one-particle adjoints per environment
+  double2* x = lds;                    // [NE][xs]
+  double2* ab = lds + NE * xs;         // [NE][as]
+  double2* red = ab + NE * as;
   const int lane = threadIdx.x & 63;
   // wave index, made visibly uniform so that slice descriptors and loop
   // bounds live in scalar registers
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
-    const double2* Ae = p.A + e * P1;
-    double2 acc = make_double2(0.0, 0.0);
+  for (int64_t e0 = (int64_t)blockIdx.x * NE; e0 < p.n_env; e0 += (int64_t)gridDim.x * NE) {
+    const int ne = (int)min((int64_t)NE, p.n_env - e0);
+    double2 acc[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) acc[e] = make_double2(0.0, 0.0);
     for (int i = threadIdx.x; i < P1; i += blockDim.x) {
-      const double2 a = Ae[i];
       const RCoef<FOLD> k = load_coef<FOLD>(p.cs, (unsigned)(p.cs_leaf + i));
-      x[i] = a;
-      if constexpr (FOLD) {
-        if (GRAD) ab[i] = make_double2(k.c.x, 0.0);
-        acc.x = fma(k.c.x, a.x, acc.x);
-        acc.y = fma(k.c.y, a.y, acc.y);
-      } else {
-        if (GRAD) ab[i] = make_double2(k.c, 0.0);
-        acc = rfma(k.c, a, acc);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const double2 a = e < ne ? p.A[(e0 + e) * P1 + i] : make_double2(0.0, 0.0);
+        x[e * xs + i] = a;
+        if constexpr (FOLD) {
+          if (GRAD) ab[e * as + i] = make_double2(k.c.x, 0.0);
+          acc[e].x = fma(k.c.x, a.x, acc[e].x);
+          acc[e].y = fma(k.c.y, a.y, acc[e].y);
+        } else {
+          if (GRAD) ab[e * as + i] = make_double2(k.c, 0.0);
+          acc[e] = rfma(k.c, a, acc[e]);
+        }
       }
     }
-    if (threadIdx.x == 0) {
-      x[ONE] = make_double2(1.0, 0.0);
-      if (GRAD) ab[ONE] = make_double2(0.0, 0.0);
+    if (threadIdx.x < NE) {
+      x[threadIdx.x * xs + ONE] = make_double2(1.0, 0.0);
+      if (GRAD) ab[threadIdx.x * as + ONE] = make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int r = threadIdx.x; r < p.n_pairs; r += blockDim.x) {
       const uint32_t q = p.pairs[r];
-      x[ONE + 1 + r] = cmul(x[q & 0xffffu], x[q >> 16]);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) x[e * xs + ONE + 1 + r] = cmul(x[e * xs + (q & 0xffffu)], x[e * xs + (q >> 16)]);
     }
     __syncthreads();
-    double2 h0 = make_double2(0.0, 0.0), h1 = h0, h2 = h0, h3 = h0;
+    double2 hot[NE][NH];
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) hot[e][h] = make_double2(0.0, 0.0);
     for (int s = wid; s < p.n_slices; s += nw) {
       const int4 sl = p.slice[s];
+      // the row's factor offsets, loaded ahead of the entries
+      const int item = sl.x + lane;
+      const uint64_t blo = p.row_lo[item];
+      const uint64_t bhi = (sl.w & 0xff) > 4 ? p.row_hi[item] : 0;
+      double2 y1[NE], y2[NE];
       switch (sl.w >> 8) {
-        case 1: remat_item<GRAD, 1, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 2: remat_item<GRAD, 2, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 3: remat_item<GRAD, 3, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 4: remat_item<GRAD, 4, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 5: remat_item<GRAD, 5, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        case 6: remat_item<GRAD, 6, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
-        default: remat_item<GRAD, 7, FOLD>(p, x, ab, sl, lane, acc, h0, h1, h2, h3); break;
+        case 1: remat_entries<1, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        case 2: remat_entries<2, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        case 3: remat_entries<3, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        case 4: remat_entries<4, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        case 5: remat_entries<5, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        case 6: remat_entries<6, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        default: remat_entries<7, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+      }
+      switch (sl.w & 0xff) {
+        case 1: remat_row<GRAD, 1, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        case 2: remat_row<GRAD, 2, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        case 3: remat_row<GRAD, 3, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        case 4: remat_row<GRAD, 4, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        case 5: remat_row<GRAD, 5, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        case 6: remat_row<GRAD, 6, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        case 7: remat_row<GRAD, 7, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
+        default: remat_row<GRAD, 8, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
       }
     }
     if (GRAD) {
-      h0 = wave_sum(h0);
-      h1 = wave_sum(h1);
-      h2 = wave_sum(h2);
-      h3 = wave_sum(h3);
-      if (lane == 0) {
-        if (p.hot.x != ONE) atomic_cadd(&ab[p.hot.x], h0);
-        if (p.hot.y != ONE) atomic_cadd(&ab[p.hot.y], h1);
-        if (p.hot.z != ONE) atomic_cadd(&ab[p.hot.z], h2);
-        if (p.hot.w != ONE) atomic_cadd(&ab[p.hot.w], h3);
-      }
+      const int hs[4] = {p.hot.x, p.hot.y, p.hot.z, p.hot.w};
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const double2 v = wave_sum(hot[e][h]);
+          if (lane == 0 && hs[h] != ONE) atomic_cadd(&ab[e * as + hs[h]], v);
+        }
     }
-    const double2 phi = block_sum(acc, red);   // synchronises the block
-    if (threadIdx.x == 0) p.phi[e] = phi;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double2 phi = block_sum(acc[e], red);   // synchronises the block
+      if (threadIdx.x == 0 && e < ne) p.phi[e0 + e] = phi;
+    }
     if (GRAD) {
-      double2* Be = p.Abar + e * P1;
-      for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
+      for (int e = 0; e < ne; ++e) {
+        double2* Be = p.Abar + (e0 + e) * P1;
+        for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[e * as + i];
+      }
     }
     __syncthreads();
   }
 }
 
-template __global__ void remat_kernel<false, false>(RematArgs);
-template __global__ void remat_kernel<true, false>(RematArgs);
-template __global__ void remat_kernel<false, true>(RematArgs);
-template __global__ void remat_kernel<true, true>(RematArgs);
+template __global__ void remat_kernel<false, false, 1, false>(RematArgs);
+template __global__ void remat_kernel<true, false, 1, false>(RematArgs);
+template __global__ void remat_kernel<false, true, 1, false>(RematArgs);
+template __global__ void remat_kernel<true, true, 1, false>(RematArgs);
+template __global__ void remat_kernel<false, false, 2, false>(RematArgs);
+template __global__ void remat_kernel<true, false, 2, false>(RematArgs);
+template __global__ void remat_kernel<false, true, 2, false>(RematArgs);
+template __global__ void remat_kernel<true, true, 2, false>(RematArgs);
+template __global__ void remat_kernel<false, false, 1, true>(RematArgs);
+template __global__ void remat_kernel<true, false, 1, true>(RematArgs);
+template __global__ void remat_kernel<false, true, 1, true>(RematArgs);
+template __global__ void remat_kernel<true, true, 1, true>(RematArgs);
+template __global__ void remat_kernel<false, false, 2, true>(RematArgs);
+template __global__ void remat_kernel<true, false, 2, true>(RematArgs);
+template __global__ void remat_kernel<false, true, 2, true>(RematArgs);
+template __global__ void remat_kernel<true, true, 2, true>(RematArgs);
 
 __global__ __launch_bounds__(256) void prep_fold_kernel(PrepFoldArgs p) {
   prep_fold_range(p, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);

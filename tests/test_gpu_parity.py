@@ -177,6 +177,54 @@ def test_forest_two_envs_per_block(device, wid, n_env):
         assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
 
 
+# ---- remat schedule: two environments per block, 1024-thread blocks -----------------
+@pytest.mark.parametrize("spec,n_env,bt,ne", [((1,), 15, 1024, 2), ((3,), 17, 512, 2), ((2,), 33, 1024, 1),
+                                              ((6, 10, 3, 3), 9, 1024, 2), ((6, 10, 3, 3), 8, 256, 2)])
+def test_remat_envs_per_block(device, spec, n_env, bt, ne):
+    """The remat kernel with env_per_block = 2 (two environments share every
+    metadata and coefficient load; an odd count leaves the last block half
+    empty) and block sizes up to 1024: contract with and without folding,
+    forward only, and the full path, against the oracle."""
+    import paper_2202_04140_amd as ace
+    print(f"remat envs per block spec={spec} n_env={n_env} block={bt} ne={ne}", flush=True)
+    if len(spec) == 1:
+        w = wl.WORKLOADS[spec[0]]
+        nu, D, nmax, lmax, seed = w.nu_max, w.degree_max, w.n_max, w.l_max, spec[0]
+        g, K, c = oracle_basis(spec[0])
+    else:
+        nu, D, nmax, lmax = spec
+        seed = 77
+        g = group_o3(nmax, lmax, D)
+        K = all_invariant_tuples(g, nu, D)
+        c = np.random.default_rng(seed).standard_normal(len(K)) / (1.0 + np.array([g.degree(k) for k in K])) ** 2
+    G = ace.Graph(nu, D, nmax, lmax)
+    G.set_schedule(schedule="remat", env_per_block=ne, block_threads=bt)
+    assert G.schedule_kind() == "remat" and G.get_schedule()["env_per_block"] == ne
+    A = wl.random_A(n_env, len(g), seed=700 + seed) * 0.5
+    tc, tA = to_dev(device, c, np.stack([A.real, A.imag], -1))
+    phi_ref, ab_ref = oc.phi_naive(K, c, A), oc.abar_naive(K, c, A)
+    phi, Ab = ace.contract(G, tc, tA, with_grad=True)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(cplx(Ab), ab_ref) <= TOL_ABAR
+    assert rel(cplx(ace.contract(G, tc, tA, with_grad=False)), phi_ref) <= TOL_PHI
+    As = wl.random_A_conj(n_env, g.labels, 800 + seed) * 0.5
+    dA = wl.random_A_conj(n_env, g.labels, 900 + seed)
+    (tAs,) = to_dev(device, np.stack([As.real, As.imag], -1))
+    phis_ref, abs_ref = oc.phi_naive(K, c, As), oc.abar_naive(K, c, As)
+    phi, Ab = ace.contract(G, tc, tAs, with_grad=True, conj_symmetric=True)
+    assert rel(cplx(phi), phis_ref) <= TOL_PHI
+    lhs = np.real(np.sum(cplx(Ab) * dA, axis=1))
+    rhs = np.real(np.sum(abs_ref * dA, axis=1))
+    assert rel(lhs, rhs) <= TOL_ABAR
+    assert rel(cplx(ace.contract(G, tc, tAs, with_grad=False, conj_symmetric=True)), phis_ref) <= TOL_PHI
+    off, pos = problem(3, n_env)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    phi, grad = ace.eval_grad(G, tc, toff, tpos)
+    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, off, pos, 5.0)
+    assert rel(cplx(phi), phi_ref) <= TOL_PHI
+    assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+
+
 # ---- full path ---------------------------------------------------------------------
 @pytest.mark.parametrize("naive", [False, True])
 @pytest.mark.parametrize("wid,n_env", [(1, None), (2, 96)])
