@@ -115,6 +115,22 @@ def test_builder_bit_exact_torus(nu, D, alg, n):
     np.testing.assert_array_equal(k2n, ok2n)
 
 
+@pytest.mark.parametrize("alg,n", [(1, 1), (2, 2), (2, 3)])
+def test_builder_matches_hand_worked_torus_graph(alg, n):
+    """The library builder against the node lists worked by hand for the
+    torus, nu <= 4, D = 6 (tests/golden/alg2_torus_nu4_D6.txt)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_oracle_graph import _hand_worked_lists
+    expected = _hand_worked_lists()[(alg, n)]
+    g = ace.Graph(4, 6, group=ace.GROUP_TORUS, algorithm=alg, alg_n=n, host_only=True)
+    _, tup, par, _ = g.export()
+    assert tup.shape[0] == 13 + len(expected)
+    for v, t, pr in expected:
+        assert tuple(x for x in tup[v] if x >= 0) == t
+        assert tuple(par[v]) == pr
+
+
 # Regression values: |K| per order, V, aux per order, depth, layer sizes, stored and
 # childless product nodes, leaves with children, naive complex products.  Computed
 # once from the definitions (Algorithm 1 with the fixed split order); the first two

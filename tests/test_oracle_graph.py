@@ -190,3 +190,39 @@ def test_dag_structure_p_norm(p):
             assert tuple(sorted(G.node_tuple[a] + G.node_tuple[b])) == G.node_tuple[v]
         assert all(G.node_tuple[G.k_to_node[q]] == k for q, k in enumerate(G.K))
         assert len(kset) == len(G.K)
+
+
+def _hand_worked_lists():
+    """Sections of tests/golden/alg2_torus_nu4_D6.txt: {(alg, n): [(id, tuple, parents)]}."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "alg2_torus_nu4_D6.txt")
+    out, cur = {}, None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("["):
+            alg, n = line.strip("[]").split()
+            cur = out.setdefault((int(alg[3:]), int(n[2:])), [])
+            continue
+        v, tup, par = [x.strip() for x in line.split("|")]
+        cur.append((int(v), tuple(int(x) for x in tup.split(",")), tuple(int(x) for x in par.split(","))))
+    return out
+
+
+@pytest.mark.parametrize("alg,n", [(1, 1), (2, 2), (2, 3)])
+def test_algorithms_match_hand_worked_torus_graph(alg, n):
+    """Algorithms 1 and 2 (Sec. 3.2, 3.3) against node lists derived by hand
+    for the torus, nu <= 4, D = 6: every product node, its id (insertion
+    order: the split-off part before the remainder) and its parents.  With
+    n = 3 the split-off triple is inserted by Algorithm 1, not by
+    Algorithm 2; with n = 2 the split-off pair precedes the remainder."""
+    expected = _hand_worked_lists()[(alg, n)]
+    G = OracleGraph(group_torus(6), 4, 6, alg, n)
+    assert G.n_nodes() == 13 + len(expected)
+    for v, tup, par in expected:
+        assert G.node_tuple[v] == tup, v
+        assert G.parents[v] == par, v
+    assert G.aux_count() == (6 if alg == 1 else 8)
+    if alg == 1:
+        assert torus_aux_count_theorem(4, 6) == 6
