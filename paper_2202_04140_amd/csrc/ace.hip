@@ -1188,10 +1188,22 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   }
   // chunks of one row go to different slices where possible: their adjoint
   // pushes hit the same addresses, which a wave would serialise
-  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+  // items of equal shape and length in a hashed order: neighbouring rows in
+  // node order share factors, and rows that share a factor in one slice push
+  // to one address (same-address LDS atomics in one instruction serialise)
+  auto mix = [](uint64_t v) {
+    v += 0x9e3779b97f4a7c15ull;
+    v = (v ^ (v >> 30)) * 0xbf58476d1ce4e5b9ull;
+    v = (v ^ (v >> 27)) * 0x94d049bb133111ebull;
+    return v ^ (v >> 31);
+  };
+  std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) {
     if (x.nb != y.nb) return x.nb < y.nb;
     if (x.sig != y.sig) return x.sig < y.sig;
     if (x.count != y.count) return x.count > y.count;
+    const uint64_t hx = mix(((uint64_t)(uint32_t)x.row << 16) | (uint32_t)x.chunk);
+    const uint64_t hy = mix(((uint64_t)(uint32_t)y.row << 16) | (uint32_t)y.chunk);
+    if (hx != hy) return hx < hy;
     return x.chunk < y.chunk;
   });
   // hot one-particle slots: the most frequent adjoint push targets
@@ -1241,9 +1253,36 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     if (R.fold) R.kbar.resize(P1 + e0 + 64 * (size_t)ncol, -1);
     // per lane: its entries, then their column and factor rotation
     std::vector<std::vector<int64_t>> lane_ents(64);
-    // lanes start their row factor lists at different positions (lane mod nb)
+    // each lane starts its row factor list at the position that adds the
+    // fewest same-address pushes to the slice's push instructions so far
+    // (push i of every lane goes to factor i of its rotated list; the hot
+    // slots, summed in registers, and the constant slot do not count)
     int rot[64] = {0};
-    for (int lane = 0; lane < 64; ++lane) rot[lane] = i0 + lane < i1 ? lane % items[i0 + lane].nb : 0;
+    {
+      const int nbs = items[i0].nb;
+      std::vector<std::map<int32_t, int>> mult(nbs);
+      for (int lane = 0; lane < 64 && i0 + lane < i1; ++lane) {
+        const Item& it = items[i0 + lane];
+        const int32_t* f = &h.node_flat[(int64_t)it.row * W];
+        int best = lane % nbs, best_cost = INT32_MAX;
+        for (int r0 = 0; r0 < nbs; ++r0) {
+          const int r = (lane + r0) % nbs;
+          int cost = 0;
+          for (int i = 0; i < nbs; ++i) {
+            const int32_t sl = f[(i + r) % nbs];
+            if (sl == ONE || sl == R.hot[0] || sl == R.hot[1]) continue;
+            const auto m = mult[i].find(sl);
+            cost += m == mult[i].end() ? 0 : m->second;
+          }
+          if (cost < best_cost) {
+            best_cost = cost;
+            best = r;
+          }
+        }
+        rot[lane] = best;
+        for (int i = 0; i < nbs; ++i) mult[i][f[(i + best) % nbs]] += 1;
+      }
+    }
     for (int lane = 0; lane < 64; ++lane) {
       if (i0 + lane < i1) {
         const Item& it = items[i0 + lane];
