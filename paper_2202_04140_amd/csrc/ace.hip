@@ -1237,10 +1237,91 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   };
   const uint64_t one16 = 16 * (uint64_t)ONE;
   const uint64_t ones = one16 | (one16 << 16) | (one16 << 32) | (one16 << 48);
+  // Slices of 64 lanes.  Within each group of equal (nb, sig), the items
+  // (in the order above) go to one of a few open slices: the one, and the
+  // factor rotation, where the item's row pushes add the least LDS atomic
+  // contention to the slice's push instructions so far.  Push i of every
+  // lane goes to factor i of its rotated row list; lanes on one address
+  // serialise, and a half-wave of 8-byte atomics is spread over the banks by
+  // slot mod 16 (the hot slots, summed in registers, and the constant slot
+  // do not count).  A slice is emitted when full; its first item is its
+  // longest, since the items come longest first.
+  std::vector<Item> ordered;
+  std::vector<int> item_rot;
+  std::vector<size_t> cut;   // slice ends in `ordered`
+  {
+    constexpr int kOpen = 4;
+    struct Open {
+      std::vector<size_t> idx;
+      std::vector<int> rot;
+      std::vector<std::map<int32_t, int>> mult;
+      std::vector<std::array<int, 32>> bank;
+    };
+    ordered.reserve(items.size());
+    item_rot.reserve(items.size());
+    for (size_t g0 = 0; g0 < items.size();) {
+      size_t g1 = g0;
+      while (g1 < items.size() && items[g1].nb == items[g0].nb && items[g1].sig == items[g0].sig) ++g1;
+      const int nbs = items[g0].nb;
+      std::vector<Open> open(kOpen);
+      auto reset = [&](Open& o) {
+        o.idx.clear();
+        o.rot.clear();
+        o.mult.assign(nbs, {});
+        o.bank.assign(nbs, {});
+        for (auto& bk : o.bank) bk.fill(0);
+      };
+      auto flush = [&](Open& o) {
+        for (size_t t = 0; t < o.idx.size(); ++t) {
+          ordered.push_back(items[o.idx[t]]);
+          item_rot.push_back(o.rot[t]);
+        }
+        cut.push_back(ordered.size());
+        reset(o);
+      };
+      for (auto& o : open) reset(o);
+      for (size_t t = g0; t < g1; ++t) {
+        const int32_t* f = &h.node_flat[(int64_t)items[t].row * W];
+        int bs = 0, br = 0, bc = INT32_MAX;
+        for (int k = 0; k < kOpen; ++k) {
+          const int lane = (int)open[k].idx.size();
+          const int half = lane >> 5;
+          for (int r0 = 0; r0 < nbs; ++r0) {
+            const int r = (lane + r0) % nbs;
+            int cost = 0;
+            for (int i = 0; i < nbs; ++i) {
+              const int32_t sl = f[(i + r) % nbs];
+              if (sl == ONE || sl == R.hot[0] || sl == R.hot[1]) continue;
+              const auto m = open[k].mult[i].find(sl);
+              cost += 2 * (m == open[k].mult[i].end() ? 0 : m->second) + open[k].bank[i][16 * half + (sl & 15)];
+            }
+            if (cost < bc) {
+              bc = cost;
+              bs = k;
+              br = r;
+            }
+          }
+        }
+        Open& o = open[bs];
+        const int half = (int)o.idx.size() >> 5;
+        for (int i = 0; i < nbs; ++i) {
+          const int32_t sl = f[(i + br) % nbs];
+          o.mult[i][sl] += 1;
+          o.bank[i][16 * half + (sl & 15)] += 1;
+        }
+        o.idx.push_back(t);
+        o.rot.push_back(br);
+        if (o.idx.size() == 64) flush(o);
+      }
+      for (auto& o : open)
+        if (!o.idx.empty()) flush(o);
+      g0 = g1;
+    }
+  }
   int64_t pos = 0;
-  for (size_t i0 = 0; i0 < items.size();) {
-    size_t i1 = i0;
-    while (i1 < items.size() && i1 - i0 < 64 && items[i1].nb == items[i0].nb && items[i1].sig == items[i0].sig) ++i1;
+  size_t i0 = 0;
+  for (const size_t i1 : cut) {
+    const std::vector<Item>& items = ordered;   // the emission below reads the slice order
     const int ncol = items[i0].count;
     if ((int64_t)R.rlo.size() + 64 > INT32_MAX || pos + 64LL * ncol > INT32_MAX)
       throw std::length_error("remat schedule larger than 2^31 entries");
@@ -1253,36 +1334,8 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     if (R.fold) R.kbar.resize(P1 + e0 + 64 * (size_t)ncol, -1);
     // per lane: its entries, then their column and factor rotation
     std::vector<std::vector<int64_t>> lane_ents(64);
-    // each lane starts its row factor list at the position that adds the
-    // fewest same-address pushes to the slice's push instructions so far
-    // (push i of every lane goes to factor i of its rotated list; the hot
-    // slots, summed in registers, and the constant slot do not count)
     int rot[64] = {0};
-    {
-      const int nbs = items[i0].nb;
-      std::vector<std::map<int32_t, int>> mult(nbs);
-      for (int lane = 0; lane < 64 && i0 + lane < i1; ++lane) {
-        const Item& it = items[i0 + lane];
-        const int32_t* f = &h.node_flat[(int64_t)it.row * W];
-        int best = lane % nbs, best_cost = INT32_MAX;
-        for (int r0 = 0; r0 < nbs; ++r0) {
-          const int r = (lane + r0) % nbs;
-          int cost = 0;
-          for (int i = 0; i < nbs; ++i) {
-            const int32_t sl = f[(i + r) % nbs];
-            if (sl == ONE || sl == R.hot[0] || sl == R.hot[1]) continue;
-            const auto m = mult[i].find(sl);
-            cost += m == mult[i].end() ? 0 : m->second;
-          }
-          if (cost < best_cost) {
-            best_cost = cost;
-            best = r;
-          }
-        }
-        rot[lane] = best;
-        for (int i = 0; i < nbs; ++i) mult[i][f[(i + best) % nbs]] += 1;
-      }
-    }
+    for (int lane = 0; lane < 64; ++lane) rot[lane] = i0 + lane < i1 ? item_rot[i0 + lane] : 0;
     for (int lane = 0; lane < 64; ++lane) {
       if (i0 + lane < i1) {
         const Item& it = items[i0 + lane];
