@@ -70,10 +70,14 @@ def radial_deriv(nmax: int, r: np.ndarray, r_cut: float) -> np.ndarray:
 
 
 def spherical_coords(pos: np.ndarray):
-    """|r|, polar angle theta in [0, pi], azimuth phi in (-pi, pi]."""
+    """|r|, polar angle theta in [0, pi], azimuth phi in (-pi, pi].
+
+    theta = atan2(sqrt(x^2 + y^2), z): the same angle as arccos(z / r), which
+    loses accuracy within a few degrees of the z-axis (its error grows like
+    eps / theta^2), whereas this form keeps full relative accuracy there."""
     pos = np.asarray(pos, dtype=np.float64)
     r = np.sqrt(np.sum(pos * pos, axis=-1))
-    theta = np.arccos(np.clip(pos[..., 2] / r, -1.0, 1.0))
+    theta = np.arctan2(np.hypot(pos[..., 0], pos[..., 1]), pos[..., 2])
     phi = np.arctan2(pos[..., 1], pos[..., 0])
     return r, theta, phi
 

@@ -152,3 +152,30 @@ def test_pooled_A_is_sum_over_neighbours():
     np.testing.assert_allclose(A[0], vals[0] + vals[1] + vals[2], atol=1e-15)
     assert np.all(A[1] == 0)
     np.testing.assert_allclose(A[2], vals[3:7].sum(0), atol=1e-15)
+
+
+def test_onebody_values_near_the_poles_against_mpmath():
+    """Positions on and within 1e-12..1e-4 of the z-axis: the one-particle values
+    against mpmath (40 digits) from the exact spherical angles of the same
+    binary64 coordinates.  Computing the polar angle as arccos(z / r) would
+    lose about 1e-16 / theta^2 relative accuracy here."""
+    mpmath.mp.dps = 40
+    labels = [(n, l, m) for n in range(3) for l in range(5) for m in range(-l, l + 1)]
+    rng = np.random.default_rng(5)
+    pts = []
+    for sign in (1.0, -1.0):
+        for delta in (0.0, 1e-12, 1e-8, 1e-6, 1e-4):
+            r, beta = rng.uniform(1.0, 4.5), rng.uniform(-np.pi, np.pi)
+            pts.append(r * np.array([math.sin(delta) * math.cos(beta), math.sin(delta) * math.sin(beta),
+                                     sign * math.cos(delta)]))
+    pos = np.array(pts)
+    vals = ob.onebody_values(labels, pos, 5.0)
+    for j, p in enumerate(pos):
+        x, y, z = (mpmath.mpf(float(v)) for v in p)
+        rr = mpmath.sqrt(x * x + y * y + z * z)
+        th = mpmath.atan2(mpmath.sqrt(x * x + y * y), z)
+        ph = mpmath.atan2(y, x)
+        for i, (n, l, m) in enumerate(labels):
+            ref = complex(mpmath.cos(n * mpmath.pi * rr / 5) * mpmath.spherharm(l, m, th, ph))
+            scale = math.sqrt((2 * l + 1) / (4 * math.pi))
+            assert abs(vals[j, i] - ref) <= 1e-14 * scale, (j, n, l, m)
