@@ -71,8 +71,14 @@ typedef int32_t ace_status;
 
 /* flags of the evaluation calls */
 #define ACE_FLAG_NAIVE 1u  /* evaluate each tuple's product directly (baseline) */
-#define ACE_FLAG_CHECK 2u  /* validate offsets on the host before launching
-                              (synchronous copy of offsets; not capture safe) */
+#define ACE_FLAG_CHECK 2u  /* ace_eval / ace_eval_grad: validate the offsets on
+                              the device ahead of the launches that read them
+                              (offsets[0] = 0, non-decreasing); if invalid those
+                              launches read no environment and the outputs are
+                              unspecified.  The result stays in the workspace:
+                              read it with ace_check_offsets_result once the
+                              stream has been synchronised.  No synchronisation
+                              in the call: capture safe. */
 #define ACE_FLAG_LAYERED 4u /* evaluate the DAG layer by layer even where the
                               forest schedule applies (for testing) */
 #define ACE_FLAG_UNFOLDED 8u /* ace_eval / ace_eval_grad: evaluate every tuple of K
@@ -299,6 +305,16 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
                          const int32_t* offsets, const double* pos, double* phi,
                          double* grad, void* workspace, size_t ws_bytes,
                          uint32_t flags, void* stream);
+
+/*
+ * Result of the device-side validation of a call made with ACE_FLAG_CHECK
+ * (ace_eval or ace_eval_grad), read from the workspace that call used, after
+ * its stream has been synchronised (synchronous 4-byte copy):
+ * ACE_OK if the offsets were valid; ACE_ERR_INVALID_ARG, with the reason in
+ * ace_last_error(), if they were not (offsets[0] != 0 or a decrease).  The
+ * check does not see offsets[n_env] against the length of pos.
+ */
+ace_status ace_check_offsets_result(const void* workspace);
 
 /*
  * ace_eval_grad without a workspace argument, for callers that cannot

@@ -100,6 +100,7 @@ EXPORTED = {
     "ace_eval": ([_P, _P, _I64, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval_grad": ([_P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P], ctypes.c_int32),
     "ace_eval_grad_noalloc": ([_P, _P, _I64, _P, _P, _P, _P, _U32, _P], ctypes.c_int32),
+    "ace_check_offsets_result": ([_P], ctypes.c_int32),
     "ace_graph_get_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_graph_set_schedule": ([_P, ctypes.POINTER(_Opts)], ctypes.c_int32),
     "ace_debug_schedule": ([_P, ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int32),
@@ -333,6 +334,13 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _check_result(ws, device):
+    """Wait for the call and read its device-side offsets validation (ACE_FLAG_CHECK)."""
+    import torch
+    torch.cuda.current_stream(device).synchronize()
+    _check(lib().ace_check_offsets_result(ws.data_ptr()))
+
+
 def basis(g: Graph, offsets, pos):
     """A[e, i] (ace_basis); returns float64 [E, P1, 2]."""
     import torch
@@ -385,6 +393,8 @@ def eval(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: bool = F
     ws = g.workspace(E, pos.device, flags)
     _check(lib().ace_eval(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                           phi.data_ptr(), ws.data_ptr(), ws.numel(), flags, _stream(pos.device)))
+    if check and E > 0:
+        _check_result(ws, pos.device)
     return phi
 
 
@@ -409,6 +419,8 @@ def eval_grad(g: Graph, coeffs, offsets, pos, *, naive: bool = False, check: boo
     _check(lib().ace_eval_grad(g.handle, coeffs.data_ptr(), E, offsets.data_ptr(), pos.data_ptr(),
                                phi.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), flags,
                                _stream(pos.device)))
+    if check and E > 0:
+        _check_result(ws, pos.device)
     return phi, grad
 
 

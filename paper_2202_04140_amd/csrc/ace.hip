@@ -1908,6 +1908,7 @@ ace_status need_device(const ace_graph* g) {
 
 // workspace layout for n_env environments
 struct Workspace {
+  int32_t* status = nullptr;   // ACE_FLAG_CHECK: result of the offsets' validation (first bytes)
   double2* A = nullptr;
   double2* Abar = nullptr;
   double2* arena_x = nullptr;
@@ -1964,6 +1965,7 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char
     return reinterpret_cast<double2*>(r);
   };
   const size_t per_env = (size_t)g->P1 * sizeof(double2);
+  if (flags & ACE_FLAG_CHECK) w.status = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
   w.A = take((size_t)n_env * per_env);
   w.Abar = take((size_t)n_env * per_env);
   const bool layered = pick_schedule(g, true, flags) == Sched::Layered || pick_schedule(g, false, flags) == Sched::Layered;
@@ -1980,14 +1982,12 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char
   return w;
 }
 
-ace_status check_offsets(const int32_t* offsets, int64_t n_env, int64_t n_nbr, hipStream_t s) {
-  std::vector<int32_t> h((size_t)n_env + 1);
-  ACE_HIP(hipMemcpyAsync(h.data(), offsets, h.size() * 4, hipMemcpyDeviceToHost, s));
-  ACE_HIP(hipStreamSynchronize(s));
-  if (h[0] != 0) return fail(ACE_ERR_INVALID_ARG, "offsets[0] must be 0");
-  for (int64_t e = 0; e < n_env; ++e)
-    if (h[e + 1] < h[e]) return fail(ACE_ERR_INVALID_ARG, "offsets must be non-decreasing");
-  if (n_nbr >= 0 && h[n_env] != n_nbr) return fail(ACE_ERR_INVALID_ARG, "offsets[n_env] must equal n_nbr");
+// ACE_FLAG_CHECK: validate the offsets on the device, ahead of the launches
+// that read them (which then read no environment if they are invalid); the
+// result stays in the workspace for ace_check_offsets_result.  Capture safe.
+ace_status launch_check(const int32_t* offsets, int64_t n_env, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(check_offsets_kernel, dim3(1), dim3(1024), 0, s, offsets, n_env, status);
+  ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
 
@@ -2044,7 +2044,7 @@ bool same_prep(const CoefPrep& a, const CoefPrep& b) {
 // prep (may be NULL): a DAG launch's coefficient preparation, done on the
 // basis kernel's grid (O(3)) or launched before the planar basis kernel.
 ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offsets, const double* pos, double2* A,
-                        hipStream_t s, const CoefPrep* prep) {
+                        hipStream_t s, const CoefPrep* prep, const int32_t* gate = nullptr) {
   if (g->h.spec.group != 0) {
     if (prep) {
       const ace_status st = launch_prep(*prep, s);
@@ -2062,6 +2062,7 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
     a.r_cut = g->h.spec.r_cut;
     a.group = g->h.spec.group;
     a.pos_stride = 3;
+    a.gate = gate;
     const size_t lds = (size_t)g->P1 * 16 + (size_t)kPlanarChunk * (((a.n_max + 1) + 2 * (a.l_max + 1)) | 1) * 8;
     if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the basis kernel");
     hipLaunchKernelGGL(planar_basis_kernel, dim3((unsigned)grid_for(n_env)), dim3(kBasisThreads), lds, s, a);
@@ -2084,6 +2085,7 @@ ace_status launch_basis(const ace_graph* g, int64_t n_env, const int32_t* offset
   a.pos_stride = a.k_max > 0 ? 4 : 3;
   a.prim = g->d_basis_prim;
   a.n_prim = (int)g->basis_prim.size();
+  a.gate = gate;
   if (prep) a.prep = *prep;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const int chunk = kBasisThreads / (a.l_max + 1);
@@ -2327,7 +2329,7 @@ ace_status launch_naive(const ace_graph* g, const double* coeffs, int64_t n_env,
 }
 
 ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets, const double* pos,
-                       const double2* Abar, double* grad, hipStream_t s) {
+                       const double2* Abar, double* grad, hipStream_t s, const int32_t* gate = nullptr) {
   if (g->h.spec.group != 0) {
     GradArgs a{};
     a.n_env = n_env;
@@ -2342,6 +2344,7 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
     a.group = g->h.spec.group;
     a.pidx = g->d_onep_index;
     a.pos_stride = 3;
+    a.gate = gate;
     const int NR = g->h.spec.group == 2 ? a.n_max : 0;
     const size_t lds = (size_t)g->P1 * sizeof(double2) +
                        (size_t)kPlanarChunk * (((kPlanarNbr + 2 * (NR + 1) + 2 * (a.l_max + 1)) | 1) + 2) * 8;
@@ -2366,6 +2369,7 @@ ace_status launch_grad(const ace_graph* g, int64_t n_env, const int32_t* offsets
   a.group = 0;
   a.k_max = g->h.spec.k_max;
   a.pos_stride = a.k_max > 0 ? 4 : 3;
+  a.gate = gate;
   const int NY = (a.l_max + 1) * (a.l_max + 2) / 2;
   const size_t lds = (g->gsrc.size() / 2) * sizeof(double2) + (size_t)((3 * NY + 1) & ~1) * 8 +
                      (size_t)kGradChunk * (grad_nbr_doubles(a.n_max) + 3) * 8;
@@ -2535,19 +2539,19 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
   if (st != ACE_OK || n_env == 0) return st;
   if (!offsets || !pos || !phi) return fail(ACE_ERR_INVALID_ARG, "offsets, pos and phi must be non-NULL");
   hipStream_t s = (hipStream_t)stream;
+  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   if (flags & ACE_FLAG_CHECK) {
-    st = check_offsets(offsets, n_env, -1, s);
+    st = launch_check(offsets, n_env, w.status, s);
     if (st != ACE_OK) return st;
   }
-  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   if (flags & ACE_FLAG_NAIVE) {
-    st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr);
+    st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr, w.status);
     if (st != ACE_OK) return st;
     return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
   }
   // the DAG launch's coefficients are prepared on the basis kernel's grid
   const CoefPrep prep = dag_prep(g, coeffs, w, false, flags, true);
-  st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep);
+  st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep, w.status);
   if (st != ACE_OK) return st;
   return launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s, flags, true, &prep);
 }
@@ -2561,24 +2565,36 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
   if (!offsets || !pos || !phi || !grad)
     return fail(ACE_ERR_INVALID_ARG, "offsets, pos, phi and grad must be non-NULL");
   hipStream_t s = (hipStream_t)stream;
+  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   if (flags & ACE_FLAG_CHECK) {
-    st = check_offsets(offsets, n_env, -1, s);
+    st = launch_check(offsets, n_env, w.status, s);
     if (st != ACE_OK) return st;
   }
-  const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   if (flags & ACE_FLAG_NAIVE) {
-    st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr);
+    st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr, w.status);
     if (st != ACE_OK) return st;
     st = launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, s);
   } else {
     // the DAG launch's coefficients are prepared on the basis kernel's grid
     const CoefPrep prep = dag_prep(g, coeffs, w, true, flags, true);
-    st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep);
+    st = launch_basis(g, n_env, offsets, pos, w.A, s, &prep, w.status);
     if (st != ACE_OK) return st;
     st = launch_dag(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s, flags, true, &prep);
   }
   if (st != ACE_OK) return st;
-  return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s);
+  return launch_grad(g, n_env, offsets, pos, w.Abar, grad, s, w.status);
+}
+
+ace_status ace_check_offsets_result(const void* workspace) {
+  if (!workspace) return fail(ACE_ERR_INVALID_ARG, "workspace is NULL");
+  int32_t v = -1;
+  ACE_HIP(hipMemcpy(&v, workspace, sizeof(v), hipMemcpyDeviceToHost));
+  switch (v) {
+    case 0: return ACE_OK;
+    case 1: return fail(ACE_ERR_INVALID_ARG, "offsets[0] must be 0 (device-side validation)");
+    case 2: return fail(ACE_ERR_INVALID_ARG, "offsets must be non-decreasing (device-side validation)");
+    default: return fail(ACE_ERR_INVALID_ARG, "no offsets validation result in this workspace");
+  }
 }
 
 ace_status ace_eval_grad_noalloc(const ace_graph* g, const double* coeffs, int64_t n_env, const int32_t* offsets,

@@ -62,6 +62,8 @@ struct BasisArgs {
   const int16_t* prim;   // O(3): [n_prim] indices of the functions with m >= 0
   int n_prim;
   CoefPrep prep;         // O(3): the next DAG launch's coefficients, prepared on this grid
+  const int32_t* gate;   // device status of the offsets' validation (ACE_FLAG_CHECK): nonzero
+                         // means invalid and no environment is read; nullptr: no validation
 };
 
 // Planar one-particle functions (torus, SO(2)): phi_i = R_n(r) e^{i s m theta}
@@ -117,6 +119,7 @@ struct GradArgs {
   int k_max;                 // O(3) feature degree
   int pos_stride;            // doubles per position: 3, or 4 with a feature
   int nb;                    // O(3): entries per (l, m) of the staged Abar (odd, >= (n_max+1)(k_max+1))
+  const int32_t* gate;       // as BasisArgs::gate
 };
 
 }  // namespace ace

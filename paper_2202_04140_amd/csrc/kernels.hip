@@ -111,6 +111,30 @@ __device__ __forceinline__ void prep_on_grid(const CoefPrep& c) {
 }
 
 // ---------------------------------------------------------------------------
+// device-side validation of CSR offsets (ACE_FLAG_CHECK)
+// ---------------------------------------------------------------------------
+// status = 0 if offsets[0] == 0 and offsets[0..n_env] is non-decreasing,
+// 1 if offsets[0] != 0, 2 if a later entry decreases.  One block; always
+// writes status, so no clearing is needed.
+__global__ __launch_bounds__(1024) void check_offsets_kernel(const int32_t* offsets, int64_t n_env, int32_t* status) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = offsets[0] != 0 ? 1 : 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t e = threadIdx.x; e < n_env; e += blockDim.x)
+    if (offsets[e + 1] < offsets[e]) mine = 2;
+  if (mine) atomicMax(&bad, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *status = bad;
+}
+
+// Environments a basis or gradient launch reads: none when a validation
+// ahead of it on the stream found the offsets invalid.
+__device__ __forceinline__ int64_t gated_envs(int64_t n_env, const int32_t* gate) {
+  return gate == nullptr || *gate == 0 ? n_env : 0;
+}
+
+// ---------------------------------------------------------------------------
 // one-particle basis
 // ---------------------------------------------------------------------------
 constexpr int kBasisBlock = 256;
@@ -145,7 +169,8 @@ __global__ __launch_bounds__(kBasisBlock) void basis_kernel(BasisArgs p) {
   // the coefficient preparation of the DAG launch that follows (independent
   // of this kernel's own work; one launch fewer per step)
   prep_on_grid(p.prep);
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+  const int64_t n_env = gated_envs(p.n_env, p.gate);
+  for (int64_t e = blockIdx.x; e < n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
     for (int i = threadIdx.x; i < p.P1; i += blockDim.x) acc[i] = make_double2(0.0, 0.0);
@@ -443,7 +468,8 @@ __global__ __launch_bounds__(64, 4) void grad_kernel(GradArgs p) {
   const double* cA = yc;
   const double* cB = yc + NY;
   const double* cS = yc + 2 * NY;
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+  const int64_t n_env = gated_envs(p.n_env, p.gate);
+  for (int64_t e = blockIdx.x; e < n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
     if (J <= 0) continue;   // block-uniform
@@ -679,7 +705,8 @@ __global__ __launch_bounds__(256) void planar_basis_kernel(BasisArgs p) {
   const double kr = M_PI / p.r_cut;
   double2* acc = reinterpret_cast<double2*>(lds_p);   // [P1]
   double* tab = lds_p + 2 * p.P1;                      // [kPlanarChunk][stride]
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+  const int64_t n_env = gated_envs(p.n_env, p.gate);
+  for (int64_t e = blockIdx.x; e < n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
     __syncthreads();
@@ -752,7 +779,8 @@ __global__ __launch_bounds__(256) void planar_grad_kernel(GradArgs p) {
   double* tab = reinterpret_cast<double*>(Ab + p.P1);              // [kPlanarChunk][stride]
   double* gacc = tab + kPlanarChunk * stride;                      // [kPlanarChunk][2]
   const int NU = (N + 1) * (M + 1);                                // (n, |m|) units per neighbour
-  for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
+  const int64_t n_env = gated_envs(p.n_env, p.gate);
+  for (int64_t e = blockIdx.x; e < n_env; e += gridDim.x) {
     const int j0 = p.offsets[e];
     const int J = p.offsets[e + 1] - j0;
     __syncthreads();

@@ -30,6 +30,24 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def per_env_max(phi, phi_ref, grad, grad_ref, offsets):
+    """Largest per-environment relative errors: |phi_e - ref_e| / |ref_e| over the
+    environments with |ref_e| >= 1e-6 RMS(ref) (the others are only counted), and
+    ||g_e - ref_e|| / ||ref_e|| over each environment's gradient rows."""
+    phi, phi_ref = np.asarray(phi), np.asarray(phi_ref)
+    mag = np.abs(phi_ref)
+    ok = mag >= 1e-6 * np.sqrt(np.mean(mag ** 2))
+    e_phi = float(np.max(np.abs(phi - phi_ref)[ok] / mag[ok])) if ok.any() else 0.0
+    e_g = 0.0
+    off = np.asarray(offsets, dtype=np.int64)
+    for e in range(len(off) - 1):
+        a, b = off[e], off[e + 1]
+        nr = np.linalg.norm(grad_ref[a:b])
+        if b > a and nr > 0:
+            e_g = max(e_g, float(np.linalg.norm(grad[a:b] - grad_ref[a:b]) / nr))
+    return e_phi, e_g, int((~ok).sum())
+
+
 _ORACLE = {}
 _GRAPH = {}
 
@@ -302,20 +320,39 @@ def test_full_size_sampled_and_dag_vs_naive(device):
     assert rel(grad[rows], g_ref) <= TOL_GRAD
 
 
-@pytest.mark.parametrize("wid,n_sample", [(3, 24), (4, 8), (5, 3)])
+def stored_oracle_sample(wid, off, pos, c):
+    """The oracle's phi and gradients on a seeded subset of a workload, written by
+    tests/golden/make_oracle_samples.py (oracle only); the inputs are checked
+    against the fingerprint stored with them."""
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    from make_oracle_samples import fingerprint, path_for
+    d = np.load(path_for(wid))
+    envs = d["envs"]
+    so, sp_ = wl.gather(off, pos, envs)
+    assert np.array_equal(so, d["offsets"])
+    assert str(d["fingerprint"]) == fingerprint(sp_, c), "inputs differ from those of the stored oracle values"
+    return envs, so, d["phi"], d["grad"]
+
+
+@pytest.mark.parametrize("wid,n_sample", [(3, 24), (4, 64), (5, 64)])
 def test_full_size_in_benchmark_schedule(device, wid, n_sample, tmp_path, monkeypatch):
     """Every environment of the 4096-, 32768- and 8192-environment workloads in one
     ace_eval_grad call, in the schedule the benchmark applies to that batch (the
     shipped autotuned choice: an empty user cache, as on a fresh machine); sampled
     environments (the smallest and largest neighbour counts among them) against the
-    oracle, all of them against the naive kernel."""
+    oracle (live for the 4096-environment basis, stored oracle values for the two
+    larger ones), all of them against the naive kernel; norm-wise over the batch
+    and per environment."""
     import paper_2202_04140_amd as ace
     from paper_2202_04140_amd import autotune
     monkeypatch.setenv("ACE_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
     w = wl.WORKLOADS[wid]
     G = ace.Graph(w.nu_max, w.degree_max, w.n_max, w.l_max, r_cut=w.r_cut)
-    g, K, c = oracle_basis(wid)
     off, pos = problem(wid)
+    c = wl.coefficients(w, G.k_degrees())
     print(f"full size wid={wid} n_env={len(off) - 1} n_nbr={len(pos)}", flush=True)
     tc, toff, tpos = to_dev(device, c, off, pos)
     tuned = autotune.tune(G, tc, ace.basis(G, toff, tpos))
@@ -327,14 +364,24 @@ def test_full_size_in_benchmark_schedule(device, wid, n_sample, tmp_path, monkey
     assert np.isfinite(phi).all() and np.isfinite(grad).all()
     assert rel(phi, phi_n) <= TOL_PHI
     assert rel(grad, grad_n) <= TOL_GRAD
-    envs = wl.subset(off, n_sample)
+    e_phi, e_g, _ = per_env_max(phi, phi_n, grad, grad_n, off)
+    assert e_phi <= TOL_PHI and e_g <= TOL_GRAD
     J = np.diff(off)
+    if wid == 3:
+        g, K, c_or = oracle_basis(wid)
+        assert np.array_equal(c_or, c)
+        envs = wl.subset(off, n_sample)
+        so, sp_ = wl.gather(off, pos, envs)
+        phi_ref, g_ref = oc.grad_naive(g.labels, K, c, so, sp_, w.r_cut)
+    else:
+        envs, so, phi_ref, g_ref = stored_oracle_sample(wid, off, pos, c)
+    assert len(envs) == n_sample
     assert J[envs].min() == J.min() and J[envs].max() == J.max()
-    so, sp_ = wl.gather(off, pos, envs)
-    phi_ref, g_ref = oc.grad_naive(g.labels, K, c, so, sp_, w.r_cut)
     rows = np.concatenate([np.arange(off[e], off[e + 1]) for e in envs])
     assert rel(phi[envs], phi_ref) <= TOL_PHI
     assert rel(grad[rows], g_ref) <= TOL_GRAD
+    e_phi, e_g, _ = per_env_max(phi[envs], phi_ref, grad[rows], g_ref, so)
+    assert e_phi <= TOL_PHI and e_g <= TOL_GRAD
 
 
 # ---- edge cases ----------------------------------------------------------------------
@@ -365,7 +412,11 @@ def test_edge_cases_empty_ragged(device):
 
 
 def test_invalid_offsets_rejected_with_check(device):
+    """ACE_FLAG_CHECK validates the offsets on the device (no synchronisation in
+    the call, so it can be captured); the result is read from the workspace
+    afterwards.  Invalid offsets make the launches that read them do nothing."""
     import paper_2202_04140_amd as ace
+    import torch
     G = graph(1, device)
     _, _, c = oracle_basis(1)
     off = np.array([0, 5, 3], np.int32)   # decreasing
@@ -373,13 +424,45 @@ def test_invalid_offsets_rejected_with_check(device):
     tc, toff, tpos = to_dev(device, c, off, pos)
     with pytest.raises((ace.AceError, ValueError)):   # binding check
         ace.eval(G, tc, toff, tpos, check=True)
-    # the library's own check (ACE_FLAG_CHECK) without the binding in front
-    import torch
+    lib = ace.lib()
     phi = torch.empty((2, 2), dtype=torch.float64, device=device)
-    ws = G.workspace(2, device)
-    st = ace.lib().ace_eval(G.handle, tc.data_ptr(), 2, toff.data_ptr(), tpos.data_ptr(), phi.data_ptr(),
-                            ws.data_ptr(), ws.numel(), ace.FLAG_CHECK, None)
-    assert st == 1 and b"non-decreasing" in ace.lib().ace_last_error()
+    grad = torch.full((5, 3), 7.0, dtype=torch.float64, device=device)
+    ws = G.workspace(2, device, ace.FLAG_CHECK)
+    # the library's own check without the binding in front
+    for bad, msg in (([0, 5, 3], b"non-decreasing"), ([1, 3, 5], b"offsets[0]")):
+        toff.copy_(torch.tensor(bad, dtype=torch.int32))
+        st = lib.ace_eval(G.handle, tc.data_ptr(), 2, toff.data_ptr(), tpos.data_ptr(), phi.data_ptr(),
+                          ws.data_ptr(), ws.numel(), ace.FLAG_CHECK, ace._stream(device))
+        assert st == 0
+        torch.cuda.synchronize()
+        assert lib.ace_check_offsets_result(ws.data_ptr()) == 1 and msg in lib.ace_last_error()
+    # inside a captured graph: the same launch sequence, replayed with valid
+    # and with invalid offsets (written between replays)
+    toff.copy_(torch.tensor([0, 2, 5], dtype=torch.int32))
+    def call():
+        st = lib.ace_eval_grad(G.handle, tc.data_ptr(), 2, toff.data_ptr(), tpos.data_ptr(), phi.data_ptr(),
+                               grad.data_ptr(), ws.data_ptr(), ws.numel(), ace.FLAG_CHECK, ace._stream(device))
+        assert st == 0
+    call()
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        call()
+    torch.cuda.synchronize()
+    g, K, _ = oracle_basis(1)
+    for valid in (True, False, True):
+        toff.copy_(torch.tensor([0, 2, 5] if valid else [0, 5, 3], dtype=torch.int32))
+        grad.fill_(7.0)
+        gr.replay()
+        torch.cuda.synchronize()
+        st = lib.ace_check_offsets_result(ws.data_ptr())
+        if valid:
+            assert st == 0
+            _, g_ref = oc.grad_naive(g.labels, K, c, np.array([0, 2, 5]), pos, 5.0)
+            assert rel(grad.cpu().numpy(), g_ref) <= TOL_GRAD
+        else:
+            assert st == 1 and b"non-decreasing" in lib.ace_last_error()
+            assert torch.all(grad == 7.0)   # the gradient launch read nothing
 
 
 def test_workspace_too_small_is_an_error(device):
@@ -448,6 +531,89 @@ def test_invariance_and_determinism(device):
     perm = np.concatenate([off[e] + rng.permutation(off[e + 1] - off[e]) for e in range(len(off) - 1)])
     phip = cplx(ace.eval(G, tc, toff, torch.from_numpy(pos[perm]).to(device)))
     assert rel(phip, phi0) <= 1e-12
+
+
+# ---- gradients on and near the z-axis (theta = 0, pi) --------------------------------
+def test_gradient_at_and_near_the_poles(device):
+    """Neighbours exactly on +-z and at angles 1e-12, 1e-8 and 1e-4 from it, beside
+    random ones: the gradient (Cartesian recurrences, no division by sin(theta))
+    against differences of the oracle's phi, which is smooth there: a central
+    difference with h = 1e-6 within 1e-6 and a five-point stencil with h = 1e-3
+    within 1e-8, and against the oracle's gradient within 1e-9 where
+    sin(theta) >= 1e-4 (the oracle's gradient divides by sin(theta))."""
+    import paper_2202_04140_amd as ace
+    wid = 1
+    w = wl.WORKLOADS[wid]
+    G = graph(wid, device)
+    g, K, c = oracle_basis(wid)
+    rng = np.random.default_rng(11)
+    special = []
+    for sign in (1.0, -1.0):
+        for delta in (0.0, 1e-12, 1e-8, 1e-4):
+            r = rng.uniform(1.0, 4.5)
+            beta = rng.uniform(-np.pi, np.pi)
+            special.append(r * np.array([math.sin(delta) * math.cos(beta), math.sin(delta) * math.sin(beta),
+                                         sign * math.cos(delta)]))
+    # one environment per special neighbour, with three random neighbours beside it
+    others = wl.positions(3 * len(special), 91)
+    pos = np.concatenate([np.concatenate([sp[None, :], others[3 * i:3 * i + 3]]) for i, sp in enumerate(special)])
+    off = np.arange(0, 4 * len(special) + 1, 4, dtype=np.int32)
+    print(f"poles: {len(special)} environments", flush=True)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    _, grad = ace.eval_grad(G, tc, toff, tpos)
+    grad = grad.cpu().numpy()
+    assert np.isfinite(grad).all()
+    rows = off[:-1]                                   # the special neighbour of each environment
+
+    def phi_re(p):
+        return oc.eval_naive(g.labels, K, c, off, p, w.r_cut).real
+
+    def diff(h, stencil):
+        out = np.zeros((len(rows), 3))
+        for d in range(3):
+            acc = np.zeros(len(rows))
+            for wgt, step in stencil:
+                p = pos.copy()
+                p[rows, d] += step * h
+                acc += wgt * phi_re(p)
+            out[:, d] = acc / h
+        return out
+
+    g_cd = diff(1e-6, [(0.5, 1.0), (-0.5, -1.0)])
+    g_5p = diff(1e-3, [(-1 / 12, 2.0), (2 / 3, 1.0), (-2 / 3, -1.0), (1 / 12, -2.0)])
+    assert rel(grad[rows], g_cd) <= 1e-6
+    assert rel(grad[rows], g_5p) <= 1e-8
+    for i in range(len(rows)):
+        assert np.linalg.norm(grad[rows[i]] - g_5p[i]) <= 1e-8 * np.linalg.norm(g_5p), i
+    # oracle gradient where sin(theta) >= 1e-4 for every neighbour of the environment
+    far = [i for i in range(len(special)) if np.hypot(*special[i][:2]) >= 0.99e-4 * np.linalg.norm(special[i])]
+    assert len(far) == 2
+    for i in far:
+        so = np.array([0, 4], dtype=np.int32)
+        _, g_ref = oc.grad_naive(g.labels, K, c, so, pos[4 * i:4 * i + 4], w.r_cut)
+        assert rel(grad[4 * i:4 * i + 4], g_ref) <= TOL_GRAD
+
+
+@pytest.mark.parametrize("wid,n_env", [(3, 256), (5, 16)])
+def test_eval_grad_repeatable(device, wid, n_env):
+    """The same ace_eval_grad call twice: phi is bitwise repeatable (fixed
+    summation order); the reverse pass adds adjoints with LDS atomics in an
+    order that may change from run to run, so the gradients are compared within
+    1e-13 (norm-wise and per environment), far below the 1e-9 target."""
+    import paper_2202_04140_amd as ace
+    w = wl.WORKLOADS[wid]
+    G = graph(wid, device)
+    c = wl.coefficients(w, G.k_degrees())
+    off, pos = problem(wid, n_env)
+    print(f"repeat wid={wid} n_env={n_env}", flush=True)
+    tc, toff, tpos = to_dev(device, c, off, pos)
+    runs = [ace.eval_grad(G, tc, toff, tpos) for _ in range(3)]
+    phis = [cplx(p) for p, _ in runs]
+    grads = [gr.cpu().numpy() for _, gr in runs]
+    for k in (1, 2):
+        assert np.array_equal(phis[k], phis[0])
+        assert rel(grads[k], grads[0]) <= 1e-13
+        assert per_env_max(phis[k], phis[0], grads[k], grads[0], off)[1] <= 1e-13
 
 
 def test_autograd_function(device):

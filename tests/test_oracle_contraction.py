@@ -202,3 +202,34 @@ def test_empty_environment_and_nu1():
     ref = sum(A[k[0]] for k in K1)
     got = oc.eval_naive(g.labels, K1, np.ones(len(K1)), np.array([0, 3]), pos, RCUT)[0]
     assert abs(got - ref) <= 1e-14 * abs(ref)
+
+
+def test_stored_oracle_samples_reproduce():
+    """The stored oracle values of the 32768-environment workload (written by
+    tests/golden/make_oracle_samples.py) match their inputs' fingerprint and a
+    live oracle run on two of their environments (the smallest and the largest
+    neighbour count)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from make_oracle_samples import fingerprint, path_for
+    import workloads as wl
+    from oracle.contraction import grad_naive
+    from oracle.indexsets import all_invariant_tuples, group_o3
+    w = wl.WORKLOADS[4]
+    g = group_o3(w.n_max, w.l_max, w.degree_max)
+    K = all_invariant_tuples(g, w.nu_max, w.degree_max)
+    c = wl.coefficients(w, np.array([g.degree(k) for k in K]))
+    off, pos = wl.batch(w)
+    d = np.load(path_for(4))
+    envs = d["envs"]
+    so, sp_ = wl.gather(off, pos, envs)
+    assert np.array_equal(so, d["offsets"]) and str(d["fingerprint"]) == fingerprint(sp_, c)
+    J = np.diff(off)
+    for e in (int(envs[np.argmin(J[envs])]), int(envs[np.argmax(J[envs])])):
+        i = int(np.nonzero(envs == e)[0][0])
+        o1, p1 = wl.gather(off, pos, [e])
+        phi, grad = grad_naive(g.labels, K, c, o1, p1, w.r_cut)
+        assert abs(phi[0] - d["phi"][i]) <= 1e-13 * abs(phi[0])
+        rows = slice(int(so[i]), int(so[i + 1]))
+        assert np.allclose(grad, d["grad"][rows], rtol=1e-12, atol=1e-14 * np.abs(grad).max())
