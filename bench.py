@@ -66,22 +66,41 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def profile_key(workload: int, schedule: dict) -> str:
+    """What a counter profile was taken on: the kernel and schedule-builder
+    sources, the schedule options and the workload (together they fix the
+    code object and the uploaded schedule arrays)."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(source_hash().encode())
+    h.update(json.dumps(schedule, sort_keys=True).encode())
+    h.update(str(workload).encode())
+    return h.hexdigest()[:16]
+
+
 def traffic_path(workload: int) -> str:
     return os.path.join(ROOT, "profiles", f"dag_kernel_traffic_w{workload}.json")
 
 
-def profiled_traffic(workload: int):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    profile, or None if absent or taken on different kernel sources."""
-    path = traffic_path(workload)
+def counters_path(workload: int) -> str:
+    return os.path.join(ROOT, "profiles", f"dag_kernel_counters_w{workload}.json")
+
+
+def _profile(path: str, workload: int, schedule: dict):
+    """A committed counter profile if it was taken on this workload, these
+    sources and this schedule, else None."""
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != source_hash() or d.get("workload") != workload:
-        return None
-    return d.get("bytes_per_launch")
+    return d if d.get("key") == profile_key(workload, schedule) else None
+
+
+def profiled_traffic(workload: int, schedule: dict):
+    """HBM bytes per launch of the dominant kernel from the committed counter profile."""
+    d = _profile(traffic_path(workload), workload, schedule)
+    return None if d is None else d.get("bytes_per_launch")
 
 
 # ---------------------------------------------------------------------------
@@ -201,7 +220,38 @@ def pmc_table(dbs) -> dict:
     return out
 
 
-def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, out_path: str) -> dict:
+def _dominant_dag_kernel(table: dict) -> str:
+    names = [n for n in table if "forest_kernel<true" in n or "remat_kernel<true" in n]
+    if not names:
+        raise RuntimeError("no forward + reverse DAG dispatch in the counter databases")
+    return max(names, key=lambda n: table[n]["dispatches"])
+
+
+def summarize_counters(dbs, workload: int, schedule: dict, out_path: str) -> dict:
+    """Mean per dispatch of every counter of the dominant DAG kernel (the forest
+    or remat kernel with its adjoint) over rocprofv3 counter databases, with
+    the quantities derived from them."""
+    table = pmc_table(dbs)
+    kernel = _dominant_dag_kernel(table)
+    v = table[kernel]
+    out = dict(workload=workload, key=profile_key(workload, schedule), schedule=schedule, kernel=kernel,
+               counters=v)
+    if "SQ_INSTS_VALU_FLOPS_FP64" in v:
+        # the counter adds 1 per FP64 add/mul and 2 per FMA of a wave; x64 lanes
+        out["fp64_flops_per_launch"] = 64.0 * v["SQ_INSTS_VALU_FLOPS_FP64"]
+    if "GRBM_GUI_ACTIVE" in v and "SQ_ACTIVE_INST_VALU" in v:
+        cyc = v["GRBM_GUI_ACTIVE"] / 8.0                        # per XCD
+        out["cycles"] = cyc
+        out["valu_busy"] = 4.0 * v["SQ_ACTIVE_INST_VALU"] / (1024.0 * cyc)   # quad-cycles over 1024 SIMDs
+        out["lds_active"] = v["SQ_LDS_IDX_ACTIVE"] / (256.0 * cyc)
+        out["lds_bank_conflict_share"] = v["SQ_LDS_BANK_CONFLICT"] / max(1.0, v["SQ_LDS_IDX_ACTIVE"])
+        out["waves_per_cu"] = 4.0 * v["SQ_WAVE_CYCLES"] / max(1.0, v["SQ_BUSY_CU_CYCLES"])
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, schedule: dict, out_path: str) -> dict:
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the fused forward +
     reverse DAG kernel (the forest or remat kernel with its adjoint, whichever
     the run dispatched most), scaled by what the same counters read for a
@@ -225,7 +275,7 @@ def summarize_pmc(fetch_db: str, write_db: str, copy_mib: int, workload: int, ou
                             kernel_dispatches=len(dag))
     fetch_b = res["FETCH_SIZE"]["kernel_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
     write_b = res["WRITE_SIZE"]["kernel_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
-    out = dict(workload=workload, source_hash=source_hash(), kernel=kernel,
+    out = dict(workload=workload, key=profile_key(workload, schedule), schedule=schedule, kernel=kernel,
                copy_mib=copy_mib, fetch_bytes=fetch_b, write_bytes=write_b, bytes_per_launch=fetch_b + write_b,
                counters=res)
     with open(out_path, "w") as f:
@@ -314,6 +364,12 @@ def main():
                     help="timed steps of the naive baseline when one of its steps takes over 50 ms")
     ap.add_argument("--no-naive", action="store_true",
                     help="skip the naive baseline (for profiling runs)")
+    ap.add_argument("--record-schedule", metavar="PATH",
+                    help="write the schedule options the run applied to PATH (for the counter summaries)")
+    ap.add_argument("--pmc-counters", nargs="+", metavar="DB",
+                    help="reduce rocprofv3 counter databases of runs that wrote --record-schedule to "
+                         "profiles/dag_kernel_counters_w<workload>.json and exit (needs --schedule-file)")
+    ap.add_argument("--schedule-file", metavar="PATH", help="schedule options written by --record-schedule")
     ap.add_argument("--pmc-table", nargs="+", metavar="DB",
                     help="print the mean per dispatch of every counter in these rocprofv3 databases, "
                          "per kernel, as JSON, and exit")
@@ -339,9 +395,16 @@ def main():
     if args.pmc_table:
         print(json.dumps(pmc_table(args.pmc_table), indent=1))
         return
-    if args.pmc_summary:
-        out = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy or 512, args.workload,
-                            traffic_path(args.workload))
+    if args.pmc_summary or args.pmc_counters:
+        with open(args.schedule_file) as f:
+            rec = json.load(f)
+        if rec["workload"] != args.workload or rec["source_hash"] != source_hash():
+            raise SystemExit("the schedule file belongs to another workload or other sources")
+        if args.pmc_counters:
+            out = summarize_counters(args.pmc_counters, args.workload, rec["schedule"], counters_path(args.workload))
+        else:
+            out = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy or 512, args.workload,
+                                rec["schedule"], traffic_path(args.workload))
         print(json.dumps(out))
         return
     if args.gpus != 1:
@@ -428,6 +491,10 @@ def main():
         print(f"[bench] schedule {tuned['opts']} ({'cached' if tuned['cached'] else 'tuned'})",
               file=sys.stderr, flush=True)
 
+    if args.record_schedule:
+        with open(args.record_schedule, "w") as f:
+            json.dump(dict(workload=args.workload, source_hash=source_hash(), schedule=G.get_schedule()), f)
+
     def step_dag():
         ace.eval_grad(G, tc, toff, tpos, out=(phi, grad))
 
@@ -472,6 +539,8 @@ def main():
     kernel_name = {"forest": "forest_kernel", "remat": "remat_kernel", "layered": "dag_kernel"}[kind] + \
         " (forward + reverse)"
     achieved = fl["total"] * E / (ms_kernel * 1e-3) / 1e12
+    sched = G.get_schedule()
+    prof = _profile(counters_path(args.workload), args.workload, sched)
 
     # parity of the timed results
     def rel(a, b):
@@ -534,7 +603,16 @@ def main():
                               "a DAG-equivalent rate: the remat kernel recomputes parents and "
                               "evaluates one tuple per conjugate pair",
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": profiled_traffic(args.workload), "kernel_ms": ms_kernel, "flops_per_env": fl},
+                     "traffic": profiled_traffic(args.workload, sched), "kernel_ms": ms_kernel,
+                     "flops_per_env": fl,
+                     "executed": None if prof is None or "fp64_flops_per_launch" not in prof else {
+                         "fp64_flops_per_launch": prof["fp64_flops_per_launch"],
+                         "achieved": prof["fp64_flops_per_launch"] / (ms_kernel * 1e-3) / 1e12,
+                         "frac": prof["fp64_flops_per_launch"] / (ms_kernel * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "valu_busy": prof.get("valu_busy"), "lds_active": prof.get("lds_active"),
+                         "lds_bank_conflict_share": prof.get("lds_bank_conflict_share"),
+                         "note": "FP64 VALU operations the kernel executes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes, "
+                                 "committed counter profile of this schedule) over the launch time"}},
         "eager_ms_per_step": ms_dag_eager,
         "step_ms_distribution": dist,
         "timing": "eager launches" if args.eager else "hipGraph replays of one captured step",

@@ -132,9 +132,9 @@ def test_builder_matches_hand_worked_torus_graph(alg, n):
 
 
 # Regression values: |K| per order, V, aux per order, depth, layer sizes, stored and
-# childless product nodes, leaves with children, naive complex products.  Computed
-# once from the definitions (Algorithm 1 with the fixed split order); the first two
-# rows are reproduced independently by the oracle builder in the test above.
+# childless product nodes, leaves with children, naive complex products.  Every row
+# equals the oracle builder's own statistics (test_builder_bit_exact_large for the
+# third; the first two come out of the bit-exact tests above).
 REGRESSION = {
     (4, 4, 8, 3): dict(k=[15, 228, 959], V=1440, aux=[128], depth=2, layers=[125, 356, 959],
                        S=356, T=959, leafpar=93, naive=2146),
@@ -161,13 +161,53 @@ def test_builder_regression_counts(spec):
     assert st["naive_cmuls"] == r["naive"]
 
 
-@pytest.mark.slow
-def test_builder_large_basis_counts():
-    st = ace.Graph(6, 16, 10, 10, host_only=True).stats()
-    assert st["n_k"] == 3692953
-    assert st["n_nodes"] == 3705306
-    assert st["n_aux_by_order"][2:6] == [4944, 4641, 1373, 314]
-    assert st["n_stored"] == 256091 and st["n_childless"] == 3448074
+def oracle_stats(G: OracleGraph, P: int) -> dict:
+    """The regression statistics computed from the oracle builder's own DAG."""
+    nu = G.nu_max
+    lay = G.layers()
+    ch = G.child_counts()
+    V = G.n_nodes()
+    k_by = [0] * (nu + 1)
+    for k in G.K:
+        k_by[len(k)] += 1
+    aux_by = [0] * (nu + 1)
+    for v in range(P, V):
+        if G.is_aux(v):
+            aux_by[len(G.node_tuple[v])] += 1
+    depth = max(lay)
+    return dict(k=k_by[1:], V=V, aux=[a for a in aux_by[2:] if a] or [], depth=depth,
+                layers=[sum(1 for x in lay if x == L) for L in range(depth + 1)],
+                S=sum(1 for v in range(P, V) if ch[v] > 0), T=sum(1 for v in range(P, V) if ch[v] == 0),
+                leafpar=sum(1 for v in range(P) if ch[v] > 0), naive=sum(len(k) - 1 for k in G.K))
+
+
+@pytest.mark.parametrize("spec", [pytest.param((8, 8, 14, 5), id="32768-env-basis"),
+                                  pytest.param((10, 10, 16, 6), id="8192-env-basis", marks=pytest.mark.slow)])
+def test_builder_bit_exact_large(spec):
+    """The library builder against the oracle builder on the nu <= 5 and nu <= 6
+    bases of the two largest workloads: node lists, parents and K map bit-exact,
+    and the stored regression counts equal to the oracle DAG's own statistics."""
+    nmax, lmax, D, nu = spec
+    g = ace.Graph(nu, D, nmax, lmax, host_only=True)
+    onep, tup, par, k2n = g.export()
+    grp = group_o3(nmax, lmax, D)
+    G = OracleGraph(grp, nu, D, 1, 1)
+    V = G.n_nodes()
+    assert tup.shape == (V, nu)
+    otup = np.full((V, nu), -1, np.int32)
+    for v, t in enumerate(G.node_tuple):
+        otup[v, :len(t)] = t
+    np.testing.assert_array_equal(tup, otup)
+    opar = np.array([p if p is not None else (-1, -1) for p in G.parents], np.int32)
+    np.testing.assert_array_equal(par, opar)
+    np.testing.assert_array_equal(k2n, np.array(G.k_to_node, np.int64))
+    ost = oracle_stats(G, len(grp))
+    if spec in REGRESSION:
+        assert ost == REGRESSION[spec]
+    else:
+        assert sum(ost["k"]) == 3692953 and ost["V"] == 3705306
+        assert ost["aux"] == [4944, 4641, 1373, 314]
+        assert ost["S"] == 256091 and ost["T"] == 3448074
 
 
 def test_torus_theorem_count_through_the_c_builder():
