@@ -56,6 +56,18 @@ def dag_flops_per_env(stats: dict) -> dict:
     return dict(forward=fwd, reverse=adj, total=fwd + adj)
 
 
+def naive_flops_per_env(stats: dict) -> dict:
+    """Algorithmic flops of one environment in the naive forward + reverse launch:
+    every tuple's product from its factors, C = sum_k (nu_k - 1) complex
+    products; forward 6 C + 2 |K|; reverse by suffix products and
+    prefix x suffix (12 C) plus the nu_k adjoint accumulations (2 per factor)."""
+    C = stats["naive_cmuls"]
+    K = stats["n_k"]
+    fwd = 6 * C + 2 * K
+    adj = 12 * C + 2 * (C + K)
+    return dict(forward=fwd, reverse=adj, total=fwd + adj)
+
+
 def source_hash() -> str:
     """Hash of the kernel and schedule sources (ties counter profiles to them)."""
     import hashlib
@@ -326,6 +338,27 @@ def dag_kernel_ms(ace, torch, G, tc, A, timed, steps, warmup) -> float:
     return ms
 
 
+def naive_kernel_ms(ace, torch, G, tc, A, timed, steps, warmup) -> float:
+    """The naive forward + reverse launch alone (ace_contract with ACE_FLAG_NAIVE,
+    its coefficient gather included), timed with events on its stream."""
+    dev = A.device
+    E = A.shape[0]
+    phi = torch.empty((E, 2), dtype=torch.float64, device=dev)
+    Abar = torch.empty_like(A)
+    ws = G.workspace(E, dev, ace.FLAG_NAIVE)
+    lib = ace.lib()
+
+    def launch():
+        st = lib.ace_contract(G.handle, tc.data_ptr(), E, A.data_ptr(), phi.data_ptr(), Abar.data_ptr(),
+                              ws.data_ptr(), ws.numel(), ace.FLAG_NAIVE, ace._stream(dev))
+        if st != 0:
+            raise RuntimeError(lib.ace_last_error().decode())
+
+    with torch.cuda.stream(torch.cuda.current_stream(dev)):
+        ms, _ = timed(launch, steps, warmup)
+    return ms
+
+
 def small_workload_figures(ace, torch, dev, timed, graphed, args) -> dict:
     """phi + forces on the 4096-environment nu <= 4 workload, beside the headline."""
     w = wl.WORKLOADS[3]
@@ -531,6 +564,7 @@ def main():
         ms_naive = ms_naive_eager if args.eager else timed(graphed(step_naive), n_steps, n_warm)[0]
         print(f"[bench] naive phi+forces: {ms_naive:.3f} ms/step ({n_steps} steps)", file=sys.stderr, flush=True)
         phi_naive, grad_naive = phi.clone(), grad.clone()
+        ms_naive_kernel = naive_kernel_ms(ace, torch, G, tc, A, timed, n_steps, 1)
     ms_fwd, _ = timed(lambda: ace.eval(G, tc, toff, tpos, out=phi), args.steps, args.warmup)
 
     ms_kernel = dag_kernel_ms(ace, torch, G, tc, A, timed, args.steps, args.warmup)
@@ -594,7 +628,10 @@ def main():
                                + (f" (n={args.alg_n})" if args.algorithm == 2 else ""),
                    "n_env": E, "n_nbr": N, "nu_max": w.nu_max, "degree_max": w.degree_max,
                    "n_max": w.n_max, "l_max": w.l_max},
-        "naive": None if ms_naive is None else {"value": E / (ms_naive * 1e-3), "ms_per_step": ms_naive},
+        "naive": None if ms_naive is None else {
+            "value": E / (ms_naive * 1e-3), "ms_per_step": ms_naive, "kernel_ms": ms_naive_kernel,
+            "frac": naive_flops_per_env(stats)["total"] * E / (ms_naive_kernel * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "flops_per_env": naive_flops_per_env(stats)},
         "dag_vs_naive": None if ms_naive is None else ms_naive / ms_dag,
         "forces_per_s": N / (ms_dag * 1e-3),
         "phi_only_env_per_s": E / (ms_fwd * 1e-3),

@@ -43,7 +43,7 @@ ace_status fail(ace_status code, const std::string& msg) {
 constexpr int kDagThreads = 256;
 constexpr int kForestThreads = 512;
 constexpr int kForwardChunk = 8;   // forest, full-adjoint mode: forwarding entries per chunk
-constexpr int kNaiveThreads = 256;
+constexpr int kNaiveChunk = 16;     // naive kernel: consecutive tuples per lane and slice
 constexpr int kBasisThreads = 256;
 constexpr int kGradThreads = 256;   // planar gradient kernel
 constexpr int kGradWave = 64;       // O(3) gradient kernel: one wave per block
@@ -93,7 +93,11 @@ struct ace_graph {
   int cl_off[kMaxLayers + 2] = {0};
   std::vector<int2> st_ab, cl_ab;
   std::vector<int32_t> st_k, cl_k, leaf_k;
-  std::vector<int16_t> naive_tup;
+  // naive schedule (naive_kernel): slices, factor indices, K index of every
+  // coefficient position (-1: padding)
+  std::vector<int4> nv_slice;
+  std::vector<int16_t> nv_idx;
+  std::vector<int32_t> nv_kmap;
   std::vector<OnepInfo> onep;
   std::vector<int16_t> onep_index;
   std::vector<int16_t> basis_prim;   // O(3): the functions with m >= 0
@@ -104,7 +108,9 @@ struct ace_graph {
   void* dmem = nullptr;
   int2 *d_st_ab = nullptr, *d_cl_ab = nullptr;
   int32_t *d_st_k = nullptr, *d_cl_k = nullptr, *d_leaf_k = nullptr;
-  int16_t *d_naive_tup = nullptr, *d_onep_index = nullptr, *d_basis_prim = nullptr;
+  int4* d_nv_slice = nullptr;
+  int32_t* d_nv_kmap = nullptr;
+  int16_t *d_nv_idx = nullptr, *d_onep_index = nullptr, *d_basis_prim = nullptr;
   int32_t* d_gsrc = nullptr;
   OnepInfo* d_onep = nullptr;
   double* d_ycoef = nullptr;
@@ -271,11 +277,37 @@ void make_schedule(ace_graph* g) {
   g->leaf_k.assign(P1, -1);
   for (int i = 0; i < P1; ++i) g->leaf_k[i] = h.node_k[i];
 
-  // naive tuples, padded with the constant-one slot P1
+  // naive schedule: K is ordered by length, so the tuples of one length are
+  // contiguous; each length is cut into slices of 64 lanes x kNaiveChunk
+  // consecutive tuples per lane, padded with the constant-one slot P1
   if (P1 > 32766) throw std::length_error("too many one-particle functions for int16 tuples");
-  g->naive_tup.assign((size_t)h.nK * h.width, (int16_t)P1);
-  for (int64_t q = 0; q < h.nK; ++q)
-    for (int t = 0; t < h.k_len[q]; ++t) g->naive_tup[(size_t)q * h.width + t] = (int16_t)h.k_flat[(size_t)q * h.width + t];
+  g->nv_slice.clear();
+  g->nv_idx.clear();
+  g->nv_kmap.clear();
+  for (int64_t b = 0; b < h.nK;) {
+    const int nu = h.k_len[b];
+    int64_t e = b;
+    while (e < h.nK && h.k_len[e] == nu) ++e;
+    const int64_t per_slice = 64LL * kNaiveChunk;
+    for (int64_t s0 = b; s0 < e; s0 += per_slice) {
+      if ((int64_t)g->nv_idx.size() + per_slice * nu > INT32_MAX)
+        throw std::length_error("naive schedule larger than 2^31 entries");
+      g->nv_slice.push_back(make_int4((int)g->nv_idx.size(), (int)g->nv_kmap.size(), nu, kNaiveChunk));
+      for (int j = 0; j < kNaiveChunk; ++j) {
+        for (int t = 0; t < nu; ++t)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int64_t q = s0 + (int64_t)lane * kNaiveChunk + j;
+            g->nv_idx.push_back(q < e ? (int16_t)h.k_flat[(size_t)q * h.width + t] : (int16_t)P1);
+          }
+      }
+      for (int j = 0; j < kNaiveChunk; ++j)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t q = s0 + (int64_t)lane * kNaiveChunk + j;
+          g->nv_kmap.push_back(q < e ? (int32_t)q : -1);
+        }
+    }
+    b = e;
+  }
 
   // one-particle tables (O(3) only)
   g->onep.clear();
@@ -1837,7 +1869,8 @@ ace_status upload(ace_graph* g) {
   size_t bytes = 0;
   bytes += align_up(g->st_ab.size() * sizeof(int2)) + align_up(g->st_k.size() * 4);
   bytes += align_up(g->cl_ab.size() * sizeof(int2)) + align_up(g->cl_k.size() * 4);
-  bytes += align_up(g->leaf_k.size() * 4) + align_up(g->naive_tup.size() * 2);
+  bytes += align_up(g->leaf_k.size() * 4) + align_up(g->nv_idx.size() * 2) + align_up(g->nv_kmap.size() * 4);
+  bytes += align_up(g->nv_slice.size() * sizeof(int4));
   bytes += align_up(g->onep.size() * sizeof(OnepInfo)) + align_up(g->onep_index.size() * 2);
   bytes += align_up(g->basis_prim.size() * 2);
   bytes += align_up(g->ycoef.size() * 8) + align_up(g->gsrc.size() * 4) + kAlign;
@@ -1852,7 +1885,9 @@ ace_status upload(ace_graph* g) {
   g->d_cl_ab = carve<int2>(p, g->cl_ab.size());
   g->d_cl_k = carve<int32_t>(p, g->cl_k.size());
   g->d_leaf_k = carve<int32_t>(p, g->leaf_k.size());
-  g->d_naive_tup = carve<int16_t>(p, g->naive_tup.size());
+  g->d_nv_idx = carve<int16_t>(p, g->nv_idx.size());
+  g->d_nv_kmap = carve<int32_t>(p, g->nv_kmap.size());
+  g->d_nv_slice = carve<int4>(p, g->nv_slice.size());
   g->d_onep = carve<OnepInfo>(p, g->onep.size());
   g->d_onep_index = carve<int16_t>(p, g->onep_index.size());
   g->d_basis_prim = carve<int16_t>(p, g->basis_prim.size());
@@ -1864,7 +1899,9 @@ ace_status upload(ace_graph* g) {
   ACE_HIP(put(g->d_cl_ab, g->cl_ab.data(), g->cl_ab.size() * sizeof(int2)));
   ACE_HIP(put(g->d_cl_k, g->cl_k.data(), g->cl_k.size() * 4));
   ACE_HIP(put(g->d_leaf_k, g->leaf_k.data(), g->leaf_k.size() * 4));
-  ACE_HIP(put(g->d_naive_tup, g->naive_tup.data(), g->naive_tup.size() * 2));
+  ACE_HIP(put(g->d_nv_idx, g->nv_idx.data(), g->nv_idx.size() * 2));
+  ACE_HIP(put(g->d_nv_kmap, g->nv_kmap.data(), g->nv_kmap.size() * 4));
+  ACE_HIP(put(g->d_nv_slice, g->nv_slice.data(), g->nv_slice.size() * sizeof(int4)));
   ACE_HIP(put(g->d_onep, g->onep.data(), g->onep.size() * sizeof(OnepInfo)));
   ACE_HIP(put(g->d_onep_index, g->onep_index.data(), g->onep_index.size() * 2));
   ACE_HIP(put(g->d_basis_prim, g->basis_prim.data(), g->basis_prim.size() * 2));
@@ -1977,6 +2014,7 @@ Workspace plan_workspace(const ace_graph* g, int64_t n_env, uint32_t flags, char
     if (F.ok) ncs = std::max(ncs, F.kmap.size() * (F.fold ? 2 : 1));
   if (g->remat_ok)
     for (const auto& R : g->rm) ncs = std::max(ncs, R.kmap.size() * (R.fold ? 2 : 1));
+  ncs = std::max(ncs, g->nv_kmap.size());
   if (ncs) w.cs = reinterpret_cast<double*>(take(ncs * sizeof(double)));
   w.bytes = off;
   return w;
@@ -2300,30 +2338,32 @@ ace_status launch_dag(const ace_graph* g, const double* coeffs, int64_t n_env, c
 }
 
 ace_status launch_naive(const ace_graph* g, const double* coeffs, int64_t n_env, const double2* A, double2* phi,
-                        double2* Abar, hipStream_t s) {
+                        double2* Abar, const Workspace& w, hipStream_t s) {
+  CoefPrep prep{};
+  prep.mode = CoefPrep::kPlain;
+  prep.plain.kmap = g->d_nv_kmap;
+  prep.plain.coeffs = coeffs;
+  prep.plain.cs = w.cs;
+  prep.plain.n = (int64_t)g->nv_kmap.size();
+  ace_status st = launch_prep(prep, s);
+  if (st != ACE_OK) return st;
   NaiveArgs a{};
   a.n_env = n_env;
   a.A = A;
   a.phi = phi;
   a.Abar = Abar;
-  a.coeffs = coeffs;
-  a.tup = g->d_naive_tup;
-  a.nK = g->h.nK;
+  a.cs = w.cs;
+  a.slice = g->d_nv_slice;
+  a.idx = g->d_nv_idx;
+  a.n_slices = (int)g->nv_slice.size();
   a.P1 = g->P1;
-  a.nu_max = g->h.width;
-  const size_t lds = (size_t)(2 * (g->P1 + 1) + kNaiveThreads / 64) * sizeof(double2);
+  const size_t lds = (size_t)(2 * (g->P1 + 1) + kNaiveBlock / 64) * sizeof(double2);
   if (lds > g->max_lds) return fail(ACE_ERR_UNSUPPORTED, "one-particle basis too large for the naive kernel");
-  const dim3 grid((unsigned)grid_for(n_env)), block(kNaiveThreads);
-  switch (a.nu_max) {
-    case 1: hipLaunchKernelGGL(naive_kernel<1>, grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL(naive_kernel<2>, grid, block, lds, s, a); break;
-    case 3: hipLaunchKernelGGL(naive_kernel<3>, grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL(naive_kernel<4>, grid, block, lds, s, a); break;
-    case 5: hipLaunchKernelGGL(naive_kernel<5>, grid, block, lds, s, a); break;
-    case 6: hipLaunchKernelGGL(naive_kernel<6>, grid, block, lds, s, a); break;
-    case 7: hipLaunchKernelGGL(naive_kernel<7>, grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL(naive_kernel<8>, grid, block, lds, s, a); break;
-  }
+  const dim3 grid((unsigned)grid_for(n_env)), block(kNaiveBlock);
+  if (Abar)
+    hipLaunchKernelGGL(naive_kernel<true>, grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL(naive_kernel<false>, grid, block, lds, s, a);
   ACE_HIP(hipGetLastError());
   return ACE_OK;
 }
@@ -2527,7 +2567,7 @@ ace_status ace_contract(const ace_graph* g, const double* coeffs, int64_t n_env,
   const Workspace w = plan_workspace(g, n_env, flags, static_cast<char*>(workspace));
   if (flags & ACE_FLAG_NAIVE)
     return launch_naive(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
-                        reinterpret_cast<double2*>(Abar), s);
+                        reinterpret_cast<double2*>(Abar), w, s);
   return launch_dag(g, coeffs, n_env, reinterpret_cast<const double2*>(A), reinterpret_cast<double2*>(phi),
                     reinterpret_cast<double2*>(Abar), w, s, flags, (flags & ACE_FLAG_CONJ_SYMMETRIC) != 0);
 }
@@ -2547,7 +2587,7 @@ ace_status ace_eval(const ace_graph* g, const double* coeffs, int64_t n_env, con
   if (flags & ACE_FLAG_NAIVE) {
     st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr, w.status);
     if (st != ACE_OK) return st;
-    return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, s);
+    return launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), nullptr, w, s);
   }
   // the DAG launch's coefficients are prepared on the basis kernel's grid
   const CoefPrep prep = dag_prep(g, coeffs, w, false, flags, true);
@@ -2573,7 +2613,7 @@ ace_status ace_eval_grad(const ace_graph* g, const double* coeffs, int64_t n_env
   if (flags & ACE_FLAG_NAIVE) {
     st = launch_basis(g, n_env, offsets, pos, w.A, s, nullptr, w.status);
     if (st != ACE_OK) return st;
-    st = launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, s);
+    st = launch_naive(g, coeffs, n_env, w.A, reinterpret_cast<double2*>(phi), w.Abar, w, s);
   } else {
     // the DAG launch's coefficients are prepared on the basis kernel's grid
     const CoefPrep prep = dag_prep(g, coeffs, w, true, flags, true);

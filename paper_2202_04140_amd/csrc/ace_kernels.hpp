@@ -91,15 +91,20 @@ struct DagArgs {
   int cl_off[kMaxLayers + 2];
 };
 
+// Naive schedule: the tuples of each length in slices of 64 lanes, each lane
+// taking kNaiveChunk consecutive tuples (in K order); a slice's factor
+// indices are stored [step][factor][lane] and its coefficients [step][lane],
+// padding tuples hold the constant-one slot P1 and a zero coefficient.
 struct NaiveArgs {
   int64_t n_env;
   const double2* A;
   double2* phi;
   double2* Abar;
-  const double* coeffs;
-  const int16_t* tup;  // [nK][nu_max], padded with P1 (the constant-one slot)
-  int64_t nK;
-  int P1, nu_max;
+  const double* cs;       // prepared coefficients in slice order
+  const int4* slice;      // [n_slices] {first index, first coefficient, length nu, steps}
+  const int16_t* idx;     // factor indices
+  int n_slices;
+  int P1;
 };
 
 struct GradArgs {

@@ -363,48 +363,107 @@ template __global__ void dag_kernel<false, false>(DagArgs);
 // ---------------------------------------------------------------------------
 // naive per-tuple evaluation (the baseline): phi = sum_k c_k prod_t A_{k_t},
 // gradient by prefix / suffix products.  A sits in LDS with one extra slot
-// holding 1 so shorter tuples need no branch.
+// holding 1 for the padding tuples of the last slice of each length.
 // ---------------------------------------------------------------------------
-template <int NU>
-__global__ __launch_bounds__(256) void naive_kernel(NaiveArgs p) {
+// One slice of the naive evaluation: every tuple's product formed from its
+// one-particle factors (Eq. (1.1)), nothing shared between tuples.  The
+// adjoint of factor t is c_k prod_{s != t} A_{k_s} by prefix and suffix
+// products; consecutive tuples of a lane share leading factors (K order), so
+// the adjoints of factors 0..NU-2 are summed in registers while the factor
+// stays the same and added to LDS when it changes; the last factor's goes to
+// LDS at once.
+template <int NU, bool GRAD>
+__device__ __forceinline__ void naive_slice(const NaiveArgs& p, const double2* x, double2* ab, const int4& sl,
+                                            int lane, double2& acc) {
+  const int16_t* ip = p.idx + sl.x + lane;
+  const double* cp = p.cs + sl.y + lane;
+  const int steps = sl.w;
+  constexpr int NR = NU > 1 ? NU - 1 : 1;
+  int rs[NR];
+  double2 rv[NR];
+#pragma unroll
+  for (int t = 0; t < NR; ++t) {
+    rs[t] = -1;
+    rv[t] = make_double2(0.0, 0.0);
+  }
+  for (int j = 0; j < steps; ++j) {
+    int f[NU];
+    double2 v[NU];
+#pragma unroll
+    for (int t = 0; t < NU; ++t) f[t] = ip[(j * NU + t) * 64];
+    const double c = cp[j * 64];
+#pragma unroll
+    for (int t = 0; t < NU; ++t) v[t] = x[f[t]];
+    double2 pre[NU];   // pre[t] = prod_{s < t} v[s]
+    pre[0] = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int t = 1; t < NU; ++t) pre[t] = t == 1 ? v[0] : cmul(pre[t - 1], v[t - 1]);
+    const double2 prod = NU == 1 ? v[0] : cmul(pre[NU - 1], v[NU - 1]);
+    acc = rfma(c, prod, acc);
+    if (GRAD) {
+      double2 suf = make_double2(c, 0.0);
+#pragma unroll
+      for (int t = NU - 1; t >= 0; --t) {
+        const double2 d = t == 0 ? suf : cmul(pre[t], suf);
+        if (t == NU - 1) {
+          atomic_cadd(&ab[f[t]], d);
+        } else {
+          if (f[t] != rs[t]) {
+            if (rs[t] >= 0) atomic_cadd(&ab[rs[t]], rv[t]);
+            rs[t] = f[t];
+            rv[t] = d;
+          } else {
+            rv[t].x += d.x;
+            rv[t].y += d.y;
+          }
+        }
+        if (t > 0) suf = cmul(suf, v[t]);
+      }
+    }
+  }
+  if (GRAD) {
+#pragma unroll
+    for (int t = 0; t < NU - 1; ++t)
+      if (rs[t] >= 0) atomic_cadd(&ab[rs[t]], rv[t]);
+  }
+}
+
+constexpr int kNaiveBlock = 256;
+
+template <bool GRAD>
+__global__ __launch_bounds__(kNaiveBlock) void naive_kernel(NaiveArgs p) {
   extern __shared__ double2 lds[];
   const int P1 = p.P1;
   double2* x = lds;                // [P1 + 1]
   double2* ab = lds + (P1 + 1);    // [P1 + 1]
   double2* red = ab + (P1 + 1);
-  const bool grad = p.Abar != nullptr;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
   for (int64_t e = blockIdx.x; e < p.n_env; e += gridDim.x) {
     const double2* Ae = p.A + e * P1;
     for (int i = threadIdx.x; i <= P1; i += blockDim.x) {
       x[i] = i < P1 ? Ae[i] : make_double2(1.0, 0.0);
-      ab[i] = make_double2(0.0, 0.0);
+      if (GRAD) ab[i] = make_double2(0.0, 0.0);
     }
     __syncthreads();
     double2 acc = make_double2(0.0, 0.0);
-    for (int64_t q = threadIdx.x; q < p.nK; q += blockDim.x) {
-      const int16_t* t = p.tup + q * NU;
-      double2 v[NU];
-#pragma unroll
-      for (int s = 0; s < NU; ++s) v[s] = x[t[s]];
-      double2 pre[NU + 1];
-      pre[0] = make_double2(1.0, 0.0);
-#pragma unroll
-      for (int s = 0; s < NU; ++s) pre[s + 1] = cmul(pre[s], v[s]);
-      const double c = p.coeffs[q];
-      acc = rfma(c, pre[NU], acc);
-      if (grad) {
-        double2 suf = make_double2(c, 0.0);
-#pragma unroll
-        for (int s = NU - 1; s >= 0; --s) {
-          atomic_cadd(&ab[t[s]], cmul(pre[s], suf));
-          suf = cmul(suf, v[s]);
-        }
+    for (int s = wid; s < p.n_slices; s += nw) {
+      const int4 sl = p.slice[s];
+      switch (sl.z) {
+        case 1: naive_slice<1, GRAD>(p, x, ab, sl, lane, acc); break;
+        case 2: naive_slice<2, GRAD>(p, x, ab, sl, lane, acc); break;
+        case 3: naive_slice<3, GRAD>(p, x, ab, sl, lane, acc); break;
+        case 4: naive_slice<4, GRAD>(p, x, ab, sl, lane, acc); break;
+        case 5: naive_slice<5, GRAD>(p, x, ab, sl, lane, acc); break;
+        case 6: naive_slice<6, GRAD>(p, x, ab, sl, lane, acc); break;
+        case 7: naive_slice<7, GRAD>(p, x, ab, sl, lane, acc); break;
+        default: naive_slice<8, GRAD>(p, x, ab, sl, lane, acc); break;
       }
     }
-    __syncthreads();
-    const double2 phi = block_sum(acc, red);
+    const double2 phi = block_sum(acc, red);   // synchronises the block
     if (threadIdx.x == 0) p.phi[e] = phi;
-    if (grad) {
+    if (GRAD) {
       double2* Be = p.Abar + e * P1;
       for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[i];
     }
@@ -412,14 +471,8 @@ __global__ __launch_bounds__(256) void naive_kernel(NaiveArgs p) {
   }
 }
 
-template __global__ void naive_kernel<1>(NaiveArgs);
-template __global__ void naive_kernel<2>(NaiveArgs);
-template __global__ void naive_kernel<3>(NaiveArgs);
-template __global__ void naive_kernel<4>(NaiveArgs);
-template __global__ void naive_kernel<5>(NaiveArgs);
-template __global__ void naive_kernel<6>(NaiveArgs);
-template __global__ void naive_kernel<7>(NaiveArgs);
-template __global__ void naive_kernel<8>(NaiveArgs);
+template __global__ void naive_kernel<false>(NaiveArgs);
+template __global__ void naive_kernel<true>(NaiveArgs);
 
 // ---------------------------------------------------------------------------
 // dA/dr chain.
