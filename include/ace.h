@@ -353,8 +353,10 @@ ace_status ace_eval_grad_noalloc(const ace_graph* g, const double* coeffs, int64
  *   with the adjoint slices, entry positions (padded, real), items, then of
  *   the forward-only schedule slices, entry positions (padded, real), the
  *   four hot slots, the pair slots of the schedule with the adjoint, the
- *   mean LDS bank cost of its entry reads (x1000), and the entries (real)
- *   of the folded schedule with the adjoint.  The rest are 0.
+ *   mean LDS bank cost of its entry reads (x1000), the entries (real)
+ *   of the folded schedule with the adjoint, and the mean bank load of its
+ *   row pushes (x1000: most lanes of a quarter-wave on one 8-byte bank
+ *   pair, slot mod 16, per push instruction).  The rest are 0.
  *
  * ace_debug_remat_eval: as ace_debug_forest_eval for the remat schedules
  *   (phi and Abar from the one with the adjoint; ACE_ERR_INTERNAL also if

@@ -252,7 +252,7 @@ class Graph:
         if k.value == 2:
             names = ["nslot", "slices", "entry_pos", "entry_real", "items", "fwd_slices", "fwd_entry_pos",
                      "fwd_entry_real", "hot0", "hot1", "hot2", "hot3", "pairs", "bank_cost_x1000",
-                     "folded_entry_real"]
+                     "folded_entry_real", "push_bank_load_x1000"]
         else:
             names = ["nslot", "tree_slices", "child_pos", "child_real", "row_slices", "entry_pos",
                      "entry_real", "grandchildren", "hot0", "hot1", "hot2", "hot3", "full_adjoint",

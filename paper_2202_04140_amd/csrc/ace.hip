@@ -42,7 +42,6 @@ ace_status fail(ace_status code, const std::string& msg) {
 
 constexpr int kDagThreads = 256;
 constexpr int kForestThreads = 512;
-constexpr int kForwardChunk = 8;   // forest, full-adjoint mode: forwarding entries per chunk
 constexpr int kNaiveChunk = 16;     // naive kernel: consecutive tuples per lane and slice
 constexpr int kBasisThreads = 256;
 constexpr int kGradThreads = 256;   // planar gradient kernel
@@ -147,8 +146,9 @@ struct ace_graph {
     int tr_wave[kMaxForestWaves + 1] = {0};   // and tree slices [tr_wave[w], tr_wave[w + 1])
     int cs_hot = 0;                  // coefficients of the hot columns, [4][n_items]
     // full-adjoint mode: order-2 -> one-particle forwarding lists, cut into
-    // chunks {one-particle slot, first entry, end entry, 0} of at most
-    // kForwardChunk entries each
+    // chunks {one-particle slot, first entry, end entry, 0} of exactly
+    // kForwardChunk entries (chunk c holds entries [c * kForwardChunk, ...),
+    // padded with the zero slot)
     std::vector<int4> fw_ck;
     std::vector<uint32_t> fw_ent;
     int4* d_fw_ck = nullptr;
@@ -911,15 +911,26 @@ void make_forest(ace_graph* g, int which) {
       fl[a].push_back(us | (b << 16));
       fl[b].push_back(us | (a << 16));
     }
-    // chunks: a one-particle node that is a parent of many order-2 nodes
-    // would otherwise hold one lane in a long serial loop
+    // chunks of a fixed size, padded with the zero slot (whose value is 0):
+    // a one-particle node that is a parent of many order-2 nodes would
+    // otherwise hold one lane in a long serial loop, and a fixed size lets a
+    // lane load all its entries at once.  Chunks go in rounds (the first
+    // chunk of every node, then the second, ...), so that the lanes of a
+    // wave add their sums to different nodes.
     F.fw_ck.clear();
     F.fw_ent.clear();
-    for (int i = 0; i < P1; ++i) {
-      const int b0 = (int)F.fw_ent.size();
-      F.fw_ent.insert(F.fw_ent.end(), fl[i].begin(), fl[i].end());
-      const int b1 = (int)F.fw_ent.size();
-      for (int c = b0; c < b1; c += kForwardChunk) F.fw_ck.push_back(make_int4(i, c, std::min(b1, c + kForwardChunk), 0));
+    const uint32_t pad = (uint32_t)P1 | ((uint32_t)P1 << 16);   // the zero slot, twice
+    for (size_t r = 0;; ++r) {
+      bool any = false;
+      for (int i = 0; i < P1; ++i) {
+        const size_t b0 = r * kForwardChunk;
+        if (b0 >= fl[i].size()) continue;
+        any = true;
+        const int c = (int)F.fw_ent.size();
+        for (size_t j = b0; j < b0 + kForwardChunk; ++j) F.fw_ent.push_back(j < fl[i].size() ? fl[i][j] : pad);
+        F.fw_ck.push_back(make_int4(i, c, c + kForwardChunk, 0));
+      }
+      if (!any) break;
     }
   }
   F.ok = true;
@@ -1273,11 +1284,13 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   // (in the order above) go to one of a few open slices: the one, and the
   // factor rotation, where the item's row pushes add the least LDS atomic
   // contention to the slice's push instructions so far.  Push i of every
-  // lane goes to factor i of its rotated row list; lanes on one address
-  // serialise, and a half-wave of 8-byte atomics is spread over the banks by
-  // slot mod 16 (the hot slots, summed in registers, and the constant slot
-  // do not count).  A slice is emitted when full; its first item is its
-  // longest, since the items come longest first.
+  // lane goes to factor i of its rotated row list.  The LDS serves the
+  // 8-byte atomics of a push a quarter-wave at a time over 16 bank pairs,
+  // each lane's first half on pair slot mod 16 (the kernel orders the two
+  // halves by bit 3 of the slot), at a cost set by the most lanes on one
+  // pair; lanes on one address serialise as well.  The hot slots, summed in
+  // registers, and the constant slot do not count.  A slice is emitted when full; its first
+  // item is its longest, since the items come longest first.
   std::vector<Item> ordered;
   std::vector<int> item_rot;
   std::vector<size_t> cut;   // slice ends in `ordered`
@@ -1286,8 +1299,15 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     struct Open {
       std::vector<size_t> idx;
       std::vector<int> rot;
-      std::vector<std::map<int32_t, int>> mult;
-      std::vector<std::array<int, 32>> bank;
+      std::vector<std::map<int32_t, int>> mult;   // per push: lanes on a slot, keyed 4 * slot + quarter
+      std::vector<std::array<int, 64>> bank;       // per push: lanes on a bank pair, [16 * quarter + slot mod 16]
+    };
+    const int nh = std::min(g->opts.hot_columns, g->opts.env_per_block > 1 ? 2 : 4);
+    auto is_hot = [&](int32_t sl) {
+      if (sl == ONE) return true;
+      for (int k = 0; k < nh; ++k)
+        if (sl == R.hot[k]) return true;
+      return false;
     };
     ordered.reserve(items.size());
     item_rot.reserve(items.size());
@@ -1317,15 +1337,15 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
         int bs = 0, br = 0, bc = INT32_MAX;
         for (int k = 0; k < kOpen; ++k) {
           const int lane = (int)open[k].idx.size();
-          const int half = lane >> 5;
+          const int quarter = lane >> 4;
           for (int r0 = 0; r0 < nbs; ++r0) {
             const int r = (lane + r0) % nbs;
             int cost = 0;
             for (int i = 0; i < nbs; ++i) {
               const int32_t sl = f[(i + r) % nbs];
-              if (sl == ONE || sl == R.hot[0] || sl == R.hot[1]) continue;
-              const auto m = open[k].mult[i].find(sl);
-              cost += 2 * (m == open[k].mult[i].end() ? 0 : m->second) + open[k].bank[i][16 * half + (sl & 15)];
+              if (is_hot(sl)) continue;
+              const auto m = open[k].mult[i].find(4 * sl + quarter);
+              cost += (m == open[k].mult[i].end() ? 0 : m->second) + open[k].bank[i][16 * quarter + (sl & 15)];
             }
             if (cost < bc) {
               bc = cost;
@@ -1335,11 +1355,12 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
           }
         }
         Open& o = open[bs];
-        const int half = (int)o.idx.size() >> 5;
+        const int quarter = (int)o.idx.size() >> 4;
         for (int i = 0; i < nbs; ++i) {
           const int32_t sl = f[(i + br) % nbs];
-          o.mult[i][sl] += 1;
-          o.bank[i][16 * half + (sl & 15)] += 1;
+          if (is_hot(sl)) continue;
+          o.mult[i][4 * sl + quarter] += 1;
+          o.bank[i][16 * quarter + (sl & 15)] += 1;
         }
         o.idx.push_back(t);
         o.rot.push_back(br);
@@ -1383,11 +1404,12 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       const int32_t o = ents[ei].oth;
       return (int)(((u < 4 ? F.lo[o] : F.hi[o]) >> (16 * (u & 3))) & 0xffffu);
     };
-    auto put_entry = [&](int lane, int j, int64_t ei, int rot) {
+    // entry ei with factor perm[u] read at position u
+    auto put_entry = [&](int lane, int j, int64_t ei, const int* perm) {
       const size_t e = e0 + (size_t)j * 64 + lane;
       uint64_t lo = 0, hi = 0;
       for (int u = 0; u < 8; ++u) {
-        const uint64_t sl = u < sig ? (uint64_t)factor(ei, (u + rot) % sig) : one16;
+        const uint64_t sl = u < sig ? (uint64_t)factor(ei, perm[u]) : one16;
         (u < 4 ? lo : hi) |= sl << (16 * (u & 3));
       }
       R.olo[e] = lo;
@@ -1395,14 +1417,32 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       R.kmap[P1 + e] = ents[ei].kmap;
       if (R.fold) R.kbar[P1 + e] = ents[ei].kbar;
     };
+    const int ident[8] = {0, 1, 2, 3, 4, 5, 6, 7};
     if (!g->opts.bank_schedule) {
       for (int lane = 0; lane < 64; ++lane)
-        for (size_t j = 0; j < lane_ents[lane].size(); ++j) put_entry(lane, (int)j, lane_ents[lane][j], 0);
+        for (size_t j = 0; j < lane_ents[lane].size(); ++j) put_entry(lane, (int)j, lane_ents[lane][j], ident);
     } else {
       // Greedy per column and quarter-wave: each lane takes the remaining
-      // entry and factor rotation that adds the fewest 16-byte bank-group
-      // collisions (slot mod 16) over the factor reads of that column; a
-      // slot already read in the quarter is a broadcast and costs nothing.
+      // entry and order of its factors (any permutation up to five factors,
+      // else a rotation: the product does not depend on it) that adds the
+      // fewest 16-byte bank-group collisions (slot mod 16) over the factor
+      // reads of that column; a slot already read in the quarter is a
+      // broadcast and costs nothing.
+      std::vector<std::array<int8_t, 8>> perms;
+      {
+        std::array<int8_t, 8> pm{};
+        for (int u = 0; u < 8; ++u) pm[u] = (int8_t)u;
+        if (sig <= 5) {
+          do perms.push_back(pm);
+          while (std::next_permutation(pm.begin(), pm.begin() + sig));
+        } else {
+          for (int r = 0; r < sig; ++r) {
+            std::array<int8_t, 8> rp{};
+            for (int u = 0; u < 8; ++u) rp[u] = (int8_t)(u < sig ? (u + r) % sig : u);
+            perms.push_back(rp);
+          }
+        }
+      }
       for (int q = 0; q < 4; ++q)
         for (int j = 0; j < ncol; ++j) {
           int16_t seen[8][16];   // per factor position and bank group: a slot read there, or -1 (-2: several)
@@ -1411,30 +1451,38 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
           for (int lane = 16 * q; lane < 16 * q + 16; ++lane) {
             auto& L = lane_ents[lane];
             if (L.empty()) continue;
-            int best = 0, best_rot = 0, best_cost = INT32_MAX;
+            int best = 0, best_cost = INT32_MAX;
+            size_t best_p = 0;
             const int ncand = std::min<int>((int)L.size(), 24);
-            for (int c = 0; c < ncand; ++c)
-              for (int rot = 0; rot < sig; ++rot) {
-                int cost = 0;
-                for (int u = 0; u < sig; ++u) {
-                  const int sl = factor(L[c], (u + rot) % sig) >> 4;
+            for (int c = 0; c < ncand && best_cost > 0; ++c) {
+              int8_t col[8][8];   // col[u][t]: factor t read at position u collides
+              for (int u = 0; u < sig; ++u)
+                for (int t = 0; t < sig; ++t) {
+                  const int sl = factor(L[c], t) >> 4;
                   const int16_t v = seen[u][sl & 15];
-                  cost += (v != -1 && v != sl) ? 1 : 0;
+                  col[u][t] = (v != -1 && v != sl) ? 1 : 0;
                 }
+              for (size_t pi = 0; pi < perms.size(); ++pi) {
+                int cost = 0;
+                for (int u = 0; u < sig; ++u) cost += col[u][perms[pi][u]];
                 if (cost < best_cost) {
                   best_cost = cost;
                   best = c;
-                  best_rot = rot;
+                  best_p = pi;
+                  if (cost == 0) break;
                 }
               }
+            }
             const int64_t ei = L[best];
             L.erase(L.begin() + best);
+            int perm[8];
+            for (int u = 0; u < 8; ++u) perm[u] = perms[best_p][u];
             for (int u = 0; u < sig; ++u) {
-              const int sl = factor(ei, (u + best_rot) % sig) >> 4;
+              const int sl = factor(ei, perm[u]) >> 4;
               int16_t& v = seen[u][sl & 15];
               v = (v == -1 || v == sl) ? (int16_t)sl : (int16_t)-2;
             }
-            put_entry(lane, j, ei, best_rot);
+            put_entry(lane, j, ei, perm);
           }
         }
     }
@@ -2798,7 +2846,9 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       info[7] = real0;
       for (int k = 0; k < 4; ++k) info[8 + k] = R.hot[k];
       info[12] = (int64_t)R.pairs.size();
-      // mean LDS bank cost of the factor reads of the entries, per quarter-wave (x1000)
+      // mean LDS cycles of the 16-byte factor reads of the entries per
+      // quarter-wave (x1000): the LDS serves a quarter in max(2, m) cycles,
+      // m the most distinct slots in one bank group (slot mod 16)
       int64_t cost = 0, nq = 0;
       for (const int4& sl : R.slice) {
         const int sig = sl.w >> 8;
@@ -2822,7 +2872,7 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
                 }
                 mx = std::max(mx, d);
               }
-              cost += mx;
+              cost += std::max(2, mx);   // LDS cycles of the quarter: two slots per bank group are free
               ++nq;
             }
       }
@@ -2830,6 +2880,35 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       int64_t real3 = 0;
       for (size_t i = g->rm[3].cs_ent; i < g->rm[3].kmap.size(); ++i) real3 += g->rm[3].kmap[i] != -1;
       info[14] = real3;
+      // mean LDS bank load of the row pushes (8-byte atomics, served a
+      // quarter-wave at a time over 16 bank pairs, slot mod 16 with the
+      // halves ordered by slot bit 3): per push instruction and quarter, the
+      // most lanes on one bank pair (x1000)
+      const int nh = std::min(g->opts.hot_columns, g->opts.env_per_block > 1 ? 2 : 4);
+      int64_t pcost = 0, npq = 0;
+      for (const int4& sl : R.slice) {
+        const int nb = sl.w & 0xff;
+        for (int i = 0; i < nb; ++i)
+          for (int q = 0; q < 4; ++q) {
+            int cnt[16] = {0};
+            bool any = false;
+            for (int l = 16 * q; l < 16 * q + 16; ++l) {
+              const size_t it = (size_t)sl.x + l;
+              const uint64_t w = i < 4 ? R.rlo[it] : R.rhi[it];
+              const int s = (int)(((w >> (16 * (i & 3))) & 0xffffu) >> 4);
+              const int s0 = (int)((R.rlo[it] & 0xffffu) >> 4);
+              bool hot = s == g->P1 || s0 == g->P1;   // constant slot, or a padding lane (no pushes)
+              for (int k = 0; k < nh; ++k) hot |= s == R.hot[k];
+              if (hot) continue;
+              cnt[s & 15] += 1;
+              any = true;
+            }
+            if (!any) continue;
+            pcost += *std::max_element(cnt, cnt + 16);
+            ++npq;
+          }
+      }
+      info[15] = npq ? (1000 * pcost) / npq : 0;
     }
     if (sc == Sched::Forest) {
       const ace_graph::Forest& F = g->fo[0];

@@ -132,6 +132,7 @@ struct GradArgs {
 namespace ace {
 
 constexpr int kMaxForestWaves = 8;   // forest kernel: waves per block at most (512 threads)
+constexpr int kForwardChunk = 8;     // forest, full-adjoint mode: forwarding entries per chunk
 
 // Forest schedule (see forest_kernel).  Value slots: one-particle nodes
 // 0..P1-1, a constant-zero slot P1, then the order-2 nodes P1+1..P1+N2.
@@ -161,11 +162,12 @@ struct ForestArgs {
   int mr_wave[kMaxForestWaves + 1];
   int tr_wave[kMaxForestWaves + 1];
   // full-adjoint mode: abar for every resident slot in LDS, order-2
-  // adjoints forwarded at the end: each chunk {one-particle slot i, first,
-  // end} gathers sum abar_u x_other over its entries and adds it to abar_i
+  // adjoints forwarded at the end: chunk c {one-particle slot i, ...}
+  // gathers sum abar_u x_other over its kForwardChunk entries
+  // fw_ent[c * kForwardChunk ...] and adds it to abar_i
   const int4* fw_ck;       // [n_fwck]
   int n_fwck;
-  const uint32_t* fw_ent;  // entries: order-2 slot | (other parent slot << 16)
+  const uint32_t* fw_ent;  // [n_fwck * kForwardChunk] order-2 slot | (other parent slot << 16)
 };
 
 // Rematerialising schedule (see remat_kernel).  LDS slots: one-particle

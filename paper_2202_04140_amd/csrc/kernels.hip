@@ -280,9 +280,16 @@ template __global__ void basis_kernel<true>(BasisArgs);
 // ---------------------------------------------------------------------------
 // DAG forward + reverse pass
 // ---------------------------------------------------------------------------
+// The two 8-byte halves go out in an order set by bit 7 of the address
+// (bit 3 of a 16-byte slot index): the LDS serves 8-byte atomics a
+// quarter-wave at a time over 16 bank pairs, so that a quarter whose slots
+// are distinct mod 16 hits 16 different pairs with each instruction (with
+// the real parts first in every lane, 16 lanes share 8 pairs).
 __device__ __forceinline__ void atomic_cadd(double2* addr, double2 v) {
-  atomicAdd(&addr->x, v.x);
-  atomicAdd(&addr->y, v.y);
+  double* d = reinterpret_cast<double*>(addr);
+  const int sw = (int)((reinterpret_cast<uintptr_t>(addr) >> 7) & 1);
+  atomicAdd(d + sw, sw ? v.y : v.x);
+  atomicAdd(d + (sw ^ 1), sw ? v.x : v.y);
 }
 
 __device__ __forceinline__ double coef_of(const double* coeffs, int k) {
@@ -1317,21 +1324,25 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
     __syncthreads();
     if (GRAD && FULL) {
       // order-2 adjoints to the one-particle adjoints, abar_a += abar_u x_b, in
-      // chunks of a few entries per lane (a one-particle node can be a parent
-      // of hundreds of order-2 nodes); the chunk sums are added atomically,
-      // and no order-2 adjoint changes in this phase
+      // chunks of kForwardChunk entries per lane (a one-particle node can be
+      // a parent of hundreds of order-2 nodes; padding entries name the zero
+      // slot); all of a chunk's entries are loaded at once, the chunk sums are
+      // added atomically, and no order-2 adjoint changes in this phase
+      static_assert(kForwardChunk == 8, "two 16-byte entry loads per chunk");
       for (int c = threadIdx.x; c < p.n_fwck; c += blockDim.x) {
-        const int4 ck = p.fw_ck[c];
+        const int tgt = p.fw_ck[c].x;
+        const uint4* e4 = reinterpret_cast<const uint4*>(p.fw_ent + (size_t)c * kForwardChunk);
+        const uint4 ea = e4[0], eb = e4[1];
+        const uint32_t en[kForwardChunk] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
         double2 s2[NE];
 #pragma unroll
         for (int q = 0; q < NE; ++q) s2[q] = z2;
-        for (int f = ck.y; f < ck.z; ++f) {
-          const uint32_t en = p.fw_ent[f];
 #pragma unroll
-          for (int q = 0; q < NE; ++q) s2[q] = cfma(ab[q][en & 0xffffu], x[q][en >> 16], s2[q]);
-        }
+        for (int f = 0; f < kForwardChunk; ++f)
 #pragma unroll
-        for (int q = 0; q < NE; ++q) atomic_cadd(&ab[q][ck.x], s2[q]);
+          for (int q = 0; q < NE; ++q) s2[q] = cfma(ab[q][en[f] & 0xffffu], x[q][en[f] >> 16], s2[q]);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) atomic_cadd(&ab[q][tgt], s2[q]);
       }
       __syncthreads();
     }
