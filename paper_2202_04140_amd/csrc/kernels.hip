@@ -1498,7 +1498,8 @@ __device__ __forceinline__ void remat_entries(const RematArgs& p, const double2*
 
 // remat_row: the row value x_b (product of the NB row factors, whose
 // packed offsets blo, bhi were loaded before the entries; the values are
-// read after them so that they hold no registers there), phi += x_b y
+// read after them so that they hold no registers there, and rows of up to
+// four factors keep them for the suffix products), phi += x_b y
 // (halved with the adjoint: every term sits in two rows), and with GRAD the
 // adjoint y pushed to the row's factors by prefix and suffix products.  NH
 // hot one-particle slots per environment are summed in registers.
@@ -1511,13 +1512,23 @@ __device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, 
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     const double2* xe = x + e * xs;
-    double2 pre[NB];
-    double2 xb = lds_at(xe, slot16(blo, bhi, 0));
+    constexpr bool KEEP = NB <= 4;   // factor values kept in registers for the suffix products
+    double2 pre[NB], xf[KEEP ? NB : 1];
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) xf[i] = lds_at(xe, slot16(blo, bhi, i));
+    } else {
+      xf[0] = lds_at(xe, slot16(blo, bhi, 0));
+    }
+    double2 xb = xf[0];
     pre[0] = make_double2(1.0, 0.0);
 #pragma unroll
     for (int i = 1; i < NB; ++i) {
       pre[i] = xb;
-      xb = cmul(xb, lds_at(xe, slot16(blo, bhi, i)));
+      if constexpr (KEEP)
+        xb = cmul(xb, xf[i]);
+      else
+        xb = cmul(xb, lds_at(xe, slot16(blo, bhi, i)));
     }
     if constexpr (FOLD) {
       acc[e].x = fma(w, xb.x * y1[e].x - xb.y * y1[e].y, acc[e].x);
@@ -1532,7 +1543,12 @@ __device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, 
 #pragma unroll
       for (int i = NB - 1; i >= 0; --i) {
         push_hot<NH>(ab + e * as, slot16(blo, bhi, i) >> 4, i == 0 ? suf : cmul(pre[i], suf), p.hot, hot[e]);
-        if (i > 0) suf = cmul(suf, lds_at(xe, slot16(blo, bhi, i)));
+        if (i > 0) {
+          if constexpr (KEEP)
+            suf = cmul(suf, xf[i]);
+          else
+            suf = cmul(suf, lds_at(xe, slot16(blo, bhi, i)));
+        }
       }
     }
   }
