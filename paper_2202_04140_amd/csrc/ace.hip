@@ -1285,11 +1285,11 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   // factor rotation, where the item's row pushes add the least LDS atomic
   // contention to the slice's push instructions so far.  Push i of every
   // lane goes to factor i of its rotated row list.  The LDS serves the
-  // 8-byte atomics of a push a quarter-wave at a time over 16 bank pairs,
-  // each lane's first half on pair slot mod 16 (the kernel orders the two
-  // halves by bit 3 of the slot), at a cost set by the most lanes on one
-  // pair; lanes on one address serialise as well.  The hot slots, summed in
-  // registers, and the constant slot do not count.  A slice is emitted when full; its first
+  // 8-byte atomics of a push a quarter-wave at a time over 16 bank pairs;
+  // with the adjoints in Re and Im planes a lane's atomic lands on pair
+  // slot mod 16 (up to a shift), and the cost is set by the most lanes on
+  // one pair; lanes on one address serialise as well.  The hot slots, summed
+  // in registers, and the constant slot do not count.  A slice is emitted when full; its first
   // item is its longest, since the items come longest first.
   std::vector<Item> ordered;
   std::vector<int> item_rot;
@@ -2880,10 +2880,10 @@ ace_status ace_debug_schedule(const ace_graph* g, int32_t* kind, int64_t* info) 
       int64_t real3 = 0;
       for (size_t i = g->rm[3].cs_ent; i < g->rm[3].kmap.size(); ++i) real3 += g->rm[3].kmap[i] != -1;
       info[14] = real3;
-      // mean LDS bank load of the row pushes (8-byte atomics, served a
-      // quarter-wave at a time over 16 bank pairs, slot mod 16 with the
-      // halves ordered by slot bit 3): per push instruction and quarter, the
-      // most lanes on one bank pair (x1000)
+      // mean LDS bank load of the row pushes (8-byte atomics into the Re or
+      // Im plane, served a quarter-wave at a time over 16 bank pairs, slot
+      // mod 16): per push instruction and quarter, the most lanes on one
+      // bank pair (x1000)
       const int nh = std::min(g->opts.hot_columns, g->opts.env_per_block > 1 ? 2 : 4);
       int64_t pcost = 0, npq = 0;
       for (const int4& sl : R.slice) {

@@ -280,16 +280,9 @@ template __global__ void basis_kernel<true>(BasisArgs);
 // ---------------------------------------------------------------------------
 // DAG forward + reverse pass
 // ---------------------------------------------------------------------------
-// The two 8-byte halves go out in an order set by bit 7 of the address
-// (bit 3 of a 16-byte slot index): the LDS serves 8-byte atomics a
-// quarter-wave at a time over 16 bank pairs, so that a quarter whose slots
-// are distinct mod 16 hits 16 different pairs with each instruction (with
-// the real parts first in every lane, 16 lanes share 8 pairs).
 __device__ __forceinline__ void atomic_cadd(double2* addr, double2 v) {
-  double* d = reinterpret_cast<double*>(addr);
-  const int sw = (int)((reinterpret_cast<uintptr_t>(addr) >> 7) & 1);
-  atomicAdd(d + sw, sw ? v.y : v.x);
-  atomicAdd(d + (sw ^ 1), sw ? v.x : v.y);
+  atomicAdd(&addr->x, v.x);
+  atomicAdd(&addr->y, v.y);
 }
 
 __device__ __forceinline__ double coef_of(const double* coeffs, int k) {
@@ -970,25 +963,45 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs p) {
 // accumulators updated with atomics, so the reverse pass is not bitwise
 // deterministic (the forward pass is).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void push_adj(int P1, const uint32_t* n2, const double2* x, double2* ab, int slot,
+// Adjoint accumulators of one environment in LDS, in two planes of doubles:
+// Re abar_s at re[s], Im abar_s at re[n + s].  The LDS serves 8-byte
+// atomics a quarter-wave at a time over 16 bank pairs; in a plane the atomic
+// on slot s lands on pair s mod 16 (up to a shift), so a quarter whose slots
+// are distinct mod 16 is served without conflicts, where with interleaved
+// complex values the real parts of 16 slots would share 8 pairs.
+struct AdjPlanes {
+  double* re;
+  int n;
+  __device__ __forceinline__ void add(int s, double2 d) const {
+    atomicAdd(re + s, d.x);
+    atomicAdd(re + n + s, d.y);
+  }
+  __device__ __forceinline__ double2 get(int s) const { return make_double2(re[s], re[n + s]); }
+  __device__ __forceinline__ void set(int s, double2 v) const {
+    re[s] = v.x;
+    re[n + s] = v.y;
+  }
+};
+
+__device__ __forceinline__ void push_adj(int P1, const uint32_t* n2, const double2* x, const AdjPlanes& ab, int slot,
                                          double2 d) {
   if (slot <= P1) {
-    atomic_cadd(&ab[slot], d);
+    ab.add(slot, d);
   } else {
     const uint32_t q = n2[slot - P1 - 1];
     const int a = (int)(q & 0xffffu), b = (int)(q >> 16);
-    atomic_cadd(&ab[a], cmul(d, x[b]));
-    atomic_cadd(&ab[b], cmul(d, x[a]));
+    ab.add(a, cmul(d, x[b]));
+    ab.add(b, cmul(d, x[a]));
   }
 }
 
 // Push with an adjoint accumulator for every resident slot (full mode) or
 // forwarding order-2 contributions to the one-particle adjoints at once.
 template <bool FULL>
-__device__ __forceinline__ void push_r(int P1, const uint32_t* n2, const double2* x, double2* ab, int slot,
+__device__ __forceinline__ void push_r(int P1, const uint32_t* n2, const double2* x, const AdjPlanes& ab, int slot,
                                        double2 d) {
   if (FULL)
-    atomic_cadd(&ab[slot], d);
+    ab.add(slot, d);
   else
     push_adj(P1, n2, x, ab, slot, d);
 }
@@ -1056,11 +1069,11 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
   const int nab = GRAD ? (FULL ? p.nslot : p.P1 + 1) : 0;
   const int per_env = p.nslot + nab;
   double2* x[NE];
-  double2* ab[NE];
+  AdjPlanes ab[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     x[q] = lds + q * per_env;
-    ab[q] = x[q] + p.nslot;
+    ab[q] = AdjPlanes{reinterpret_cast<double*>(x[q] + p.nslot), nab};
   }
   uint32_t* n2 = reinterpret_cast<uint32_t*>(lds + NE * per_env);
   double2* red = reinterpret_cast<double2*>(n2) + (TAB ? (p.N2 + 3) / 4 : 0);
@@ -1079,19 +1092,19 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         x[q][i] = e0 + q < p.n_env ? p.A[(e0 + q) * P1 + i] : z2;
-        if (GRAD) ab[q][i] = make_double2(leaf, 0.0);
+        if (GRAD) ab[q].set(i, make_double2(leaf, 0.0));
       }
     }
     if (threadIdx.x == 0)
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         x[q][ZERO] = z2;
-        if (GRAD) ab[q][ZERO] = z2;
+        if (GRAD) ab[q].set(ZERO, z2);
       }
     if (GRAD && FULL)
       for (int u = threadIdx.x; u < p.N2; u += blockDim.x)
 #pragma unroll
-        for (int q = 0; q < NE; ++q) ab[q][P1 + 1 + u] = z2;
+        for (int q = 0; q < NE; ++q) ab[q].set(P1 + 1 + u, z2);
     __syncthreads();
     // phi = acc (unfolded); Re acc + i Im acci (folded)
     double2 acc[NE], acci[NE];
@@ -1340,9 +1353,9 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
 #pragma unroll
         for (int f = 0; f < kForwardChunk; ++f)
 #pragma unroll
-          for (int q = 0; q < NE; ++q) s2[q] = cfma(ab[q][en[f] & 0xffffu], x[q][en[f] >> 16], s2[q]);
+          for (int q = 0; q < NE; ++q) s2[q] = cfma(ab[q].get(en[f] & 0xffffu), x[q][en[f] >> 16], s2[q]);
 #pragma unroll
-        for (int q = 0; q < NE; ++q) atomic_cadd(&ab[q][tgt], s2[q]);
+        for (int q = 0; q < NE; ++q) ab[q].add(tgt, s2[q]);
       }
       __syncthreads();
     }
@@ -1357,7 +1370,7 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
       for (int q = 0; q < NE; ++q)
         if (e0 + q < p.n_env) {
           double2* Be = p.Abar + (e0 + q) * P1;
-          for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[q][i];
+          for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[q].get(i);
         }
     __syncthreads();
   }
@@ -1401,7 +1414,8 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
 // d added to abar_s: in the register accumulator of s if s is one of the
 // NH hot slots, else atomically in LDS (every index into h is a constant).
 template <int K, int NH>
-__device__ __forceinline__ void push_hot_from(double2* ab, int s, double2 d, const int4& hot, double2 (&h)[NH]) {
+__device__ __forceinline__ void push_hot_from(const AdjPlanes& ab, int s, double2 d, const int4& hot,
+                                              double2 (&h)[NH]) {
   if constexpr (K < NH) {
     const int hk = K == 0 ? hot.x : K == 1 ? hot.y : K == 2 ? hot.z : hot.w;
     if (s == hk) {
@@ -1411,11 +1425,11 @@ __device__ __forceinline__ void push_hot_from(double2* ab, int s, double2 d, con
       push_hot_from<K + 1, NH>(ab, s, d, hot, h);
     }
   } else {
-    atomic_cadd(&ab[s], d);
+    ab.add(s, d);
   }
 }
 template <int NH>
-__device__ __forceinline__ void push_hot(double2* ab, int s, double2 d, const int4& hot, double2 (&h)[NH]) {
+__device__ __forceinline__ void push_hot(const AdjPlanes& ab, int s, double2 d, const int4& hot, double2 (&h)[NH]) {
   push_hot_from<0, NH>(ab, s, d, hot, h);
 }
 
@@ -1504,7 +1518,7 @@ __device__ __forceinline__ void remat_entries(const RematArgs& p, const double2*
 // adjoint y pushed to the row's factors by prefix and suffix products.  NH
 // hot one-particle slots per environment are summed in registers.
 template <bool GRAD, int NB, bool FOLD, int NE, int NH>
-__device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, double2* ab, int xs, int as,
+__device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, double* ab, int xs, int as,
                                           uint64_t blo, uint64_t bhi, const double2 (&y1)[NE],
                                           const double2 (&y2)[NE], double2 (&acc)[NE], double2 (&hot)[NE][NH]) {
   const double w = GRAD ? 0.5 : 1.0;
@@ -1542,7 +1556,8 @@ __device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, 
       double2 suf = y1[e];
 #pragma unroll
       for (int i = NB - 1; i >= 0; --i) {
-        push_hot<NH>(ab + e * as, slot16(blo, bhi, i) >> 4, i == 0 ? suf : cmul(pre[i], suf), p.hot, hot[e]);
+        push_hot<NH>(AdjPlanes{ab + 2 * e * as, as}, slot16(blo, bhi, i) >> 4, i == 0 ? suf : cmul(pre[i], suf),
+                     p.hot, hot[e]);
         if (i > 0) {
           if constexpr (KEEP)
             suf = cmul(suf, xf[i]);
@@ -1570,8 +1585,8 @@ __global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_ker
   const int xs = P1 + 1 + p.n_pairs;   // values per environment: one-particle, constant one, pair products
   const int as = GRAD ? P1 + 1 : 0;    // one-particle adjoints per environment
   double2* x = lds;                    // [NE][xs]
-  double2* ab = lds + NE * xs;         // [NE][as]
-  double2* red = ab + NE * as;
+  double* ab = reinterpret_cast<double*>(lds + NE * xs);   // [NE][2][as]: Re and Im planes (AdjPlanes)
+  double2* red = reinterpret_cast<double2*>(ab + 2 * NE * as);
   const int lane = threadIdx.x & 63;
   // wave index, made visibly uniform so that slice descriptors and loop
   // bounds live in scalar registers
@@ -1589,18 +1604,24 @@ __global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_ker
         const double2 a = e < ne ? p.A[(e0 + e) * P1 + i] : make_double2(0.0, 0.0);
         x[e * xs + i] = a;
         if constexpr (FOLD) {
-          if (GRAD) ab[e * as + i] = make_double2(k.c.x, 0.0);
+          if (GRAD) {
+            ab[2 * e * as + i] = k.c.x;
+            ab[(2 * e + 1) * as + i] = 0.0;
+          }
           acc[e].x = fma(k.c.x, a.x, acc[e].x);
           acc[e].y = fma(k.c.y, a.y, acc[e].y);
         } else {
-          if (GRAD) ab[e * as + i] = make_double2(k.c, 0.0);
+          if (GRAD) {
+            ab[2 * e * as + i] = k.c;
+            ab[(2 * e + 1) * as + i] = 0.0;
+          }
           acc[e] = rfma(k.c, a, acc[e]);
         }
       }
     }
     if (threadIdx.x < NE) {
       x[threadIdx.x * xs + ONE] = make_double2(1.0, 0.0);
-      if (GRAD) ab[threadIdx.x * as + ONE] = make_double2(0.0, 0.0);
+      if (GRAD) ab[2 * threadIdx.x * as + ONE] = ab[(2 * threadIdx.x + 1) * as + ONE] = 0.0;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < p.n_pairs; r += blockDim.x) {
@@ -1648,7 +1669,7 @@ __global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_ker
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
           const double2 v = wave_sum(hot[e][h]);
-          if (lane == 0 && hs[h] != ONE) atomic_cadd(&ab[e * as + hs[h]], v);
+          if (lane == 0 && hs[h] != ONE) AdjPlanes{ab + 2 * e * as, as}.add(hs[h], v);
         }
     }
 #pragma unroll
@@ -1659,7 +1680,8 @@ __global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_ker
     if (GRAD) {
       for (int e = 0; e < ne; ++e) {
         double2* Be = p.Abar + (e0 + e) * P1;
-        for (int i = threadIdx.x; i < P1; i += blockDim.x) Be[i] = ab[e * as + i];
+        for (int i = threadIdx.x; i < P1; i += blockDim.x)
+          Be[i] = make_double2(ab[2 * e * as + i], ab[(2 * e + 1) * as + i]);
       }
     }
     __syncthreads();
