@@ -1264,19 +1264,39 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     for (int k = 0; k < 4; ++k)
       R.hot[k] = (k < g->opts.hot_columns && k < P1 && freq[ord[k]] * 64 >= npush) ? ord[k] : ONE;
   }
-  // factors of a row node, rotated by `rot`: lanes of a slice start their
-  // factor lists at different positions, so rows that share leading factors
-  // (neighbours in tuple order) do not push to one address in one instruction
-  auto pack = [&](int32_t node, int from, int rot = 0) {
+  // factors of a row node in the order perm (factor perm[u] at position u):
+  // lanes of a slice order their factor lists differently, so rows that
+  // share factors do not push to one address, or one bank pair, in one
+  // instruction (the product does not depend on the order)
+  using Perm = std::array<int8_t, 8>;
+  auto pack = [&](int32_t node, int from, const Perm& perm) {
     const int count = h.node_len[node];
     uint64_t w = 0;
     for (int u = 0; u < 4; ++u) {
       const int idx = from + u;
       const uint64_t sl =
-          16 * (idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + (idx + rot) % count] : (uint64_t)ONE);
+          16 * (idx < count ? (uint64_t)h.node_flat[(int64_t)node * W + perm[idx]] : (uint64_t)ONE);
       w |= sl << (16 * u);
     }
     return w;
+  };
+  // the factor orders tried for a row of nb factors: every permutation up to
+  // five factors, else the rotations
+  auto perms_of = [](int nb) {
+    std::vector<Perm> ps;
+    Perm pm{};
+    for (int u = 0; u < 8; ++u) pm[u] = (int8_t)u;
+    if (nb <= 5) {
+      do ps.push_back(pm);
+      while (std::next_permutation(pm.begin(), pm.begin() + nb));
+    } else {
+      for (int r = 0; r < nb; ++r) {
+        Perm rp{};
+        for (int u = 0; u < 8; ++u) rp[u] = (int8_t)(u < nb ? (u + r) % nb : u);
+        ps.push_back(rp);
+      }
+    }
+    return ps;
   };
   const uint64_t one16 = 16 * (uint64_t)ONE;
   const uint64_t ones = one16 | (one16 << 16) | (one16 << 32) | (one16 << 48);
@@ -1292,13 +1312,13 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   // in registers, and the constant slot do not count.  A slice is emitted when full; its first
   // item is its longest, since the items come longest first.
   std::vector<Item> ordered;
-  std::vector<int> item_rot;
+  std::vector<Perm> item_perm;
   std::vector<size_t> cut;   // slice ends in `ordered`
   {
     constexpr int kOpen = 4;
     struct Open {
       std::vector<size_t> idx;
-      std::vector<int> rot;
+      std::vector<Perm> perm;
       std::vector<std::map<int32_t, int>> mult;   // per push: lanes on a slot, keyed 4 * slot + quarter
       std::vector<std::array<int, 64>> bank;       // per push: lanes on a bank pair, [16 * quarter + slot mod 16]
     };
@@ -1310,15 +1330,16 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       return false;
     };
     ordered.reserve(items.size());
-    item_rot.reserve(items.size());
+    item_perm.reserve(items.size());
     for (size_t g0 = 0; g0 < items.size();) {
       size_t g1 = g0;
       while (g1 < items.size() && items[g1].nb == items[g0].nb && items[g1].sig == items[g0].sig) ++g1;
       const int nbs = items[g0].nb;
+      const std::vector<Perm> perms = perms_of(nbs);
       std::vector<Open> open(kOpen);
       auto reset = [&](Open& o) {
         o.idx.clear();
-        o.rot.clear();
+        o.perm.clear();
         o.mult.assign(nbs, {});
         o.bank.assign(nbs, {});
         for (auto& bk : o.bank) bk.fill(0);
@@ -1326,7 +1347,7 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       auto flush = [&](Open& o) {
         for (size_t t = 0; t < o.idx.size(); ++t) {
           ordered.push_back(items[o.idx[t]]);
-          item_rot.push_back(o.rot[t]);
+          item_perm.push_back(o.perm[t]);
         }
         cut.push_back(ordered.size());
         reset(o);
@@ -1334,36 +1355,45 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
       for (auto& o : open) reset(o);
       for (size_t t = g0; t < g1; ++t) {
         const int32_t* f = &h.node_flat[(int64_t)items[t].row * W];
-        int bs = 0, br = 0, bc = INT32_MAX;
-        for (int k = 0; k < kOpen; ++k) {
+        int bs = 0, bc = INT32_MAX;
+        size_t bp = 0;
+        for (int k = 0; k < kOpen && bc > 0; ++k) {
           const int lane = (int)open[k].idx.size();
           const int quarter = lane >> 4;
-          for (int r0 = 0; r0 < nbs; ++r0) {
-            const int r = (lane + r0) % nbs;
-            int cost = 0;
-            for (int i = 0; i < nbs; ++i) {
-              const int32_t sl = f[(i + r) % nbs];
+          int col[8][8];   // col[i][u]: contention of factor u pushed at position i
+          for (int i = 0; i < nbs; ++i)
+            for (int u = 0; u < nbs; ++u) {
+              const int32_t sl = f[u];
+              col[i][u] = 0;
               if (is_hot(sl)) continue;
               const auto m = open[k].mult[i].find(4 * sl + quarter);
-              cost += (m == open[k].mult[i].end() ? 0 : m->second) + open[k].bank[i][16 * quarter + (sl & 15)];
+              col[i][u] = (m == open[k].mult[i].end() ? 0 : m->second) + open[k].bank[i][16 * quarter + (sl & 15)];
             }
+          // start the scan at a lane-dependent order: among equal costs,
+          // neighbouring lanes take different orders
+          for (size_t q0 = 0; q0 < perms.size(); ++q0) {
+            const size_t q = (q0 + (size_t)lane) % perms.size();
+            int cost = 0;
+            for (int i = 0; i < nbs; ++i) cost += col[i][perms[q][i]];
             if (cost < bc) {
               bc = cost;
               bs = k;
-              br = r;
+              bp = q;
+              if (cost == 0) break;
             }
           }
         }
         Open& o = open[bs];
+        const Perm& pm = perms[bp];
         const int quarter = (int)o.idx.size() >> 4;
         for (int i = 0; i < nbs; ++i) {
-          const int32_t sl = f[(i + br) % nbs];
+          const int32_t sl = f[pm[i]];
           if (is_hot(sl)) continue;
           o.mult[i][4 * sl + quarter] += 1;
           o.bank[i][16 * quarter + (sl & 15)] += 1;
         }
         o.idx.push_back(t);
-        o.rot.push_back(br);
+        o.perm.push_back(pm);
         if (o.idx.size() == 64) flush(o);
       }
       for (auto& o : open)
@@ -1387,13 +1417,11 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
     if (R.fold) R.kbar.resize(P1 + e0 + 64 * (size_t)ncol, -1);
     // per lane: its entries, then their column and factor rotation
     std::vector<std::vector<int64_t>> lane_ents(64);
-    int rot[64] = {0};
-    for (int lane = 0; lane < 64; ++lane) rot[lane] = i0 + lane < i1 ? item_rot[i0 + lane] : 0;
     for (int lane = 0; lane < 64; ++lane) {
       if (i0 + lane < i1) {
         const Item& it = items[i0 + lane];
-        R.rlo.push_back(pack(it.row, 0, rot[lane]));
-        R.rhi.push_back(pack(it.row, 4, rot[lane]));
+        R.rlo.push_back(pack(it.row, 0, item_perm[i0 + lane]));
+        R.rhi.push_back(pack(it.row, 4, item_perm[i0 + lane]));
         for (int j = 0; j < it.count; ++j) lane_ents[lane].push_back(it.first + j);
       } else {
         R.rlo.push_back(ones);
