@@ -48,6 +48,7 @@ constexpr int kGradThreads = 256;   // planar gradient kernel
 constexpr int kGradWave = 64;       // O(3) gradient kernel: one wave per block
 constexpr int kArenaBlocks = 1024;
 constexpr int kRematMaxSlots = 4096;   // remat factor fields are 16-bit LDS byte offsets
+constexpr int64_t kRematMaxEntries = 1 << 26;   // coefficients plus entry positions of one remat schedule
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -1406,8 +1407,8 @@ void pack_remat(ace_graph* g, std::vector<REnt>& ents, ace_graph::Remat& R, bool
   for (const size_t i1 : cut) {
     const std::vector<Item>& items = ordered;   // the emission below reads the slice order
     const int ncol = items[i0].count;
-    if ((int64_t)R.rlo.size() + 64 > INT32_MAX || pos + 64LL * ncol > INT32_MAX)
-      throw std::length_error("remat schedule larger than 2^31 entries");
+    if ((int64_t)R.rlo.size() + 64 > INT32_MAX || P1 + pos + 64LL * ncol > kRematMaxEntries)
+      throw std::length_error("remat schedule larger than 2^26 entries");
     const int sig = items[i0].sig;
     R.slice.push_back(make_int4((int)R.rlo.size(), (int)pos, ncol, items[i0].nb | (sig << 8)));
     const size_t e0 = R.olo.size();
@@ -2312,6 +2313,7 @@ ace_status launch_remat(const ace_graph* g, const double* coeffs, int64_t n_env,
   a.n_slices = R.nslices;
   a.pairs = R.d_pairs;
   a.n_pairs = (int)R.pairs.size();
+  a.n_ent = (int)R.olo.size();
   a.hot = make_int4(R.hot[0], R.hot[1], R.hot[2], R.hot[3]);
   const int ne = remat_env_per_block(g, which);
   const size_t lds = remat_lds_bytes(g, which, ne);

@@ -189,6 +189,7 @@ struct RematArgs {
   const uint32_t* pairs;     // [n_pairs] one-particle slots a | b << 16 of the pair products
   int cs_leaf, cs_ent;
   int P1, n_slices, n_pairs;
+  int n_ent;                 // entry positions (at most 2^26: byte offsets of the entry loads fit in 31 bits)
   int4 hot;                  // one-particle slots whose adjoints are summed in registers (P1 = unused)
 };
 

@@ -1450,6 +1450,31 @@ __device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo,
   return v;
 }
 
+// Entry metadata and coefficients of the remat schedule are read with
+// buffer loads: a per-lane byte offset fixed for the whole slice and a
+// wave-uniform offset (scalar register) that advances with the entry
+// column, so no per-entry address arithmetic runs on the vector ALU.
+// Resource word 3 as for raw buffers on CDNA; out-of-range loads return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+struct EntryBufs {
+  __amdgpu_buffer_rsrc_t lo, hi, cs;
+};
+__device__ __forceinline__ uint64_t buf_u64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// coefficient of entry column index u (wave-uniform part of the coefficient index)
+template <bool FOLD>
+__device__ __forceinline__ RCoef<FOLD> buf_coef(__amdgpu_buffer_rsrc_t r, int lane, int u) {
+  RCoef<FOLD> k;
+  if constexpr (FOLD)
+    k.c = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16, u * 16, 0));
+  else
+    k.c = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, u * 8, 0));
+  return k;
+}
+
 // One lane item is a chunk of a row: the terms that share one parent (the
 // row's base, a product of NB one-particle values) for NE environments,
 // which share every metadata and coefficient load; environment e's values
@@ -1459,22 +1484,22 @@ __device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo,
 // folded) over the item's entries, x_j the other parent of term j, a
 // product of SIG factors (one-particle values or pair products).
 template <int SIG, bool FOLD, int NE>
-__device__ __forceinline__ void remat_entries(const RematArgs& p, const double2* x, int xs, const int4& sl, int lane,
-                                              double2 (&y1)[NE], double2 (&y2)[NE]) {
+__device__ __forceinline__ void remat_entries(const RematArgs& p, const EntryBufs& eb, const double2* x, int xs,
+                                              const int4& sl, int lane, double2 (&y1)[NE], double2 (&y2)[NE]) {
   // entry metadata of this slice, prefetched one entry ahead of its use in
-  // two register sets (the loop is unrolled by two)
-  const uint64_t* olo_p = p.oth_lo + sl.y + lane;
-  const uint64_t* ohi_p = p.oth_hi + sl.y + lane;
-  const unsigned c0 = (unsigned)(p.cs_ent + sl.y + lane);
+  // two register sets (the loop is unrolled by two); entry column j of the
+  // slice sits at entry index sl.y + 64 j + lane
+  const int vo = lane * 8;
+  const int c0 = p.cs_ent + sl.y;   // wave-uniform coefficient index of column 0, lane 0
   const int n = sl.z;
 #pragma unroll
   for (int e = 0; e < NE; ++e) y1[e] = y2[e] = make_double2(0.0, 0.0);
   if constexpr (NE > 1 && SIG > 4) {
     // long products of several environments: one entry in flight (registers)
     for (int j = 0; j < n; ++j) {
-      const unsigned o = (unsigned)j * 64u;
-      const uint64_t lo = olo_p[o], hi = ohi_p[o];
-      const RCoef<FOLD> c = load_coef<FOLD>(p.cs, c0 + o);
+      const int so = (sl.y + 64 * j) * 8;
+      const uint64_t lo = buf_u64(eb.lo, vo, so), hi = buf_u64(eb.hi, vo, so);
+      const RCoef<FOLD> c = buf_coef<FOLD>(eb.cs, lane, c0 + 64 * j);
 #pragma unroll
       for (int e = 0; e < NE; ++e) coef_fma<FOLD>(c, factor_product<SIG>(x + e * xs, lo, hi), y1[e], y2[e]);
     }
@@ -1483,23 +1508,23 @@ __device__ __forceinline__ void remat_entries(const RematArgs& p, const double2*
   uint64_t a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
   RCoef<FOLD> a_c{}, b_c{};
   if (n > 0) {
-    a_lo = olo_p[0];
-    if (SIG > 4) a_hi = ohi_p[0];
-    a_c = load_coef<FOLD>(p.cs, c0);
+    a_lo = buf_u64(eb.lo, vo, sl.y * 8);
+    if (SIG > 4) a_hi = buf_u64(eb.hi, vo, sl.y * 8);
+    a_c = buf_coef<FOLD>(eb.cs, lane, c0);
   }
   int j = 0;
   for (; j + 1 < n; j += 2) {
-    const unsigned o1 = (unsigned)(j + 1) * 64u;
-    b_lo = olo_p[o1];
-    if (SIG > 4) b_hi = ohi_p[o1];
-    b_c = load_coef<FOLD>(p.cs, c0 + o1);
+    const int so1 = (sl.y + 64 * (j + 1)) * 8;
+    b_lo = buf_u64(eb.lo, vo, so1);
+    if (SIG > 4) b_hi = buf_u64(eb.hi, vo, so1);
+    b_c = buf_coef<FOLD>(eb.cs, lane, c0 + 64 * (j + 1));
 #pragma unroll
     for (int e = 0; e < NE; ++e) coef_fma<FOLD>(a_c, factor_product<SIG>(x + e * xs, a_lo, a_hi), y1[e], y2[e]);
     if (j + 2 < n) {
-      const unsigned o2 = (unsigned)(j + 2) * 64u;
-      a_lo = olo_p[o2];
-      if (SIG > 4) a_hi = ohi_p[o2];
-      a_c = load_coef<FOLD>(p.cs, c0 + o2);
+      const int so2 = (sl.y + 64 * (j + 2)) * 8;
+      a_lo = buf_u64(eb.lo, vo, so2);
+      if (SIG > 4) a_hi = buf_u64(eb.hi, vo, so2);
+      a_c = buf_coef<FOLD>(eb.cs, lane, c0 + 64 * (j + 2));
     }
 #pragma unroll
     for (int e = 0; e < NE; ++e) coef_fma<FOLD>(b_c, factor_product<SIG>(x + e * xs, b_lo, b_hi), y1[e], y2[e]);
@@ -1592,6 +1617,8 @@ __global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_ker
   // bounds live in scalar registers
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
+  const EntryBufs eb{raw_rsrc(p.oth_lo, p.n_ent * 8), raw_rsrc(p.oth_hi, p.n_ent * 8),
+                     raw_rsrc(p.cs, (p.cs_ent + p.n_ent) * (FOLD ? 16 : 8))};
   for (int64_t e0 = (int64_t)blockIdx.x * NE; e0 < p.n_env; e0 += (int64_t)gridDim.x * NE) {
     const int ne = (int)min((int64_t)NE, p.n_env - e0);
     double2 acc[NE];
@@ -1643,13 +1670,13 @@ __global__ __launch_bounds__(BIG ? kRematBlock : kRematBlock / 2) void remat_ker
       const uint64_t bhi = (sl.w & 0xff) > 4 ? p.row_hi[item] : 0;
       double2 y1[NE], y2[NE];
       switch (sl.w >> 8) {
-        case 1: remat_entries<1, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
-        case 2: remat_entries<2, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
-        case 3: remat_entries<3, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
-        case 4: remat_entries<4, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
-        case 5: remat_entries<5, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
-        case 6: remat_entries<6, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
-        default: remat_entries<7, FOLD, NE>(p, x, xs, sl, lane, y1, y2); break;
+        case 1: remat_entries<1, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
+        case 2: remat_entries<2, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
+        case 3: remat_entries<3, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
+        case 4: remat_entries<4, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
+        case 5: remat_entries<5, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
+        case 6: remat_entries<6, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
+        default: remat_entries<7, FOLD, NE>(p, eb, x, xs, sl, lane, y1, y2); break;
       }
       switch (sl.w & 0xff) {
         case 1: remat_row<GRAD, 1, FOLD, NE, NH>(p, x, ab, xs, as, blo, bhi, y1, y2, acc, hot); break;
