@@ -934,6 +934,9 @@ void make_forest(ace_graph* g, int which) {
       if (!any) break;
     }
   }
+  if (F.kmap.size() > (size_t)(INT32_MAX / 16) || F.me_col.size() > (size_t)(INT32_MAX / 2) ||
+      F.ch_s.size() > (size_t)(INT32_MAX / 2))
+    return fail_forest("forest schedule larger than 2^27 coefficients");
   F.ok = true;
 }
 
@@ -2250,6 +2253,9 @@ ace_status launch_forest(const ace_graph* g, const double* coeffs, int64_t n_env
   a.cs_ch = F.cs_ch;
   a.cs_gc = F.cs_gc;
   a.cs_hot = F.cs_hot;
+  a.n_me = (int)F.me_col.size();
+  a.n_ch = (int)F.ch_s.size();
+  a.n_cs = (int)F.kmap.size();
   a.n_items = F.n_items;
   for (int w = 0; w <= kMaxForestWaves; ++w) {
     a.mr_wave[w] = F.mr_wave[w];

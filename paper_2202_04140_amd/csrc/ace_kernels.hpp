@@ -154,6 +154,7 @@ struct ForestArgs {
   const int2* ch_g;          // children: grandchild range [x, y) (nullptr if none exist)
   const uint16_t* gc_s;      // grandchildren: resident sibling slot
   int cs_leaf, cs_me, cs_it, cs_ch, cs_gc, cs_hot;
+  int n_me, n_ch, n_cs;      // sizes of me_col, ch_s and cs (in coefficients; byte sizes below 2^31)
   int P1, N2, nslot, n_mslices, n_tslices;
   int n_items;   // 64 * n_tslices
   int4 hot;      // slots of the four hot-sibling columns (P1 = unused)

@@ -1049,6 +1049,34 @@ __device__ __forceinline__ double re_w(const RCoef<FOLD>& k) {
     return k.c;
 }
 
+// Schedule metadata and coefficients of the forest and remat kernels are
+// read with buffer loads: a per-lane byte offset fixed for the whole slice
+// and a wave-uniform offset (scalar register) that advances with the entry
+// column, so no per-entry address arithmetic runs on the vector ALU.
+// Resource word 3 as for raw buffers on CDNA; out-of-range loads return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+struct EntryBufs {
+  __amdgpu_buffer_rsrc_t lo, hi, cs;
+};
+__device__ __forceinline__ int buf_u16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+}
+__device__ __forceinline__ uint64_t buf_u64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// coefficient of entry column index u (wave-uniform part of the coefficient index)
+template <bool FOLD>
+__device__ __forceinline__ RCoef<FOLD> buf_coef(__amdgpu_buffer_rsrc_t r, int lane, int u) {
+  RCoef<FOLD> k;
+  if constexpr (FOLD)
+    k.c = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16, u * 16, 0));
+  else
+    k.c = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, u * 8, 0));
+  return k;
+}
+
 constexpr int kForestBlock = 512;
 
 // FOLD: the folded schedule (one tuple of each conjugate pair, with
@@ -1085,6 +1113,9 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
   const double2 z2 = make_double2(0.0, 0.0);
   if (TAB)
     for (int u = threadIdx.x; u < p.N2; u += blockDim.x) n2[u] = p.nu2_ab[u];
+  const __amdgpu_buffer_rsrc_t r_me = raw_rsrc(p.me_col, p.n_me * 2);
+  const __amdgpu_buffer_rsrc_t r_ch = raw_rsrc(p.ch_s, p.n_ch * 2);
+  const __amdgpu_buffer_rsrc_t r_cs = raw_rsrc(cs, p.n_cs * (FOLD ? 16 : 8));
   for (int64_t e0 = (int64_t)blockIdx.x * NE; e0 < p.n_env; e0 += (int64_t)gridDim.x * NE) {
     // phase 0: one-particle values and adjoint accumulators
     for (int i = threadIdx.x; i < P1; i += blockDim.x) {
@@ -1144,19 +1175,22 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
 #pragma unroll
       for (int q = 0; q < NE; ++q) y0[q] = y1[q] = y0i[q] = y1i[q] = z2;
       const int z4 = sl.z & ~3;
+      // entry column j of the slice: entry sl.y + 64 j + lane (wave-uniform part u)
       for (int j = z4; j < sl.z; ++j) {
-        const int pos = sl.y + j * 64 + lane;
-        const int c0 = p.me_col[pos];
-        const RCoef<FOLD> k0 = load_coef<FOLD>(cs, p.cs_me + pos);
+        const int u = sl.y + j * 64;
+        const int c0 = buf_u16(r_me, 2 * lane, 2 * u);
+        const RCoef<FOLD> k0 = buf_coef<FOLD>(r_cs, lane, p.cs_me + u);
 #pragma unroll
         for (int q = 0; q < NE; ++q) coef_fma(k0, x[q][c0], y0[q], y0i[q]);
       }
       for (int j = 0; j < z4; j += 4) {
-        const int pos = sl.y + j * 64 + lane;
-        const int c0 = p.me_col[pos], c1 = p.me_col[pos + 64];
-        const int c2 = p.me_col[pos + 128], c3 = p.me_col[pos + 192];
-        const RCoef<FOLD> k0 = load_coef<FOLD>(cs, p.cs_me + pos), k1 = load_coef<FOLD>(cs, p.cs_me + pos + 64);
-        const RCoef<FOLD> k2 = load_coef<FOLD>(cs, p.cs_me + pos + 128), k3 = load_coef<FOLD>(cs, p.cs_me + pos + 192);
+        const int u = sl.y + j * 64;
+        const int c0 = buf_u16(r_me, 2 * lane, 2 * u), c1 = buf_u16(r_me, 2 * lane, 2 * (u + 64));
+        const int c2 = buf_u16(r_me, 2 * lane, 2 * (u + 128)), c3 = buf_u16(r_me, 2 * lane, 2 * (u + 192));
+        const RCoef<FOLD> k0 = buf_coef<FOLD>(r_cs, lane, p.cs_me + u);
+        const RCoef<FOLD> k1 = buf_coef<FOLD>(r_cs, lane, p.cs_me + u + 64);
+        const RCoef<FOLD> k2 = buf_coef<FOLD>(r_cs, lane, p.cs_me + u + 128);
+        const RCoef<FOLD> k3 = buf_coef<FOLD>(r_cs, lane, p.cs_me + u + 192);
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           const double2 x0 = x[q][c0], x1 = x[q][c1], x2 = x[q][c2], x3 = x[q][c3];
@@ -1233,9 +1267,9 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
         // four children at a time, then the remainder (padding: sibling ZERO, coefficient 0)
         const int z4 = sl.z & ~3;
         for (int j = z4; j < sl.z; ++j) {
-          const int pos = sl.y + j * 64 + lane;
-          const int s0 = p.ch_s[pos];
-          const RCoef<FOLD> k0 = load_coef<FOLD>(cs, cc + pos);
+          const int u = sl.y + j * 64;
+          const int s0 = buf_u16(r_ch, 2 * lane, 2 * u);
+          const RCoef<FOLD> k0 = buf_coef<FOLD>(r_cs, lane, cc + u);
           const double r0 = re_w(k0);
 #pragma unroll
           for (int q = 0; q < NE; ++q) {
@@ -1244,10 +1278,11 @@ __global__ __launch_bounds__(kForestBlock, NE == 1 ? 4 : 2) void forest_kernel(F
           }
         }
         for (int j = 0; j < z4; j += 4) {
-          const int pos = sl.y + j * 64 + lane;
-          const int s0 = p.ch_s[pos], s1 = p.ch_s[pos + 64], s2 = p.ch_s[pos + 128], s3 = p.ch_s[pos + 192];
-          const RCoef<FOLD> k0 = load_coef<FOLD>(cs, cc + pos), k1 = load_coef<FOLD>(cs, cc + pos + 64);
-          const RCoef<FOLD> k2 = load_coef<FOLD>(cs, cc + pos + 128), k3 = load_coef<FOLD>(cs, cc + pos + 192);
+          const int u = sl.y + j * 64;
+          const int s0 = buf_u16(r_ch, 2 * lane, 2 * u), s1 = buf_u16(r_ch, 2 * lane, 2 * (u + 64));
+          const int s2 = buf_u16(r_ch, 2 * lane, 2 * (u + 128)), s3 = buf_u16(r_ch, 2 * lane, 2 * (u + 192));
+          const RCoef<FOLD> k0 = buf_coef<FOLD>(r_cs, lane, cc + u), k1 = buf_coef<FOLD>(r_cs, lane, cc + u + 64);
+          const RCoef<FOLD> k2 = buf_coef<FOLD>(r_cs, lane, cc + u + 128), k3 = buf_coef<FOLD>(r_cs, lane, cc + u + 192);
           const double r0 = re_w(k0), r1 = re_w(k1), r2 = re_w(k2), r3 = re_w(k3);
 #pragma unroll
           for (int q = 0; q < NE; ++q) {
@@ -1448,31 +1483,6 @@ __device__ __forceinline__ double2 factor_product(const double2* x, uint64_t lo,
 #pragma unroll
   for (int u = 1; u < SIG; ++u) v = cmul(v, lds_at(x, slot16(lo, hi, u)));
   return v;
-}
-
-// Entry metadata and coefficients of the remat schedule are read with
-// buffer loads: a per-lane byte offset fixed for the whole slice and a
-// wave-uniform offset (scalar register) that advances with the entry
-// column, so no per-entry address arithmetic runs on the vector ALU.
-// Resource word 3 as for raw buffers on CDNA; out-of-range loads return 0.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
-}
-struct EntryBufs {
-  __amdgpu_buffer_rsrc_t lo, hi, cs;
-};
-__device__ __forceinline__ uint64_t buf_u64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-// coefficient of entry column index u (wave-uniform part of the coefficient index)
-template <bool FOLD>
-__device__ __forceinline__ RCoef<FOLD> buf_coef(__amdgpu_buffer_rsrc_t r, int lane, int u) {
-  RCoef<FOLD> k;
-  if constexpr (FOLD)
-    k.c = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16, u * 16, 0));
-  else
-    k.c = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, u * 8, 0));
-  return k;
 }
 
 // One lane item is a chunk of a row: the terms that share one parent (the
