@@ -565,3 +565,22 @@ def test_aux_ratio_trends_of_sec_3_4():
     assert a2["A"] < a1["A"]
     rows = counts.table(ace.GROUP_TORUS, 1, [4], [8, 12])
     assert [r[:2] for r in rows] == [(4, 8), (4, 12)] and all(0 < r[5] < 1 for r in rows)
+
+
+def test_remat_lds_bank_statistics():
+    """The remat schedule's LDS statistics follow the bank rules measured on
+    gfx950: a quarter-wave of 16-byte reads costs max(2, m) cycles (so the
+    mean is at least 2000 x1000), a push instruction puts at least one lane
+    on its busiest bank pair, and ordering the entry columns by bank group
+    lowers the read cost against the plain order."""
+    g = ace.Graph(4, 10, 4, 4, host_only=True)
+    cost = {}
+    for bs in (1, 0):
+        g.set_schedule(schedule="remat", bank_schedule=bs, env_per_block=2, block_threads=1024, hot_columns=2,
+                       term_chunk=16)
+        info = g.schedule_info()
+        assert info["kind"] == "remat"
+        assert info["bank_cost_x1000"] >= 2000
+        assert 1000 <= info["push_bank_load_x1000"] <= 16000
+        cost[bs] = info["bank_cost_x1000"]
+    assert cost[1] < cost[0]
