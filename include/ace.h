@@ -194,7 +194,10 @@ ace_status ace_graph_build(const ace_basis_spec* spec, ace_graph** out);
  *                  environments' values do not fit in LDS)
  * hot_columns also sets the number of one-particle slots whose adjoints
  * the remat kernel sums in registers (at most 2 with two environments per
- * block).
+ * block).  The kernels read schedule metadata with 32-bit byte offsets: a
+ * remat schedule of more than 2^26 entries, or a forest schedule of more
+ * than 2^27 coefficients, is not built (the graph then has no such
+ * schedule, and AUTO takes the next one).
  */
 #define ACE_SCHEDULE_AUTO 0
 #define ACE_SCHEDULE_FOREST 1   /* one-particle and order-2 values resident in LDS */
