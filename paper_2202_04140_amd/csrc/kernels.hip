@@ -1548,7 +1548,7 @@ __device__ __forceinline__ void remat_entries(const RematArgs& p, const EntryBuf
 // remat_row: the row value x_b (product of the NB row factors, whose
 // packed offsets blo, bhi were loaded before the entries; the values are
 // read after them so that they hold no registers there, and rows of up to
-// four factors keep them for the suffix products), phi += x_b y
+// five factors keep them for the suffix products), phi += x_b y
 // (halved with the adjoint: every term sits in two rows), and with GRAD the
 // adjoint y pushed to the row's factors by prefix and suffix products.  NH
 // hot one-particle slots per environment are summed in registers.
@@ -1561,7 +1561,7 @@ __device__ __forceinline__ void remat_row(const RematArgs& p, const double2* x, 
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     const double2* xe = x + e * xs;
-    constexpr bool KEEP = NB <= 4;   // factor values kept in registers for the suffix products
+    constexpr bool KEEP = NB <= 5;   // factor values kept in registers for the suffix products
     double2 pre[NB], xf[KEEP ? NB : 1];
     if constexpr (KEEP) {
 #pragma unroll
